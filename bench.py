@@ -1,0 +1,169 @@
+#!/usr/bin/env python3
+"""Benchmark of the coupled LB + thermal time step on one MI355X.
+
+Workload: the 1024x512 boiling lattice (a = 2/49, T_s = 0.86 T_c,
+full-width heater at 0.10 T_c, G_w = 0.154 for ~60 deg), FP32 storage, inputs
+resident in HBM before the timed region.  A "step" is one time step of the
+whole hot path (LB launch + thermal launch, with the mass and heat-flux
+reductions) over the lattice.  --steps K steps are timed with HIP events on
+the library's stream around graph replays; value = nx*ny*K / time in MLUPS.
+
+Prints ONE JSON line.  --gpus N > 1 exits: this build runs on one GPU.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes per lattice update of the method in FP32 storage: the nine
+# populations and T, each read once and written once.
+ALG_BYTES_STEP = {"f32": 80, "f64": 160}
+# The LB launch's share of it: the nine populations read and written.
+ALG_BYTES_LB = {"f32": 72, "f64": 144}
+
+# HBM traffic of the LB launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
+# (KiB per dispatch, scaled by the same counters on a plain copy kernel), taken
+# on the kernel sources whose hash is recorded here; reported as null once the
+# sources change.
+MEASURED_TRAFFIC = None
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1501_03857_amd", "csrc")
+    for fn in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, fn), "rb") as fh:
+            h.update(fn.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(w, steps):
+    """The oracle, as it stands, on the host cores over a bounded sample."""
+    import oracle as O
+
+    tc = O.Tc(w.a, w.b, w.R)
+    rv, rl, _ = O.maxwell(w.a, w.b, w.R, w.omega, w.Ts_over_Tc * tc)
+    p = O.Params(nx=w.nx, ny=w.ny, a=w.a, b=w.b, sigma=w.sigma, g=w.g, Gw_bottom=w.Gw_bottom, rho_L=rl, rho_V=rv)
+    s = O.State(p, w.density(rl, rv), T_bottom=w.heater_T(tc))
+    t0 = time.perf_counter()
+    s.step(steps)
+    dt = time.perf_counter() - t0
+    return {"value": round(w.nx * w.ny * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": f"first {steps} steps of the {w.nx}x{w.ny} workload in FP64 "
+                      f"({w.nx * w.ny * steps:.3g} lattice updates, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="large", choices=["large", "large4096", "plain"])
+    ap.add_argument("--kernel-steps", type=int, default=400, help="steps timed per launch for the roofline")
+    ap.add_argument("--cpu-steps", type=int, default=100, help="oracle steps for the CPU baseline (0: skip)")
+    ap.add_argument("--profile", action="store_true", help="timed region only (for rocprofv3 runs)")
+    ap.add_argument("--copy-probe", action="store_true", help="run a plain 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the path would shard by instances or x-slabs, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    torch.cuda.set_device(0)
+    if args.copy_probe:
+        n = 1 << 28
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "launches": 5}))
+        return
+
+    from paper_1501_03857_amd import lbboil as L
+    from paper_1501_03857_amd import workloads as WL
+
+    w = {"large": WL.LARGE_1024x512, "large4096": WL.LARGE_4096x2048, "plain": WL.PLAIN_128x64}[args.workload]
+    store = "f32" if w.precision == "fp32" else "f64"
+    Tc, _ = L.eos_constants(w.a, w.b, w.R, w.omega)
+    rv, rl = L.coexistence(w.a, w.b, w.R, w.omega, w.Ts_over_Tc * Tc)
+    p = L.Params(nx=w.nx, ny=w.ny, precision=L.FP32 if store == "f32" else L.FP64, liquid_rows=w.liquid_rows,
+                 a=w.a, b=w.b, R=w.R, omega=w.omega, Ts_over_Tc=w.Ts_over_Tc, sigma=w.sigma, g=w.g,
+                 Gw_bottom=w.Gw_bottom, rho_L=rl, rho_V=rv)
+    d = L.Domain(p, T_bottom=w.heater_T(Tc), rho0=w.density(rl, rv))
+    cells = w.nx * w.ny
+    print(f"[bench] {w.name}: {w.nx}x{w.ny} {store} storage, warmup {args.warmup}, timed {args.steps}",
+          file=sys.stderr, flush=True)
+
+    d.step(args.warmup)
+    stream = torch.cuda.ExternalStream(d.stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    e0.record(stream)
+    d.step_async(args.steps)
+    e1.record(stream)
+    d.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = e0.elapsed_time(e1)
+    ms_step = ms / args.steps
+    mlups = cells * args.steps / (ms / 1e3) / 1e6
+    hf = d.heat_flux(local=False)
+    print(f"[bench] timed {args.steps} steps: {ms:.2f} ms (host wall {wall * 1e3:.1f} ms), {mlups:.1f} MLUPS, "
+          f"q_mean {hf['q_mean']:.6e}", file=sys.stderr, flush=True)
+    if args.profile:
+        print(json.dumps({"metric": "MLUPS", "value": round(mlups, 2), "ms_per_step": ms_step}))
+        return
+
+    ms_lb, ms_th, ms_seq = d.time_kernels(args.kernel_steps)
+    achieved = ALG_BYTES_LB[store] * cells / (ms_lb * 1e-3) / 1e9
+    traffic = None
+    if MEASURED_TRAFFIC and MEASURED_TRAFFIC.get("source_hash") == source_hash() \
+            and MEASURED_TRAFFIC.get("workload") == w.name:
+        traffic = MEASURED_TRAFFIC["bytes_per_launch"]
+    step_bytes = ALG_BYTES_STEP[store] * cells
+    cpu = cpu_baseline(w, args.cpu_steps) if args.cpu_steps > 0 else None
+
+    line = {
+        "metric": "MLUPS of coupled LB+thermal step, % HBM peak; batched vs plain; adjoint/fwd",
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "storage": store, "global_batch": 1,
+                   "parallelism": "none", "launches_per_step": 2, "graph_steps": 32},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "k_lb", "kernel_ms": round(ms_lb, 6),
+                     "alg_bytes_per_update": ALG_BYTES_LB[store]},
+        "step_roofline": {"achieved": round(step_bytes / (ms_step * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                          "unit": "GB/s", "frac": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                          "alg_bytes_per_update": ALG_BYTES_STEP[store]},
+        "kernels_ms": {"k_lb": round(ms_lb, 6), "k_thermal": round(ms_th, 6), "step_single_launch": round(ms_seq, 6)},
+        "heat_flux_mean": hf["q_mean"],
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,179 @@
+/*
+ * lbboil: MI355X (gfx950) library for the hybrid thermal pseudopotential
+ * lattice Boltzmann boiling model of Li, Kang, Francois, He and Luo,
+ * "Lattice Boltzmann modeling of boiling heat transfer: the boiling curve and
+ * the effects of wettability" (arXiv:1501.03857).
+ *
+ * One time step (Sec. 2) advances
+ *   - the D2Q9 distributions f by the MRT collision with the improved forcing
+ *     term (Eqs. (2), (4), (5), (8)) and streaming (Eq. (3)), driven by the
+ *     Peng-Robinson pseudopotential force (Eq. (7), Eq. (21)), the fluid-solid
+ *     force (Eq. (22)) and buoyancy (Eq. (9)), with Zou-He no-slip walls and
+ *     periodic x (Sec. 3.1);
+ *   - the temperature T by one classical RK4 step (Eqs. (19)-(20)) of the
+ *     finite-difference temperature equation (Eq. (18)) with rho and v frozen
+ *     at the old time level, Dirichlet walls T_b (bottom) and T_s (top);
+ * and samples the bottom-wall heat flux q(t) = <-lambda dT/dy>_x (Sec. 3.2).
+ *
+ * Conventions of every call:
+ *   - Return value: LBB_OK (0) or a negative LBB_E* code; nothing else crosses
+ *     the boundary.  lbb_last_error() returns a message for the last failure
+ *     of the calling thread (valid until that thread's next call).
+ *   - Handles are opaque, owned by the library, released with lbb_destroy.
+ *     A handle must not be used by two threads at once.
+ *   - All array arguments are caller-owned HOST buffers in row-major order
+ *     [ny][nx] (x fastest), FP64, unless stated otherwise.  The library never
+ *     keeps a pointer past the call.  Distribution arrays are [9][ny][nx] with
+ *     velocities ordered rest, E, N, W, S, NE, NW, SW, SE.
+ *   - Calls are synchronous with respect to the host unless the name ends in
+ *     _async.
+ *   - Lattice units throughout (c = dx = dt = 1, c_s^2 = 1/3).
+ */
+#ifndef LBBOIL_H
+#define LBBOIL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBB_OK 0
+#define LBB_EINVAL (-1)       /* invalid argument or parameter                 */
+#define LBB_ENOMEM (-2)       /* device or host allocation failed              */
+#define LBB_EDEVICE (-3)      /* HIP runtime error or no usable gfx950 device  */
+#define LBB_ENONFINITE (-4)   /* non-finite value, rho <= 0, T <= 0 or a
+                                 negative pseudopotential radicand detected     */
+#define LBB_EUNSUPPORTED (-5) /* request not supported by this build           */
+#define LBB_ESTATE (-6)       /* domain poisoned by an earlier LBB_ENONFINITE  */
+
+enum { LBB_FP64 = 0, LBB_FP32 = 1 };
+/* Test modes: COUPLED is the model; ISOTHERMAL freezes T; THERMAL_ONLY
+ * freezes f and advances only T with v = sum_a e_a f_a / rho. */
+enum { LBB_COUPLED = 0, LBB_ISOTHERMAL = 1, LBB_THERMAL_ONLY = 2 };
+
+/* Model parameters (Sec. 2 and Sec. 3.1).  lbb_default_params fills the
+ * paper's values (with a = 2/49; the paper's own runs use a = 3/49). */
+typedef struct lbb_params {
+    int32_t nx, ny;          /* lattice nodes; rows 0 and ny-1 are the walls   */
+    int32_t precision;       /* LBB_FP64, or LBB_FP32: f, T, rho, v stored in
+                                FP32; all arithmetic stays in FP64             */
+    int32_t periodic_y;      /* 1: no walls, periodic in y (test mode)         */
+    int32_t thermal_mode;    /* LBB_COUPLED / LBB_ISOTHERMAL / LBB_THERMAL_ONLY */
+    int32_t liquid_rows;     /* built-in initial state: rows j < liquid_rows
+                                are liquid (used when rho0 == NULL)            */
+    /* Peng-Robinson EOS, Eq. (21) */
+    double a, b, R, omega;
+    double Ts_over_Tc;       /* saturation temperature T_s / T_c               */
+    /* pseudopotential force, Eq. (7), and improved forcing, Eq. (8) */
+    double G, sigma;         /* G < 0                                          */
+    /* MRT relaxation rates of Eq. (4); the shear rate follows from nu        */
+    double s_rho, s_e, s_zeta, s_j, s_q;
+    double nu_L, nu_V;       /* kinematic viscosities of liquid and vapour     */
+    double rho_L, rho_V;     /* densities between which tau_nu is interpolated
+                                linearly; both 0: Maxwell coexistence at T_s   */
+    /* temperature equation, Eq. (18): lambda = rho c_v chi */
+    double cv, cv_chi;
+    double g;                /* gravity magnitude, Eq. (9), along -y           */
+    double Gw_bottom, Gw_top;/* fluid-solid strengths, Eq. (22)                */
+    double noise_amp;        /* built-in initial state: uniform noise in
+                                [-noise_amp, noise_amp) on rho                 */
+    uint64_t seed;           /* built-in initial state: SplitMix64 seed        */
+} lbb_params;
+
+typedef struct lbb_domain lbb_domain;
+
+/* Fill *p with the paper's parameters (Sec. 3.1): a = 2/49, b = 2/21, R = 1,
+ * omega = 0.344, T_s = 0.86 T_c, G = -1, sigma = 1.2, s = (1, 0.8, 0.8, 1, 1.1),
+ * nu_L = 0.1, nu_V = 0.5/3, c_v = 6, c_v chi = 0.028, g = 3e-5, G_w = 0,
+ * 128x64 FP64, liquid_rows = 0.6 ny, noise 1e-3, seed 1, rho_L = rho_V = 0. */
+void lbb_default_params(lbb_params *p);
+
+/* T_c and kappa(omega) of the Peng-Robinson EOS, Eq. (21):
+ * T_c = (a/b)(0.0778/0.45724)/R. */
+int lbb_eos_constants(double a, double b, double R, double omega, double *Tc, double *kappa);
+
+/* Maxwell equal-area coexistence densities of Eq. (21) at temperature T < T_c
+ * (the coexistence the paper starts from, Sec. 3.1).  EINVAL if T >= T_c. */
+int lbb_coexistence(double a, double b, double R, double omega, double T,
+                    double *rho_V, double *rho_L);
+
+/* Create a domain on the current HIP device (Sec. 3.1 set-up).
+ *   T_bottom [nx] : bottom-wall temperature T_b(x); NULL means T_s.
+ *   rho0 [ny*nx]  : initial density; NULL builds the layered state
+ *                   (liquid below vapour at rho_L/rho_V plus SplitMix64 noise
+ *                   of the (j*nx+i+1)-th output of the generator seeded with
+ *                   seed, top 53 bits mapped to [0,1), amplitude noise_amp).
+ * f starts at equilibrium at rest, T = T_s with the Dirichlet wall rows.
+ * EINVAL: nx < 3, ny < 4 (ny < 3 when periodic_y), G >= 0, non-finite or
+ * non-positive inputs, b*rho >= 1, rho_L == rho_V.  ENOMEM/EDEVICE on HIP
+ * failures.  Device memory: about (20 + 5) * nx * ny * sizeof(real) bytes. */
+int lbb_init_domain(const lbb_params *p, const double *T_bottom, const double *rho0,
+                    lbb_domain **out);
+
+/* Replace the state: f = f_eq(rho, u) (equilibrium with velocity u) and T
+ * (wall rows of T are then reset to T_b and T_s unless periodic_y).  ux, uy,
+ * T may be NULL (zero velocity; T_s).  Resets the step counter and the
+ * heat-flux average. */
+int lbb_set_fields(lbb_domain *d, const double *rho, const double *ux, const double *uy,
+                   const double *T);
+
+/* Advance n >= 0 time steps and append one heat-flux sample per step (state
+ * after the step).  On LBB_ENONFINITE the message names the first failing
+ * step and the domain is poisoned (LBB_ESTATE) until lbb_load_state or
+ * lbb_set_fields. */
+int lbb_step(lbb_domain *d, int64_t n);
+
+/* Enqueue n steps on the library stream without waiting and without the
+ * error check (for timing).  lbb_sync waits and performs the check. */
+int lbb_step_async(lbb_domain *d, int64_t n);
+int lbb_sync(lbb_domain *d);
+/* The HIP stream (hipStream_t) the library launches on, so a caller can
+ * record events around lbb_step_async. */
+void *lbb_stream(lbb_domain *d);
+
+/* Advance n >= 1 steps with single launches (no graph) and a HIP event
+ * before and after each kernel on the library stream; returns the mean
+ * duration in milliseconds of the LB launch (collision, forces, streaming)
+ * and of the thermal launch (RK4 temperature step), and the mean wall time
+ * per step of the whole sequence.  For measurement only; the state advances
+ * exactly as with lbb_step. */
+int lbb_time_kernels(lbb_domain *d, int64_t n, double *ms_lb, double *ms_thermal, double *ms_step);
+
+/* Read the current state, widened to FP64: rho = sum_a f_a; v from Eq. (6)
+ * with the total force of the current state; T; and f (post-streaming, wall
+ * rule applied).  Any pointer may be NULL. */
+int lbb_read_fields(lbb_domain *d, double *rho, double *ux, double *uy, double *T, double *f);
+
+/* Bottom-wall heat flux (Sec. 3.2): q_now = q(t) of the current state, q_mean
+ * = mean of the samples since creation or lbb_reset_average, n_samples their
+ * count; q_local [nx] (optional) = q_w(x) of the current state.
+ * q_w = -c_v chi rho (-3 T_0 + 4 T_1 - T_2)/2 at each bottom-wall node. */
+int lbb_wall_heat_flux(lbb_domain *d, double *q_now, double *q_mean, double *q_local,
+                       int64_t *n_samples);
+int lbb_reset_average(lbb_domain *d);
+
+/* Change the bottom-wall temperature T_b(x) [nx] (the paper raises the
+ * superheat mid-run, Sec. 3.2) or the bottom-wall strength G_w (Eq. (22)). */
+int lbb_set_heater(lbb_domain *d, const double *T_bottom);
+int lbb_set_wettability(lbb_domain *d, double Gw_bottom);
+
+/* Checkpoint: *len in/out.  With buf == NULL, *len receives the size needed.
+ * The blob holds f, T, T_b, G_w, the step counter and the heat-flux
+ * accumulators, with a parameter hash and a checksum; load rejects a blob of
+ * another domain shape/parameters or a corrupted one (EINVAL). */
+int lbb_save_state(lbb_domain *d, void *buf, size_t *len);
+int lbb_load_state(lbb_domain *d, const void *buf, size_t len);
+
+/* Current step count, grid shape and device bytes held by the domain. */
+int lbb_info(lbb_domain *d, int64_t *t, int32_t *nx, int32_t *ny, int64_t *device_bytes);
+
+int lbb_destroy(lbb_domain *d);
+
+const char *lbb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBBOIL_H */

@@ -17,6 +17,7 @@ from .oracle import (  # noqa: F401
     ISOTHERMAL,
     THERMAL_ONLY,
     lib,
+    num_threads,
     Tc,
     kappa,
     phi,

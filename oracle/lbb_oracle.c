@@ -100,6 +100,19 @@ static void set_err(const char *msg, int64_t t)
 
 const char *orc_last_error(void) { return g_err; }
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+/* threads the row loops use (1 without OpenMP) */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 void orc_lattice(int32_t ex[9], int32_t ey[9], double W[9], double wpsi[9], double M[81])
 {
     for (int a = 0; a < 9; ++a) {

@@ -98,6 +98,7 @@ void orc_reset_average(orc_state *s);
 void orc_set_heater(orc_state *s, const double *T_bottom);
 void orc_set_wettability(orc_state *s, double Gw_bottom);
 const char *orc_last_error(void);
+int orc_num_threads(void);
 void orc_constants(const orc_state *s, double *Tc, double *kappa, double *Ts);
 /* Copy/restore the full state (f, T, time, heat-flux accumulators). */
 int64_t orc_state_size(const orc_state *s);

@@ -115,6 +115,7 @@ lib.orc_reset_average.argtypes = [C.c_void_p]
 lib.orc_set_heater.argtypes = [C.c_void_p, _pd]
 lib.orc_set_wettability.argtypes = [C.c_void_p, _d]
 lib.orc_last_error.restype = C.c_char_p
+lib.orc_num_threads.restype = C.c_int
 lib.orc_constants.argtypes = [C.c_void_p, _pd, _pd, _pd]
 lib.orc_state_size.restype = _i64
 lib.orc_state_size.argtypes = [C.c_void_p]
@@ -131,6 +132,10 @@ def _ptr(a):
 
 def _f64(a):
     return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+def num_threads() -> int:
+    return lib.orc_num_threads()
 
 
 def Tc(a, b, R=1.0):

@@ -1,0 +1,726 @@
+// Device code of the lbboil library: the two kernels of one time step of the
+// hybrid thermal pseudopotential LB boiling model (arXiv:1501.03857, Sec. 2)
+// plus the small kernels used at set-up and read-back.  gfx950, wave64.
+//
+// Data layout in HBM (structure of arrays, x fastest, row pitch nx):
+//   f[2][9][ny][nx]  post-streaming distributions, double-buffered.  Wall-row
+//                    populations that would arrive from outside the lattice
+//                    are never written; every reader completes them with the
+//                    Zou-He rule from the populations of the same node.
+//   T[2][ny][nx]     temperature stored as T - T_ref (T_ref = 0 in FP64,
+//                    T_s in FP32 for precision), double-buffered; the wall
+//                    rows hold the Dirichlet values in both buffers.
+//   rho, vx, vy      density and the velocity the temperature equation sees,
+//                    written by the LB kernel for the thermal kernel.
+//   partials         per-block FP64 partial sums of mass and heat flux.
+//
+// One step t -> t+1 is two launches:
+//   k_lb      : per tile (64x8, halo 1): rho and psi (FP64 EOS, Eq. (21)) of
+//               the tile and its halo into LDS; per interior node the forces
+//               (Eqs. (7), (9), (22)), velocity (Eq. (6)), MRT collision with
+//               the improved forcing (Eqs. (2), (4), (5), (8)) and push
+//               streaming (Eq. (3)) into the other buffer; FP64 mass partials
+//               of the streamed state (exact identity, so the next step's
+//               rho_ave needs no extra pass).  One extra block reduces the
+//               heat-flux partials of the previous thermal launch.
+//   k_thermal: per tile (64x8, halo 4): RK4 (Eqs. (19)-(20)) of Eq. (18) in
+//               LDS with the region shrinking by one node per stage; FP64
+//               heat-flux partials of the new state on the bottom tile row.
+//               One extra block reduces the mass partials of k_lb into
+//               rho_ave for the next step.
+// All reductions run in a fixed order, so results are bitwise reproducible.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbb {
+
+constexpr int NT = 256;   // threads per block (4 waves)
+constexpr int TXA = 64;   // LB tile
+constexpr int TYA = 8;
+constexpr int TXB = 64;   // thermal tile
+constexpr int TYB = 8;
+constexpr int HB = 4;     // thermal halo (RK4 has four stencil stages)
+
+enum : int { MODE_COUPLED = 0, MODE_ISOTHERMAL = 1, MODE_THERMAL_ONLY = 2 };
+enum : int { ERR_RHO = 1, ERR_PSI = 2, ERR_T = 4 };
+
+struct DevParams {
+    int nx, ny;
+    int periodic_y, mode;
+    double a, b, R, Tc, kappa;
+    double Ts, T_ref;            // saturation temperature, storage offset of T
+    double G, sigma;
+    double s_rho, s_e, s_zeta, s_j, s_q;
+    double tau_V, tau_slope;     // tau_nu(rho) = tau_V + (rho - rho_V) tau_slope
+    double rho_V;
+    double cv, chi, cv_chi;
+    double g, Gw_bottom, Gw_top;
+    double sig_e, sig_z;         // sigma/(tau_e - 1/2), sigma/(tau_zeta - 1/2)
+};
+
+// Device-resident scalars of one domain.  tA is the state index seen by the
+// LB launch, tB the one seen by the thermal launch; each is written only by
+// the other launch's reduction block, so no launch reads a counter it writes.
+struct Scalars {
+    double rho_ave;
+    double q_now;
+    double q_sum;
+    long long n_samples;
+    long long last_counted;      // state index of the last heat-flux sample
+    long long tA;
+    long long tB;
+    unsigned long long err_step; // first failing step, ~0 if none
+    unsigned int err_code;
+    unsigned int pad;
+};
+
+__device__ __forceinline__ int wrapi(int i, int n)
+{
+    int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+// Zou-He completion of a wall node with zero wall velocity (Sec. 3.1): the
+// three populations arriving from outside follow from the known ones.
+__device__ __forceinline__ void zou_he(double f[9], int bottom)
+{
+    const double d13 = f[1] - f[3];
+    if (bottom) {
+        f[2] = f[4];
+        f[5] = f[7] - 0.5 * d13;
+        f[6] = f[8] + 0.5 * d13;
+    } else {
+        f[4] = f[2];
+        f[7] = f[5] + 0.5 * d13;
+        f[8] = f[6] - 0.5 * d13;
+    }
+}
+
+// Load the 9 populations of node c, completing wall nodes when the state
+// came from streaming (every mode but THERMAL_ONLY, where f is frozen).
+template <typename S>
+__device__ __forceinline__ void load_node(const DevParams &P, const S *__restrict__ f, size_t N, size_t c,
+                                          int gy, double fl[9])
+{
+#pragma unroll
+    for (int a = 0; a < 9; ++a) fl[a] = (double)f[(size_t)a * N + c];
+    if (!P.periodic_y && P.mode != MODE_THERMAL_ONLY) {
+        if (gy == 0) zou_he(fl, 1);
+        else if (gy == P.ny - 1) zou_he(fl, 0);
+    }
+}
+
+// psi = sqrt(2 (p_EOS - rho/3) / G) with the Peng-Robinson p_EOS (Eq. (21)),
+// always in FP64.  Returns a negative value on a negative radicand.
+__device__ __forceinline__ double pseudopotential(const DevParams &P, double rho, double T)
+{
+    const double s = 1.0 + P.kappa * (1.0 - sqrt(T / P.Tc));
+    const double phi = s * s;
+    const double p = rho * P.R * T / (1.0 - P.b * rho) -
+                     P.a * phi * rho * rho / (1.0 + 2.0 * P.b * rho - P.b * P.b * rho * rho);
+    const double r = 2.0 * (p - rho / 3.0) / P.G;
+    return (r >= 0.0) ? sqrt(r) : -1.0;
+}
+
+__device__ __forceinline__ void flag_error(Scalars *sc, long long t, unsigned code)
+{
+    atomicMin(&sc->err_step, (unsigned long long)t);
+    atomicOr(&sc->err_code, code);
+}
+
+// Wave64 + block sum of one double per thread, result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double *red /* [NT/64] */)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < NT / 64; ++k) s += red[k];
+    return s;
+}
+
+// Fixed-order sum of n doubles by one block; result valid in thread 0.
+__device__ __forceinline__ double block_sum_array(const double *__restrict__ a, int n, double *red)
+{
+    double s = 0.0;
+    for (int k = threadIdx.x; k < n; k += NT) s += a[k];
+    return block_sum(s, red);
+}
+
+// Heat-flux bookkeeping: q of state t from the partial sums over x; counted
+// once per state index (t > last_counted), never for the initial state.
+__device__ __forceinline__ void reduce_heat_flux(const double *__restrict__ hf_part, int n_hf, int nx,
+                                                 Scalars *sc, long long t)
+{
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int k = 0; k < n_hf; ++k) s += hf_part[k];
+        const double q = s / (double)nx;
+        sc->q_now = q;
+        if (t > sc->last_counted) {
+            sc->q_sum += q;
+            sc->n_samples += 1;
+            sc->last_counted = t;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Velocity-independent pieces shared by the LB step and the read-back.
+// Total force on an interior node (Eq. (7) + Eq. (22) + Eq. (9)) and
+// Q = |F_m|^2 / psi^2 (Eq. (8)), from the LDS psi tile with a halo of one.
+// Wall rows carry no force (F = 0, Q = 0): the paper does not apply F_m
+// there (Sec. 3.2), and any body force on a Zou-He node would become a mass
+// flux through the wall.  The fluid-solid force acts on the rows next to the
+// walls, with the wall rows as the solid of Eq. (22).
+template <int W>
+__device__ __forceinline__ void node_force(const DevParams &P, const double *psi_s, int lx, int ly, int gy,
+                                           double rho, double rho_ave, double &Fx, double &Fy, double &Q)
+{
+    Fx = Fy = Q = 0.0;
+    if (!P.periodic_y && (gy == 0 || gy == P.ny - 1)) return;
+    const int c = (ly + 1) * W + (lx + 1);
+    const double pc = psi_s[c];
+    const double pE = psi_s[c + 1], pW = psi_s[c - 1], pN = psi_s[c + W], pS = psi_s[c - W];
+    const double pNE = psi_s[c + W + 1], pNW = psi_s[c + W - 1], pSW = psi_s[c - W - 1], pSE = psi_s[c - W + 1];
+    // sum_a w_a psi(x + e_a) e_a with w = 1/3 (axes), 1/12 (diagonals)
+    const double sx = (pE - pW) * (1.0 / 3.0) + (pNE - pNW - pSW + pSE) * (1.0 / 12.0);
+    const double sy = (pN - pS) * (1.0 / 3.0) + (pNE + pNW - pSW - pSE) * (1.0 / 12.0);
+    Fx = -P.G * pc * sx;
+    Fy = -P.G * pc * sy;
+    Q = P.G * P.G * (sx * sx + sy * sy);
+    // fluid-solid force on the rows next to the walls (wall rows are the solid)
+    if (!P.periodic_y) {
+        if (gy == 1) Fy += P.Gw_bottom * pc * pc * (1.0 / 6.0);
+        if (gy == P.ny - 2) Fy -= P.Gw_top * pc * pc * (1.0 / 6.0);
+    }
+    // buoyancy, Eq. (9)
+    Fy -= (rho - rho_ave) * P.g;
+}
+
+// MRT collision of one node (Eqs. (2), (4), (5), (8)) in moment space with
+// the D2Q9 basis (rho, e, zeta, jx, qx, jy, qy, pxx, pxy); returns f*.
+__device__ __forceinline__ void collide(const DevParams &P, double f[9], double rho, double vx, double vy,
+                                        double Fx, double Fy, double Q)
+{
+    const double s14 = f[1] + f[2] + f[3] + f[4];
+    const double s58 = f[5] + f[6] + f[7] + f[8];
+    const double m_e = -(4) * f[0] - s14 + (2) * s58;
+    const double m_z = (4) * f[0] - (2) * s14 + s58;
+    const double jx = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
+    const double qx = -(2) * f[1] + (2) * f[3] + f[5] - f[6] - f[7] + f[8];
+    const double jy = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
+    const double qy = -(2) * f[2] + (2) * f[4] + f[5] + f[6] - f[7] - f[8];
+    const double pxx = f[1] - f[2] + f[3] - f[4];
+    const double pxy = f[5] - f[6] + f[7] - f[8];
+
+    const double v2 = vx * vx + vy * vy;
+    const double vF = vx * Fx + vy * Fy;
+    const double s_e = (P.s_e), s_z = (P.s_zeta), s_j = (P.s_j), s_q = (P.s_q);
+    const double s_nu = (1) / ((P.tau_V) + (rho - (P.rho_V)) * (P.tau_slope));
+
+    // m* = m - L (m - m_eq) + (I - L/2) S
+    const double e_s = m_e - s_e * (m_e - rho * ((-2) + (3) * v2)) + ((1) - (0.5) * s_e) * ((6) * vF + (P.sig_e) * Q);
+    const double z_s = m_z - s_z * (m_z - rho * ((1) - (3) * v2)) + ((1) - (0.5) * s_z) * (-(6) * vF - (P.sig_z) * Q);
+    const double jx_s = jx - s_j * (jx - rho * vx) + ((1) - (0.5) * s_j) * Fx;
+    const double qx_s = qx - s_q * (qx + rho * vx) - ((1) - (0.5) * s_q) * Fx;
+    const double jy_s = jy - s_j * (jy - rho * vy) + ((1) - (0.5) * s_j) * Fy;
+    const double qy_s = qy - s_q * (qy + rho * vy) - ((1) - (0.5) * s_q) * Fy;
+    const double pxx_s = pxx - s_nu * (pxx - rho * (vx * vx - vy * vy)) + ((1) - (0.5) * s_nu) * (2) * (vx * Fx - vy * Fy);
+    const double pxy_s = pxy - s_nu * (pxy - rho * vx * vy) + ((1) - (0.5) * s_nu) * (vx * Fy + vy * Fx);
+    // rho* = rho (s_rho drops out: m_eq,rho = rho and S_rho = 0)
+
+    // f* = M^{-1} m* with M^{-1} = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
+    const double r9 = rho * (1.0 / 9.0);
+    const double e36 = e_s * (1.0 / 36.0), z36 = z_s * (1.0 / 36.0);
+    const double jx6 = jx_s * (1.0 / 6.0), jy6 = jy_s * (1.0 / 6.0);
+    const double qx12 = qx_s * (1.0 / 12.0), qy12 = qy_s * (1.0 / 12.0);
+    const double pxx4 = pxx_s * (0.25), pxy4 = pxy_s * (0.25);
+    const double axis = r9 - e36 - (2) * z36;
+    const double diag = r9 + (2) * e36 + z36;
+    f[0] = r9 - (4) * e36 + (4) * z36;
+    f[1] = axis + jx6 - (2) * qx12 + pxx4;
+    f[2] = axis + jy6 - (2) * qy12 - pxx4;
+    f[3] = axis - jx6 + (2) * qx12 + pxx4;
+    f[4] = axis - jy6 + (2) * qy12 - pxx4;
+    f[5] = diag + jx6 + jy6 + qx12 + qy12 + pxy4;
+    f[6] = diag - jx6 + jy6 - qx12 + qy12 - pxy4;
+    f[7] = diag - jx6 - jy6 - qx12 - qy12 + pxy4;
+    f[8] = diag + jx6 - jy6 + qx12 - qy12 - pxy4;
+}
+
+__constant__ const int kEX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__constant__ const int kEY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+
+// Phase 1 shared by the LB step and the read-back: rho and psi of the tile
+// and a halo of one into LDS.  Nodes beyond a wall get psi = 0 (never read).
+template <typename S, int TX, int TY>
+__device__ __forceinline__ void tile_psi(const DevParams &P, const S *__restrict__ fin, const S *__restrict__ Tin,
+                                         int x0, int y0, double *psi_s, Scalars *sc, long long t)
+{
+    constexpr int W = TX + 2, H = TY + 2;
+    const size_t N = (size_t)P.nx * P.ny;
+    for (int k = threadIdx.x; k < W * H; k += NT) {
+        const int lx = k % W - 1, ly = k / W - 1;
+        const int gx = wrapi(x0 + lx, P.nx);
+        int gy = y0 + ly;
+        if (P.periodic_y) gy = wrapi(gy, P.ny);
+        else if (gy < 0 || gy >= P.ny) {
+            psi_s[k] = 0.0;
+            continue;
+        }
+        const size_t c = (size_t)gy * P.nx + gx;
+        double fl[9];
+        load_node(P, fin, N, c, gy, fl);
+        double rho = 0.0;
+        {
+            double r = fl[0];
+#pragma unroll
+            for (int a = 1; a < 9; ++a) r += fl[a];
+            rho = r;
+        }
+        const double T = P.T_ref + (double)Tin[c];
+        const double psi = pseudopotential(P, rho, T);
+        if (!(rho > 0.0) || !(rho < 1e300)) flag_error(sc, t, ERR_RHO);
+        if (!(psi >= 0.0) || !(psi < 1e300)) flag_error(sc, t, ERR_PSI);
+        psi_s[k] = psi;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// LB step: forces, collision and push streaming; mass partials.
+template <typename S>
+__global__ __launch_bounds__(NT) void k_lb(DevParams P, const S *__restrict__ fin, S *__restrict__ fout,
+                                           const S *__restrict__ Tin, S *__restrict__ rho_o,
+                                           S *__restrict__ vx_o, S *__restrict__ vy_o,
+                                           double *__restrict__ mass_part, const double *__restrict__ hf_part,
+                                           int n_hf, Scalars *__restrict__ sc, int nbx, int nby)
+{
+    __shared__ double psi_s[(TXA + 2) * (TYA + 2)];
+    __shared__ double red[NT / 64];
+    const long long t = sc->tA;
+    if ((int)blockIdx.x == nbx * nby) {
+        reduce_heat_flux(hf_part, n_hf, P.nx, sc, t);
+        if (threadIdx.x == 0) sc->tB = t;  // the thermal launch of this step
+        return;
+    }
+    const int bx = blockIdx.x % nbx, by = blockIdx.x / nbx;
+    const int x0 = bx * TXA, y0 = by * TYA;
+    const size_t N = (size_t)P.nx * P.ny;
+    const bool walls = !P.periodic_y;
+    const bool frozen = P.mode == MODE_THERMAL_ONLY;
+
+    if (!frozen) tile_psi<S, TXA, TYA>(P, fin, Tin, x0, y0, psi_s, sc, t);
+    __syncthreads();
+    const double rho_ave = sc->rho_ave;
+
+    double mass = 0.0;
+    const int tx = threadIdx.x % TXA;
+    for (int ly = threadIdx.x / TXA; ly < TYA; ly += NT / TXA) {
+        const int gx = x0 + tx, gy = y0 + ly;
+        if (gx >= P.nx || gy >= P.ny) continue;
+        const size_t c = (size_t)gy * P.nx + gx;
+        double fl[9];
+        load_node(P, fin, N, c, gy, fl);
+        double rho = fl[0];
+#pragma unroll
+        for (int a = 1; a < 9; ++a) rho += fl[a];
+        const double jx = fl[1] - fl[3] + fl[5] - fl[6] - fl[7] + fl[8];
+        const double jy = fl[2] - fl[4] + fl[5] + fl[6] - fl[7] - fl[8];
+        const bool wall_row = walls && (gy == 0 || gy == P.ny - 1);
+        if (frozen) {
+            // THERMAL_ONLY: f is frozen, the temperature sees sum e f / rho
+            rho_o[c] = S(rho);
+            vx_o[c] = wall_row ? S(0) : S(jx / rho);
+            vy_o[c] = wall_row ? S(0) : S(jy / rho);
+            double m = 0.0;
+#pragma unroll
+            for (int a = 0; a < 9; ++a) m += fl[a];
+            mass += m;
+            continue;
+        }
+        double Fx, Fy, Q;
+        node_force<TXA + 2>(P, psi_s, tx, ly, gy, rho, rho_ave, Fx, Fy, Q);
+        const double vx = (jx + 0.5 * Fx) / rho;
+        const double vy = (jy + 0.5 * Fy) / rho;
+        rho_o[c] = S(rho);
+        vx_o[c] = wall_row ? S(0) : S(vx);
+        vy_o[c] = wall_row ? S(0) : S(vy);
+        collide(P, fl, rho, vx, vy, Fx, Fy, Q);
+        // round to the storage precision once; the mass partial sees what is stored
+#pragma unroll
+        for (int a = 0; a < 9; ++a) fl[a] = (double)S(fl[a]);
+        // push streaming, Eq. (3); populations leaving through a wall are
+        // dropped.  Mass of the streamed state: each population counts once,
+        // except those that leave through a wall (0) and those that arrive on
+        // a wall row, whose Zou-He partners are reconstructed with the same
+        // sum (2).
+        const int xe = gx + 1 == P.nx ? 0 : gx + 1;
+        const int xw = gx == 0 ? P.nx - 1 : gx - 1;
+        int yn = gy + 1, ys = gy - 1;
+        if (P.periodic_y) {
+            if (yn == P.ny) yn = 0;
+            if (ys < 0) ys = P.ny - 1;
+        }
+        const bool has_n = yn < P.ny, has_s = ys >= 0;
+        const size_t rowc = (size_t)gy * P.nx, rown = (size_t)yn * P.nx, rows = (size_t)ys * P.nx;
+        fout[0 * N + rowc + gx] = S(fl[0]);
+        fout[1 * N + rowc + xe] = S(fl[1]);
+        fout[3 * N + rowc + xw] = S(fl[3]);
+        if (has_n) {
+            fout[2 * N + rown + gx] = S(fl[2]);
+            fout[5 * N + rown + xe] = S(fl[5]);
+            fout[6 * N + rown + xw] = S(fl[6]);
+        }
+        if (has_s) {
+            fout[4 * N + rows + gx] = S(fl[4]);
+            fout[7 * N + rows + xw] = S(fl[7]);
+            fout[8 * N + rows + xe] = S(fl[8]);
+        }
+        const double up = fl[2] + fl[5] + fl[6];
+        const double dn = fl[4] + fl[7] + fl[8];
+        double m = fl[0] + fl[1] + fl[3];
+        const double wu = !walls ? 1.0 : (gy == P.ny - 1 ? 0.0 : (gy == P.ny - 2 ? 2.0 : 1.0));
+        const double wd = !walls ? 1.0 : (gy == 0 ? 0.0 : (gy == 1 ? 2.0 : 1.0));
+        m += wu * up + wd * dn;
+        mass += m;
+    }
+    const double bm = block_sum(mass, red);
+    if (threadIdx.x == 0) mass_part[blockIdx.x] = bm;
+}
+
+// ---------------------------------------------------------------------------
+// Thermal step: RK4 of Eq. (18) with rho, v frozen; heat-flux partials.
+//   K = -(ax d_x T + ay d_y T) + chi lap T - cw T + cq T phi'(T)
+// with ax = vx - chi d_x rho / rho, ay likewise, w = div v / (rho c_v),
+// cw = A(rho) w, cq = B(rho) w, A = rho R/(1 - b rho),
+// B = a rho^2/(1 + 2 b rho - b^2 rho^2), so that (dp/dT)_rho = A - B phi'(T)
+// and T phi'(T) = kappa^2 T/T_c - kappa (1 + kappa) sqrt(T/T_c).
+template <typename S>
+__global__ __launch_bounds__(NT) void k_thermal(DevParams P, const S *__restrict__ Tin, S *__restrict__ Tout,
+                                                const S *__restrict__ rho_i, const S *__restrict__ vx_i,
+                                                const S *__restrict__ vy_i, const S *__restrict__ fnew,
+                                                double *__restrict__ hf_part, const double *__restrict__ mass_part,
+                                                int n_mass, Scalars *__restrict__ sc, int nbx, int nby)
+{
+    constexpr int W = TXB + 2 * HB, H = TYB + 2 * HB, A = W * H;
+    __shared__ double T0[A];
+    __shared__ double cf[4][A];
+    __shared__ double un[3][A];   // rho, vx, vy; then stage buffers Ta, Tb and acc
+    __shared__ double red[NT / 64];
+    const long long t = sc->tB;
+    if ((int)blockIdx.x == nbx * nby) {
+        const double m = block_sum_array(mass_part, n_mass, red);
+        if (threadIdx.x == 0) {
+            sc->rho_ave = m / ((double)P.nx * (double)P.ny);
+            sc->tA = t + 1;
+        }
+        return;
+    }
+    const int bx = blockIdx.x % nbx, by = blockIdx.x / nbx;
+    const int x0 = bx * TXB, y0 = by * TYB;
+    const bool walls = !P.periodic_y;
+    const bool run = P.mode != MODE_ISOTHERMAL;
+
+    auto gyof = [&](int ly, int &gy) -> bool {  // false if outside the lattice
+        gy = y0 + ly;
+        if (P.periodic_y) {
+            gy = wrapi(gy, P.ny);
+            return true;
+        }
+        return gy >= 0 && gy < P.ny;
+    };
+
+    // load T, rho, v on the tile with a halo of HB
+    for (int k = threadIdx.x; k < A; k += NT) {
+        const int lx = k % W - HB, ly = k / W - HB;
+        int gy;
+        if (!gyof(ly, gy)) continue;
+        const size_t c = (size_t)gy * P.nx + wrapi(x0 + lx, P.nx);
+        T0[k] = (double)Tin[c];
+        if (run) {
+            un[0][k] = (double)rho_i[c];
+            un[1][k] = (double)vx_i[c];
+            un[2][k] = (double)vy_i[c];
+        }
+    }
+    __syncthreads();
+
+    const double chi = double(P.chi);
+    if (run) {
+        // per-node coefficients on the tile with a halo of HB - 1
+        for (int k = threadIdx.x; k < A; k += NT) {
+            const int lx = k % W - HB, ly = k / W - HB;
+            if (lx < -(HB - 1) || lx >= TXB + HB - 1 || ly < -(HB - 1) || ly >= TYB + HB - 1) continue;
+            int gy;
+            if (!gyof(ly, gy)) continue;
+            if (walls && (gy == 0 || gy == P.ny - 1)) continue;
+            const double *r = un[0], *u = un[1], *v = un[2];
+            const double rr = (double)r[k];
+            const double drx = (r[k + 1] - r[k - 1]) * double(1.0 / 3.0) +
+                          (r[k + W + 1] - r[k + W - 1] + r[k - W + 1] - r[k - W - 1]) * double(1.0 / 12.0);
+            const double dry = (r[k + W] - r[k - W]) * double(1.0 / 3.0) +
+                          (r[k + W + 1] + r[k + W - 1] - r[k - W + 1] - r[k - W - 1]) * double(1.0 / 12.0);
+            const double dux = (u[k + 1] - u[k - 1]) * double(1.0 / 3.0) +
+                          (u[k + W + 1] - u[k + W - 1] + u[k - W + 1] - u[k - W - 1]) * double(1.0 / 12.0);
+            const double dvy = (v[k + W] - v[k - W]) * double(1.0 / 3.0) +
+                          (v[k + W + 1] + v[k + W - 1] - v[k - W + 1] - v[k - W - 1]) * double(1.0 / 12.0);
+            const double w = (double)(dux + dvy) / (rr * P.cv);
+            const double Acoef = rr * P.R / (1.0 - P.b * rr);
+            const double Bcoef = P.a * rr * rr / (1.0 + 2.0 * P.b * rr - P.b * P.b * rr * rr);
+            cf[0][k] = u[k] - chi * drx / double(rr);
+            cf[1][k] = v[k] - chi * dry / double(rr);
+            cf[2][k] = double(Acoef * w);
+            cf[3][k] = double(Bcoef * w);
+        }
+    }
+    __syncthreads();
+
+    double *Ta = un[0], *Tb = un[1], *acc = un[2];
+    const double kap = double(P.kappa), k1k = double(P.kappa * (1.0 + P.kappa)), k2 = double(P.kappa * P.kappa / P.Tc);
+    const double inv_Tc = double(1.0 / P.Tc), Tref = double(P.T_ref);
+    (void)kap;
+    if (run) {
+        // stage k reads `in` on radius r+1 and writes T0 + c h on radius r
+        const double *in = T0;
+        double *outs[3] = {Ta, Tb, Ta};
+        const double cst[4] = {double(0.5), double(0.5), double(1.0), double(0.0)};
+        const double wst[4] = {double(1), double(2), double(2), double(1)};
+#pragma unroll 1
+        for (int st = 0; st < 4; ++st) {
+            const int r = HB - 1 - st;
+            double *out = st < 3 ? outs[st] : nullptr;
+            for (int k = threadIdx.x; k < A; k += NT) {
+                const int lx = k % W - HB, ly = k / W - HB;
+                if (lx < -r || lx >= TXB + r || ly < -r || ly >= TYB + r) continue;
+                int gy;
+                if (!gyof(ly, gy)) continue;
+                const bool interior = lx >= 0 && lx < TXB && ly >= 0 && ly < TYB;
+                double h = double(0);
+                if (!(walls && (gy == 0 || gy == P.ny - 1))) {
+                    const double tE = in[k + 1], tW = in[k - 1], tN = in[k + W], tS = in[k - W];
+                    const double tNE = in[k + W + 1], tNW = in[k + W - 1], tSW = in[k - W - 1], tSE = in[k - W + 1];
+                    const double tc = in[k];
+                    const double dTx = (tE - tW) * double(1.0 / 3.0) + (tNE - tNW + tSE - tSW) * double(1.0 / 12.0);
+                    const double dTy = (tN - tS) * double(1.0 / 3.0) + (tNE + tNW - tSE - tSW) * double(1.0 / 12.0);
+                    const double lap = (tE + tW + tN + tS) * double(2.0 / 3.0) + (tNE + tNW + tSE + tSW) * double(1.0 / 6.0) -
+                                  double(10.0 / 3.0) * tc;
+                    const double T = Tref + tc;
+                    const double sq = sqrt(T * inv_Tc);
+                    const double Tphi = k2 * T - k1k * sq;
+                    h = -(cf[0][k] * dTx + cf[1][k] * dTy) + chi * lap - cf[2][k] * T + cf[3][k] * Tphi;
+                }
+                if (out) out[k] = T0[k] + cst[st] * h;
+                if (interior) acc[k] = (st == 0 ? double(0) : acc[k]) + wst[st] * h;
+            }
+            __syncthreads();
+            in = out;
+        }
+    }
+
+    // write the new interior temperature (wall rows keep their values)
+    const int tx = threadIdx.x % TXB;
+    for (int ly = threadIdx.x / TXB; ly < TYB; ly += NT / TXB) {
+        const int gx = x0 + tx;
+        int gy;
+        if (gx >= P.nx || !gyof(ly, gy) || y0 + ly >= P.ny) continue;
+        const int k = (ly + HB) * W + tx + HB;
+        const bool wall_row = walls && (gy == 0 || gy == P.ny - 1);
+        double Tn = T0[k];
+        if (run && !wall_row) {
+            Tn = T0[k] + acc[k] / double(6);
+            const double Ta_ = P.T_ref + (double)Tn;
+            if (!(Ta_ > 0.0) || !(Ta_ < 1e300)) flag_error(sc, t, ERR_T);
+            Tout[(size_t)gy * P.nx + gx] = S(Tn);
+            Tn = (double)S(Tn);  // the heat flux sees the stored value
+        }
+        acc[k] = Tn;
+    }
+    __syncthreads();
+
+    // heat-flux partials of the new state (bottom tile row only)
+    if (walls && by == 0 && threadIdx.x < TXB) {
+        const int gx = x0 + threadIdx.x;
+        double qw = 0.0;
+        if (gx < P.nx) {
+            const size_t N = (size_t)P.nx * P.ny;
+            double fl[9];
+            load_node(P, fnew, N, (size_t)gx, 0, fl);
+            double r0 = fl[0];
+#pragma unroll
+            for (int a = 1; a < 9; ++a) r0 += fl[a];
+            const int k1 = (1 + HB) * W + threadIdx.x + HB, k2i = (2 + HB) * W + threadIdx.x + HB;
+            const double t0 = (double)T0[HB * W + threadIdx.x + HB];
+            const double t1 = (double)acc[k1], t2 = (double)acc[k2i];
+            qw = -P.cv_chi * (double)r0 * (-3.0 * t0 + 4.0 * t1 - t2) / 2.0;
+        }
+        double s = qw;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+        if (threadIdx.x == 0) hf_part[bx] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Set-up and read-back kernels.
+
+// f = f_eq(rho, u), T as given (FP64 inputs), wall rows of T at T_b and T_s.
+template <typename S>
+__global__ void k_set_state(DevParams P, const double *__restrict__ rho, const double *__restrict__ ux,
+                            const double *__restrict__ uy, const double *__restrict__ T,
+                            const double *__restrict__ Tb, S *__restrict__ f, S *__restrict__ T0,
+                            S *__restrict__ T1, Scalars *sc)
+{
+    const size_t N = (size_t)P.nx * P.ny;
+    for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < N; c += (size_t)gridDim.x * blockDim.x) {
+        const int gy = (int)(c / P.nx), gx = (int)(c % P.nx);
+        const bool wall_row = !P.periodic_y && (gy == 0 || gy == P.ny - 1);
+        const double r = rho[c];
+        const double u = (ux && !wall_row) ? ux[c] : 0.0, v = (uy && !wall_row) ? uy[c] : 0.0;
+        const double u2 = u * u + v * v;
+        const double W[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+        for (int a = 0; a < 9; ++a) {
+            const double eu = kEX[a] * u + kEY[a] * v;
+            f[(size_t)a * N + c] = S(W[a] * r * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * u2));
+        }
+        double Tv = T ? T[c] : P.Ts;
+        if (!P.periodic_y && gy == 0) Tv = Tb[gx];
+        if (!P.periodic_y && gy == P.ny - 1) Tv = P.Ts;
+        T0[c] = S(Tv - P.T_ref);
+        T1[c] = S(Tv - P.T_ref);
+        if (!(r > 0.0) || !(Tv > 0.0) || !(P.b * r < 1.0)) flag_error(sc, 0, ERR_RHO);
+    }
+}
+
+// Mass partials of the current (post-streaming) state, plain sum of f.
+template <typename S>
+__global__ __launch_bounds__(NT) void k_mass(DevParams P, const S *__restrict__ f, double *__restrict__ part)
+{
+    __shared__ double red[NT / 64];
+    const size_t N = (size_t)P.nx * P.ny;
+    double m = 0.0;
+    for (size_t c = blockIdx.x * (size_t)NT + threadIdx.x; c < N; c += (size_t)gridDim.x * NT) {
+        double fl[9];
+        load_node(P, f, N, c, (int)(c / P.nx), fl);
+        double r = fl[0];
+#pragma unroll
+        for (int a = 1; a < 9; ++a) r += fl[a];
+        m += r;
+    }
+    const double s = block_sum(m, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void k_reduce_mass(DevParams P, const double *__restrict__ part, int n, Scalars *sc)
+{
+    __shared__ double red[NT / 64];
+    const double m = block_sum_array(part, n, red);
+    if (threadIdx.x == 0) sc->rho_ave = m / ((double)P.nx * (double)P.ny);
+}
+
+// Heat-flux partials of the current state (set-up, heater change, load).
+template <typename S>
+__global__ __launch_bounds__(NT) void k_heat_flux_state(DevParams P, const S *__restrict__ f,
+                                                        const S *__restrict__ T, double *__restrict__ hf_part,
+                                                        double *__restrict__ q_local)
+{
+    const int gx = blockIdx.x * TXB + threadIdx.x;
+    if (threadIdx.x >= TXB) return;
+    double qw = 0.0;
+    if (!P.periodic_y && gx < P.nx) {
+        const size_t N = (size_t)P.nx * P.ny;
+        double fl[9];
+        load_node(P, f, N, (size_t)gx, 0, fl);
+        double r0 = fl[0];
+#pragma unroll
+        for (int a = 1; a < 9; ++a) r0 += fl[a];
+        const double t0 = (double)T[gx], t1 = (double)T[P.nx + gx], t2 = (double)T[2 * P.nx + gx];
+        qw = -P.cv_chi * (double)r0 * (-3.0 * t0 + 4.0 * t1 - t2) / 2.0;
+        if (q_local) q_local[gx] = qw;
+    }
+    double s = qw;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (threadIdx.x == 0 && hf_part) hf_part[blockIdx.x] = s;
+}
+
+__global__ void k_flush_heat_flux(DevParams P, const double *__restrict__ hf_part, int n_hf, Scalars *sc)
+{
+    reduce_heat_flux(hf_part, n_hf, P.nx, sc, sc->tA);
+}
+
+// Read-back: rho, v of Eq. (6) with the force of the current state, T, and
+// the completed f, all widened to FP64.
+template <typename S>
+__global__ __launch_bounds__(NT) void k_read(DevParams P, const S *__restrict__ fin, const S *__restrict__ Tin,
+                                             double *__restrict__ rho_o, double *__restrict__ ux_o,
+                                             double *__restrict__ uy_o, double *__restrict__ T_o,
+                                             double *__restrict__ f_o, Scalars *sc, int nbx)
+{
+    __shared__ double psi_s[(TXA + 2) * (TYA + 2)];
+    const int bx = blockIdx.x % nbx, by = blockIdx.x / nbx;
+    const int x0 = bx * TXA, y0 = by * TYA;
+    const size_t N = (size_t)P.nx * P.ny;
+    const bool frozen = P.mode == MODE_THERMAL_ONLY;
+    if (!frozen) tile_psi<S, TXA, TYA>(P, fin, Tin, x0, y0, psi_s, sc, sc->tA);
+    __syncthreads();
+    const double rho_ave = sc->rho_ave;
+    const int tx = threadIdx.x % TXA;
+    for (int ly = threadIdx.x / TXA; ly < TYA; ly += NT / TXA) {
+        const int gx = x0 + tx, gy = y0 + ly;
+        if (gx >= P.nx || gy >= P.ny) continue;
+        const size_t c = (size_t)gy * P.nx + gx;
+        double fl[9];
+        load_node(P, fin, N, c, gy, fl);
+        double rho = 0.0, jx = 0.0, jy = 0.0;
+        {
+            double r = fl[0];
+#pragma unroll
+            for (int a = 1; a < 9; ++a) r += fl[a];
+            rho = r;
+            jx = (double)(fl[1] - fl[3] + fl[5] - fl[6] - fl[7] + fl[8]);
+            jy = (double)(fl[2] - fl[4] + fl[5] + fl[6] - fl[7] - fl[8]);
+        }
+        double Fx = 0.0, Fy = 0.0, Q = 0.0;
+        if (!frozen) node_force<TXA + 2>(P, psi_s, tx, ly, gy, rho, rho_ave, Fx, Fy, Q);
+        if (rho_o) rho_o[c] = rho;
+        if (ux_o) ux_o[c] = (jx + 0.5 * Fx) / rho;
+        if (uy_o) uy_o[c] = (jy + 0.5 * Fy) / rho;
+        if (T_o) T_o[c] = P.T_ref + (double)Tin[c];
+        if (f_o)
+            for (int a = 0; a < 9; ++a) f_o[(size_t)a * N + c] = (double)fl[a];
+    }
+}
+
+// Write the Zou-He completion into the stored wall rows (before a checkpoint).
+template <typename S>
+__global__ void k_complete_walls(DevParams P, S *__restrict__ f)
+{
+    const int gx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (P.periodic_y || P.mode == MODE_THERMAL_ONLY || gx >= P.nx) return;
+    const size_t N = (size_t)P.nx * P.ny;
+    for (int side = 0; side < 2; ++side) {
+        const int gy = side ? P.ny - 1 : 0;
+        const size_t c = (size_t)gy * P.nx + gx;
+        double fl[9];
+        load_node(P, f, N, c, gy, fl);
+        for (int a = 0; a < 9; ++a) f[(size_t)a * N + c] = S(fl[a]);
+    }
+}
+
+// Set the bottom-wall row of both temperature buffers.
+template <typename S>
+__global__ void k_set_heater(DevParams P, const double *__restrict__ Tb, S *__restrict__ T0, S *__restrict__ T1)
+{
+    const int gx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (P.periodic_y || gx >= P.nx) return;
+    T0[gx] = S(Tb[gx] - P.T_ref);
+    T1[gx] = S(Tb[gx] - P.T_ref);
+}
+
+}  // namespace lbb

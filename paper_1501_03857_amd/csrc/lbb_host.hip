@@ -1,0 +1,841 @@
+// Host runtime of the lbboil C-ABI (include/lbboil.h): parameter validation,
+// EOS set-up (T_c, Maxwell coexistence), device allocation, the built-in
+// initial state, the step loop with captured HIP graphs, read-back,
+// heat-flux bookkeeping and checkpoints.
+#include "lbboil.h"
+
+#include "lbb_device.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define LBB_HIP(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) return fail(LBB_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int kGraphSteps = 32;  // steps per captured graph (even: buffers return)
+
+// ---- Peng-Robinson EOS on the host (Eq. (21)) ---------------------------
+
+struct Eos {
+    double a, b, R, Tc, kappa, T;
+    double phi() const
+    {
+        const double s = 1.0 + kappa * (1.0 - std::sqrt(T / Tc));
+        return s * s;
+    }
+    double p(double r) const { return r * R * T / (1.0 - b * r) - a * phi() * r * r / (1.0 + 2.0 * b * r - b * b * r * r); }
+    double dp(double r) const
+    {
+        const double q = 1.0 + 2.0 * b * r - b * b * r * r;
+        return R * T / ((1.0 - b * r) * (1.0 - b * r)) - 2.0 * a * phi() * r * (1.0 + b * r) / (q * q);
+    }
+    // antiderivative of p/rho^2: R T ln(rho/(1 - b rho)) - a phi int drho/(2 - (1 - b rho)^2)
+    double prim(double r) const
+    {
+        const double x = 1.0 - b * r, s2 = std::sqrt(2.0);
+        return R * T * std::log(r / x) + a * phi() / (2.0 * s2 * b) * std::log((s2 + x) / (s2 - x));
+    }
+};
+
+template <typename Fn>
+double solve_bracket(Fn fn, double lo, double hi)
+{
+    double flo = fn(lo);
+    for (int it = 0; it < 300; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (!(mid > lo && mid < hi)) break;
+        const double fm = fn(mid);
+        if ((fm < 0.0) == (flo < 0.0)) {
+            lo = mid;
+            flo = fm;
+        } else {
+            hi = mid;
+        }
+    }
+    return 0.5 * (lo + hi);
+}
+
+// Maxwell equal-area rule: p(rho_V) = p(rho_L) = p0 and
+// int_{rho_V}^{rho_L} (p - p0)/rho^2 drho = 0.
+bool maxwell(const Eos &e, double &rv, double &rl)
+{
+    const double top = (1.0 / e.b) * (1.0 - 1e-10);
+    // spinodals: the two roots of dp/drho on (0, 1/b)
+    double sp[2];
+    int ns = 0;
+    const int n = 100000;
+    double r0 = top / n, d0 = e.dp(r0);
+    for (int k = 2; k <= n && ns < 2; ++k) {
+        const double r1 = top * k / n, d1 = e.dp(r1);
+        if ((d0 < 0.0) != (d1 < 0.0)) sp[ns++] = solve_bracket([&](double r) { return e.dp(r); }, r0, r1);
+        r0 = r1;
+        d0 = d1;
+    }
+    if (ns != 2) return false;
+    double plo = e.p(sp[1]), phi_ = e.p(sp[0]);
+    if (plo < 1e-14 * phi_) plo = 1e-14 * phi_;
+    for (int it = 0; it < 200; ++it) {
+        const double p0 = 0.5 * (plo + phi_);
+        if (!(p0 > plo && p0 < phi_)) break;
+        rv = solve_bracket([&](double r) { return e.p(r) - p0; }, 1e-300, sp[0]);
+        rl = solve_bracket([&](double r) { return e.p(r) - p0; }, sp[1], top);
+        const double area = (e.prim(rl) + p0 / rl) - (e.prim(rv) + p0 / rv);
+        if (area > 0.0) plo = p0; else phi_ = p0;
+    }
+    return true;
+}
+
+// ---- SplitMix64 (Steele, Lea, Flood 2014), counter-based use -------------
+uint64_t splitmix64_at(uint64_t seed, uint64_t counter)
+{
+    uint64_t z = seed + (counter + 1) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+uint64_t fnv1a(const void *data, size_t n, uint64_t h = 1469598103934665603ULL)
+{
+    const unsigned char *p = static_cast<const unsigned char *>(data);
+    for (size_t k = 0; k < n; ++k) {
+        h ^= p[k];
+        h *= 1099511628211ULL;
+    }
+    return h;
+}
+
+struct BlobHeader {
+    uint64_t magic;
+    uint32_t version, precision;
+    int32_t nx, ny, mode, periodic_y;
+    uint64_t param_hash;
+    uint64_t payload_bytes;
+    uint64_t checksum;
+};
+constexpr uint64_t kMagic = 0x6c62626f696c3031ULL;  // "lbboil01"
+
+}  // namespace
+
+struct lbb_domain {
+    lbb_params p{};
+    lbb::DevParams dp{};
+    size_t esz = 8;
+    size_t N = 0;
+    hipStream_t stream = nullptr;
+    void *f[2] = {nullptr, nullptr};
+    void *T[2] = {nullptr, nullptr};
+    void *rho = nullptr, *vx = nullptr, *vy = nullptr;
+    double *mass_part = nullptr, *hf_part = nullptr, *Tb_dev = nullptr;
+    lbb::Scalars *sc = nullptr;
+    int nbxA = 0, nbyA = 0, nbxB = 0, nbyB = 0;
+    int cf = 0, cT = 0;
+    bool poisoned = false;
+    hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    std::vector<double> Tb;
+    int64_t dev_bytes = 0;
+};
+
+namespace {
+
+int validate(const lbb_params *p)
+{
+    if (!p) return fail(LBB_EINVAL, "params is NULL");
+    if (p->nx < 3) return fail(LBB_EINVAL, "nx must be >= 3");
+    if (p->periodic_y ? p->ny < 3 : p->ny < 4) return fail(LBB_EINVAL, "ny must be >= 4 (>= 3 when periodic_y)");
+    if ((int64_t)p->nx * p->ny > 2147483647LL) return fail(LBB_EINVAL, "nx*ny must fit in 31 bits");
+    if (p->precision != LBB_FP64 && p->precision != LBB_FP32) return fail(LBB_EINVAL, "unknown precision");
+    if (p->thermal_mode < LBB_COUPLED || p->thermal_mode > LBB_THERMAL_ONLY) return fail(LBB_EINVAL, "unknown thermal_mode");
+    const double v[] = {p->a, p->b, p->R, p->omega, p->Ts_over_Tc, p->G, p->sigma, p->s_rho, p->s_e, p->s_zeta,
+                        p->s_j, p->s_q, p->nu_L, p->nu_V, p->rho_L, p->rho_V, p->cv, p->cv_chi, p->g,
+                        p->Gw_bottom, p->Gw_top, p->noise_amp};
+    for (double x : v)
+        if (!std::isfinite(x)) return fail(LBB_EINVAL, "non-finite parameter");
+    if (!(p->a > 0 && p->b > 0 && p->R > 0 && p->cv > 0 && p->Ts_over_Tc > 0)) return fail(LBB_EINVAL, "a, b, R, c_v, T_s must be > 0");
+    if (!(p->G < 0)) return fail(LBB_EINVAL, "G must be < 0");
+    if (!(p->s_e > 0 && p->s_e < 2 && p->s_zeta > 0 && p->s_zeta < 2)) return fail(LBB_EINVAL, "s_e, s_zeta must lie in (0, 2)");
+    if (!(p->nu_L > 0 && p->nu_V > 0)) return fail(LBB_EINVAL, "viscosities must be > 0");
+    if (p->rho_L < 0 || p->rho_V < 0) return fail(LBB_EINVAL, "rho_L, rho_V must be >= 0");
+    if (p->noise_amp < 0) return fail(LBB_EINVAL, "noise_amp must be >= 0");
+    if (p->liquid_rows < 0 || p->liquid_rows > p->ny) return fail(LBB_EINVAL, "liquid_rows out of range");
+    return LBB_OK;
+}
+
+uint64_t param_hash(const lbb_params &p)
+{
+    lbb_params q = p;
+    q.Gw_bottom = 0.0;  // changeable at run time
+    q.noise_amp = 0.0;
+    q.seed = 0;
+    q.liquid_rows = 0;
+    return fnv1a(&q, sizeof q);
+}
+
+template <typename S>
+void launch_lb(lbb_domain *d)
+{
+    using namespace lbb;
+    const int nA = d->nbxA * d->nbyA;
+    S *f0 = static_cast<S *>(d->f[d->cf]), *f1 = static_cast<S *>(d->f[d->cf ^ 1]);
+    S *T0 = static_cast<S *>(d->T[d->cT]);
+    hipLaunchKernelGGL(k_lb<S>, dim3(nA + 1), dim3(NT), 0, d->stream, d->dp, f0, f1, T0, static_cast<S *>(d->rho),
+                       static_cast<S *>(d->vx), static_cast<S *>(d->vy), d->mass_part, d->hf_part, d->nbxB, d->sc,
+                       d->nbxA, d->nbyA);
+}
+
+template <typename S>
+void launch_thermal(lbb_domain *d)
+{
+    using namespace lbb;
+    const int nA = d->nbxA * d->nbyA, nB = d->nbxB * d->nbyB;
+    const bool frozen = d->dp.mode == MODE_THERMAL_ONLY;
+    S *fnew = static_cast<S *>(d->f[frozen ? d->cf : d->cf ^ 1]);
+    S *T0 = static_cast<S *>(d->T[d->cT]), *T1 = static_cast<S *>(d->T[d->cT ^ 1]);
+    hipLaunchKernelGGL(k_thermal<S>, dim3(nB + 1), dim3(NT), 0, d->stream, d->dp, T0, T1, static_cast<S *>(d->rho),
+                       static_cast<S *>(d->vx), static_cast<S *>(d->vy), fnew, d->hf_part, d->mass_part, nA, d->sc,
+                       d->nbxB, d->nbyB);
+}
+
+void advance_buffers(lbb_domain *d)
+{
+    if (d->dp.mode != lbb::MODE_THERMAL_ONLY) d->cf ^= 1;
+    if (d->dp.mode != lbb::MODE_ISOTHERMAL) d->cT ^= 1;
+}
+
+template <typename S>
+void enqueue_step(lbb_domain *d)
+{
+    launch_lb<S>(d);
+    launch_thermal<S>(d);
+    advance_buffers(d);
+}
+
+void enqueue_step_any(lbb_domain *d)
+{
+    if (d->p.precision == LBB_FP64) enqueue_step<double>(d);
+    else enqueue_step<float>(d);
+}
+
+void drop_graphs(lbb_domain *d)
+{
+    for (auto &row : d->graph)
+        for (auto &g : row)
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
+}
+
+int build_graph(lbb_domain *d, hipGraphExec_t *out)
+{
+    const int cf = d->cf, cT = d->cT;
+    LBB_HIP(hipStreamBeginCapture(d->stream, hipStreamCaptureModeThreadLocal));
+    for (int k = 0; k < kGraphSteps; ++k) enqueue_step_any(d);
+    hipGraph_t g = nullptr;
+    LBB_HIP(hipStreamEndCapture(d->stream, &g));
+    d->cf = cf;  // capture recorded the launches; the state did not move
+    d->cT = cT;
+    hipError_t e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(LBB_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    return LBB_OK;
+}
+
+int enqueue_steps(lbb_domain *d, int64_t n)
+{
+    while (n >= kGraphSteps) {
+        hipGraphExec_t &g = d->graph[d->cf][d->cT];
+        if (!g) {
+            int rc = build_graph(d, &g);
+            if (rc) return rc;
+        }
+        LBB_HIP(hipGraphLaunch(g, d->stream));
+        // the buffers return to the same parity after an even number of steps
+        n -= kGraphSteps;
+    }
+    for (int64_t k = 0; k < n; ++k) enqueue_step_any(d);
+    hipLaunchKernelGGL(lbb::k_flush_heat_flux, dim3(1), dim3(lbb::NT), 0, d->stream, d->dp, d->hf_part, d->nbxB, d->sc);
+    LBB_HIP(hipGetLastError());
+    return LBB_OK;
+}
+
+int check_errors(lbb_domain *d)
+{
+    lbb::Scalars s;
+    LBB_HIP(hipMemcpyAsync(&s, d->sc, sizeof s, hipMemcpyDeviceToHost, d->stream));
+    LBB_HIP(hipStreamSynchronize(d->stream));
+    if (s.err_step != ~0ULL) {
+        d->poisoned = true;
+        std::string what;
+        if (s.err_code & lbb::ERR_RHO) what += " non-positive or non-finite density;";
+        if (s.err_code & lbb::ERR_PSI) what += " negative or non-finite pseudopotential radicand;";
+        if (s.err_code & lbb::ERR_T) what += " non-positive or non-finite temperature;";
+        return fail(LBB_ENONFINITE, "state became invalid at step " + std::to_string(s.err_step) + ":" + what);
+    }
+    return LBB_OK;
+}
+
+// Recompute rho_ave and the heat-flux partials from the current state.
+template <typename S>
+int refresh_reductions(lbb_domain *d)
+{
+    using namespace lbb;
+    const int nm = d->nbxA * d->nbyA;
+    hipLaunchKernelGGL(k_mass<S>, dim3(nm), dim3(NT), 0, d->stream, d->dp, static_cast<const S *>(d->f[d->cf]), d->mass_part);
+    hipLaunchKernelGGL(k_reduce_mass, dim3(1), dim3(NT), 0, d->stream, d->dp, d->mass_part, nm, d->sc);
+    hipLaunchKernelGGL(k_heat_flux_state<S>, dim3(d->nbxB), dim3(NT), 0, d->stream, d->dp,
+                       static_cast<const S *>(d->f[d->cf]), static_cast<const S *>(d->T[d->cT]), d->hf_part,
+                       (double *)nullptr);
+    hipLaunchKernelGGL(k_flush_heat_flux, dim3(1), dim3(NT), 0, d->stream, d->dp, d->hf_part, d->nbxB, d->sc);
+    LBB_HIP(hipGetLastError());
+    return LBB_OK;
+}
+
+// Upload FP64 fields and build f = f_eq(rho, u), T; resets the counters.
+template <typename S>
+int set_state(lbb_domain *d, const double *rho, const double *ux, const double *uy, const double *T)
+{
+    const size_t N = d->N, nb = N * sizeof(double);
+    double *buf = nullptr;
+    LBB_HIP(hipMalloc(&buf, 4 * nb));
+    double *drho = buf, *dux = buf + N, *duy = buf + 2 * N, *dT = buf + 3 * N;
+    int rc = LBB_OK;
+    do {
+        if (hipMemcpyAsync(drho, rho, nb, hipMemcpyHostToDevice, d->stream) != hipSuccess ||
+            (ux && hipMemcpyAsync(dux, ux, nb, hipMemcpyHostToDevice, d->stream) != hipSuccess) ||
+            (uy && hipMemcpyAsync(duy, uy, nb, hipMemcpyHostToDevice, d->stream) != hipSuccess) ||
+            (T && hipMemcpyAsync(dT, T, nb, hipMemcpyHostToDevice, d->stream) != hipSuccess)) {
+            rc = fail(LBB_EDEVICE, "upload of the initial fields failed");
+            break;
+        }
+        lbb::Scalars s{};
+        s.err_step = ~0ULL;
+        if (hipMemcpyAsync(d->sc, &s, sizeof s, hipMemcpyHostToDevice, d->stream) != hipSuccess) {
+            rc = fail(LBB_EDEVICE, "scalar reset failed");
+            break;
+        }
+        hipLaunchKernelGGL(lbb::k_set_state<S>, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, d->stream, d->dp,
+                           drho, ux ? dux : nullptr, uy ? duy : nullptr, T ? dT : nullptr, d->Tb_dev,
+                           static_cast<S *>(d->f[0]), static_cast<S *>(d->T[0]), static_cast<S *>(d->T[1]), d->sc);
+        d->cf = d->cT = 0;
+        rc = refresh_reductions<S>(d);
+        if (rc) break;
+        if (hipStreamSynchronize(d->stream) != hipSuccess) {
+            rc = fail(LBB_EDEVICE, "set-up kernels failed");
+            break;
+        }
+    } while (0);
+    (void)hipFree(buf);
+    if (rc) return rc;
+    rc = check_errors(d);
+    if (rc) return fail(LBB_EINVAL, "initial state invalid (rho <= 0, T <= 0 or b rho >= 1)");
+    d->poisoned = false;
+    return LBB_OK;
+}
+
+void release(lbb_domain *d)
+{
+    if (!d) return;
+    drop_graphs(d);
+    for (void *q : {d->f[0], d->f[1], d->T[0], d->T[1], d->rho, d->vx, d->vy})
+        if (q) (void)hipFree(q);
+    for (void *q : {(void *)d->mass_part, (void *)d->hf_part, (void *)d->Tb_dev, (void *)d->sc})
+        if (q) (void)hipFree(q);
+    if (d->stream) (void)hipStreamDestroy(d->stream);
+    delete d;
+}
+
+template <typename S>
+int read_impl(lbb_domain *d, double *rho, double *ux, double *uy, double *T, double *f)
+{
+    const size_t N = d->N, nb = N * sizeof(double);
+    double *buf = nullptr;
+    LBB_HIP(hipMalloc(&buf, 13 * nb));
+    double *r = buf, *u = buf + N, *v = buf + 2 * N, *t = buf + 3 * N, *ff = buf + 4 * N;
+    hipLaunchKernelGGL(lbb::k_read<S>, dim3(d->nbxA * d->nbyA), dim3(lbb::NT), 0, d->stream, d->dp,
+                       static_cast<const S *>(d->f[d->cf]), static_cast<const S *>(d->T[d->cT]), r, u, v, t, ff,
+                       d->sc, d->nbxA);
+    int rc = LBB_OK;
+    if (hipGetLastError() != hipSuccess) rc = fail(LBB_EDEVICE, "read-back kernel failed");
+    const struct { double *dst, *src; size_t n; } cp[] = {{rho, r, N}, {ux, u, N}, {uy, v, N}, {T, t, N}, {f, ff, 9 * N}};
+    for (auto &c : cp)
+        if (!rc && c.dst && hipMemcpyAsync(c.dst, c.src, c.n * sizeof(double), hipMemcpyDeviceToHost, d->stream) != hipSuccess)
+            rc = fail(LBB_EDEVICE, "read-back copy failed");
+    if (!rc && hipStreamSynchronize(d->stream) != hipSuccess) rc = fail(LBB_EDEVICE, "read-back failed");
+    (void)hipFree(buf);
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lbb_last_error(void) { return g_err.c_str(); }
+
+void lbb_default_params(lbb_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->nx = 128;
+    p->ny = 64;
+    p->precision = LBB_FP64;
+    p->periodic_y = 0;
+    p->thermal_mode = LBB_COUPLED;
+    p->liquid_rows = (int32_t)std::floor(0.6 * 64);
+    p->a = 2.0 / 49.0;
+    p->b = 2.0 / 21.0;
+    p->R = 1.0;
+    p->omega = 0.344;
+    p->Ts_over_Tc = 0.86;
+    p->G = -1.0;
+    p->sigma = 1.2;
+    p->s_rho = 1.0;
+    p->s_e = 0.8;
+    p->s_zeta = 0.8;
+    p->s_j = 1.0;
+    p->s_q = 1.1;
+    p->nu_L = 0.1;
+    p->nu_V = 0.5 / 3.0;
+    p->rho_L = 0.0;
+    p->rho_V = 0.0;
+    p->cv = 6.0;
+    p->cv_chi = 0.028;
+    p->g = 3e-5;
+    p->Gw_bottom = 0.0;
+    p->Gw_top = 0.0;
+    p->noise_amp = 1e-3;
+    p->seed = 1;
+}
+
+int lbb_eos_constants(double a, double b, double R, double omega, double *Tc, double *kappa)
+{
+    if (!(finite_pos(a) && finite_pos(b) && finite_pos(R) && std::isfinite(omega)))
+        return fail(LBB_EINVAL, "a, b, R must be finite and > 0");
+    if (Tc) *Tc = (a / b) * (0.0778 / 0.45724) / R;
+    if (kappa) *kappa = 0.37464 + 1.54226 * omega - 0.26992 * omega * omega;
+    return LBB_OK;
+}
+
+int lbb_coexistence(double a, double b, double R, double omega, double T, double *rho_V, double *rho_L)
+{
+    double Tc = 0, kap = 0;
+    int rc = lbb_eos_constants(a, b, R, omega, &Tc, &kap);
+    if (rc) return rc;
+    if (!(finite_pos(T) && T < Tc)) return fail(LBB_EINVAL, "coexistence needs 0 < T < T_c");
+    Eos e{a, b, R, Tc, kap, T};
+    double rv = 0, rl = 0;
+    if (!maxwell(e, rv, rl)) return fail(LBB_EINVAL, "no two-phase region at this temperature");
+    if (rho_V) *rho_V = rv;
+    if (rho_L) *rho_L = rl;
+    return LBB_OK;
+}
+
+int lbb_init_domain(const lbb_params *pin, const double *T_bottom, const double *rho0, lbb_domain **out)
+{
+    if (!out) return fail(LBB_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate(pin);
+    if (rc) return rc;
+    lbb_params p = *pin;
+    double Tc = 0, kap = 0;
+    lbb_eos_constants(p.a, p.b, p.R, p.omega, &Tc, &kap);
+    const double Ts = p.Ts_over_Tc * Tc;
+    if (p.rho_L == 0.0 && p.rho_V == 0.0) {
+        rc = lbb_coexistence(p.a, p.b, p.R, p.omega, Ts, &p.rho_V, &p.rho_L);
+        if (rc) return fail(LBB_EINVAL, "rho_L = rho_V = 0 needs T_s < T_c for the Maxwell densities");
+    }
+    if (p.rho_L == p.rho_V) return fail(LBB_EINVAL, "rho_L must differ from rho_V");
+    const size_t N = (size_t)p.nx * p.ny;
+    std::vector<double> rho_host;
+    if (!rho0) {
+        rho_host.resize(N);
+        for (int j = 0; j < p.ny; ++j)
+            for (int i = 0; i < p.nx; ++i) {
+                const size_t c = (size_t)j * p.nx + i;
+                const double u = (double)(splitmix64_at(p.seed, c) >> 11) * (1.0 / 9007199254740992.0);
+                rho_host[c] = (j < p.liquid_rows ? p.rho_L : p.rho_V) + p.noise_amp * (2.0 * u - 1.0);
+            }
+        rho0 = rho_host.data();
+    }
+    for (size_t c = 0; c < N; ++c)
+        if (!finite_pos(rho0[c]) || p.b * rho0[c] >= 1.0) return fail(LBB_EINVAL, "initial density must satisfy 0 < rho < 1/b");
+    std::vector<double> Tb(p.nx, Ts);
+    if (T_bottom)
+        for (int i = 0; i < p.nx; ++i) {
+            if (!finite_pos(T_bottom[i])) return fail(LBB_EINVAL, "T_bottom must be finite and > 0");
+            Tb[i] = T_bottom[i];
+        }
+
+    int dev = 0;
+    LBB_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    LBB_HIP(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(LBB_EDEVICE, std::string("this library is built for gfx950, device is ") + prop.gcnArchName);
+
+    lbb_domain *d = new (std::nothrow) lbb_domain();
+    if (!d) return fail(LBB_ENOMEM, "host allocation failed");
+    d->p = p;
+    d->N = N;
+    d->esz = p.precision == LBB_FP64 ? 8 : 4;
+    d->Tb = Tb;
+    lbb::DevParams &q = d->dp;
+    q.nx = p.nx;
+    q.ny = p.ny;
+    q.periodic_y = p.periodic_y ? 1 : 0;
+    q.mode = p.thermal_mode;
+    q.a = p.a;
+    q.b = p.b;
+    q.R = p.R;
+    q.Tc = Tc;
+    q.kappa = kap;
+    q.Ts = Ts;
+    q.T_ref = p.precision == LBB_FP64 ? 0.0 : Ts;
+    q.G = p.G;
+    q.sigma = p.sigma;
+    q.s_rho = p.s_rho;
+    q.s_e = p.s_e;
+    q.s_zeta = p.s_zeta;
+    q.s_j = p.s_j;
+    q.s_q = p.s_q;
+    const double tauL = 3.0 * p.nu_L + 0.5, tauV = 3.0 * p.nu_V + 0.5;
+    q.tau_V = tauV;
+    q.tau_slope = (tauL - tauV) / (p.rho_L - p.rho_V);
+    q.rho_V = p.rho_V;
+    q.cv = p.cv;
+    q.cv_chi = p.cv_chi;
+    q.chi = p.cv_chi / p.cv;
+    q.g = p.g;
+    q.Gw_bottom = p.Gw_bottom;
+    q.Gw_top = p.Gw_top;
+    q.sig_e = p.sigma / (1.0 / p.s_e - 0.5);
+    q.sig_z = p.sigma / (1.0 / p.s_zeta - 0.5);
+    d->nbxA = (p.nx + lbb::TXA - 1) / lbb::TXA;
+    d->nbyA = (p.ny + lbb::TYA - 1) / lbb::TYA;
+    d->nbxB = (p.nx + lbb::TXB - 1) / lbb::TXB;
+    d->nbyB = (p.ny + lbb::TYB - 1) / lbb::TYB;
+
+    auto alloc = [&](void **ptr, size_t bytes) -> bool {
+        if (hipMalloc(ptr, bytes) != hipSuccess) return false;
+        d->dev_bytes += (int64_t)bytes;
+        return hipMemset(*ptr, 0, bytes) == hipSuccess;
+    };
+    const size_t es = d->esz;
+    bool ok = hipStreamCreateWithFlags(&d->stream, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && alloc(&d->f[0], 9 * N * es) && alloc(&d->f[1], 9 * N * es);
+    ok = ok && alloc(&d->T[0], N * es) && alloc(&d->T[1], N * es);
+    ok = ok && alloc(&d->rho, N * es) && alloc(&d->vx, N * es) && alloc(&d->vy, N * es);
+    ok = ok && alloc((void **)&d->mass_part, (size_t)d->nbxA * d->nbyA * sizeof(double));
+    ok = ok && alloc((void **)&d->hf_part, (size_t)d->nbxB * sizeof(double));
+    ok = ok && alloc((void **)&d->Tb_dev, (size_t)p.nx * sizeof(double));
+    ok = ok && alloc((void **)&d->sc, sizeof(lbb::Scalars));
+    if (!ok) {
+        (void)hipGetLastError();
+        release(d);
+        return fail(LBB_ENOMEM, "device allocation failed");
+    }
+    if (hipMemcpy(d->Tb_dev, Tb.data(), p.nx * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        release(d);
+        return fail(LBB_EDEVICE, "upload of T_bottom failed");
+    }
+    rc = p.precision == LBB_FP64 ? set_state<double>(d, rho0, nullptr, nullptr, nullptr)
+                                 : set_state<float>(d, rho0, nullptr, nullptr, nullptr);
+    if (rc) {
+        std::string m = g_err;
+        release(d);
+        return fail(rc, m);
+    }
+    *out = d;
+    return LBB_OK;
+}
+
+int lbb_set_fields(lbb_domain *d, const double *rho, const double *ux, const double *uy, const double *T)
+{
+    if (!d || !rho) return fail(LBB_EINVAL, "domain and rho are required");
+    for (size_t c = 0; c < d->N; ++c) {
+        if (!finite_pos(rho[c]) || d->p.b * rho[c] >= 1.0) return fail(LBB_EINVAL, "rho must satisfy 0 < rho < 1/b");
+        if ((ux && !std::isfinite(ux[c])) || (uy && !std::isfinite(uy[c]))) return fail(LBB_EINVAL, "non-finite velocity");
+        if (T && !finite_pos(T[c])) return fail(LBB_EINVAL, "T must be finite and > 0");
+    }
+    return d->p.precision == LBB_FP64 ? set_state<double>(d, rho, ux, uy, T) : set_state<float>(d, rho, ux, uy, T);
+}
+
+int lbb_step_async(lbb_domain *d, int64_t n)
+{
+    if (!d) return fail(LBB_EINVAL, "domain is NULL");
+    if (n < 0) return fail(LBB_EINVAL, "n must be >= 0");
+    if (d->poisoned) return fail(LBB_ESTATE, "domain poisoned by an earlier invalid state; load a state first");
+    return enqueue_steps(d, n);
+}
+
+int lbb_sync(lbb_domain *d)
+{
+    if (!d) return fail(LBB_EINVAL, "domain is NULL");
+    LBB_HIP(hipStreamSynchronize(d->stream));
+    return check_errors(d);
+}
+
+int lbb_step(lbb_domain *d, int64_t n)
+{
+    int rc = lbb_step_async(d, n);
+    if (rc) return rc;
+    return lbb_sync(d);
+}
+
+void *lbb_stream(lbb_domain *d) { return d ? (void *)d->stream : nullptr; }
+
+int lbb_time_kernels(lbb_domain *d, int64_t n, double *ms_lb, double *ms_thermal, double *ms_step)
+{
+    if (!d) return fail(LBB_EINVAL, "domain is NULL");
+    if (n < 1) return fail(LBB_EINVAL, "n must be >= 1");
+    if (d->poisoned) return fail(LBB_ESTATE, "domain poisoned by an earlier invalid state; load a state first");
+    std::vector<hipEvent_t> ev(3 * (size_t)n + 1, nullptr);
+    for (auto &e : ev) LBB_HIP(hipEventCreate(&e));
+    const bool fp64 = d->p.precision == LBB_FP64;
+    LBB_HIP(hipEventRecord(ev[0], d->stream));
+    for (int64_t k = 0; k < n; ++k) {
+        LBB_HIP(hipEventRecord(ev[3 * k + 1], d->stream));
+        if (fp64) launch_lb<double>(d); else launch_lb<float>(d);
+        LBB_HIP(hipEventRecord(ev[3 * k + 2], d->stream));
+        if (fp64) launch_thermal<double>(d); else launch_thermal<float>(d);
+        LBB_HIP(hipEventRecord(ev[3 * k + 3], d->stream));
+        advance_buffers(d);
+    }
+    hipLaunchKernelGGL(lbb::k_flush_heat_flux, dim3(1), dim3(lbb::NT), 0, d->stream, d->dp, d->hf_part, d->nbxB, d->sc);
+    LBB_HIP(hipGetLastError());
+    LBB_HIP(hipStreamSynchronize(d->stream));
+    double a = 0, b = 0;
+    float ms = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        LBB_HIP(hipEventElapsedTime(&ms, ev[3 * k + 1], ev[3 * k + 2]));
+        a += ms;
+        LBB_HIP(hipEventElapsedTime(&ms, ev[3 * k + 2], ev[3 * k + 3]));
+        b += ms;
+    }
+    LBB_HIP(hipEventElapsedTime(&ms, ev[0], ev[3 * n]));
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    if (ms_lb) *ms_lb = a / (double)n;
+    if (ms_thermal) *ms_thermal = b / (double)n;
+    if (ms_step) *ms_step = (double)ms / (double)n;
+    return check_errors(d);
+}
+
+int lbb_read_fields(lbb_domain *d, double *rho, double *ux, double *uy, double *T, double *f)
+{
+    if (!d) return fail(LBB_EINVAL, "domain is NULL");
+    return d->p.precision == LBB_FP64 ? read_impl<double>(d, rho, ux, uy, T, f) : read_impl<float>(d, rho, ux, uy, T, f);
+}
+
+int lbb_wall_heat_flux(lbb_domain *d, double *q_now, double *q_mean, double *q_local, int64_t *n_samples)
+{
+    if (!d) return fail(LBB_EINVAL, "domain is NULL");
+    lbb::Scalars s;
+    LBB_HIP(hipMemcpyAsync(&s, d->sc, sizeof s, hipMemcpyDeviceToHost, d->stream));
+    if (q_local) {
+        double *ql = nullptr;
+        LBB_HIP(hipMalloc(&ql, d->p.nx * sizeof(double)));
+        if (d->p.precision == LBB_FP64)
+            hipLaunchKernelGGL(lbb::k_heat_flux_state<double>, dim3(d->nbxB), dim3(lbb::NT), 0, d->stream, d->dp,
+                               static_cast<const double *>(d->f[d->cf]), static_cast<const double *>(d->T[d->cT]),
+                               (double *)nullptr, ql);
+        else
+            hipLaunchKernelGGL(lbb::k_heat_flux_state<float>, dim3(d->nbxB), dim3(lbb::NT), 0, d->stream, d->dp,
+                               static_cast<const float *>(d->f[d->cf]), static_cast<const float *>(d->T[d->cT]),
+                               (double *)nullptr, ql);
+        hipError_t e = hipMemcpyAsync(q_local, ql, d->p.nx * sizeof(double), hipMemcpyDeviceToHost, d->stream);
+        hipError_t e2 = hipStreamSynchronize(d->stream);
+        (void)hipFree(ql);
+        if (e != hipSuccess || e2 != hipSuccess) return fail(LBB_EDEVICE, "heat-flux read-back failed");
+    }
+    LBB_HIP(hipStreamSynchronize(d->stream));
+    if (q_now) *q_now = s.q_now;
+    if (q_mean) *q_mean = s.n_samples ? s.q_sum / (double)s.n_samples : NAN;
+    if (n_samples) *n_samples = s.n_samples;
+    return LBB_OK;
+}
+
+int lbb_reset_average(lbb_domain *d)
+{
+    if (!d) return fail(LBB_EINVAL, "domain is NULL");
+    lbb::Scalars s;
+    LBB_HIP(hipMemcpyAsync(&s, d->sc, sizeof s, hipMemcpyDeviceToHost, d->stream));
+    LBB_HIP(hipStreamSynchronize(d->stream));
+    s.q_sum = 0.0;
+    s.n_samples = 0;
+    LBB_HIP(hipMemcpyAsync(d->sc, &s, sizeof s, hipMemcpyHostToDevice, d->stream));
+    LBB_HIP(hipStreamSynchronize(d->stream));
+    return LBB_OK;
+}
+
+int lbb_set_heater(lbb_domain *d, const double *T_bottom)
+{
+    if (!d) return fail(LBB_EINVAL, "domain is NULL");
+    std::vector<double> Tb(d->p.nx, d->dp.Ts);
+    if (T_bottom)
+        for (int i = 0; i < d->p.nx; ++i) {
+            if (!finite_pos(T_bottom[i])) return fail(LBB_EINVAL, "T_bottom must be finite and > 0");
+            Tb[i] = T_bottom[i];
+        }
+    d->Tb = Tb;
+    LBB_HIP(hipMemcpyAsync(d->Tb_dev, Tb.data(), d->p.nx * sizeof(double), hipMemcpyHostToDevice, d->stream));
+    const unsigned nb = (unsigned)((d->p.nx + 255) / 256);
+    if (d->p.precision == LBB_FP64)
+        hipLaunchKernelGGL(lbb::k_set_heater<double>, dim3(nb), dim3(256), 0, d->stream, d->dp, d->Tb_dev,
+                           static_cast<double *>(d->T[0]), static_cast<double *>(d->T[1]));
+    else
+        hipLaunchKernelGGL(lbb::k_set_heater<float>, dim3(nb), dim3(256), 0, d->stream, d->dp, d->Tb_dev,
+                           static_cast<float *>(d->T[0]), static_cast<float *>(d->T[1]));
+    LBB_HIP(hipGetLastError());
+    LBB_HIP(hipStreamSynchronize(d->stream));
+    return LBB_OK;
+}
+
+int lbb_set_wettability(lbb_domain *d, double Gw_bottom)
+{
+    if (!d) return fail(LBB_EINVAL, "domain is NULL");
+    if (!std::isfinite(Gw_bottom)) return fail(LBB_EINVAL, "G_w must be finite");
+    d->p.Gw_bottom = Gw_bottom;
+    d->dp.Gw_bottom = Gw_bottom;
+    drop_graphs(d);  // the captured launches carry the old parameters
+    return LBB_OK;
+}
+
+int lbb_save_state(lbb_domain *d, void *buf, size_t *len)
+{
+    if (!d || !len) return fail(LBB_EINVAL, "domain and len are required");
+    const size_t es = d->esz, N = d->N;
+    const size_t payload = 10 * N * es + d->p.nx * sizeof(double) + sizeof(double) + sizeof(lbb::Scalars) +
+                           d->nbxB * sizeof(double);
+    const size_t need = sizeof(BlobHeader) + payload;
+    if (!buf) {
+        *len = need;
+        return LBB_OK;
+    }
+    if (*len < need) return fail(LBB_EINVAL, "buffer too small");
+    if (d->p.precision == LBB_FP64)
+        hipLaunchKernelGGL(lbb::k_complete_walls<double>, dim3((d->p.nx + 255) / 256), dim3(256), 0, d->stream, d->dp,
+                           static_cast<double *>(d->f[d->cf]));
+    else
+        hipLaunchKernelGGL(lbb::k_complete_walls<float>, dim3((d->p.nx + 255) / 256), dim3(256), 0, d->stream, d->dp,
+                           static_cast<float *>(d->f[d->cf]));
+    unsigned char *o = static_cast<unsigned char *>(buf) + sizeof(BlobHeader);
+    unsigned char *p = o;
+    LBB_HIP(hipMemcpyAsync(p, d->f[d->cf], 9 * N * es, hipMemcpyDeviceToHost, d->stream));
+    p += 9 * N * es;
+    LBB_HIP(hipMemcpyAsync(p, d->T[d->cT], N * es, hipMemcpyDeviceToHost, d->stream));
+    p += N * es;
+    std::memcpy(p, d->Tb.data(), d->p.nx * sizeof(double));
+    p += d->p.nx * sizeof(double);
+    std::memcpy(p, &d->p.Gw_bottom, sizeof(double));
+    p += sizeof(double);
+    LBB_HIP(hipMemcpyAsync(p, d->sc, sizeof(lbb::Scalars), hipMemcpyDeviceToHost, d->stream));
+    p += sizeof(lbb::Scalars);
+    LBB_HIP(hipMemcpyAsync(p, d->hf_part, d->nbxB * sizeof(double), hipMemcpyDeviceToHost, d->stream));
+    LBB_HIP(hipStreamSynchronize(d->stream));
+    BlobHeader h{};
+    h.magic = kMagic;
+    h.version = 1;
+    h.precision = (uint32_t)d->p.precision;
+    h.nx = d->p.nx;
+    h.ny = d->p.ny;
+    h.mode = d->p.thermal_mode;
+    h.periodic_y = d->p.periodic_y;
+    h.param_hash = param_hash(d->p);
+    h.payload_bytes = payload;
+    h.checksum = fnv1a(o, payload);
+    std::memcpy(buf, &h, sizeof h);
+    *len = need;
+    return LBB_OK;
+}
+
+int lbb_load_state(lbb_domain *d, const void *buf, size_t len)
+{
+    if (!d || !buf) return fail(LBB_EINVAL, "domain and buf are required");
+    if (len < sizeof(BlobHeader)) return fail(LBB_EINVAL, "blob too short");
+    BlobHeader h;
+    std::memcpy(&h, buf, sizeof h);
+    const size_t es = d->esz, N = d->N;
+    const size_t payload = 10 * N * es + d->p.nx * sizeof(double) + sizeof(double) + sizeof(lbb::Scalars) +
+                           d->nbxB * sizeof(double);
+    if (h.magic != kMagic || h.version != 1) return fail(LBB_EINVAL, "not an lbboil state blob");
+    if (h.nx != d->p.nx || h.ny != d->p.ny || h.precision != (uint32_t)d->p.precision ||
+        h.mode != d->p.thermal_mode || h.periodic_y != d->p.periodic_y || h.param_hash != param_hash(d->p))
+        return fail(LBB_EINVAL, "blob belongs to a domain with other shape or parameters");
+    if (h.payload_bytes != payload || len < sizeof h + payload) return fail(LBB_EINVAL, "blob size mismatch");
+    const unsigned char *o = static_cast<const unsigned char *>(buf) + sizeof h;
+    if (fnv1a(o, payload) != h.checksum) return fail(LBB_EINVAL, "blob checksum mismatch (corrupted)");
+    const unsigned char *p = o;
+    LBB_HIP(hipMemcpyAsync(d->f[0], p, 9 * N * es, hipMemcpyHostToDevice, d->stream));
+    p += 9 * N * es;
+    LBB_HIP(hipMemcpyAsync(d->T[0], p, N * es, hipMemcpyHostToDevice, d->stream));
+    LBB_HIP(hipMemcpyAsync(d->T[1], p, N * es, hipMemcpyHostToDevice, d->stream));
+    p += N * es;
+    std::vector<double> Tb(d->p.nx);
+    std::memcpy(Tb.data(), p, d->p.nx * sizeof(double));
+    p += d->p.nx * sizeof(double);
+    double Gw;
+    std::memcpy(&Gw, p, sizeof Gw);
+    p += sizeof(double);
+    lbb::Scalars s;
+    std::memcpy(&s, p, sizeof s);
+    p += sizeof s;
+    s.err_step = ~0ULL;
+    s.err_code = 0;
+    LBB_HIP(hipMemcpyAsync(d->sc, &s, sizeof s, hipMemcpyHostToDevice, d->stream));
+    LBB_HIP(hipMemcpyAsync(d->hf_part, p, d->nbxB * sizeof(double), hipMemcpyHostToDevice, d->stream));
+    LBB_HIP(hipStreamSynchronize(d->stream));
+    d->Tb = Tb;
+    LBB_HIP(hipMemcpy(d->Tb_dev, Tb.data(), d->p.nx * sizeof(double), hipMemcpyHostToDevice));
+    d->cf = d->cT = 0;
+    if (Gw != d->dp.Gw_bottom) {
+        d->p.Gw_bottom = d->dp.Gw_bottom = Gw;
+        drop_graphs(d);
+    }
+    d->poisoned = false;
+    return LBB_OK;
+}
+
+int lbb_info(lbb_domain *d, int64_t *t, int32_t *nx, int32_t *ny, int64_t *device_bytes)
+{
+    if (!d) return fail(LBB_EINVAL, "domain is NULL");
+    if (t) {
+        lbb::Scalars s;
+        LBB_HIP(hipMemcpyAsync(&s, d->sc, sizeof s, hipMemcpyDeviceToHost, d->stream));
+        LBB_HIP(hipStreamSynchronize(d->stream));
+        *t = s.tA;
+    }
+    if (nx) *nx = d->p.nx;
+    if (ny) *ny = d->p.ny;
+    if (device_bytes) *device_bytes = d->dev_bytes;
+    return LBB_OK;
+}
+
+int lbb_destroy(lbb_domain *d)
+{
+    if (!d) return fail(LBB_EINVAL, "domain is NULL");
+    if (d->stream) (void)hipStreamSynchronize(d->stream);
+    release(d);
+    return LBB_OK;
+}
+
+}  // extern "C"

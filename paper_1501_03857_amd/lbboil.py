@@ -1,0 +1,268 @@
+"""ctypes binding of the lbboil C-ABI (include/lbboil.h).
+
+Argument marshalling only: every step of the model runs in the gfx950 HIP
+kernels of ``liblbboil.so``.  Loading fails loudly when the library has not
+been built (``python -m paper_1501_03857_amd.build``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, fields
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbboil.so")
+
+LBB_OK, LBB_EINVAL, LBB_ENOMEM, LBB_EDEVICE, LBB_ENONFINITE, LBB_EUNSUPPORTED, LBB_ESTATE = 0, -1, -2, -3, -4, -5, -6
+FP64, FP32 = 0, 1
+COUPLED, ISOTHERMAL, THERMAL_ONLY = 0, 1, 2
+
+
+class LbbError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lbboil error {code}: {msg}")
+        self.code = code
+
+
+_d = C.c_double
+_pd = C.POINTER(C.c_double)
+_i32 = C.c_int32
+_i64 = C.c_int64
+
+
+class CParams(C.Structure):
+    _fields_ = [
+        ("nx", _i32), ("ny", _i32), ("precision", _i32), ("periodic_y", _i32), ("thermal_mode", _i32),
+        ("liquid_rows", _i32),
+        ("a", _d), ("b", _d), ("R", _d), ("omega", _d), ("Ts_over_Tc", _d),
+        ("G", _d), ("sigma", _d),
+        ("s_rho", _d), ("s_e", _d), ("s_zeta", _d), ("s_j", _d), ("s_q", _d),
+        ("nu_L", _d), ("nu_V", _d), ("rho_L", _d), ("rho_V", _d),
+        ("cv", _d), ("cv_chi", _d), ("g", _d), ("Gw_bottom", _d), ("Gw_top", _d),
+        ("noise_amp", _d), ("seed", C.c_uint64),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises if it is missing: no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing; build it with python -m paper_1501_03857_amd.build")
+        L = C.CDLL(LIB_PATH)
+        _P = C.POINTER(CParams)
+        vp = C.c_void_p
+        sig = {
+            "lbb_default_params": (None, [_P]),
+            "lbb_eos_constants": (C.c_int, [_d, _d, _d, _d, _pd, _pd]),
+            "lbb_coexistence": (C.c_int, [_d, _d, _d, _d, _d, _pd, _pd]),
+            "lbb_init_domain": (C.c_int, [_P, _pd, _pd, C.POINTER(vp)]),
+            "lbb_set_fields": (C.c_int, [vp, _pd, _pd, _pd, _pd]),
+            "lbb_step": (C.c_int, [vp, _i64]),
+            "lbb_step_async": (C.c_int, [vp, _i64]),
+            "lbb_sync": (C.c_int, [vp]),
+            "lbb_stream": (vp, [vp]),
+            "lbb_time_kernels": (C.c_int, [vp, _i64, _pd, _pd, _pd]),
+            "lbb_read_fields": (C.c_int, [vp, _pd, _pd, _pd, _pd, _pd]),
+            "lbb_wall_heat_flux": (C.c_int, [vp, _pd, _pd, _pd, C.POINTER(_i64)]),
+            "lbb_reset_average": (C.c_int, [vp]),
+            "lbb_set_heater": (C.c_int, [vp, _pd]),
+            "lbb_set_wettability": (C.c_int, [vp, _d]),
+            "lbb_save_state": (C.c_int, [vp, vp, C.POINTER(C.c_size_t)]),
+            "lbb_load_state": (C.c_int, [vp, vp, C.c_size_t]),
+            "lbb_info": (C.c_int, [vp, C.POINTER(_i64), C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i64)]),
+            "lbb_destroy": (C.c_int, [vp]),
+            "lbb_last_error": (C.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != LBB_OK:
+        raise LbbError(rc, lib().lbb_last_error().decode())
+
+
+def _ptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_pd)
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+@dataclass
+class Params:
+    """lbb_params with the library's defaults (lbb_default_params)."""
+    nx: int = 128
+    ny: int = 64
+    precision: int = FP64
+    periodic_y: int = 0
+    thermal_mode: int = COUPLED
+    liquid_rows: int = 38
+    a: float = 2.0 / 49.0
+    b: float = 2.0 / 21.0
+    R: float = 1.0
+    omega: float = 0.344
+    Ts_over_Tc: float = 0.86
+    G: float = -1.0
+    sigma: float = 1.2
+    s_rho: float = 1.0
+    s_e: float = 0.8
+    s_zeta: float = 0.8
+    s_j: float = 1.0
+    s_q: float = 1.1
+    nu_L: float = 0.1
+    nu_V: float = 0.5 / 3.0
+    rho_L: float = 0.0
+    rho_V: float = 0.0
+    cv: float = 6.0
+    cv_chi: float = 0.028
+    g: float = 3e-5
+    Gw_bottom: float = 0.0
+    Gw_top: float = 0.0
+    noise_amp: float = 1e-3
+    seed: int = 1
+
+    def c(self) -> CParams:
+        return CParams(**{f.name: getattr(self, f.name) for f in fields(self)})
+
+
+def default_params() -> CParams:
+    p = CParams()
+    lib().lbb_default_params(C.byref(p))
+    return p
+
+
+def eos_constants(a, b, R, omega):
+    tc, k = _d(), _d()
+    _check(lib().lbb_eos_constants(a, b, R, omega, C.byref(tc), C.byref(k)))
+    return tc.value, k.value
+
+
+def coexistence(a, b, R, omega, T):
+    rv, rl = _d(), _d()
+    _check(lib().lbb_coexistence(a, b, R, omega, T, C.byref(rv), C.byref(rl)))
+    return rv.value, rl.value
+
+
+class Domain:
+    """One lattice on the current GPU (lbb_init_domain ... lbb_destroy)."""
+
+    def __init__(self, p: Params, T_bottom=None, rho0=None):
+        self.p = p
+        self._cp = p.c()
+        T_bottom, rho0 = _f64(T_bottom), _f64(rho0)
+        if rho0 is not None:
+            assert rho0.shape == (p.ny, p.nx)
+        if T_bottom is not None:
+            assert T_bottom.shape == (p.nx,)
+        h = C.c_void_p()
+        _check(lib().lbb_init_domain(C.byref(self._cp), _ptr(T_bottom), _ptr(rho0), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().lbb_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_fields(self, rho, ux=None, uy=None, T=None):
+        rho, ux, uy, T = (_f64(x) for x in (rho, ux, uy, T))
+        _check(lib().lbb_set_fields(self._h, _ptr(rho), _ptr(ux), _ptr(uy), _ptr(T)))
+
+    def step(self, n: int = 1):
+        _check(lib().lbb_step(self._h, int(n)))
+        return self
+
+    def step_async(self, n: int):
+        _check(lib().lbb_step_async(self._h, int(n)))
+
+    def sync(self):
+        _check(lib().lbb_sync(self._h))
+
+    def time_kernels(self, n: int):
+        """Mean (LB launch, thermal launch, whole step) durations in ms over n
+        single-launch steps, from HIP events on the library stream."""
+        a, b, c = _d(), _d(), _d()
+        _check(lib().lbb_time_kernels(self._h, int(n), C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
+    @property
+    def stream(self) -> int:
+        return lib().lbb_stream(self._h)
+
+    def fields(self, f: bool = True):
+        ny, nx = self.p.ny, self.p.nx
+        rho, ux, uy, T = (np.zeros((ny, nx)) for _ in range(4))
+        ff = np.zeros((9, ny, nx)) if f else None
+        _check(lib().lbb_read_fields(self._h, _ptr(rho), _ptr(ux), _ptr(uy), _ptr(T), _ptr(ff)))
+        out = dict(rho=rho, ux=ux, uy=uy, T=T)
+        if f:
+            out["f"] = ff
+        return out
+
+    def heat_flux(self, local: bool = True):
+        qn, qm, ns = _d(), _d(), _i64()
+        ql = np.zeros(self.p.nx) if local else None
+        _check(lib().lbb_wall_heat_flux(self._h, C.byref(qn), C.byref(qm), _ptr(ql), C.byref(ns)))
+        return dict(q_now=qn.value, q_mean=qm.value, n_samples=ns.value, q_local=ql)
+
+    def reset_average(self):
+        _check(lib().lbb_reset_average(self._h))
+
+    def set_heater(self, T_bottom):
+        T_bottom = _f64(T_bottom)
+        _check(lib().lbb_set_heater(self._h, _ptr(T_bottom)))
+
+    def set_wettability(self, Gw):
+        _check(lib().lbb_set_wettability(self._h, float(Gw)))
+
+    def save(self) -> bytes:
+        n = C.c_size_t(0)
+        _check(lib().lbb_save_state(self._h, None, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        _check(lib().lbb_save_state(self._h, buf, C.byref(n)))
+        return buf.raw[: n.value]
+
+    def load(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        _check(lib().lbb_load_state(self._h, buf, len(blob)))
+
+    def info(self):
+        t, nx, ny, nb = _i64(), _i32(), _i32(), _i64()
+        _check(lib().lbb_info(self._h, C.byref(t), C.byref(nx), C.byref(ny), C.byref(nb)))
+        return dict(t=t.value, nx=nx.value, ny=ny.value, device_bytes=nb.value)
+
+    @property
+    def t(self) -> int:
+        return self.info()["t"]

@@ -1,0 +1,95 @@
+"""The C-ABI library loads, exports every symbol its header declares, and its
+host-side logic (parameter validation, EOS constants, Maxwell coexistence)
+behaves; none of these tests launches a kernel."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1501_03857_amd import lbboil as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for fn in os.listdir(inc):
+        if fn.endswith(".h"):
+            src = open(os.path.join(inc, fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(lbb_[a-z0-9_]+)\s*\(", src))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared_symbols()
+    assert len(names) >= 19
+    lib = C.CDLL(L.LIB_PATH)
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_default_params_match_binding_layout():
+    """lbb_default_params fills the struct the binding declares (layout check)."""
+    p = L.default_params()
+    q = L.Params()
+    for name, _ in L.CParams._fields_:
+        v = getattr(p, name)
+        if name in ("liquid_rows",):
+            continue
+        assert v == pytest.approx(getattr(q, name), rel=1e-15, abs=0), name
+    assert p.liquid_rows == int(np.floor(0.6 * p.ny))
+
+
+@pytest.mark.parametrize("field,value", [
+    ("nx", 2), ("ny", 3), ("precision", 7), ("thermal_mode", 3), ("G", 1.0), ("a", -1.0),
+    ("s_e", 2.0), ("nu_L", 0.0), ("cv", float("nan")), ("liquid_rows", 65), ("noise_amp", -1.0),
+])
+def test_init_rejects_invalid_parameters(field, value):
+    p = L.Params()
+    setattr(p, field, value)
+    with pytest.raises(L.LbbError) as e:
+        L.Domain(p)
+    assert e.value.code == L.LBB_EINVAL
+
+
+def test_init_rejects_bad_initial_density():
+    p = L.Params(nx=8, ny=6)
+    rho = np.full((6, 8), 2.0)
+    rho[2, 3] = 1.0 / p.b  # b rho >= 1
+    with pytest.raises(L.LbbError) as e:
+        L.Domain(p, rho0=rho)
+    assert e.value.code == L.LBB_EINVAL
+    rho[2, 3] = -1.0
+    with pytest.raises(L.LbbError):
+        L.Domain(p, rho0=rho)
+    with pytest.raises(L.LbbError):
+        L.Domain(p, T_bottom=np.full(8, -0.1))
+
+
+@pytest.mark.parametrize("a", [2.0 / 49.0, 3.0 / 49.0])
+def test_eos_constants_match_oracle(a):
+    tc, k = L.eos_constants(a, 2.0 / 21.0, 1.0, 0.344)
+    assert tc == pytest.approx(O.Tc(a, 2.0 / 21.0, 1.0), rel=1e-15)
+    assert k == pytest.approx(O.kappa(0.344), rel=1e-15)
+
+
+@pytest.mark.parametrize("theta", [0.6, 0.86, 0.97])
+def test_library_coexistence_matches_oracle(theta):
+    a, b = 2.0 / 49.0, 2.0 / 21.0
+    tc = O.Tc(a, b, 1.0)
+    rv, rl = L.coexistence(a, b, 1.0, 0.344, theta * tc)
+    orv, orl, _ = O.maxwell(a, b, 1.0, 0.344, theta * tc)
+    assert rv == pytest.approx(orv, rel=1e-9)
+    assert rl == pytest.approx(orl, rel=1e-9)
+
+
+def test_coexistence_rejects_supercritical():
+    a, b = 2.0 / 49.0, 2.0 / 21.0
+    tc, _ = L.eos_constants(a, b, 1.0, 0.344)
+    with pytest.raises(L.LbbError):
+        L.coexistence(a, b, 1.0, 0.344, 1.01 * tc)

@@ -1,0 +1,207 @@
+"""GPU (HIP, gfx950) vs CPU oracle parity of the coupled time step.
+
+Every comparison feeds both sides the same seeded inputs and compares the
+fields normwise (max |gpu - oracle| / max |oracle| per field):
+  FP64 storage: <= 1e-12 over the horizon (rounding-order differences only);
+  FP32 storage: <= 1e-5 (FP32 f and T, FP64 EOS and reductions).
+Sizes span several 64x8 tiles with ragged tails in x and y.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1501_03857_amd import lbboil as L
+from paper_1501_03857_amd import workloads as WL
+from parity_utils import compare, heat_flux_scale, make_pair, normwise
+
+pytestmark = pytest.mark.gpu
+
+TOL64, TOL32 = 1e-12, 1e-5
+PLAIN = WL.PLAIN_128x64
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+@pytest.mark.parametrize("steps", [0, 1, 200, 1000])
+def test_plain_fp64_matches_oracle(steps):
+    _say("plain 128x64 fp64", steps)
+    o, d, _ = make_pair(PLAIN)
+    o.step(steps)
+    d.step(steps)
+    errs, bad = compare(o, d, TOL64)
+    assert not bad, errs
+    ho, hd = o.heat_flux(), d.heat_flux()
+    assert hd["n_samples"] == ho["n_samples"] == steps
+    qs = heat_flux_scale(o)
+    assert abs(hd["q_now"] - ho["q_now"]) <= TOL64 * qs
+    if steps:
+        assert abs(hd["q_mean"] - ho["q_mean"]) <= TOL64 * qs
+    assert normwise(hd["q_local"], ho["q_local"], qs) <= TOL64
+
+
+def test_plain_fp32_matches_oracle():
+    _say("plain 128x64 fp32 200")
+    o, d, _ = make_pair(PLAIN, precision=L.FP32)
+    o.step(200)
+    d.step(200)
+    errs, bad = compare(o, d, TOL32)
+    assert not bad, errs
+    assert abs(d.heat_flux()["q_mean"] / o.heat_flux()["q_mean"] - 1) < 1e-4
+
+
+@pytest.mark.parametrize("nx,ny", [(100, 37), (3, 4), (65, 9), (130, 17)])
+def test_ragged_sizes_fp64(nx, ny):
+    _say("ragged", nx, ny)
+    w = PLAIN.resized(nx, ny, heater=(nx // 4, nx // 2 + 1), Gw_bottom=0.05)
+    o, d, _ = make_pair(w, Gw_top=-0.03)
+    o.step(120)
+    d.step(120)
+    errs, bad = compare(o, d, TOL64)
+    assert not bad, errs
+
+
+@pytest.mark.parametrize("mode", [O.ISOTHERMAL, O.THERMAL_ONLY])
+def test_test_modes_fp64(mode):
+    _say("mode", mode)
+    w = PLAIN.resized(96, 40, heater=(10, 60))
+    ux0 = uy0 = T0 = None
+    if mode == O.THERMAL_ONLY:
+        y, x = np.mgrid[0:w.ny, 0:w.nx].astype(float)
+        ux0 = 0.02 * np.sin(2 * np.pi * x / w.nx) * np.sin(np.pi * y / (w.ny - 1))
+        uy0 = 0.01 * np.cos(2 * np.pi * x / w.nx) * np.sin(np.pi * y / (w.ny - 1))
+        ux0[[0, -1]] = 0.0
+        uy0[[0, -1]] = 0.0
+    o, d, info = make_pair(w, mode=mode, ux0=ux0, uy0=uy0, T0=T0)
+    o.step(150)
+    d.step(150)
+    errs, bad = compare(o, d, TOL64)
+    assert not bad, errs
+
+
+@pytest.mark.parametrize("precision,tol", [(L.FP64, TOL64), (L.FP32, TOL32)])
+def test_periodic_box(precision, tol):
+    _say("periodic", precision)
+    w = PLAIN.resized(80, 48)
+    tc = O.Tc(w.a, w.b, w.R)
+    rv, rl, _ = O.maxwell(w.a, w.b, w.R, w.omega, w.Ts_over_Tc * tc)
+    rho0 = WL.layered_density(w.nx, w.ny, rl, rv, 24, 0.05, seed=11)
+    y, x = np.mgrid[0:w.ny, 0:w.nx]
+    T0 = w.Ts_over_Tc * tc * (1 + 0.01 * np.sin(2 * np.pi * x / w.nx) * np.cos(2 * np.pi * y / w.ny))
+    o, d, _ = make_pair(w, precision=precision, periodic_y=1, rho0=rho0, T0=T0)
+    o.step(200)
+    d.step(200)
+    errs, bad = compare(o, d, tol)
+    assert not bad, errs
+    # mass is conserved exactly up to rounding in the fully periodic box
+    assert abs(d.fields(f=False)["rho"].sum() / o.fields()["rho"].sum() - 1) < (1e-13 if precision == L.FP64 else 1e-6)
+
+
+def test_library_initial_state_matches_generator():
+    """rho0 = NULL builds the layered state from the library's own SplitMix64;
+    it must equal the shared input generator bitwise."""
+    _say("built-in initial state")
+    w = PLAIN
+    tc = O.Tc(w.a, w.b, w.R)
+    rv, rl, _ = O.maxwell(w.a, w.b, w.R, w.omega, w.Ts_over_Tc * tc)
+    p = L.Params(nx=w.nx, ny=w.ny, liquid_rows=w.liquid_rows, noise_amp=w.noise_amp, seed=w.seed,
+                 rho_L=rl, rho_V=rv)
+    d = L.Domain(p)
+    o = O.State(O.Params(nx=w.nx, ny=w.ny, rho_L=rl, rho_V=rv), w.density(rl, rv))
+    assert np.array_equal(d.fields()["rho"], o.fields()["rho"])
+    assert np.array_equal(d.fields()["f"], o.fields()["f"])
+
+
+def test_chunking_and_determinism_bitwise():
+    """Graph replays and single launches give the same bits; reruns too."""
+    _say("chunking")
+    runs = []
+    for chunks in ([200], [37, 131, 32], [1] * 5 + [195]):
+        _, d, _ = make_pair(PLAIN)
+        for c in chunks:
+            d.step(c)
+        runs.append((d.fields(), d.heat_flux()))
+    for f, h in runs[1:]:
+        for k in ("f", "T"):
+            assert np.array_equal(f[k], runs[0][0][k])
+        assert h["q_mean"] == runs[0][1]["q_mean"] and h["n_samples"] == 200
+
+
+def test_save_load_resume_bitwise():
+    _say("save/load")
+    _, d, _ = make_pair(PLAIN, precision=L.FP32)
+    d.step(50)
+    blob = d.save()
+    d.step(77)
+    a, qa = d.fields(), d.heat_flux()
+    d.load(blob)
+    assert d.t == 50
+    d.step(77)
+    b, qb = d.fields(), d.heat_flux()
+    for k in ("f", "T"):
+        assert np.array_equal(a[k], b[k])
+    assert qa["q_mean"] == qb["q_mean"] and qa["n_samples"] == qb["n_samples"] == 127
+    bad = bytearray(blob)
+    bad[len(bad) // 2] ^= 0xFF
+    with pytest.raises(L.LbbError) as e:
+        d.load(bytes(bad))
+    assert e.value.code == L.LBB_EINVAL
+
+
+def test_superheat_step_and_wettability_change():
+    """Raise the heater mid-run (Sec. 3.2 protocol) and change G_w."""
+    _say("superheat step")
+    w = PLAIN.resized(96, 48, heater=(20, 70), Gw_bottom=0.065)
+    o, d, info = make_pair(w)
+    o.step(60)
+    d.step(60)
+    Tb2 = WL.heater_profile(w.nx, w.Ts_over_Tc * info["Tc"], (w.Ts_over_Tc + 0.12) * info["Tc"], 10, 80)
+    o.set_heater(Tb2)
+    d.set_heater(Tb2)
+    o.set_wettability(0.105)
+    d.set_wettability(0.105)
+    o.reset_average()
+    d.reset_average()
+    o.step(90)
+    d.step(90)
+    errs, bad = compare(o, d, TOL64)
+    assert not bad, errs
+    assert d.heat_flux()["n_samples"] == 90
+    assert abs(d.heat_flux()["q_mean"] - o.heat_flux()["q_mean"]) <= TOL64 * heat_flux_scale(o)
+
+
+def test_invalid_state_is_reported_and_recoverable():
+    """Above T_c a dense state has a negative pseudopotential radicand: the
+    step reports ENONFINITE with the step index, the domain is poisoned,
+    and loading a saved state recovers it."""
+    _say("error path")
+    a = 3.0 / 49.0
+    tc = O.Tc(a, 2.0 / 21.0, 1.0)
+    p = L.Params(nx=16, ny=8, a=a, Ts_over_Tc=1.1, periodic_y=1, thermal_mode=L.ISOTHERMAL, rho_L=6.5, rho_V=0.4,
+                 liquid_rows=4)
+    rho = np.full((8, 16), 6.0)
+    d = L.Domain(p, rho0=rho)
+    blob = d.save()
+    d.set_fields(np.full((8, 16), 8.5), T=np.full((8, 16), 1.1 * tc))
+    with pytest.raises(L.LbbError) as e:
+        d.step(3)
+    assert e.value.code == L.LBB_ENONFINITE and "step 0" in str(e.value)
+    with pytest.raises(L.LbbError) as e:
+        d.step(1)
+    assert e.value.code == L.LBB_ESTATE
+    d.load(blob)
+    d.step(5)
+
+
+@pytest.mark.slow
+def test_large_fp32_matches_oracle_200_steps():
+    """The benchmarked workload (1024x512, FP32, full-width heater, G_w for
+    ~60 deg) over 200 steps through the same launch path as the benchmark."""
+    _say("large 1024x512 fp32 200")
+    o, d, _ = make_pair(WL.LARGE_1024x512)
+    d.step(200)
+    o.step(200)
+    errs, bad = compare(o, d, TOL32)
+    assert not bad, errs
+    assert abs(d.heat_flux()["q_mean"] / o.heat_flux()["q_mean"] - 1) < 1e-4
