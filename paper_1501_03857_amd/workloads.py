@@ -101,6 +101,17 @@ class Workload:
         return replace(self, nx=nx, ny=ny, **kw)
 
 
+def scaled_gravity(ny: int, a: float, g_paper: float = 3e-5, ny_paper: int = 150, a_paper: float = 3.0 / 49.0) -> float:
+    """Gravity for a lattice of height ny that keeps the paper's ratio of the
+    hydrostatic load to the saturation pressure (600x150, a = 3/49, g = 3e-5,
+    Sec. 3.1).  Buoyancy is measured against the domain-mean density
+    (Eq. (9)), so the vapour layer is pushed up with (rho_ave - rho_V) g per
+    node; over a tall layer that load exceeds p_sat (which scales with a) and
+    the vapour next to the interface empties.  Scaling g with
+    (ny_paper / ny) (a / a_paper) keeps the load at the paper's fraction."""
+    return g_paper * (ny_paper / ny) * (a / a_paper)
+
+
 # Provisional wall-strength values for the contact-angle labels of the sweep
 # workloads: a straight-line fit through the three (G_w, angle) pairs the paper
 # reports (0 -> 44.5 deg, 0.065 -> 50 deg, 0.105 -> 55.5 deg, Sec. 3.3).
@@ -110,13 +121,17 @@ CONTACT_ANGLE_GW = {40: -0.041, 60: 0.154, 90: 0.446, 120: 0.737}
 PLAIN_128x64 = Workload("plain_128x64_fp64", 128, 64, "fp64", 1000, dT_over_Tc=0.05,
                         heater=(48, 80), Gw_bottom=0.0, seed=1)
 # Single large instance: 1024x512, FP32 storage, full-width heater at 0.10 T_c,
-# contact angle ~60 deg, 20000 steps.
+# contact angle ~60 deg, 20000 steps; gravity scaled to the lattice height
+# (with g = 3e-5 the 205-row vapour layer carries a buoyant load above p_sat
+# and empties within ~1000 steps).
 LARGE_1024x512 = Workload("large_1024x512_fp32", 1024, 512, "fp32", 20000, dT_over_Tc=0.10,
-                          heater=(0, -1), Gw_bottom=CONTACT_ANGLE_GW[60], seed=2)
+                          heater=(0, -1), Gw_bottom=CONTACT_ANGLE_GW[60], seed=2,
+                          g=scaled_gravity(512, 2.0 / 49.0))
 # Bandwidth-truth supplement: the same physics on a lattice far larger than
 # the 256 MB last-level cache.
 LARGE_4096x2048 = Workload("large_4096x2048_fp32", 4096, 2048, "fp32", 2000, dT_over_Tc=0.10,
-                           heater=(0, -1), Gw_bottom=CONTACT_ANGLE_GW[60], seed=2)
+                           heater=(0, -1), Gw_bottom=CONTACT_ANGLE_GW[60], seed=2,
+                           g=scaled_gravity(2048, 2.0 / 49.0))
 # Adjoint case: 256x128, heater i in [96, 160) at 0.10 T_c, G_w = 0.065, 400 steps.
 ADJOINT_256x128 = Workload("adjoint_256x128", 256, 128, "fp64", 400, dT_over_Tc=0.10,
                            heater=(96, 160), Gw_bottom=0.065, seed=4)
@@ -135,6 +150,6 @@ def sweep_workloads(steps: int = 10000):
             nx, ny = SWEEP_SIZES[int(pick[i])]
             out.append(Workload(f"sweep_{i:02d}", nx, ny, "fp32", steps, dT_over_Tc=0.02 * k,
                                 heater=(0, -1), Gw_bottom=CONTACT_ANGLE_GW[ang], seed=1000 + i,
-                                extra={"angle": ang}))
+                                g=scaled_gravity(ny, 2.0 / 49.0), extra={"angle": ang}))
             i += 1
     return out
