@@ -36,12 +36,34 @@
 
 namespace lbb {
 
-constexpr int NT = 256;   // threads per block (4 waves)
-constexpr int TXA = 64;   // LB tile
-constexpr int TYA = 8;
-constexpr int TXB = 64;   // thermal tile
-constexpr int TYB = 8;
+constexpr int NT = 256;   // threads per block of the small kernels (4 waves)
+constexpr int TXR = 64;   // read-back tile
+constexpr int TYR = 8;
+constexpr int TXA = 62;   // LB tile width: tile + halo of one is one wave wide
+constexpr int TYA = 8;    // LB tile height
+constexpr int NWA = 4;    // waves per LB block
+constexpr int IPW_A = TYA / NWA;  // interior rows per LB wave
+static_assert(TYA % NWA == 0, "LB rows must split evenly over the waves");
 constexpr int HB = 4;     // thermal halo (RK4 has four stencil stages)
+constexpr int TXB = 64 - 2 * HB;  // thermal tile width: tile + halo is one wave wide
+constexpr int NWB = 8;    // waves per thermal block
+
+// Thermal tile height and the type of the RK4 stage arithmetic: FP64 storage
+// keeps FP64; FP32 storage runs the stages in FP32 on T - T_s (rounding
+// ~4e-10 absolute) with the EOS coefficients formed in FP64.
+template <typename S> struct ThermalCfg;
+// sqrt of the stage arithmetic: correctly rounded in FP64, the hardware
+// instruction (1 ulp) in FP32
+__device__ __forceinline__ double stage_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float stage_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+template <> struct ThermalCfg<float> {
+    using C = float;
+    static constexpr int TY = 32;
+};
+template <> struct ThermalCfg<double> {
+    using C = double;
+    static constexpr int TY = 16;
+};
 
 enum : int { MODE_COUPLED = 0, MODE_ISOTHERMAL = 1, MODE_THERMAL_ONLY = 2 };
 enum : int { ERR_RHO = 1, ERR_PSI = 2, ERR_T = 4 };
@@ -58,6 +80,7 @@ struct DevParams {
     double cv, chi, cv_chi;
     double g, Gw_bottom, Gw_top;
     double sig_e, sig_z;         // sigma/(tau_e - 1/2), sigma/(tau_zeta - 1/2)
+    double inv_Tc, two_over_G;
 };
 
 // Device-resident scalars of one domain.  tA is the state index seen by the
@@ -112,15 +135,31 @@ __device__ __forceinline__ void load_node(const DevParams &P, const S *__restric
     }
 }
 
+// Widen the 9 stored populations of a node to FP64 and complete a wall node.
+template <typename S>
+__device__ __forceinline__ void complete_node(const DevParams &P, const S fs[9], int gy, double fl[9])
+{
+#pragma unroll
+    for (int a = 0; a < 9; ++a) fl[a] = (double)fs[a];
+    if (!P.periodic_y && P.mode != MODE_THERMAL_ONLY) {
+        if (gy == 0) zou_he(fl, 1);
+        else if (gy == P.ny - 1) zou_he(fl, 0);
+    }
+}
+
 // psi = sqrt(2 (p_EOS - rho/3) / G) with the Peng-Robinson p_EOS (Eq. (21)),
 // always in FP64.  Returns a negative value on a negative radicand.
+// The two fractions of p_EOS share one division:
+//   p = [rho R T D2 - a phi rho^2 D1] / (D1 D2), D1 = 1 - b rho,
+//   D2 = 1 + 2 b rho - b^2 rho^2.
 __device__ __forceinline__ double pseudopotential(const DevParams &P, double rho, double T)
 {
-    const double s = 1.0 + P.kappa * (1.0 - sqrt(T / P.Tc));
+    const double s = 1.0 + P.kappa * (1.0 - sqrt(T * P.inv_Tc));
     const double phi = s * s;
-    const double p = rho * P.R * T / (1.0 - P.b * rho) -
-                     P.a * phi * rho * rho / (1.0 + 2.0 * P.b * rho - P.b * P.b * rho * rho);
-    const double r = 2.0 * (p - rho / 3.0) / P.G;
+    const double D1 = 1.0 - P.b * rho;
+    const double D2 = 1.0 + 2.0 * P.b * rho - P.b * P.b * rho * rho;
+    const double p = (rho * P.R * T * D2 - P.a * phi * rho * rho * D1) / (D1 * D2);
+    const double r = P.two_over_G * (p - rho * (1.0 / 3.0));
     return (r >= 0.0) ? sqrt(r) : -1.0;
 }
 
@@ -130,8 +169,10 @@ __device__ __forceinline__ void flag_error(Scalars *sc, long long t, unsigned co
     atomicOr(&sc->err_code, code);
 }
 
-// Wave64 + block sum of one double per thread, result valid in thread 0.
-__device__ __forceinline__ double block_sum(double v, double *red /* [NT/64] */)
+// Wave64 + block sum of one double per thread (NTH threads), result valid in
+// thread 0.  Fixed tree, so the result is reproducible.
+template <int NTH = NT>
+__device__ __forceinline__ double block_sum(double v, double *red /* [NTH/64] */)
 {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -140,16 +181,17 @@ __device__ __forceinline__ double block_sum(double v, double *red /* [NT/64] */)
     __syncthreads();
     double s = 0.0;
     if (threadIdx.x == 0)
-        for (int k = 0; k < NT / 64; ++k) s += red[k];
+        for (int k = 0; k < NTH / 64; ++k) s += red[k];
     return s;
 }
 
 // Fixed-order sum of n doubles by one block; result valid in thread 0.
+template <int NTH = NT>
 __device__ __forceinline__ double block_sum_array(const double *__restrict__ a, int n, double *red)
 {
     double s = 0.0;
-    for (int k = threadIdx.x; k < n; k += NT) s += a[k];
-    return block_sum(s, red);
+    for (int k = threadIdx.x; k < n; k += NTH) s += a[k];
+    return block_sum<NTH>(s, red);
 }
 
 // Heat-flux bookkeeping: q of state t from the partial sums over x; counted
@@ -294,15 +336,20 @@ __device__ __forceinline__ void tile_psi(const DevParams &P, const S *__restrict
 
 // ---------------------------------------------------------------------------
 // LB step: forces, collision and push streaming; mass partials.
+// Layout: the tile (TXA x TYA) with its halo of one node is 64 columns wide,
+// lane = column, and each of the NWA waves owns every NWA-th row.  Phase 1
+// forms rho and psi (FP64 EOS) on the tile and halo, keeping each node's
+// populations in registers; phase 2 collides the interior nodes and pushes.
 template <typename S>
-__global__ __launch_bounds__(NT) void k_lb(DevParams P, const S *__restrict__ fin, S *__restrict__ fout,
-                                           const S *__restrict__ Tin, S *__restrict__ rho_o,
-                                           S *__restrict__ vx_o, S *__restrict__ vy_o,
-                                           double *__restrict__ mass_part, const double *__restrict__ hf_part,
-                                           int n_hf, Scalars *__restrict__ sc, int nbx, int nby)
+__global__ __launch_bounds__(64 * NWA) void k_lb(DevParams P, const S *__restrict__ fin, S *__restrict__ fout,
+                                                 const S *__restrict__ Tin, S *__restrict__ rho_o,
+                                                 S *__restrict__ vx_o, S *__restrict__ vy_o,
+                                                 double *__restrict__ mass_part, const double *__restrict__ hf_part,
+                                                 int n_hf, Scalars *__restrict__ sc, int nbx, int nby)
 {
-    __shared__ double psi_s[(TXA + 2) * (TYA + 2)];
-    __shared__ double red[NT / 64];
+    constexpr int H = TYA + 2;                   // region rows (halo rows 0 and H-1)
+    __shared__ double psi_s[H * 64];
+    __shared__ double red[NWA];
     const long long t = sc->tA;
     if ((int)blockIdx.x == nbx * nby) {
         reduce_heat_flux(hf_part, n_hf, P.nx, sc, t);
@@ -314,47 +361,107 @@ __global__ __launch_bounds__(NT) void k_lb(DevParams P, const S *__restrict__ fi
     const size_t N = (size_t)P.nx * P.ny;
     const bool walls = !P.periodic_y;
     const bool frozen = P.mode == MODE_THERMAL_ONLY;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int gx = wrapi(x0 + lane - 1, P.nx);
 
-    if (!frozen) tile_psi<S, TXA, TYA>(P, fin, Tin, x0, y0, psi_s, sc, t);
+    // lattice row of region row r (wrapped when periodic); false beyond a wall
+    auto row_of = [&](int r, int &gy) -> bool {
+        gy = y0 + r - 1;
+        if (P.periodic_y) {
+            gy = wrapi(gy, P.ny);
+            return true;
+        }
+        return gy >= 0 && gy < P.ny;
+    };
+    // rho and psi of node (r, lane) into LDS; returns rho
+    auto psi_node = [&](int r, int gy, const S fs[9]) -> double {
+        double fl[9];
+        complete_node(P, fs, gy, fl);
+        double rr = fl[0];
+#pragma unroll
+        for (int a = 1; a < 9; ++a) rr += fl[a];
+        if (!frozen) {
+            const double T = P.T_ref + (double)Tin[(size_t)gy * P.nx + gx];
+            const double psi = pseudopotential(P, rr, T);
+            if (!(rr > 0.0) || !(rr < 1e300)) flag_error(sc, t, ERR_RHO);
+            if (!(psi >= 0.0) || !(psi < 1e300)) flag_error(sc, t, ERR_PSI);
+            psi_s[r * 64 + lane] = psi;
+        }
+        return rr;
+    };
+
+    // phase 1: the wave's interior rows (populations kept in registers) and,
+    // for waves 0 and 1, the halo rows 0 and H-1 (psi only)
+    S fs[IPW_A][9];
+    double rho[IPW_A];
+    int gys[IPW_A];
+    bool live[IPW_A];
+#pragma unroll
+    for (int m = 0; m < IPW_A; ++m) {
+        const int r = 1 + wv + NWA * m;
+        int gy;
+        const bool in_lattice = row_of(r, gy);
+        // a ragged last tile row beyond ny is not collided here, but with
+        // periodic y it wraps onto a real row whose psi its neighbour needs
+        live[m] = in_lattice && y0 + r - 1 < P.ny;
+        gys[m] = gy;
+        rho[m] = 1.0;
+        if (!in_lattice) continue;
+        const size_t c = (size_t)gy * P.nx + gx;
+#pragma unroll
+        for (int a = 0; a < 9; ++a) fs[m][a] = fin[(size_t)a * N + c];
+        rho[m] = psi_node(r, gy, fs[m]);
+    }
+    if (wv < 2) {
+        const int r = wv == 0 ? 0 : H - 1;
+        int gy;
+        if (row_of(r, gy)) {
+            const size_t c = (size_t)gy * P.nx + gx;
+            S hs[9];
+#pragma unroll
+            for (int a = 0; a < 9; ++a) hs[a] = fin[(size_t)a * N + c];
+            (void)psi_node(r, gy, hs);
+        }
+    }
     __syncthreads();
     const double rho_ave = sc->rho_ave;
 
     double mass = 0.0;
-    const int tx = threadIdx.x % TXA;
-    for (int ly = threadIdx.x / TXA; ly < TYA; ly += NT / TXA) {
-        const int gx = x0 + tx, gy = y0 + ly;
-        if (gx >= P.nx || gy >= P.ny) continue;
-        const size_t c = (size_t)gy * P.nx + gx;
-        double fl[9];
-        load_node(P, fin, N, c, gy, fl);
-        double rho = fl[0];
 #pragma unroll
-        for (int a = 1; a < 9; ++a) rho += fl[a];
-        const double jx = fl[1] - fl[3] + fl[5] - fl[6] - fl[7] + fl[8];
-        const double jy = fl[2] - fl[4] + fl[5] + fl[6] - fl[7] - fl[8];
+    for (int m = 0; m < IPW_A; ++m) {
+        const int r = 1 + wv + NWA * m;
+        const int gy = gys[m];
+        if (!live[m] || lane < 1 || lane > TXA || x0 + lane - 1 >= P.nx) continue;
+        const size_t c = (size_t)gy * P.nx + gx;
+        double f[9];
+        complete_node(P, fs[m], gy, f);
+        const double rh = rho[m];
+        const double jx = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
+        const double jy = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
         const bool wall_row = walls && (gy == 0 || gy == P.ny - 1);
         if (frozen) {
             // THERMAL_ONLY: f is frozen, the temperature sees sum e f / rho
-            rho_o[c] = S(rho);
-            vx_o[c] = wall_row ? S(0) : S(jx / rho);
-            vy_o[c] = wall_row ? S(0) : S(jy / rho);
-            double m = 0.0;
+            rho_o[c] = S(rh);
+            vx_o[c] = wall_row ? S(0) : S(jx / rh);
+            vy_o[c] = wall_row ? S(0) : S(jy / rh);
+            double mm = 0.0;
 #pragma unroll
-            for (int a = 0; a < 9; ++a) m += fl[a];
-            mass += m;
+            for (int a = 0; a < 9; ++a) mm += f[a];
+            mass += mm;
             continue;
         }
         double Fx, Fy, Q;
-        node_force<TXA + 2>(P, psi_s, tx, ly, gy, rho, rho_ave, Fx, Fy, Q);
-        const double vx = (jx + 0.5 * Fx) / rho;
-        const double vy = (jy + 0.5 * Fy) / rho;
-        rho_o[c] = S(rho);
+        node_force<64>(P, psi_s, lane - 1, r - 1, gy, rh, rho_ave, Fx, Fy, Q);
+        const double inv_rho = 1.0 / rh;
+        const double vx = (jx + 0.5 * Fx) * inv_rho;
+        const double vy = (jy + 0.5 * Fy) * inv_rho;
+        rho_o[c] = S(rh);
         vx_o[c] = wall_row ? S(0) : S(vx);
         vy_o[c] = wall_row ? S(0) : S(vy);
-        collide(P, fl, rho, vx, vy, Fx, Fy, Q);
+        collide(P, f, rh, vx, vy, Fx, Fy, Q);
         // round to the storage precision once; the mass partial sees what is stored
 #pragma unroll
-        for (int a = 0; a < 9; ++a) fl[a] = (double)S(fl[a]);
+        for (int a = 0; a < 9; ++a) f[a] = (double)S(f[a]);
         // push streaming, Eq. (3); populations leaving through a wall are
         // dropped.  Mass of the streamed state: each population counts once,
         // except those that leave through a wall (0) and those that arrive on
@@ -369,28 +476,28 @@ __global__ __launch_bounds__(NT) void k_lb(DevParams P, const S *__restrict__ fi
         }
         const bool has_n = yn < P.ny, has_s = ys >= 0;
         const size_t rowc = (size_t)gy * P.nx, rown = (size_t)yn * P.nx, rows = (size_t)ys * P.nx;
-        fout[0 * N + rowc + gx] = S(fl[0]);
-        fout[1 * N + rowc + xe] = S(fl[1]);
-        fout[3 * N + rowc + xw] = S(fl[3]);
+        fout[0 * N + rowc + gx] = S(f[0]);
+        fout[1 * N + rowc + xe] = S(f[1]);
+        fout[3 * N + rowc + xw] = S(f[3]);
         if (has_n) {
-            fout[2 * N + rown + gx] = S(fl[2]);
-            fout[5 * N + rown + xe] = S(fl[5]);
-            fout[6 * N + rown + xw] = S(fl[6]);
+            fout[2 * N + rown + gx] = S(f[2]);
+            fout[5 * N + rown + xe] = S(f[5]);
+            fout[6 * N + rown + xw] = S(f[6]);
         }
         if (has_s) {
-            fout[4 * N + rows + gx] = S(fl[4]);
-            fout[7 * N + rows + xw] = S(fl[7]);
-            fout[8 * N + rows + xe] = S(fl[8]);
+            fout[4 * N + rows + gx] = S(f[4]);
+            fout[7 * N + rows + xw] = S(f[7]);
+            fout[8 * N + rows + xe] = S(f[8]);
         }
-        const double up = fl[2] + fl[5] + fl[6];
-        const double dn = fl[4] + fl[7] + fl[8];
-        double m = fl[0] + fl[1] + fl[3];
+        const double up = f[2] + f[5] + f[6];
+        const double dn = f[4] + f[7] + f[8];
+        double mm = f[0] + f[1] + f[3];
         const double wu = !walls ? 1.0 : (gy == P.ny - 1 ? 0.0 : (gy == P.ny - 2 ? 2.0 : 1.0));
         const double wd = !walls ? 1.0 : (gy == 0 ? 0.0 : (gy == 1 ? 2.0 : 1.0));
-        m += wu * up + wd * dn;
-        mass += m;
+        mm += wu * up + wd * dn;
+        mass += mm;
     }
-    const double bm = block_sum(mass, red);
+    const double bm = block_sum<64 * NWA>(mass, red);
     if (threadIdx.x == 0) mass_part[blockIdx.x] = bm;
 }
 
@@ -401,21 +508,30 @@ __global__ __launch_bounds__(NT) void k_lb(DevParams P, const S *__restrict__ fi
 // cw = A(rho) w, cq = B(rho) w, A = rho R/(1 - b rho),
 // B = a rho^2/(1 + 2 b rho - b^2 rho^2), so that (dp/dT)_rho = A - B phi'(T)
 // and T phi'(T) = kappa^2 T/T_c - kappa (1 + kappa) sqrt(T/T_c).
+// Layout: the tile (TXB x TY) with its halo of HB nodes is 64 columns wide,
+// so lane = column and each of the NWB waves owns every NWB-th row of the
+// region; stage k is evaluated on the region shrunk by k+1 nodes, with the
+// stage values updated in place between barriers and the RK4 sums in
+// registers.
 template <typename S>
-__global__ __launch_bounds__(NT) void k_thermal(DevParams P, const S *__restrict__ Tin, S *__restrict__ Tout,
-                                                const S *__restrict__ rho_i, const S *__restrict__ vx_i,
-                                                const S *__restrict__ vy_i, const S *__restrict__ fnew,
-                                                double *__restrict__ hf_part, const double *__restrict__ mass_part,
-                                                int n_mass, Scalars *__restrict__ sc, int nbx, int nby)
+__global__ __launch_bounds__(64 * NWB) void k_thermal(DevParams P, const S *__restrict__ Tin, S *__restrict__ Tout,
+                                                      const S *__restrict__ rho_i, const S *__restrict__ vx_i,
+                                                      const S *__restrict__ vy_i, const S *__restrict__ fnew,
+                                                      double *__restrict__ hf_part,
+                                                      const double *__restrict__ mass_part, int n_mass,
+                                                      Scalars *__restrict__ sc, int nbx, int nby)
 {
-    constexpr int W = TXB + 2 * HB, H = TYB + 2 * HB, A = W * H;
-    __shared__ double T0[A];
-    __shared__ double cf[4][A];
-    __shared__ double un[3][A];   // rho, vx, vy; then stage buffers Ta, Tb and acc
-    __shared__ double red[NT / 64];
+    using C = typename ThermalCfg<S>::C;
+    constexpr int TY = ThermalCfg<S>::TY;
+    constexpr int H = TY + 2 * HB;               // region rows
+    constexpr int RPW = (H + NWB - 1) / NWB;     // region rows per wave
+    __shared__ C T0[H][64];
+    __shared__ C X[4][H][64];   // rho, vx, vy after the load; then ax, ay, cw, cq
+    __shared__ C Ts[H][64];     // stage values T0 + c h; new T for the heat flux
+    __shared__ double red[NWB];
     const long long t = sc->tB;
     if ((int)blockIdx.x == nbx * nby) {
-        const double m = block_sum_array(mass_part, n_mass, red);
+        const double m = block_sum_array<64 * NWB>(mass_part, n_mass, red);
         if (threadIdx.x == 0) {
             sc->rho_ave = m / ((double)P.nx * (double)P.ny);
             sc->tA = t + 1;
@@ -423,12 +539,15 @@ __global__ __launch_bounds__(NT) void k_thermal(DevParams P, const S *__restrict
         return;
     }
     const int bx = blockIdx.x % nbx, by = blockIdx.x / nbx;
-    const int x0 = bx * TXB, y0 = by * TYB;
+    const int x0 = bx * TXB, y0 = by * TY;
     const bool walls = !P.periodic_y;
     const bool run = P.mode != MODE_ISOTHERMAL;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int gx = wrapi(x0 + lane - HB, P.nx);
 
-    auto gyof = [&](int ly, int &gy) -> bool {  // false if outside the lattice
-        gy = y0 + ly;
+    // lattice row of region row r; false beyond a wall
+    auto row_of = [&](int r, int &gy) -> bool {
+        gy = y0 + r - HB;
         if (P.periodic_y) {
             gy = wrapi(gy, P.ny);
             return true;
@@ -436,133 +555,150 @@ __global__ __launch_bounds__(NT) void k_thermal(DevParams P, const S *__restrict
         return gy >= 0 && gy < P.ny;
     };
 
-    // load T, rho, v on the tile with a halo of HB
-    for (int k = threadIdx.x; k < A; k += NT) {
-        const int lx = k % W - HB, ly = k / W - HB;
+#pragma unroll
+    for (int m = 0; m < RPW; ++m) {
+        const int r = wv + NWB * m;
         int gy;
-        if (!gyof(ly, gy)) continue;
-        const size_t c = (size_t)gy * P.nx + wrapi(x0 + lx, P.nx);
-        T0[k] = (double)Tin[c];
+        if (r >= H || !row_of(r, gy)) continue;
+        const size_t c = (size_t)gy * P.nx + gx;
+        T0[r][lane] = (C)Tin[c];
         if (run) {
-            un[0][k] = (double)rho_i[c];
-            un[1][k] = (double)vx_i[c];
-            un[2][k] = (double)vy_i[c];
+            X[0][r][lane] = (C)rho_i[c];
+            X[1][r][lane] = (C)vx_i[c];
+            X[2][r][lane] = (C)vy_i[c];
         }
     }
     __syncthreads();
 
-    const double chi = double(P.chi);
+    const C chi = (C)P.chi;
+    C acc[RPW];
+#pragma unroll
+    for (int m = 0; m < RPW; ++m) acc[m] = C(0);
+
     if (run) {
-        // per-node coefficients on the tile with a halo of HB - 1
-        for (int k = threadIdx.x; k < A; k += NT) {
-            const int lx = k % W - HB, ly = k / W - HB;
-            if (lx < -(HB - 1) || lx >= TXB + HB - 1 || ly < -(HB - 1) || ly >= TYB + HB - 1) continue;
+        // per-node coefficients on the region shrunk by one node
+        C cfr[4][RPW];
+#pragma unroll
+        for (int m = 0; m < RPW; ++m) {
+            const int r = wv + NWB * m;
             int gy;
-            if (!gyof(ly, gy)) continue;
+            cfr[0][m] = cfr[1][m] = cfr[2][m] = cfr[3][m] = C(0);
+            if (r < 1 || r >= H - 1 || lane < 1 || lane >= 63 || !row_of(r, gy)) continue;
             if (walls && (gy == 0 || gy == P.ny - 1)) continue;
-            const double *r = un[0], *u = un[1], *v = un[2];
-            const double rr = (double)r[k];
-            const double drx = (r[k + 1] - r[k - 1]) * double(1.0 / 3.0) +
-                          (r[k + W + 1] - r[k + W - 1] + r[k - W + 1] - r[k - W - 1]) * double(1.0 / 12.0);
-            const double dry = (r[k + W] - r[k - W]) * double(1.0 / 3.0) +
-                          (r[k + W + 1] + r[k + W - 1] - r[k - W + 1] - r[k - W - 1]) * double(1.0 / 12.0);
-            const double dux = (u[k + 1] - u[k - 1]) * double(1.0 / 3.0) +
-                          (u[k + W + 1] - u[k + W - 1] + u[k - W + 1] - u[k - W - 1]) * double(1.0 / 12.0);
-            const double dvy = (v[k + W] - v[k - W]) * double(1.0 / 3.0) +
-                          (v[k + W + 1] + v[k + W - 1] - v[k - W + 1] - v[k - W - 1]) * double(1.0 / 12.0);
-            const double w = (double)(dux + dvy) / (rr * P.cv);
-            const double Acoef = rr * P.R / (1.0 - P.b * rr);
-            const double Bcoef = P.a * rr * rr / (1.0 + 2.0 * P.b * rr - P.b * P.b * rr * rr);
-            cf[0][k] = u[k] - chi * drx / double(rr);
-            cf[1][k] = v[k] - chi * dry / double(rr);
-            cf[2][k] = double(Acoef * w);
-            cf[3][k] = double(Bcoef * w);
+            const C(*rr)[64] = X[0];
+            const C(*uu)[64] = X[1];
+            const C(*vv)[64] = X[2];
+            const int l = lane;
+            const double rho = (double)rr[r][l];
+            const C drx = (rr[r][l + 1] - rr[r][l - 1]) * C(1.0 / 3.0) +
+                          (rr[r + 1][l + 1] - rr[r + 1][l - 1] + rr[r - 1][l + 1] - rr[r - 1][l - 1]) * C(1.0 / 12.0);
+            const C dry = (rr[r + 1][l] - rr[r - 1][l]) * C(1.0 / 3.0) +
+                          (rr[r + 1][l + 1] + rr[r + 1][l - 1] - rr[r - 1][l + 1] - rr[r - 1][l - 1]) * C(1.0 / 12.0);
+            const C dux = (uu[r][l + 1] - uu[r][l - 1]) * C(1.0 / 3.0) +
+                          (uu[r + 1][l + 1] - uu[r + 1][l - 1] + uu[r - 1][l + 1] - uu[r - 1][l - 1]) * C(1.0 / 12.0);
+            const C dvy = (vv[r + 1][l] - vv[r - 1][l]) * C(1.0 / 3.0) +
+                          (vv[r + 1][l + 1] + vv[r + 1][l - 1] - vv[r - 1][l + 1] - vv[r - 1][l - 1]) * C(1.0 / 12.0);
+            // A w = (R/c_v) div v / D1 and B w = (a/c_v) rho div v / D2 with
+            // D1 = 1 - b rho, D2 = 1 + 2 b rho - b^2 rho^2; one reciprocal
+            // 1/(rho D1 D2) gives 1/rho, 1/D1 and 1/D2
+            const double D1 = 1.0 - P.b * rho;
+            const double D2 = 1.0 + 2.0 * P.b * rho - P.b * P.b * rho * rho;
+            const double inv = 1.0 / (rho * D1 * D2);
+            const double div = (double)(dux + dvy);
+            const C chi_rho = (C)(P.chi * D1 * D2 * inv);
+            cfr[0][m] = uu[r][l] - chi_rho * drx;
+            cfr[1][m] = vv[r][l] - chi_rho * dry;
+            cfr[2][m] = (C)(P.R / P.cv * div * (rho * D2 * inv));
+            cfr[3][m] = (C)(P.a / P.cv * rho * div * (rho * D1 * inv));
         }
-    }
-    __syncthreads();
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < RPW; ++m) {
+            const int r = wv + NWB * m;
+            if (r >= H) continue;
+            X[0][r][lane] = cfr[0][m];
+            X[1][r][lane] = cfr[1][m];
+            X[2][r][lane] = cfr[2][m];
+            X[3][r][lane] = cfr[3][m];
+        }
+        __syncthreads();
 
-    double *Ta = un[0], *Tb = un[1], *acc = un[2];
-    const double kap = double(P.kappa), k1k = double(P.kappa * (1.0 + P.kappa)), k2 = double(P.kappa * P.kappa / P.Tc);
-    const double inv_Tc = double(1.0 / P.Tc), Tref = double(P.T_ref);
-    (void)kap;
-    if (run) {
-        // stage k reads `in` on radius r+1 and writes T0 + c h on radius r
-        const double *in = T0;
-        double *outs[3] = {Ta, Tb, Ta};
-        const double cst[4] = {double(0.5), double(0.5), double(1.0), double(0.0)};
-        const double wst[4] = {double(1), double(2), double(2), double(1)};
-#pragma unroll 1
+        const C k1k = (C)(P.kappa * (1.0 + P.kappa)), k2 = (C)(P.kappa * P.kappa / P.Tc);
+        const C inv_Tc = (C)(1.0 / P.Tc), Tref = (C)P.T_ref;
+        const C cst[3] = {C(0.5), C(0.5), C(1.0)};
+        const C wst[4] = {C(1), C(2), C(2), C(1)};
+#pragma unroll
         for (int st = 0; st < 4; ++st) {
-            const int r = HB - 1 - st;
-            double *out = st < 3 ? outs[st] : nullptr;
-            for (int k = threadIdx.x; k < A; k += NT) {
-                const int lx = k % W - HB, ly = k / W - HB;
-                if (lx < -r || lx >= TXB + r || ly < -r || ly >= TYB + r) continue;
+            const int rad = HB - 1 - st;
+            const C(*in)[64] = st == 0 ? T0 : Ts;
+            C h[RPW];
+#pragma unroll
+            for (int m = 0; m < RPW; ++m) {
+                const int r = wv + NWB * m;
+                h[m] = C(0);
                 int gy;
-                if (!gyof(ly, gy)) continue;
-                const bool interior = lx >= 0 && lx < TXB && ly >= 0 && ly < TYB;
-                double h = double(0);
-                if (!(walls && (gy == 0 || gy == P.ny - 1))) {
-                    const double tE = in[k + 1], tW = in[k - 1], tN = in[k + W], tS = in[k - W];
-                    const double tNE = in[k + W + 1], tNW = in[k + W - 1], tSW = in[k - W - 1], tSE = in[k - W + 1];
-                    const double tc = in[k];
-                    const double dTx = (tE - tW) * double(1.0 / 3.0) + (tNE - tNW + tSE - tSW) * double(1.0 / 12.0);
-                    const double dTy = (tN - tS) * double(1.0 / 3.0) + (tNE + tNW - tSE - tSW) * double(1.0 / 12.0);
-                    const double lap = (tE + tW + tN + tS) * double(2.0 / 3.0) + (tNE + tNW + tSE + tSW) * double(1.0 / 6.0) -
-                                  double(10.0 / 3.0) * tc;
-                    const double T = Tref + tc;
-                    const double sq = sqrt(T * inv_Tc);
-                    const double Tphi = k2 * T - k1k * sq;
-                    h = -(cf[0][k] * dTx + cf[1][k] * dTy) + chi * lap - cf[2][k] * T + cf[3][k] * Tphi;
-                }
-                if (out) out[k] = T0[k] + cst[st] * h;
-                if (interior) acc[k] = (st == 0 ? double(0) : acc[k]) + wst[st] * h;
+                if (r < HB - rad || r >= HB + TY + rad || lane < HB - rad || lane >= HB + TXB + rad) continue;
+                if (!row_of(r, gy) || (walls && (gy == 0 || gy == P.ny - 1))) continue;
+                const int l = lane;
+                const C tE = in[r][l + 1], tW = in[r][l - 1], tN = in[r + 1][l], tS = in[r - 1][l];
+                const C tNE = in[r + 1][l + 1], tNW = in[r + 1][l - 1], tSW = in[r - 1][l - 1], tSE = in[r - 1][l + 1];
+                const C tc = in[r][l];
+                const C dTx = (tE - tW) * C(1.0 / 3.0) + (tNE - tNW + tSE - tSW) * C(1.0 / 12.0);
+                const C dTy = (tN - tS) * C(1.0 / 3.0) + (tNE + tNW - tSE - tSW) * C(1.0 / 12.0);
+                const C lap = (tE + tW + tN + tS) * C(2.0 / 3.0) + (tNE + tNW + tSE + tSW) * C(1.0 / 6.0) - C(10.0 / 3.0) * tc;
+                const C T = Tref + tc;
+                const C Tphi = k2 * T - k1k * stage_sqrt(T * inv_Tc);
+                h[m] = -(X[0][r][l] * dTx + X[1][r][l] * dTy) + chi * lap - X[2][r][l] * T + X[3][r][l] * Tphi;
+                acc[m] += wst[st] * h[m];
             }
-            __syncthreads();
-            in = out;
+            if (st < 3) {
+                if (st > 0) __syncthreads();  // every read of the old stage values is done
+#pragma unroll
+                for (int m = 0; m < RPW; ++m) {
+                    const int r = wv + NWB * m;
+                    if (r >= H || r < HB - rad || r >= HB + TY + rad || lane < HB - rad || lane >= HB + TXB + rad) continue;
+                    Ts[r][lane] = T0[r][lane] + cst[st] * h[m];
+                }
+                __syncthreads();
+            }
         }
     }
+    if (run) __syncthreads();  // the last stage read Ts; it is reused below
 
-    // write the new interior temperature (wall rows keep their values)
-    const int tx = threadIdx.x % TXB;
-    for (int ly = threadIdx.x / TXB; ly < TYB; ly += NT / TXB) {
-        const int gx = x0 + tx;
+    // new interior temperature (wall rows keep their Dirichlet values)
+#pragma unroll
+    for (int m = 0; m < RPW; ++m) {
+        const int r = wv + NWB * m;
+        if (r < HB || r >= HB + TY || lane < HB || lane >= HB + TXB) continue;
         int gy;
-        if (gx >= P.nx || !gyof(ly, gy) || y0 + ly >= P.ny) continue;
-        const int k = (ly + HB) * W + tx + HB;
-        const bool wall_row = walls && (gy == 0 || gy == P.ny - 1);
-        double Tn = T0[k];
-        if (run && !wall_row) {
-            Tn = T0[k] + acc[k] / double(6);
-            const double Ta_ = P.T_ref + (double)Tn;
-            if (!(Ta_ > 0.0) || !(Ta_ < 1e300)) flag_error(sc, t, ERR_T);
-            Tout[(size_t)gy * P.nx + gx] = S(Tn);
-            Tn = (double)S(Tn);  // the heat flux sees the stored value
+        if (x0 + lane - HB >= P.nx || y0 + r - HB >= P.ny || !row_of(r, gy)) continue;
+        C Tn = T0[r][lane];
+        if (run && !(walls && (gy == 0 || gy == P.ny - 1))) {
+            Tn = (C)(S)(T0[r][lane] + acc[m] / C(6));
+            const double Tabs = P.T_ref + (double)Tn;
+            if (!(Tabs > 0.0) || !(Tabs < 1e300)) flag_error(sc, t, ERR_T);
+            Tout[(size_t)gy * P.nx + gx] = (S)Tn;
         }
-        acc[k] = Tn;
+        Ts[r][lane] = Tn;
     }
     __syncthreads();
 
     // heat-flux partials of the new state (bottom tile row only)
-    if (walls && by == 0 && threadIdx.x < TXB) {
-        const int gx = x0 + threadIdx.x;
+    if (walls && by == 0 && wv == 0) {
         double qw = 0.0;
-        if (gx < P.nx) {
+        if (lane >= HB && lane < HB + TXB && x0 + lane - HB < P.nx) {
             const size_t N = (size_t)P.nx * P.ny;
             double fl[9];
             load_node(P, fnew, N, (size_t)gx, 0, fl);
             double r0 = fl[0];
 #pragma unroll
             for (int a = 1; a < 9; ++a) r0 += fl[a];
-            const int k1 = (1 + HB) * W + threadIdx.x + HB, k2i = (2 + HB) * W + threadIdx.x + HB;
-            const double t0 = (double)T0[HB * W + threadIdx.x + HB];
-            const double t1 = (double)acc[k1], t2 = (double)acc[k2i];
-            qw = -P.cv_chi * (double)r0 * (-3.0 * t0 + 4.0 * t1 - t2) / 2.0;
+            const double t0 = (double)T0[HB][lane], t1 = (double)Ts[HB + 1][lane], t2 = (double)Ts[HB + 2][lane];
+            qw = -P.cv_chi * r0 * (-3.0 * t0 + 4.0 * t1 - t2) / 2.0;
         }
-        double s = qw;
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-        if (threadIdx.x == 0) hf_part[bx] = s;
+        for (int off = 32; off > 0; off >>= 1) qw += __shfl_xor(qw, off, 64);
+        if (lane == 0) hf_part[bx] = qw;
     }
 }
 
@@ -623,16 +759,17 @@ __global__ void k_reduce_mass(DevParams P, const double *__restrict__ part, int 
     if (threadIdx.x == 0) sc->rho_ave = m / ((double)P.nx * (double)P.ny);
 }
 
-// Heat-flux partials of the current state (set-up, heater change, load).
+// Heat-flux partials of the current state (set-up, heater change, load),
+// with the lane layout of the thermal kernel: 64 threads per tile of TXB
+// columns, lane = column + HB.
 template <typename S>
-__global__ __launch_bounds__(NT) void k_heat_flux_state(DevParams P, const S *__restrict__ f,
-                                                        const S *__restrict__ T, double *__restrict__ hf_part,
-                                                        double *__restrict__ q_local)
+__global__ void k_heat_flux_state(DevParams P, const S *__restrict__ f, const S *__restrict__ T,
+                                  double *__restrict__ hf_part, double *__restrict__ q_local)
 {
-    const int gx = blockIdx.x * TXB + threadIdx.x;
-    if (threadIdx.x >= TXB) return;
+    const int lane = threadIdx.x;
+    const int gx = blockIdx.x * TXB + lane - HB;
     double qw = 0.0;
-    if (!P.periodic_y && gx < P.nx) {
+    if (!P.periodic_y && lane >= HB && lane < HB + TXB && gx < P.nx) {
         const size_t N = (size_t)P.nx * P.ny;
         double fl[9];
         load_node(P, f, N, (size_t)gx, 0, fl);
@@ -640,13 +777,12 @@ __global__ __launch_bounds__(NT) void k_heat_flux_state(DevParams P, const S *__
 #pragma unroll
         for (int a = 1; a < 9; ++a) r0 += fl[a];
         const double t0 = (double)T[gx], t1 = (double)T[P.nx + gx], t2 = (double)T[2 * P.nx + gx];
-        qw = -P.cv_chi * (double)r0 * (-3.0 * t0 + 4.0 * t1 - t2) / 2.0;
+        qw = -P.cv_chi * r0 * (-3.0 * t0 + 4.0 * t1 - t2) / 2.0;
         if (q_local) q_local[gx] = qw;
     }
-    double s = qw;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    if (threadIdx.x == 0 && hf_part) hf_part[blockIdx.x] = s;
+    for (int off = 32; off > 0; off >>= 1) qw += __shfl_xor(qw, off, 64);
+    if (lane == 0 && hf_part) hf_part[blockIdx.x] = qw;
 }
 
 __global__ void k_flush_heat_flux(DevParams P, const double *__restrict__ hf_part, int n_hf, Scalars *sc)
@@ -662,16 +798,16 @@ __global__ __launch_bounds__(NT) void k_read(DevParams P, const S *__restrict__ 
                                              double *__restrict__ uy_o, double *__restrict__ T_o,
                                              double *__restrict__ f_o, Scalars *sc, int nbx)
 {
-    __shared__ double psi_s[(TXA + 2) * (TYA + 2)];
+    __shared__ double psi_s[(TXR + 2) * (TYR + 2)];
     const int bx = blockIdx.x % nbx, by = blockIdx.x / nbx;
-    const int x0 = bx * TXA, y0 = by * TYA;
+    const int x0 = bx * TXR, y0 = by * TYR;
     const size_t N = (size_t)P.nx * P.ny;
     const bool frozen = P.mode == MODE_THERMAL_ONLY;
-    if (!frozen) tile_psi<S, TXA, TYA>(P, fin, Tin, x0, y0, psi_s, sc, sc->tA);
+    if (!frozen) tile_psi<S, TXR, TYR>(P, fin, Tin, x0, y0, psi_s, sc, sc->tA);
     __syncthreads();
     const double rho_ave = sc->rho_ave;
-    const int tx = threadIdx.x % TXA;
-    for (int ly = threadIdx.x / TXA; ly < TYA; ly += NT / TXA) {
+    const int tx = threadIdx.x % TXR;
+    for (int ly = threadIdx.x / TXR; ly < TYR; ly += NT / TXR) {
         const int gx = x0 + tx, gy = y0 + ly;
         if (gx >= P.nx || gy >= P.ny) continue;
         const size_t c = (size_t)gy * P.nx + gx;
@@ -687,7 +823,7 @@ __global__ __launch_bounds__(NT) void k_read(DevParams P, const S *__restrict__ 
             jy = (double)(fl[2] - fl[4] + fl[5] + fl[6] - fl[7] - fl[8]);
         }
         double Fx = 0.0, Fy = 0.0, Q = 0.0;
-        if (!frozen) node_force<TXA + 2>(P, psi_s, tx, ly, gy, rho, rho_ave, Fx, Fy, Q);
+        if (!frozen) node_force<TXR + 2>(P, psi_s, tx, ly, gy, rho, rho_ave, Fx, Fy, Q);
         if (rho_o) rho_o[c] = rho;
         if (ux_o) ux_o[c] = (jx + 0.5 * Fx) / rho;
         if (uy_o) uy_o[c] = (jy + 0.5 * Fy) / rho;

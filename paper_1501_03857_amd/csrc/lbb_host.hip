@@ -198,7 +198,7 @@ void launch_lb(lbb_domain *d)
     const int nA = d->nbxA * d->nbyA;
     S *f0 = static_cast<S *>(d->f[d->cf]), *f1 = static_cast<S *>(d->f[d->cf ^ 1]);
     S *T0 = static_cast<S *>(d->T[d->cT]);
-    hipLaunchKernelGGL(k_lb<S>, dim3(nA + 1), dim3(NT), 0, d->stream, d->dp, f0, f1, T0, static_cast<S *>(d->rho),
+    hipLaunchKernelGGL(k_lb<S>, dim3(nA + 1), dim3(64 * NWA), 0, d->stream, d->dp, f0, f1, T0, static_cast<S *>(d->rho),
                        static_cast<S *>(d->vx), static_cast<S *>(d->vy), d->mass_part, d->hf_part, d->nbxB, d->sc,
                        d->nbxA, d->nbyA);
 }
@@ -211,7 +211,7 @@ void launch_thermal(lbb_domain *d)
     const bool frozen = d->dp.mode == MODE_THERMAL_ONLY;
     S *fnew = static_cast<S *>(d->f[frozen ? d->cf : d->cf ^ 1]);
     S *T0 = static_cast<S *>(d->T[d->cT]), *T1 = static_cast<S *>(d->T[d->cT ^ 1]);
-    hipLaunchKernelGGL(k_thermal<S>, dim3(nB + 1), dim3(NT), 0, d->stream, d->dp, T0, T1, static_cast<S *>(d->rho),
+    hipLaunchKernelGGL(k_thermal<S>, dim3(nB + 1), dim3(64 * NWB), 0, d->stream, d->dp, T0, T1, static_cast<S *>(d->rho),
                        static_cast<S *>(d->vx), static_cast<S *>(d->vy), fnew, d->hf_part, d->mass_part, nA, d->sc,
                        d->nbxB, d->nbyB);
 }
@@ -303,7 +303,7 @@ int refresh_reductions(lbb_domain *d)
     const int nm = d->nbxA * d->nbyA;
     hipLaunchKernelGGL(k_mass<S>, dim3(nm), dim3(NT), 0, d->stream, d->dp, static_cast<const S *>(d->f[d->cf]), d->mass_part);
     hipLaunchKernelGGL(k_reduce_mass, dim3(1), dim3(NT), 0, d->stream, d->dp, d->mass_part, nm, d->sc);
-    hipLaunchKernelGGL(k_heat_flux_state<S>, dim3(d->nbxB), dim3(NT), 0, d->stream, d->dp,
+    hipLaunchKernelGGL(k_heat_flux_state<S>, dim3(d->nbxB), dim3(64), 0, d->stream, d->dp,
                        static_cast<const S *>(d->f[d->cf]), static_cast<const S *>(d->T[d->cT]), d->hf_part,
                        (double *)nullptr);
     hipLaunchKernelGGL(k_flush_heat_flux, dim3(1), dim3(NT), 0, d->stream, d->dp, d->hf_part, d->nbxB, d->sc);
@@ -372,9 +372,10 @@ int read_impl(lbb_domain *d, double *rho, double *ux, double *uy, double *T, dou
     double *buf = nullptr;
     LBB_HIP(hipMalloc(&buf, 13 * nb));
     double *r = buf, *u = buf + N, *v = buf + 2 * N, *t = buf + 3 * N, *ff = buf + 4 * N;
-    hipLaunchKernelGGL(lbb::k_read<S>, dim3(d->nbxA * d->nbyA), dim3(lbb::NT), 0, d->stream, d->dp,
+    const int nbxR = (d->p.nx + lbb::TXR - 1) / lbb::TXR, nbyR = (d->p.ny + lbb::TYR - 1) / lbb::TYR;
+    hipLaunchKernelGGL(lbb::k_read<S>, dim3(nbxR * nbyR), dim3(lbb::NT), 0, d->stream, d->dp,
                        static_cast<const S *>(d->f[d->cf]), static_cast<const S *>(d->T[d->cT]), r, u, v, t, ff,
-                       d->sc, d->nbxA);
+                       d->sc, nbxR);
     int rc = LBB_OK;
     if (hipGetLastError() != hipSuccess) rc = fail(LBB_EDEVICE, "read-back kernel failed");
     const struct { double *dst, *src; size_t n; } cp[] = {{rho, r, N}, {ux, u, N}, {uy, v, N}, {T, t, N}, {f, ff, 9 * N}};
@@ -530,10 +531,13 @@ int lbb_init_domain(const lbb_params *pin, const double *T_bottom, const double 
     q.Gw_top = p.Gw_top;
     q.sig_e = p.sigma / (1.0 / p.s_e - 0.5);
     q.sig_z = p.sigma / (1.0 / p.s_zeta - 0.5);
+    q.inv_Tc = 1.0 / Tc;
+    q.two_over_G = 2.0 / p.G;
     d->nbxA = (p.nx + lbb::TXA - 1) / lbb::TXA;
     d->nbyA = (p.ny + lbb::TYA - 1) / lbb::TYA;
     d->nbxB = (p.nx + lbb::TXB - 1) / lbb::TXB;
-    d->nbyB = (p.ny + lbb::TYB - 1) / lbb::TYB;
+    const int tyB = p.precision == LBB_FP64 ? lbb::ThermalCfg<double>::TY : lbb::ThermalCfg<float>::TY;
+    d->nbyB = (p.ny + tyB - 1) / tyB;
 
     auto alloc = [&](void **ptr, size_t bytes) -> bool {
         if (hipMalloc(ptr, bytes) != hipSuccess) return false;
@@ -655,11 +659,11 @@ int lbb_wall_heat_flux(lbb_domain *d, double *q_now, double *q_mean, double *q_l
         double *ql = nullptr;
         LBB_HIP(hipMalloc(&ql, d->p.nx * sizeof(double)));
         if (d->p.precision == LBB_FP64)
-            hipLaunchKernelGGL(lbb::k_heat_flux_state<double>, dim3(d->nbxB), dim3(lbb::NT), 0, d->stream, d->dp,
+            hipLaunchKernelGGL(lbb::k_heat_flux_state<double>, dim3(d->nbxB), dim3(64), 0, d->stream, d->dp,
                                static_cast<const double *>(d->f[d->cf]), static_cast<const double *>(d->T[d->cT]),
                                (double *)nullptr, ql);
         else
-            hipLaunchKernelGGL(lbb::k_heat_flux_state<float>, dim3(d->nbxB), dim3(lbb::NT), 0, d->stream, d->dp,
+            hipLaunchKernelGGL(lbb::k_heat_flux_state<float>, dim3(d->nbxB), dim3(64), 0, d->stream, d->dp,
                                static_cast<const float *>(d->f[d->cf]), static_cast<const float *>(d->T[d->cT]),
                                (double *)nullptr, ql);
         hipError_t e = hipMemcpyAsync(q_local, ql, d->p.nx * sizeof(double), hipMemcpyDeviceToHost, d->stream);

@@ -80,13 +80,14 @@ def test_test_modes_fp64(mode):
     assert not bad, errs
 
 
-@pytest.mark.parametrize("precision,tol", [(L.FP64, TOL64), (L.FP32, TOL32)])
-def test_periodic_box(precision, tol):
-    _say("periodic", precision)
-    w = PLAIN.resized(80, 48)
+@pytest.mark.parametrize("precision,tol,nx,ny", [(L.FP64, TOL64, 80, 48), (L.FP32, TOL32, 80, 48),
+                                                (L.FP64, TOL64, 70, 37), (L.FP64, TOL64, 3, 3)])
+def test_periodic_box(precision, tol, nx, ny):
+    _say("periodic", precision, nx, ny)
+    w = PLAIN.resized(nx, ny)
     tc = O.Tc(w.a, w.b, w.R)
     rv, rl, _ = O.maxwell(w.a, w.b, w.R, w.omega, w.Ts_over_Tc * tc)
-    rho0 = WL.layered_density(w.nx, w.ny, rl, rv, 24, 0.05, seed=11)
+    rho0 = WL.layered_density(w.nx, w.ny, rl, rv, ny // 2, 0.05, seed=11)
     y, x = np.mgrid[0:w.ny, 0:w.nx]
     T0 = w.Ts_over_Tc * tc * (1 + 0.01 * np.sin(2 * np.pi * x / w.nx) * np.cos(2 * np.pi * y / w.ny))
     o, d, _ = make_pair(w, precision=precision, periodic_y=1, rho0=rho0, T0=T0)
