@@ -61,6 +61,57 @@ def cpu_baseline(w, steps):
                       f"({w.nx * w.ny * steps:.3g} lattice updates, {dt:.1f} s)"}
 
 
+def sweep_bench(steps, warmup=50):
+    """The 48-lattice boiling-curve sweep: aggregate MLUPS of one batch
+    (shared launches) against the same lattices run one after another through
+    the single-lattice path, each timed with HIP events on its stream."""
+    import torch
+    from paper_1501_03857_amd import lbboil as L
+    from paper_1501_03857_amd import workloads as WL
+
+    ws = WL.sweep_workloads(steps)
+    params, tbs, rhos = [], [], []
+    for w in ws:
+        Tc, _ = L.eos_constants(w.a, w.b, w.R, w.omega)
+        rv, rl = L.coexistence(w.a, w.b, w.R, w.omega, w.Ts_over_Tc * Tc)
+        params.append(L.Params(nx=w.nx, ny=w.ny, precision=L.FP32, liquid_rows=w.liquid_rows, a=w.a, b=w.b,
+                               R=w.R, omega=w.omega, Ts_over_Tc=w.Ts_over_Tc, sigma=w.sigma, g=w.g,
+                               Gw_bottom=w.Gw_bottom, rho_L=rl, rho_V=rv))
+        tbs.append(w.heater_T(Tc))
+        rhos.append(w.density(rl, rv))
+    cells = sum(w.nx * w.ny for w in ws)
+
+    def timed(obj, n):
+        st = torch.cuda.ExternalStream(obj.stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        obj.step_async(n)
+        e1.record(st)
+        obj.sync()
+        return e0.elapsed_time(e1)
+
+    b = L.Batch(params, tbs, rhos)
+    b.step(warmup)
+    ms_batch = timed(b, steps)
+    q_batch = b.heat_flux()["q_mean"]
+    b.close()
+    ms_plain = 0.0
+    for p, tb, rho in zip(params, tbs, rhos):
+        d = L.Domain(p, T_bottom=tb, rho0=rho)
+        d.step(warmup)
+        ms_plain += timed(d, steps)
+        d.close()
+    mb = cells * steps / (ms_batch * 1e-3) / 1e6
+    mp = cells * steps / (ms_plain * 1e-3) / 1e6
+    sizes = {}
+    for w in ws:
+        sizes[f"{w.nx}x{w.ny}"] = sizes.get(f"{w.nx}x{w.ny}", 0) + 1
+    return {"instances": len(ws), "cells": cells, "steps": steps, "sizes": sizes,
+            "batched_mlups": round(mb, 1), "plain_sequential_mlups": round(mp, 1),
+            "speedup": round(mb / mp, 2), "batched_ms": round(ms_batch, 3), "plain_ms": round(ms_plain, 3),
+            "q_mean_range": [float(min(q_batch)), float(max(q_batch))]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,6 +120,7 @@ def main():
     ap.add_argument("--workload", default="large", choices=["large", "large4096", "plain"])
     ap.add_argument("--kernel-steps", type=int, default=400, help="steps timed per launch for the roofline")
     ap.add_argument("--cpu-steps", type=int, default=100, help="oracle steps for the CPU baseline (0: skip)")
+    ap.add_argument("--sweep-steps", type=int, default=2000, help="steps of the 48-lattice sweep comparison (0: skip)")
     ap.add_argument("--profile", action="store_true", help="timed region only (for rocprofv3 runs)")
     ap.add_argument("--copy-probe", action="store_true", help="run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -134,6 +186,10 @@ def main():
             and MEASURED_TRAFFIC.get("workload") == w.name:
         traffic = MEASURED_TRAFFIC["bytes_per_launch"]
     step_bytes = ALG_BYTES_STEP[store] * cells
+    sweep = sweep_bench(args.sweep_steps) if args.sweep_steps > 0 else None
+    if sweep:
+        print(f"[bench] sweep: batched {sweep['batched_mlups']} MLUPS vs sequential {sweep['plain_sequential_mlups']} "
+              f"MLUPS ({sweep['speedup']}x)", file=sys.stderr, flush=True)
     cpu = cpu_baseline(w, args.cpu_steps) if args.cpu_steps > 0 else None
 
     line = {
@@ -160,6 +216,7 @@ def main():
                           "alg_bytes_per_update": ALG_BYTES_STEP[store]},
         "kernels_ms": {"k_lb": round(ms_lb, 6), "k_thermal": round(ms_th, 6), "step_single_launch": round(ms_seq, 6)},
         "heat_flux_mean": hf["q_mean"],
+        "batched_sweep": sweep,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

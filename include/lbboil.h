@@ -166,6 +166,36 @@ int lbb_set_wettability(lbb_domain *d, double Gw_bottom);
 int lbb_save_state(lbb_domain *d, void *buf, size_t *len);
 int lbb_load_state(lbb_domain *d, const void *buf, size_t len);
 
+/* ---- Batched lattices (boiling-curve sweeps) ---------------------------
+ * n independent lattices of any sizes and parameters (superheat, wettability,
+ * seed) advanced together: each step is one LB launch and one thermal launch
+ * covering every lattice, replayed from captured HIP graphs.  Each lattice
+ * evolves bitwise as it would alone.  All members share precision and
+ * thermal_mode.
+ *   ps [n]        : parameters of each lattice (validated as lbb_init_domain).
+ *   T_bottoms [n] : per-lattice bottom-wall temperature arrays [nx_i], or NULL
+ *                   (the array itself or an entry: T_s).
+ *   rho0s [n]     : per-lattice initial densities [ny_i*nx_i], or NULL
+ *                   (built-in layered state).
+ * EINVAL on an empty batch, mixed precision or modes, or any invalid member. */
+typedef struct lbb_batch lbb_batch;
+int lbb_batch_init(const lbb_params *ps, int n, const double *const *T_bottoms, const double *const *rho0s,
+                   lbb_batch **out);
+int lbb_batch_step(lbb_batch *b, int64_t n);
+int lbb_batch_step_async(lbb_batch *b, int64_t n);
+int lbb_batch_sync(lbb_batch *b);
+void *lbb_batch_stream(lbb_batch *b);
+/* Per-lattice heat flux [n] each (any pointer may be NULL), as
+ * lbb_wall_heat_flux. */
+int lbb_batch_heat_flux(lbb_batch *b, double *q_now, double *q_mean, int64_t *n_samples);
+/* Borrowed handle of member i for the single-lattice calls (read_fields,
+ * heat flux, save/load, set_heater ...); owned by the batch, NULL if out of
+ * range.  Stepping a member alone puts it out of phase with the batch, which
+ * then refuses to step (EINVAL). */
+lbb_domain *lbb_batch_domain(lbb_batch *b, int i);
+int lbb_batch_size(lbb_batch *b);
+int lbb_batch_destroy(lbb_batch *b);
+
 /* Current step count, grid shape and device bytes held by the domain. */
 int lbb_info(lbb_domain *d, int64_t *t, int32_t *nx, int32_t *ny, int64_t *device_bytes);
 

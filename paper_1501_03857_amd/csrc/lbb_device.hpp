@@ -99,6 +99,19 @@ struct Scalars {
     unsigned int pad;
 };
 
+// One lattice of a launch: its parameters, buffers and place in the grid.
+// The LB and thermal launches cover any number of lattices of any sizes; a
+// block finds its lattice through a block -> lattice table.
+struct Inst {
+    DevParams P;
+    void *f[2], *T[2];
+    void *rho, *vx, *vy;
+    double *mass_part, *hf_part;
+    Scalars *sc;
+    int nbxA, nbyA, nbxB, nbyB;
+    int blkA0, blkB0;  // first block of this lattice in the LB / thermal grids
+};
+
 __device__ __forceinline__ int wrapi(int i, int n)
 {
     int r = i % n;
@@ -341,26 +354,34 @@ __device__ __forceinline__ void tile_psi(const DevParams &P, const S *__restrict
 // forms rho and psi (FP64 EOS) on the tile and halo, keeping each node's
 // populations in registers; phase 2 collides the interior nodes and pushes.
 template <typename S>
-__global__ __launch_bounds__(64 * NWA) void k_lb(DevParams P, const S *__restrict__ fin, S *__restrict__ fout,
-                                                 const S *__restrict__ Tin, S *__restrict__ rho_o,
-                                                 S *__restrict__ vx_o, S *__restrict__ vy_o,
-                                                 double *__restrict__ mass_part, const double *__restrict__ hf_part,
-                                                 int n_hf, Scalars *__restrict__ sc, int nbx, int nby)
+__global__ __launch_bounds__(64 * NWA) void k_lb(const Inst *__restrict__ insts, const int *__restrict__ blk2inst,
+                                                 int cf, int cT)
 {
+    const Inst &I = insts[blk2inst[blockIdx.x]];
+    const DevParams P = I.P;
+    const bool frozen = P.mode == MODE_THERMAL_ONLY;
+    const S *__restrict__ fin = static_cast<const S *>(I.f[cf]);
+    S *__restrict__ fout = static_cast<S *>(I.f[cf ^ 1]);
+    const S *__restrict__ Tin = static_cast<const S *>(I.T[cT]);
+    S *__restrict__ rho_o = static_cast<S *>(I.rho);
+    S *__restrict__ vx_o = static_cast<S *>(I.vx);
+    S *__restrict__ vy_o = static_cast<S *>(I.vy);
+    Scalars *__restrict__ sc = I.sc;
+    const int nbx = I.nbxA, nby = I.nbyA;
+    const int blk = (int)blockIdx.x - I.blkA0;
     constexpr int H = TYA + 2;                   // region rows (halo rows 0 and H-1)
     __shared__ double psi_s[H * 64];
     __shared__ double red[NWA];
     const long long t = sc->tA;
-    if ((int)blockIdx.x == nbx * nby) {
-        reduce_heat_flux(hf_part, n_hf, P.nx, sc, t);
+    if (blk == nbx * nby) {
+        reduce_heat_flux(I.hf_part, I.nbxB, P.nx, sc, t);
         if (threadIdx.x == 0) sc->tB = t;  // the thermal launch of this step
         return;
     }
-    const int bx = blockIdx.x % nbx, by = blockIdx.x / nbx;
+    const int bx = blk % nbx, by = blk / nbx;
     const int x0 = bx * TXA, y0 = by * TYA;
     const size_t N = (size_t)P.nx * P.ny;
     const bool walls = !P.periodic_y;
-    const bool frozen = P.mode == MODE_THERMAL_ONLY;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int gx = wrapi(x0 + lane - 1, P.nx);
 
@@ -498,7 +519,7 @@ __global__ __launch_bounds__(64 * NWA) void k_lb(DevParams P, const S *__restric
         mass += mm;
     }
     const double bm = block_sum<64 * NWA>(mass, red);
-    if (threadIdx.x == 0) mass_part[blockIdx.x] = bm;
+    if (threadIdx.x == 0) I.mass_part[blk] = bm;
 }
 
 // ---------------------------------------------------------------------------
@@ -514,13 +535,20 @@ __global__ __launch_bounds__(64 * NWA) void k_lb(DevParams P, const S *__restric
 // stage values updated in place between barriers and the RK4 sums in
 // registers.
 template <typename S>
-__global__ __launch_bounds__(64 * NWB) void k_thermal(DevParams P, const S *__restrict__ Tin, S *__restrict__ Tout,
-                                                      const S *__restrict__ rho_i, const S *__restrict__ vx_i,
-                                                      const S *__restrict__ vy_i, const S *__restrict__ fnew,
-                                                      double *__restrict__ hf_part,
-                                                      const double *__restrict__ mass_part, int n_mass,
-                                                      Scalars *__restrict__ sc, int nbx, int nby)
+__global__ __launch_bounds__(64 * NWB) void k_thermal(const Inst *__restrict__ insts,
+                                                      const int *__restrict__ blk2inst, int cf, int cT)
 {
+    const Inst &I = insts[blk2inst[blockIdx.x]];
+    const DevParams P = I.P;
+    const S *__restrict__ Tin = static_cast<const S *>(I.T[cT]);
+    S *__restrict__ Tout = static_cast<S *>(I.T[cT ^ 1]);
+    const S *__restrict__ rho_i = static_cast<const S *>(I.rho);
+    const S *__restrict__ vx_i = static_cast<const S *>(I.vx);
+    const S *__restrict__ vy_i = static_cast<const S *>(I.vy);
+    const S *__restrict__ fnew = static_cast<const S *>(I.f[P.mode == MODE_THERMAL_ONLY ? cf : cf ^ 1]);
+    Scalars *__restrict__ sc = I.sc;
+    const int nbx = I.nbxB, nby = I.nbyB;
+    const int blk = (int)blockIdx.x - I.blkB0;
     using C = typename ThermalCfg<S>::C;
     constexpr int TY = ThermalCfg<S>::TY;
     constexpr int H = TY + 2 * HB;               // region rows
@@ -530,15 +558,15 @@ __global__ __launch_bounds__(64 * NWB) void k_thermal(DevParams P, const S *__re
     __shared__ C Ts[H][64];     // stage values T0 + c h; new T for the heat flux
     __shared__ double red[NWB];
     const long long t = sc->tB;
-    if ((int)blockIdx.x == nbx * nby) {
-        const double m = block_sum_array<64 * NWB>(mass_part, n_mass, red);
+    if (blk == nbx * nby) {
+        const double m = block_sum_array<64 * NWB>(I.mass_part, I.nbxA * I.nbyA, red);
         if (threadIdx.x == 0) {
             sc->rho_ave = m / ((double)P.nx * (double)P.ny);
             sc->tA = t + 1;
         }
         return;
     }
-    const int bx = blockIdx.x % nbx, by = blockIdx.x / nbx;
+    const int bx = blk % nbx, by = blk / nbx;
     const int x0 = bx * TXB, y0 = by * TY;
     const bool walls = !P.periodic_y;
     const bool run = P.mode != MODE_ISOTHERMAL;
@@ -698,7 +726,7 @@ __global__ __launch_bounds__(64 * NWB) void k_thermal(DevParams P, const S *__re
         }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) qw += __shfl_xor(qw, off, 64);
-        if (lane == 0) hf_part[bx] = qw;
+        if (lane == 0) I.hf_part[bx] = qw;
     }
 }
 
@@ -785,9 +813,11 @@ __global__ void k_heat_flux_state(DevParams P, const S *__restrict__ f, const S 
     if (lane == 0 && hf_part) hf_part[blockIdx.x] = qw;
 }
 
-__global__ void k_flush_heat_flux(DevParams P, const double *__restrict__ hf_part, int n_hf, Scalars *sc)
+// Heat-flux bookkeeping of the state after the last step, one block per lattice.
+__global__ void k_flush_heat_flux(const Inst *__restrict__ insts)
 {
-    reduce_heat_flux(hf_part, n_hf, P.nx, sc, sc->tA);
+    const Inst &I = insts[blockIdx.x];
+    reduce_heat_flux(I.hf_part, I.nbxB, I.P.nx, I.sc, I.sc->tA);
 }
 
 // Read-back: rho, v of Eq. (6) with the force of the current state, T, and

@@ -150,6 +150,8 @@ struct lbb_domain {
     lbb::Scalars *sc = nullptr;
     int nbxA = 0, nbyA = 0, nbxB = 0, nbyB = 0;
     int cf = 0, cT = 0;
+    lbb::Inst *d_inst = nullptr;         // this lattice as a one-entry launch table
+    int *d_blkA = nullptr, *d_blkB = nullptr;
     bool poisoned = false;
     hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     std::vector<double> Tb;
@@ -191,29 +193,60 @@ uint64_t param_hash(const lbb_params &p)
     return fnv1a(&q, sizeof q);
 }
 
+lbb::Inst make_inst(const lbb_domain *d)
+{
+    lbb::Inst I{};
+    I.P = d->dp;
+    I.f[0] = d->f[0];
+    I.f[1] = d->f[1];
+    I.T[0] = d->T[0];
+    I.T[1] = d->T[1];
+    I.rho = d->rho;
+    I.vx = d->vx;
+    I.vy = d->vy;
+    I.mass_part = d->mass_part;
+    I.hf_part = d->hf_part;
+    I.sc = d->sc;
+    I.nbxA = d->nbxA;
+    I.nbyA = d->nbyA;
+    I.nbxB = d->nbxB;
+    I.nbyB = d->nbyB;
+    I.blkA0 = 0;
+    I.blkB0 = 0;
+    return I;
+}
+
+// Upload the one-entry launch table (after any parameter change).
+int push_inst(lbb_domain *d)
+{
+    const lbb::Inst I = make_inst(d);
+    LBB_HIP(hipMemcpyAsync(d->d_inst, &I, sizeof I, hipMemcpyHostToDevice, d->stream));
+    LBB_HIP(hipStreamSynchronize(d->stream));
+    return LBB_OK;
+}
+
+template <typename S>
+void launch_lb(hipStream_t st, const lbb::Inst *insts, const int *blk, int nblocks, int cf, int cT)
+{
+    hipLaunchKernelGGL(lbb::k_lb<S>, dim3(nblocks), dim3(64 * lbb::NWA), 0, st, insts, blk, cf, cT);
+}
+
+template <typename S>
+void launch_thermal(hipStream_t st, const lbb::Inst *insts, const int *blk, int nblocks, int cf, int cT)
+{
+    hipLaunchKernelGGL(lbb::k_thermal<S>, dim3(nblocks), dim3(64 * lbb::NWB), 0, st, insts, blk, cf, cT);
+}
+
 template <typename S>
 void launch_lb(lbb_domain *d)
 {
-    using namespace lbb;
-    const int nA = d->nbxA * d->nbyA;
-    S *f0 = static_cast<S *>(d->f[d->cf]), *f1 = static_cast<S *>(d->f[d->cf ^ 1]);
-    S *T0 = static_cast<S *>(d->T[d->cT]);
-    hipLaunchKernelGGL(k_lb<S>, dim3(nA + 1), dim3(64 * NWA), 0, d->stream, d->dp, f0, f1, T0, static_cast<S *>(d->rho),
-                       static_cast<S *>(d->vx), static_cast<S *>(d->vy), d->mass_part, d->hf_part, d->nbxB, d->sc,
-                       d->nbxA, d->nbyA);
+    launch_lb<S>(d->stream, d->d_inst, d->d_blkA, d->nbxA * d->nbyA + 1, d->cf, d->cT);
 }
 
 template <typename S>
 void launch_thermal(lbb_domain *d)
 {
-    using namespace lbb;
-    const int nA = d->nbxA * d->nbyA, nB = d->nbxB * d->nbyB;
-    const bool frozen = d->dp.mode == MODE_THERMAL_ONLY;
-    S *fnew = static_cast<S *>(d->f[frozen ? d->cf : d->cf ^ 1]);
-    S *T0 = static_cast<S *>(d->T[d->cT]), *T1 = static_cast<S *>(d->T[d->cT ^ 1]);
-    hipLaunchKernelGGL(k_thermal<S>, dim3(nB + 1), dim3(64 * NWB), 0, d->stream, d->dp, T0, T1, static_cast<S *>(d->rho),
-                       static_cast<S *>(d->vx), static_cast<S *>(d->vy), fnew, d->hf_part, d->mass_part, nA, d->sc,
-                       d->nbxB, d->nbyB);
+    launch_thermal<S>(d->stream, d->d_inst, d->d_blkB, d->nbxB * d->nbyB + 1, d->cf, d->cT);
 }
 
 void advance_buffers(lbb_domain *d)
@@ -274,7 +307,7 @@ int enqueue_steps(lbb_domain *d, int64_t n)
         n -= kGraphSteps;
     }
     for (int64_t k = 0; k < n; ++k) enqueue_step_any(d);
-    hipLaunchKernelGGL(lbb::k_flush_heat_flux, dim3(1), dim3(lbb::NT), 0, d->stream, d->dp, d->hf_part, d->nbxB, d->sc);
+    hipLaunchKernelGGL(lbb::k_flush_heat_flux, dim3(1), dim3(lbb::NT), 0, d->stream, d->d_inst);
     LBB_HIP(hipGetLastError());
     return LBB_OK;
 }
@@ -306,7 +339,7 @@ int refresh_reductions(lbb_domain *d)
     hipLaunchKernelGGL(k_heat_flux_state<S>, dim3(d->nbxB), dim3(64), 0, d->stream, d->dp,
                        static_cast<const S *>(d->f[d->cf]), static_cast<const S *>(d->T[d->cT]), d->hf_part,
                        (double *)nullptr);
-    hipLaunchKernelGGL(k_flush_heat_flux, dim3(1), dim3(NT), 0, d->stream, d->dp, d->hf_part, d->nbxB, d->sc);
+    hipLaunchKernelGGL(k_flush_heat_flux, dim3(1), dim3(NT), 0, d->stream, d->d_inst);
     LBB_HIP(hipGetLastError());
     return LBB_OK;
 }
@@ -359,7 +392,8 @@ void release(lbb_domain *d)
     drop_graphs(d);
     for (void *q : {d->f[0], d->f[1], d->T[0], d->T[1], d->rho, d->vx, d->vy})
         if (q) (void)hipFree(q);
-    for (void *q : {(void *)d->mass_part, (void *)d->hf_part, (void *)d->Tb_dev, (void *)d->sc})
+    for (void *q : {(void *)d->mass_part, (void *)d->hf_part, (void *)d->Tb_dev, (void *)d->sc,
+                    (void *)d->d_inst, (void *)d->d_blkA, (void *)d->d_blkB})
         if (q) (void)hipFree(q);
     if (d->stream) (void)hipStreamDestroy(d->stream);
     delete d;
@@ -553,14 +587,18 @@ int lbb_init_domain(const lbb_params *pin, const double *T_bottom, const double 
     ok = ok && alloc((void **)&d->hf_part, (size_t)d->nbxB * sizeof(double));
     ok = ok && alloc((void **)&d->Tb_dev, (size_t)p.nx * sizeof(double));
     ok = ok && alloc((void **)&d->sc, sizeof(lbb::Scalars));
+    ok = ok && alloc((void **)&d->d_inst, sizeof(lbb::Inst));
+    ok = ok && alloc((void **)&d->d_blkA, (size_t)(d->nbxA * d->nbyA + 1) * sizeof(int));
+    ok = ok && alloc((void **)&d->d_blkB, (size_t)(d->nbxB * d->nbyB + 1) * sizeof(int));
     if (!ok) {
         (void)hipGetLastError();
         release(d);
         return fail(LBB_ENOMEM, "device allocation failed");
     }
-    if (hipMemcpy(d->Tb_dev, Tb.data(), p.nx * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+    if (hipMemcpy(d->Tb_dev, Tb.data(), p.nx * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        push_inst(d) != LBB_OK) {
         release(d);
-        return fail(LBB_EDEVICE, "upload of T_bottom failed");
+        return fail(LBB_EDEVICE, "upload of T_bottom or the launch table failed");
     }
     rc = p.precision == LBB_FP64 ? set_state<double>(d, rho0, nullptr, nullptr, nullptr)
                                  : set_state<float>(d, rho0, nullptr, nullptr, nullptr);
@@ -625,7 +663,7 @@ int lbb_time_kernels(lbb_domain *d, int64_t n, double *ms_lb, double *ms_thermal
         LBB_HIP(hipEventRecord(ev[3 * k + 3], d->stream));
         advance_buffers(d);
     }
-    hipLaunchKernelGGL(lbb::k_flush_heat_flux, dim3(1), dim3(lbb::NT), 0, d->stream, d->dp, d->hf_part, d->nbxB, d->sc);
+    hipLaunchKernelGGL(lbb::k_flush_heat_flux, dim3(1), dim3(lbb::NT), 0, d->stream, d->d_inst);
     LBB_HIP(hipGetLastError());
     LBB_HIP(hipStreamSynchronize(d->stream));
     double a = 0, b = 0;
@@ -720,8 +758,7 @@ int lbb_set_wettability(lbb_domain *d, double Gw_bottom)
     if (!std::isfinite(Gw_bottom)) return fail(LBB_EINVAL, "G_w must be finite");
     d->p.Gw_bottom = Gw_bottom;
     d->dp.Gw_bottom = Gw_bottom;
-    drop_graphs(d);  // the captured launches carry the old parameters
-    return LBB_OK;
+    return push_inst(d);  // captured graphs read the table, so they stay valid
 }
 
 int lbb_save_state(lbb_domain *d, void *buf, size_t *len)
@@ -813,7 +850,8 @@ int lbb_load_state(lbb_domain *d, const void *buf, size_t len)
     d->cf = d->cT = 0;
     if (Gw != d->dp.Gw_bottom) {
         d->p.Gw_bottom = d->dp.Gw_bottom = Gw;
-        drop_graphs(d);
+        int rc = push_inst(d);
+        if (rc) return rc;
     }
     d->poisoned = false;
     return LBB_OK;
@@ -831,6 +869,208 @@ int lbb_info(lbb_domain *d, int64_t *t, int32_t *nx, int32_t *ny, int64_t *devic
     if (nx) *nx = d->p.nx;
     if (ny) *ny = d->p.ny;
     if (device_bytes) *device_bytes = d->dev_bytes;
+    return LBB_OK;
+}
+
+// ---- batched lattices --------------------------------------------------
+
+struct lbb_batch {
+    std::vector<lbb_domain *> doms;
+    hipStream_t stream = nullptr;
+    lbb::Inst *d_insts = nullptr;
+    int *d_blkA = nullptr, *d_blkB = nullptr;
+    int totA = 0, totB = 0;
+    int cf = 0, cT = 0;
+    int precision = 0, mode = 0;
+    hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+};
+
+static void batch_release(lbb_batch *b)
+{
+    if (!b) return;
+    for (auto &row : b->graph)
+        for (auto &g : row)
+            if (g) (void)hipGraphExecDestroy(g);
+    for (void *q : {(void *)b->d_insts, (void *)b->d_blkA, (void *)b->d_blkB})
+        if (q) (void)hipFree(q);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    for (lbb_domain *d : b->doms) release(d);
+    delete b;
+}
+
+// Upload the launch table (all members, with their block offsets).
+static int batch_push(lbb_batch *b)
+{
+    std::vector<lbb::Inst> insts;
+    int a0 = 0, b0 = 0;
+    for (lbb_domain *d : b->doms) {
+        lbb::Inst I = make_inst(d);
+        I.blkA0 = a0;
+        I.blkB0 = b0;
+        a0 += d->nbxA * d->nbyA + 1;
+        b0 += d->nbxB * d->nbyB + 1;
+        insts.push_back(I);
+    }
+    LBB_HIP(hipMemcpyAsync(b->d_insts, insts.data(), insts.size() * sizeof(lbb::Inst), hipMemcpyHostToDevice,
+                           b->stream));
+    LBB_HIP(hipStreamSynchronize(b->stream));
+    return LBB_OK;
+}
+
+static void batch_enqueue_step(lbb_batch *b)
+{
+    if (b->precision == LBB_FP64) {
+        launch_lb<double>(b->stream, b->d_insts, b->d_blkA, b->totA, b->cf, b->cT);
+        launch_thermal<double>(b->stream, b->d_insts, b->d_blkB, b->totB, b->cf, b->cT);
+    } else {
+        launch_lb<float>(b->stream, b->d_insts, b->d_blkA, b->totA, b->cf, b->cT);
+        launch_thermal<float>(b->stream, b->d_insts, b->d_blkB, b->totB, b->cf, b->cT);
+    }
+    if (b->mode != LBB_THERMAL_ONLY) b->cf ^= 1;
+    if (b->mode != LBB_ISOTHERMAL) b->cT ^= 1;
+}
+
+extern "C" int lbb_batch_init(const lbb_params *ps, int n, const double *const *T_bottoms,
+                              const double *const *rho0s, lbb_batch **out)
+{
+    if (!out) return fail(LBB_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!ps || n < 1) return fail(LBB_EINVAL, "a batch needs n >= 1 parameter sets");
+    for (int i = 1; i < n; ++i)
+        if (ps[i].precision != ps[0].precision || ps[i].thermal_mode != ps[0].thermal_mode)
+            return fail(LBB_EINVAL, "batch members must share precision and thermal_mode");
+    lbb_batch *b = new (std::nothrow) lbb_batch();
+    if (!b) return fail(LBB_ENOMEM, "host allocation failed");
+    b->precision = ps[0].precision;
+    b->mode = ps[0].thermal_mode;
+    for (int i = 0; i < n; ++i) {
+        lbb_domain *d = nullptr;
+        int rc = lbb_init_domain(&ps[i], T_bottoms ? T_bottoms[i] : nullptr, rho0s ? rho0s[i] : nullptr, &d);
+        if (rc) {
+            std::string m = "batch member " + std::to_string(i) + ": " + g_err;
+            batch_release(b);
+            return fail(rc, m);
+        }
+        b->doms.push_back(d);
+        b->totA += d->nbxA * d->nbyA + 1;
+        b->totB += d->nbxB * d->nbyB + 1;
+    }
+    std::vector<int> ta, tb;
+    for (int i = 0; i < n; ++i) {
+        ta.insert(ta.end(), b->doms[i]->nbxA * b->doms[i]->nbyA + 1, i);
+        tb.insert(tb.end(), b->doms[i]->nbxB * b->doms[i]->nbyB + 1, i);
+    }
+    bool ok = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) == hipSuccess &&
+              hipMalloc(&b->d_insts, n * sizeof(lbb::Inst)) == hipSuccess &&
+              hipMalloc(&b->d_blkA, ta.size() * sizeof(int)) == hipSuccess &&
+              hipMalloc(&b->d_blkB, tb.size() * sizeof(int)) == hipSuccess &&
+              hipMemcpy(b->d_blkA, ta.data(), ta.size() * sizeof(int), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(b->d_blkB, tb.data(), tb.size() * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+    if (!ok || batch_push(b) != LBB_OK) {
+        (void)hipGetLastError();
+        batch_release(b);
+        return fail(LBB_ENOMEM, "batch launch tables could not be allocated");
+    }
+    *out = b;
+    return LBB_OK;
+}
+
+// The batch steps its members together; they must share the buffer phase.
+static int batch_phase(lbb_batch *b)
+{
+    b->cf = b->doms[0]->cf;
+    b->cT = b->doms[0]->cT;
+    for (lbb_domain *d : b->doms) {
+        if (d->cf != b->cf || d->cT != b->cT)
+            return fail(LBB_EINVAL, "batch members were stepped individually and are out of phase");
+        if (d->poisoned) return fail(LBB_ESTATE, "a batch member is poisoned by an earlier invalid state");
+    }
+    return LBB_OK;
+}
+
+extern "C" int lbb_batch_step_async(lbb_batch *b, int64_t n)
+{
+    if (!b) return fail(LBB_EINVAL, "batch is NULL");
+    if (n < 0) return fail(LBB_EINVAL, "n must be >= 0");
+    int rc = batch_phase(b);
+    if (rc) return rc;
+    rc = batch_push(b);  // members' parameters may have changed through their handles
+    if (rc) return rc;
+    while (n >= kGraphSteps) {
+        hipGraphExec_t &g = b->graph[b->cf][b->cT];
+        if (!g) {
+            const int cf = b->cf, cT = b->cT;
+            LBB_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+            for (int k = 0; k < kGraphSteps; ++k) batch_enqueue_step(b);
+            hipGraph_t gr = nullptr;
+            LBB_HIP(hipStreamEndCapture(b->stream, &gr));
+            b->cf = cf;
+            b->cT = cT;
+            hipError_t e = hipGraphInstantiate(&g, gr, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(gr);
+            if (e != hipSuccess) return fail(LBB_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        }
+        LBB_HIP(hipGraphLaunch(g, b->stream));
+        n -= kGraphSteps;
+    }
+    for (int64_t k = 0; k < n; ++k) batch_enqueue_step(b);
+    hipLaunchKernelGGL(lbb::k_flush_heat_flux, dim3((unsigned)b->doms.size()), dim3(lbb::NT), 0, b->stream, b->d_insts);
+    LBB_HIP(hipGetLastError());
+    for (lbb_domain *d : b->doms) {
+        d->cf = b->cf;
+        d->cT = b->cT;
+    }
+    return LBB_OK;
+}
+
+extern "C" int lbb_batch_sync(lbb_batch *b)
+{
+    if (!b) return fail(LBB_EINVAL, "batch is NULL");
+    LBB_HIP(hipStreamSynchronize(b->stream));
+    for (size_t i = 0; i < b->doms.size(); ++i) {
+        int rc = check_errors(b->doms[i]);
+        if (rc) return fail(rc, "batch member " + std::to_string(i) + ": " + g_err);
+    }
+    return LBB_OK;
+}
+
+extern "C" int lbb_batch_step(lbb_batch *b, int64_t n)
+{
+    int rc = lbb_batch_step_async(b, n);
+    if (rc) return rc;
+    return lbb_batch_sync(b);
+}
+
+extern "C" void *lbb_batch_stream(lbb_batch *b) { return b ? (void *)b->stream : nullptr; }
+
+extern "C" int lbb_batch_heat_flux(lbb_batch *b, double *q_now, double *q_mean, int64_t *n_samples)
+{
+    if (!b) return fail(LBB_EINVAL, "batch is NULL");
+    for (size_t i = 0; i < b->doms.size(); ++i) {
+        double qn = 0, qm = 0;
+        int64_t ns = 0;
+        int rc = lbb_wall_heat_flux(b->doms[i], &qn, &qm, nullptr, &ns);
+        if (rc) return rc;
+        if (q_now) q_now[i] = qn;
+        if (q_mean) q_mean[i] = qm;
+        if (n_samples) n_samples[i] = ns;
+    }
+    return LBB_OK;
+}
+
+extern "C" lbb_domain *lbb_batch_domain(lbb_batch *b, int i)
+{
+    if (!b || i < 0 || i >= (int)b->doms.size()) return nullptr;
+    return b->doms[i];
+}
+
+extern "C" int lbb_batch_size(lbb_batch *b) { return b ? (int)b->doms.size() : 0; }
+
+extern "C" int lbb_batch_destroy(lbb_batch *b)
+{
+    if (!b) return fail(LBB_EINVAL, "batch is NULL");
+    (void)hipStreamSynchronize(b->stream);
+    batch_release(b);
     return LBB_OK;
 }
 

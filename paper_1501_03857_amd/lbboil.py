@@ -78,6 +78,15 @@ def lib():
             "lbb_load_state": (C.c_int, [vp, vp, C.c_size_t]),
             "lbb_info": (C.c_int, [vp, C.POINTER(_i64), C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i64)]),
             "lbb_destroy": (C.c_int, [vp]),
+            "lbb_batch_init": (C.c_int, [_P, C.c_int, C.POINTER(_pd), C.POINTER(_pd), C.POINTER(vp)]),
+            "lbb_batch_step": (C.c_int, [vp, _i64]),
+            "lbb_batch_step_async": (C.c_int, [vp, _i64]),
+            "lbb_batch_sync": (C.c_int, [vp]),
+            "lbb_batch_stream": (vp, [vp]),
+            "lbb_batch_heat_flux": (C.c_int, [vp, _pd, _pd, C.POINTER(_i64)]),
+            "lbb_batch_domain": (vp, [vp, C.c_int]),
+            "lbb_batch_size": (C.c_int, [vp]),
+            "lbb_batch_destroy": (C.c_int, [vp]),
             "lbb_last_error": (C.c_char_p, []),
         }
         for name, (res, args) in sig.items():
@@ -162,6 +171,15 @@ def coexistence(a, b, R, omega, T):
 class Domain:
     """One lattice on the current GPU (lbb_init_domain ... lbb_destroy)."""
 
+    @classmethod
+    def borrowed(cls, handle, p: Params):
+        """A view of a lattice owned elsewhere (a batch member); never destroyed here."""
+        d = cls.__new__(cls)
+        d.p = p
+        d._h = C.c_void_p(handle)
+        d._owner = False
+        return d
+
     def __init__(self, p: Params, T_bottom=None, rho0=None):
         self.p = p
         self._cp = p.c()
@@ -173,12 +191,13 @@ class Domain:
         h = C.c_void_p()
         _check(lib().lbb_init_domain(C.byref(self._cp), _ptr(T_bottom), _ptr(rho0), C.byref(h)))
         self._h = h
+        self._owner = True
 
     def close(self):
         h = getattr(self, "_h", None)
-        if h:
+        if h and getattr(self, "_owner", False):
             lib().lbb_destroy(h)
-            self._h = None
+        self._h = None
 
     def __del__(self):
         try:
@@ -266,3 +285,75 @@ class Domain:
     @property
     def t(self) -> int:
         return self.info()["t"]
+
+
+class Batch:
+    """Many lattices advanced together by shared launches (lbb_batch_*)."""
+
+    def __init__(self, params, T_bottoms=None, rho0s=None):
+        n = len(params)
+        self.params = list(params)
+        self._cps = (CParams * n)(*[p.c() for p in params])
+        keep = []
+
+        def arr(xs, shape_of):
+            if xs is None:
+                return None
+            out = (_pd * n)()
+            for i, x in enumerate(xs):
+                if x is None:
+                    out[i] = None
+                    continue
+                a = np.ascontiguousarray(x, dtype=np.float64)
+                assert a.shape == shape_of(params[i])
+                keep.append(a)
+                out[i] = _ptr(a)
+            return out
+
+        tb = arr(T_bottoms, lambda p: (p.nx,))
+        r0 = arr(rho0s, lambda p: (p.ny, p.nx))
+        h = C.c_void_p()
+        _check(lib().lbb_batch_init(self._cps, n, tb, r0, C.byref(h)))
+        self._h = h
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().lbb_batch_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __len__(self):
+        return lib().lbb_batch_size(self._h)
+
+    def step(self, n: int = 1):
+        _check(lib().lbb_batch_step(self._h, int(n)))
+        return self
+
+    def step_async(self, n: int):
+        _check(lib().lbb_batch_step_async(self._h, int(n)))
+
+    def sync(self):
+        _check(lib().lbb_batch_sync(self._h))
+
+    @property
+    def stream(self) -> int:
+        return lib().lbb_batch_stream(self._h)
+
+    def heat_flux(self):
+        n = len(self)
+        qn, qm = np.zeros(n), np.zeros(n)
+        ns = (_i64 * n)()
+        _check(lib().lbb_batch_heat_flux(self._h, _ptr(qn), _ptr(qm), ns))
+        return dict(q_now=qn, q_mean=qm, n_samples=np.array(ns[:]))
+
+    def domain(self, i: int) -> Domain:
+        h = lib().lbb_batch_domain(self._h, int(i))
+        if not h:
+            raise IndexError(i)
+        return Domain.borrowed(h, self.params[i])

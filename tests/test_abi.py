@@ -93,3 +93,11 @@ def test_coexistence_rejects_supercritical():
     tc, _ = L.eos_constants(a, b, 1.0, 0.344)
     with pytest.raises(L.LbbError):
         L.coexistence(a, b, 1.0, 0.344, 1.01 * tc)
+
+
+def test_batch_rejects_mixed_precision_and_empty():
+    with pytest.raises(L.LbbError) as e:
+        L.Batch([L.Params(precision=L.FP64), L.Params(precision=L.FP32)])
+    assert e.value.code == L.LBB_EINVAL
+    with pytest.raises(L.LbbError):
+        L.Batch([])
