@@ -50,7 +50,7 @@
  *  - q_w uses the second-order one-sided difference at the wall and lambda
  *    of the wall node; it is sampled on the state after each step.
  */
-#include "lbb_oracle.h"
+#include "lbb_oracle_internal.h"
 
 #include <math.h>
 #include <stdio.h>
@@ -433,21 +433,6 @@ void orc_thermal_rhs(const orc_params *p, const double *rho, const double *vx, c
 /* ---------------------------------------------------------------------- */
 /* Whole-domain state                                                      */
 /* ---------------------------------------------------------------------- */
-
-struct orc_state {
-    orc_params p;
-    double Tc, kappa, Ts;
-    int64_t t;
-    double *f, *fpost;           /* [9][ny][nx] */
-    double *T;                   /* [ny][nx]    */
-    double *Tb;                  /* [nx] bottom-wall temperature */
-    /* work arrays of one step */
-    double *rho, *psi, *Fx, *Fy, *Q, *vx, *vy, *vTx, *vTy;
-    double *Tst, *h, *acc;
-    double *ws[7];               /* stencil scratch of the RK4 stages */
-    double q_now, q_sum;
-    int64_t n_samples;
-};
 
 #define F_AT(s, a, c) ((s)->f[(size_t)(a) * (size_t)(s)->p.nx * (s)->p.ny + (c)])
 

@@ -100,6 +100,15 @@ void orc_set_wettability(orc_state *s, double Gw_bottom);
 const char *orc_last_error(void);
 int orc_num_threads(void);
 void orc_constants(const orc_state *s, double *Tc, double *kappa, double *Ts);
+/* ---- discrete adjoint (lbb_oracle_adjoint.c) ------------------------- */
+/* J = (1/N) sum_{n=1..N} q^n over N steps from the current state (left
+ * unchanged) and dJ/dT_b [nx], dJ/dG_w,bottom; checkpoints every K steps. */
+int orc_adjoint(const orc_state *s, int64_t N, int64_t K, double *J, double *dJ_dTb, double *dJ_dGw);
+/* One step transposed at the current state: adjoints (lf1 [9n], lT1 [n]) of
+ * the next state -> adjoints (lf0, lT0) of the current one; *gGw += dJ/dG_w. */
+int orc_step_vjp(const orc_state *s, const double *lf1, const double *lT1, double *lf0, double *lT0,
+                 double *gGw);
+
 /* Copy/restore the full state (f, T, time, heat-flux accumulators). */
 int64_t orc_state_size(const orc_state *s);
 void orc_save(const orc_state *s, double *buf);

@@ -120,6 +120,10 @@ lib.orc_constants.argtypes = [C.c_void_p, _pd, _pd, _pd]
 lib.orc_state_size.restype = _i64
 lib.orc_state_size.argtypes = [C.c_void_p]
 lib.orc_save.argtypes = [C.c_void_p, _pd]
+lib.orc_adjoint.restype = C.c_int
+lib.orc_adjoint.argtypes = [C.c_void_p, _i64, _i64, _pd, _pd, _pd]
+lib.orc_step_vjp.restype = C.c_int
+lib.orc_step_vjp.argtypes = [C.c_void_p, _pd, _pd, _pd, _pd, _pd]
 lib.orc_load.argtypes = [C.c_void_p, _pd]
 
 
@@ -290,6 +294,26 @@ class State:
 
     def set_wettability(self, Gw):
         lib.orc_set_wettability(self._h, float(Gw))
+
+    def adjoint(self, n_steps: int, K: int = 0):
+        """J = mean of q over n_steps from the current state (unchanged), and
+        dJ/dT_b [nx], dJ/dG_w (bottom wall)."""
+        J, gGw = _d(), _d()
+        gTb = np.zeros(self.p.nx)
+        rc = lib.orc_adjoint(self._h, int(n_steps), int(K), C.byref(J), _ptr(gTb), C.byref(gGw))
+        if rc != 0:
+            raise OracleError(rc, "adjoint failed")
+        return J.value, gTb, gGw.value
+
+    def step_vjp(self, lf1, lT1):
+        """One step transposed at the current state."""
+        lf1, lT1 = _f64(lf1), _f64(lT1)
+        lf0, lT0 = np.zeros_like(lf1), np.zeros_like(lT1)
+        g = _d(0.0)
+        rc = lib.orc_step_vjp(self._h, _ptr(lf1), _ptr(lT1), _ptr(lf0), _ptr(lT0), C.byref(g))
+        if rc != 0:
+            raise OracleError(rc, "step_vjp failed")
+        return lf0, lT0, g.value
 
     def save(self) -> np.ndarray:
         buf = np.zeros(lib.orc_state_size(self._h))
