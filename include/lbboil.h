@@ -196,6 +196,19 @@ lbb_domain *lbb_batch_domain(lbb_batch *b, int i);
 int lbb_batch_size(lbb_batch *b);
 int lbb_batch_destroy(lbb_batch *b);
 
+/* ---- Adjoint -----------------------------------------------------------
+ * J = (1/N) sum_{n=1..N} q^n, the bottom-wall heat flux (Sec. 3.2) averaged
+ * over the next N steps from the current state, and its gradient with
+ * respect to the bottom-wall temperatures T_b(x) (all nx nodes, FP64 [nx])
+ * and the bottom wall strength G_w (Eq. (22)), by a hand-written discrete
+ * adjoint of the whole coupled step (FP64 arithmetic, FP64 adjoint fields).
+ * States are checkpointed every K steps (K <= 0: K = min(N, 50)) and each
+ * segment is recomputed before its reverse sweep.  The domain's state, step
+ * count and heat-flux average are restored afterwards.  Device memory:
+ * about (N/K + K) * 10 * nx*ny * sizeof(real) + 75 * nx*ny * 8 bytes.
+ * EUNSUPPORTED for periodic_y or a test mode; EINVAL for N < 1. */
+int lbb_adjoint(lbb_domain *d, int64_t N, int64_t K, double *J, double *dJ_dTb, double *dJ_dGw);
+
 /* Current step count, grid shape and device bytes held by the domain. */
 int lbb_info(lbb_domain *d, int64_t *t, int32_t *nx, int32_t *ny, int64_t *device_bytes);
 

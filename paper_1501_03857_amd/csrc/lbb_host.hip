@@ -5,6 +5,7 @@
 #include "lbboil.h"
 
 #include "lbb_device.hpp"
+#include "lbb_adjoint.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -1073,6 +1074,171 @@ extern "C" int lbb_batch_destroy(lbb_batch *b)
     batch_release(b);
     return LBB_OK;
 }
+
+}  // extern "C"
+
+// ---- adjoint --------------------------------------------------------------
+
+namespace {
+
+struct DevBuf {
+    std::vector<void *> ptrs;
+    ~DevBuf()
+    {
+        for (void *q : ptrs) (void)hipFree(q);
+    }
+    template <typename T>
+    bool get(T **out, size_t n)
+    {
+        void *q = nullptr;
+        if (hipMalloc(&q, n * sizeof(T)) != hipSuccess) return false;
+        ptrs.push_back(q);
+        *out = static_cast<T *>(q);
+        return hipMemset(q, 0, n * sizeof(T)) == hipSuccess;
+    }
+};
+
+template <typename S>
+int adjoint_impl(lbb_domain *d, int64_t N, int64_t K, double *J, double *dJ_dTb, double *dJ_dGw)
+{
+    using namespace lbb;
+    const size_t n = d->N, es = sizeof(S);
+    const size_t state_bytes = 10 * n * es;  // f (9) and T
+    const int64_t nck = (N + K - 1) / K;
+    DevBuf mem;
+    unsigned char *backup = nullptr, *ck = nullptr, *seg = nullptr;
+    Scalars *ck_sc = nullptr;
+    double *hf_backup = nullptr;
+    AdjW w{};
+    double *lf[2], *lT[2];
+    double *arrs[29];
+    bool ok = mem.get(&backup, state_bytes) && mem.get(&ck, (size_t)nck * state_bytes) &&
+              mem.get(&seg, (size_t)K * state_bytes) && mem.get(&ck_sc, (size_t)nck + 1) &&
+              mem.get(&hf_backup, (size_t)d->nbxB) && mem.get(&lf[0], 9 * n) && mem.get(&lf[1], 9 * n) &&
+              mem.get(&lT[0], n) && mem.get(&lT[1], n);
+    for (int k = 0; k < 29 && ok; ++k) ok = mem.get(&arrs[k], n);
+    const int nb = (int)((n + NTA - 1) / NTA);
+    ok = ok && mem.get(&w.part, 2 * (size_t)nb) && mem.get(&w.scal, 4);
+    if (!ok) return fail(LBB_ENOMEM, "adjoint work memory could not be allocated");
+    {
+        double **dst[] = {&w.rho, &w.jx, &w.jy, &w.psi, &w.sx, &w.sy, &w.Fx, &w.Fy, &w.Q, &w.vx, &w.vy, &w.vTx,
+                          &w.vTy, &w.Drx, &w.Dry, &w.divv, &w.gDrx, &w.gDry, &w.gdiv, &w.grho, &w.gvx, &w.gvy,
+                          &w.gFx, &w.gFy, &w.gQ, &w.gsx, &w.gsy, &w.gpsi};
+        for (int k = 0; k < 28; ++k) *dst[k] = arrs[k];
+    }
+    double *tk = nullptr, *ghs = nullptr;
+    if (!mem.get(&tk, 4 * n) || !mem.get(&ghs, 4 * n)) return fail(LBB_ENOMEM, "adjoint work memory could not be allocated");
+    for (int k = 0; k < 4; ++k) {
+        w.Tk[k] = tk + k * n;
+        w.gh[k] = ghs + k * n;
+    }
+    (void)arrs[28];
+    hipStream_t st = d->stream;
+    auto copy_state_out = [&](unsigned char *dst) -> hipError_t {
+        hipError_t e = hipMemcpyAsync(dst, d->f[d->cf], 9 * n * es, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(dst + 9 * n * es, d->T[d->cT], n * es, hipMemcpyDeviceToDevice, st);
+        return e;
+    };
+    auto copy_state_in = [&](const unsigned char *src) -> hipError_t {
+        d->cf = d->cT = 0;
+        hipError_t e = hipMemcpyAsync(d->f[0], src, 9 * n * es, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(d->T[0], src + 9 * n * es, n * es, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(d->T[1], src + 9 * n * es, n * es, hipMemcpyDeviceToDevice, st);
+        return e;
+    };
+    // keep the caller's state, counters and heat-flux partials
+    LBB_HIP(copy_state_out(backup));
+    LBB_HIP(hipMemcpyAsync(&ck_sc[nck], d->sc, sizeof(Scalars), hipMemcpyDeviceToDevice, st));
+    LBB_HIP(hipMemcpyAsync(hf_backup, d->hf_part, d->nbxB * sizeof(double), hipMemcpyDeviceToDevice, st));
+    // forward with the average restarted: J = q_sum / N afterwards
+    Scalars s0;
+    LBB_HIP(hipMemcpyAsync(&s0, d->sc, sizeof s0, hipMemcpyDeviceToHost, st));
+    LBB_HIP(hipStreamSynchronize(st));
+    s0.q_sum = 0.0;
+    s0.n_samples = 0;
+    LBB_HIP(hipMemcpyAsync(d->sc, &s0, sizeof s0, hipMemcpyHostToDevice, st));
+    for (int64_t t = 0; t < N; ++t) {
+        if (t % K == 0) {
+            LBB_HIP(copy_state_out(ck + (size_t)(t / K) * state_bytes));
+            LBB_HIP(hipMemcpyAsync(&ck_sc[t / K], d->sc, sizeof(Scalars), hipMemcpyDeviceToDevice, st));
+        }
+        enqueue_step<S>(d);
+    }
+    hipLaunchKernelGGL(k_flush_heat_flux, dim3(1), dim3(NT), 0, st, d->d_inst);
+    int rc = check_errors(d);
+    if (rc) return rc;
+    Scalars s1;
+    LBB_HIP(hipMemcpyAsync(&s1, d->sc, sizeof s1, hipMemcpyDeviceToHost, st));
+    LBB_HIP(hipStreamSynchronize(st));
+    *J = s1.q_sum / (double)N;
+
+    // reverse sweep
+    const DevParams P = d->dp;
+    const double wq = 1.0 / (double)N;
+    const unsigned nbx_hf = (unsigned)((d->p.nx + 255) / 256);
+    hipLaunchKernelGGL(a_hf<S>, dim3(nbx_hf), dim3(256), 0, st, P, static_cast<const S *>(d->f[d->cf]),
+                       static_cast<const S *>(d->T[d->cT]), wq, lf[1], lT[1]);
+    const double cst[4] = {0.0, 0.5, 0.5, 1.0};
+    for (int64_t sg = nck - 1; sg >= 0; --sg) {
+        const int64_t t0 = sg * K, t1 = (t0 + K < N) ? t0 + K : N;
+        LBB_HIP(copy_state_in(ck + (size_t)sg * state_bytes));
+        LBB_HIP(hipMemcpyAsync(d->sc, &ck_sc[sg], sizeof(Scalars), hipMemcpyDeviceToDevice, st));
+        for (int64_t t = t0; t < t1; ++t) {
+            LBB_HIP(copy_state_out(seg + (size_t)(t - t0) * state_bytes));
+            if (t + 1 < t1) enqueue_step<S>(d);
+        }
+        for (int64_t t = t1 - 1; t >= t0; --t) {
+            const S *fs = reinterpret_cast<const S *>(seg + (size_t)(t - t0) * state_bytes);
+            const S *Ts = fs + 9 * n;
+            hipLaunchKernelGGL(a_macro<S>, dim3(nb), dim3(NTA), 0, st, P, fs, Ts, w);
+            hipLaunchKernelGGL(a_reduce_mass, dim3(1), dim3(NTA), 0, st, P, w, nb);
+            hipLaunchKernelGGL(a_force, dim3(nb), dim3(NTA), 0, st, P, w);
+            hipLaunchKernelGGL(a_divv, dim3(nb), dim3(NTA), 0, st, P, w);
+            for (int k = 0; k < 3; ++k) hipLaunchKernelGGL(a_stage, dim3(nb), dim3(NTA), 0, st, P, w, k, cst[k + 1]);
+            hipLaunchKernelGGL(a_tinit, dim3(nb), dim3(NTA), 0, st, P, w, lT[1], lT[0]);
+            for (int k = 3; k >= 0; --k) hipLaunchKernelGGL(a_tstage, dim3(nb), dim3(NTA), 0, st, P, w, k, cst[k], lT[0]);
+            hipLaunchKernelGGL(a_tstencil, dim3(nb), dim3(NTA), 0, st, P, w);
+            hipLaunchKernelGGL(a_lb<S>, dim3(nb), dim3(NTA), 0, st, P, w, fs, lf[1], lf[0]);
+            hipLaunchKernelGGL(a_reduce_force, dim3(1), dim3(NTA), 0, st, w, nb);
+            hipLaunchKernelGGL(a_final<S>, dim3(nb), dim3(NTA), 0, st, P, w, Ts, lf[0], lT[0]);
+            if (t >= 1) hipLaunchKernelGGL(a_hf<S>, dim3(nbx_hf), dim3(256), 0, st, P, fs, Ts, wq, lf[0], lT[0]);
+            std::swap(lf[0], lf[1]);
+            std::swap(lT[0], lT[1]);
+        }
+        LBB_HIP(hipGetLastError());
+    }
+    std::vector<double> g(d->p.nx);
+    double gGw = 0.0;
+    LBB_HIP(hipMemcpyAsync(g.data(), lT[1], d->p.nx * sizeof(double), hipMemcpyDeviceToHost, st));
+    LBB_HIP(hipMemcpyAsync(&gGw, w.scal + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+    // restore the caller's state
+    LBB_HIP(copy_state_in(backup));
+    LBB_HIP(hipMemcpyAsync(d->sc, &ck_sc[nck], sizeof(Scalars), hipMemcpyDeviceToDevice, st));
+    LBB_HIP(hipMemcpyAsync(d->hf_part, hf_backup, d->nbxB * sizeof(double), hipMemcpyDeviceToDevice, st));
+    LBB_HIP(hipStreamSynchronize(st));
+    if (dJ_dTb) std::memcpy(dJ_dTb, g.data(), d->p.nx * sizeof(double));
+    if (dJ_dGw) *dJ_dGw = gGw;
+    for (double v : g)
+        if (!std::isfinite(v)) return fail(LBB_ENONFINITE, "adjoint produced a non-finite gradient");
+    return LBB_OK;
+}
+
+}  // namespace
+
+extern "C" int lbb_adjoint(lbb_domain *d, int64_t N, int64_t K, double *J, double *dJ_dTb, double *dJ_dGw)
+{
+    if (!d || !J) return fail(LBB_EINVAL, "domain and J are required");
+    if (N < 1) return fail(LBB_EINVAL, "N must be >= 1");
+    if (d->p.periodic_y || d->p.thermal_mode != LBB_COUPLED)
+        return fail(LBB_EUNSUPPORTED, "the adjoint covers the coupled model with walls");
+    if (d->poisoned) return fail(LBB_ESTATE, "domain poisoned by an earlier invalid state; load a state first");
+    if (K <= 0) K = N < 50 ? N : 50;
+    if (K > N) K = N;
+    return d->p.precision == LBB_FP64 ? adjoint_impl<double>(d, N, K, J, dJ_dTb, dJ_dGw)
+                                      : adjoint_impl<float>(d, N, K, J, dJ_dTb, dJ_dGw);
+}
+
+extern "C" {
 
 int lbb_destroy(lbb_domain *d)
 {

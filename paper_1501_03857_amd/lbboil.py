@@ -87,6 +87,7 @@ def lib():
             "lbb_batch_domain": (vp, [vp, C.c_int]),
             "lbb_batch_size": (C.c_int, [vp]),
             "lbb_batch_destroy": (C.c_int, [vp]),
+            "lbb_adjoint": (C.c_int, [vp, _i64, _i64, _pd, _pd, _pd]),
             "lbb_last_error": (C.c_char_p, []),
         }
         for name, (res, args) in sig.items():
@@ -240,6 +241,14 @@ class Domain:
     def stream(self) -> int:
         return lib().lbb_stream(self._h)
 
+    def adjoint(self, n_steps: int, K: int = 0):
+        """J = mean bottom-wall heat flux over the next n_steps and its
+        gradient w.r.t. T_b (all nx) and G_w; the state is left unchanged."""
+        J, gGw = _d(), _d()
+        gTb = np.zeros(self.p.nx)
+        _check(lib().lbb_adjoint(self._h, int(n_steps), int(K), C.byref(J), _ptr(gTb), C.byref(gGw)))
+        return J.value, gTb, gGw.value
+
     def fields(self, f: bool = True):
         ny, nx = self.p.ny, self.p.nx
         rho, ux, uy, T = (np.zeros((ny, nx)) for _ in range(4))
@@ -249,6 +258,12 @@ class Domain:
         if f:
             out["f"] = ff
         return out
+
+    def bottom_temperature(self) -> np.ndarray:
+        """The current bottom-wall temperatures T_b(x)."""
+        T = np.zeros((self.p.ny, self.p.nx))
+        _check(lib().lbb_read_fields(self._h, None, None, None, _ptr(T), None))
+        return T[0].copy()
 
     def heat_flux(self, local: bool = True):
         qn, qm, ns = _d(), _d(), _i64()
