@@ -112,6 +112,37 @@ def sweep_bench(steps, warmup=50):
             "q_mean_range": [float(min(q_batch)), float(max(q_batch))]}
 
 
+def adjoint_bench():
+    """Cost of the adjoint against the forward on the adjoint workload
+    (256x128, heater i in [96, 160) at 0.10 T_c, G_w = 0.065, 400 steps,
+    checkpoints every 50), wall time of synchronous calls."""
+    from paper_1501_03857_amd import lbboil as L
+    from paper_1501_03857_amd import workloads as WL
+
+    w = WL.ADJOINT_256x128
+    out = {"workload": w.name, "steps": w.steps, "K": 50}
+    Tc, _ = L.eos_constants(w.a, w.b, w.R, w.omega)
+    rv, rl = L.coexistence(w.a, w.b, w.R, w.omega, w.Ts_over_Tc * Tc)
+    for name, prec in (("f64", L.FP64), ("f32", L.FP32)):
+        p = L.Params(nx=w.nx, ny=w.ny, precision=prec, liquid_rows=w.liquid_rows, sigma=w.sigma, g=w.g,
+                     Gw_bottom=w.Gw_bottom, rho_L=rl, rho_V=rv)
+        d = L.Domain(p, T_bottom=w.heater_T(Tc), rho0=w.density(rl, rv))
+        d.adjoint(8, 4)  # warm-up (allocations, first launches)
+        d.step(8)
+        blob = d.save()
+        t0 = time.perf_counter()
+        d.step(w.steps)
+        fwd = time.perf_counter() - t0
+        d.load(blob)
+        t0 = time.perf_counter()
+        J, g, gw = d.adjoint(w.steps, 50)
+        adj = time.perf_counter() - t0
+        out[name] = {"forward_ms": round(fwd * 1e3, 3), "adjoint_ms": round(adj * 1e3, 3),
+                     "ratio": round(adj / fwd, 2), "J": J, "dJ_dGw": gw}
+        d.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +152,7 @@ def main():
     ap.add_argument("--kernel-steps", type=int, default=400, help="steps timed per launch for the roofline")
     ap.add_argument("--cpu-steps", type=int, default=100, help="oracle steps for the CPU baseline (0: skip)")
     ap.add_argument("--sweep-steps", type=int, default=2000, help="steps of the 48-lattice sweep comparison (0: skip)")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost measurement")
     ap.add_argument("--profile", action="store_true", help="timed region only (for rocprofv3 runs)")
     ap.add_argument("--copy-probe", action="store_true", help="run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -134,11 +166,13 @@ def main():
 
     torch.cuda.set_device(0)
     if args.copy_probe:
+        # An elementwise kernel that reads 1 GiB and writes 1 GiB (a same-type
+        # copy_ may go to a DMA engine, which the shader counters never see).
         n = 1 << 28
         a = torch.ones(n, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
         for _ in range(5):
-            b.copy_(a)
+            torch.neg(a, out=b)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "launches": 5}))
         return
@@ -190,6 +224,10 @@ def main():
     if sweep:
         print(f"[bench] sweep: batched {sweep['batched_mlups']} MLUPS vs sequential {sweep['plain_sequential_mlups']} "
               f"MLUPS ({sweep['speedup']}x)", file=sys.stderr, flush=True)
+    adj = None if args.no_adjoint else adjoint_bench()
+    if adj:
+        print(f"[bench] adjoint/forward: f64 {adj['f64']['ratio']}x, f32 {adj['f32']['ratio']}x",
+              file=sys.stderr, flush=True)
     cpu = cpu_baseline(w, args.cpu_steps) if args.cpu_steps > 0 else None
 
     line = {
@@ -217,6 +255,7 @@ def main():
         "kernels_ms": {"k_lb": round(ms_lb, 6), "k_thermal": round(ms_th, 6), "step_single_launch": round(ms_seq, 6)},
         "heat_flux_mean": hf["q_mean"],
         "batched_sweep": sweep,
+        "adjoint": adj,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

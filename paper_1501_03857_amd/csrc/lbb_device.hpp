@@ -354,7 +354,7 @@ __device__ __forceinline__ void tile_psi(const DevParams &P, const S *__restrict
 // forms rho and psi (FP64 EOS) on the tile and halo, keeping each node's
 // populations in registers; phase 2 collides the interior nodes and pushes.
 template <typename S>
-__global__ __launch_bounds__(64 * NWA) void k_lb(const Inst *__restrict__ insts, const int *__restrict__ blk2inst,
+__global__ __launch_bounds__(64 * NWA, 4) void k_lb(const Inst *__restrict__ insts, const int *__restrict__ blk2inst,
                                                  int cf, int cT)
 {
     const Inst &I = insts[blk2inst[blockIdx.x]];
