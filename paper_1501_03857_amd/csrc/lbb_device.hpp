@@ -15,7 +15,7 @@
 //   partials         per-block FP64 partial sums of mass and heat flux.
 //
 // One step t -> t+1 is two launches:
-//   k_lb      : per tile (64x8, halo 1): rho and psi (FP64 EOS, Eq. (21)) of
+//   k_lb      : per tile (62x12, halo 1; 4 waves): rho and psi (FP64 EOS, Eq. (21)) of
 //               the tile and its halo into LDS; per interior node the forces
 //               (Eqs. (7), (9), (22)), velocity (Eq. (6)), MRT collision with
 //               the improved forcing (Eqs. (2), (4), (5), (8)) and push
@@ -23,7 +23,7 @@
 //               of the streamed state (exact identity, so the next step's
 //               rho_ave needs no extra pass).  One extra block reduces the
 //               heat-flux partials of the previous thermal launch.
-//   k_thermal: per tile (64x8, halo 4): RK4 (Eqs. (19)-(20)) of Eq. (18) in
+//   k_thermal: per tile (56x24, halo 4; 16 waves): RK4 (Eqs. (19)-(20)) of Eq. (18) in
 //               LDS with the region shrinking by one node per stage; FP64
 //               heat-flux partials of the new state on the bottom tile row.
 //               One extra block reduces the mass partials of k_lb into
@@ -40,13 +40,13 @@ constexpr int NT = 256;   // threads per block of the small kernels (4 waves)
 constexpr int TXR = 64;   // read-back tile
 constexpr int TYR = 8;
 constexpr int TXA = 62;   // LB tile width: tile + halo of one is one wave wide
-constexpr int TYA = 8;    // LB tile height
+constexpr int TYA = 12;   // LB tile height
 constexpr int NWA = 4;    // waves per LB block
 constexpr int IPW_A = TYA / NWA;  // interior rows per LB wave
 static_assert(TYA % NWA == 0, "LB rows must split evenly over the waves");
 constexpr int HB = 4;     // thermal halo (RK4 has four stencil stages)
 constexpr int TXB = 64 - 2 * HB;  // thermal tile width: tile + halo is one wave wide
-constexpr int NWB = 8;    // waves per thermal block
+constexpr int NWB = 16;   // waves per thermal block
 
 // Thermal tile height and the type of the RK4 stage arithmetic: FP64 storage
 // keeps FP64; FP32 storage runs the stages in FP32 on T - T_s (rounding
@@ -58,11 +58,11 @@ __device__ __forceinline__ double stage_sqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float stage_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 template <> struct ThermalCfg<float> {
     using C = float;
-    static constexpr int TY = 32;
+    static constexpr int TY = 24;
 };
 template <> struct ThermalCfg<double> {
     using C = double;
-    static constexpr int TY = 16;
+    static constexpr int TY = 24;
 };
 
 enum : int { MODE_COUPLED = 0, MODE_ISOTHERMAL = 1, MODE_THERMAL_ONLY = 2 };
@@ -354,7 +354,7 @@ __device__ __forceinline__ void tile_psi(const DevParams &P, const S *__restrict
 // forms rho and psi (FP64 EOS) on the tile and halo, keeping each node's
 // populations in registers; phase 2 collides the interior nodes and pushes.
 template <typename S>
-__global__ __launch_bounds__(64 * NWA, 4) void k_lb(const Inst *__restrict__ insts, const int *__restrict__ blk2inst,
+__global__ __launch_bounds__(64 * NWA) void k_lb(const Inst *__restrict__ insts, const int *__restrict__ blk2inst,
                                                  int cf, int cT)
 {
     const Inst &I = insts[blk2inst[blockIdx.x]];
@@ -382,7 +382,8 @@ __global__ __launch_bounds__(64 * NWA, 4) void k_lb(const Inst *__restrict__ ins
     const int x0 = bx * TXA, y0 = by * TYA;
     const size_t N = (size_t)P.nx * P.ny;
     const bool walls = !P.periodic_y;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // the wave index is uniform over the wave: keep row logic on the scalar unit
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int gx = wrapi(x0 + lane - 1, P.nx);
 
     // lattice row of region row r (wrapped when periodic); false beyond a wall
@@ -570,7 +571,7 @@ __global__ __launch_bounds__(64 * NWB) void k_thermal(const Inst *__restrict__ i
     const int x0 = bx * TXB, y0 = by * TY;
     const bool walls = !P.periodic_y;
     const bool run = P.mode != MODE_ISOTHERMAL;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int gx = wrapi(x0 + lane - HB, P.nx);
 
     // lattice row of region row r; false beyond a wall

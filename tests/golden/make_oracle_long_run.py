@@ -1,0 +1,64 @@
+#!/usr/bin/env python3
+"""Write the oracle's long-horizon heat flux of the 1024x512 benchmark lattice.
+
+Runs the CPU oracle (FP64) on the 1024x512 workload (a = 2/49, T_s = 0.86 T_c,
+full-width heater at T_s + 0.10 T_c, G_w = 0.154, seed 2, gravity scaled to
+the lattice height) for 20000 steps, and stores:
+  * q (Sec. 3.2) of the state after every 1000th step,
+  * the time average of q over steps 10001-20000 (average reset after step
+    10000), the window the GPU test compares with,
+  * the total mass after step 20000.
+Only the oracle and the seeded input generator are used.  Takes about half an
+hour on 8 cores.
+
+    python tests/golden/make_oracle_long_run.py [--steps 20000]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import oracle as O  # noqa: E402
+from paper_1501_03857_amd import workloads as WL  # noqa: E402
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--out", default=os.path.join(HERE, "oracle_large_1024x512.json"))
+    args = ap.parse_args()
+    w = WL.LARGE_1024x512
+    tc = O.Tc(w.a, w.b, w.R)
+    rv, rl, _ = O.maxwell(w.a, w.b, w.R, w.omega, w.Ts_over_Tc * tc)
+    p = O.Params(nx=w.nx, ny=w.ny, a=w.a, b=w.b, R=w.R, omega=w.omega, Ts_over_Tc=w.Ts_over_Tc,
+                 sigma=w.sigma, g=w.g, Gw_bottom=w.Gw_bottom, rho_L=rl, rho_V=rv)
+    s = O.State(p, w.density(rl, rv), T_bottom=w.heater_T(tc))
+    half = args.steps // 2
+    q_trace = []
+    t0 = time.time()
+    for k in range(args.steps // 1000):
+        if k * 1000 == half:
+            s.reset_average()
+        s.step(1000)
+        q_trace.append([s.t, s.heat_flux()["q_now"]])
+        print(f"step {s.t}: q = {q_trace[-1][1]:.6e}  ({time.time() - t0:.0f} s)", flush=True)
+    hf = s.heat_flux()
+    mass = float(np.sum(s.fields()["rho"]))
+    out = {"workload": w.name, "nx": w.nx, "ny": w.ny, "steps": args.steps, "g": w.g, "Gw_bottom": w.Gw_bottom,
+           "dT_over_Tc": w.dT_over_Tc, "seed": w.seed, "q_trace": q_trace,
+           "q_mean_window": [half + 1, args.steps], "q_mean": hf["q_mean"], "n_samples": hf["n_samples"],
+           "mass_final": mass, "oracle_threads": O.num_threads(), "seconds": round(time.time() - t0, 1)}
+    with open(args.out, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps({k: out[k] for k in ("q_mean", "n_samples", "mass_final", "seconds")}))
+
+
+if __name__ == "__main__":
+    main()
