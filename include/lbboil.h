@@ -133,12 +133,12 @@ int lbb_sync(lbb_domain *d);
  * record events around lbb_step_async. */
 void *lbb_stream(lbb_domain *d);
 
-/* Advance n >= 1 steps with single launches (no graph) and a HIP event
- * before and after each kernel on the library stream; returns the mean
- * duration in milliseconds of the LB launch (collision, forces, streaming)
- * and of the thermal launch (RK4 temperature step), and the mean wall time
- * per step of the whole sequence.  For measurement only; the state advances
- * exactly as with lbb_step. */
+/* Advance n >= 1 steps with single launches (no graph), each launch
+ * carrying HIP events that its dispatch records at kernel start and end;
+ * returns the mean kernel duration in milliseconds of the LB launch
+ * (collision, forces, streaming) and of the thermal launch (RK4 temperature
+ * step), and the mean wall time per step of the whole sequence.  For
+ * measurement only; the state advances exactly as with lbb_step. */
 int lbb_time_kernels(lbb_domain *d, int64_t n, double *ms_lb, double *ms_thermal, double *ms_step);
 
 /* Read the current state, widened to FP64: rho = sum_a f_a; v from Eq. (6)

@@ -3,62 +3,107 @@
 // bottom-wall temperatures T_b(x) (Sec. 3.1) and the wall strength G_w
 // (Eq. (22)).  One reverse step transposes the forward step of
 // lbb_device.hpp stage by stage, in reverse order, over whole-lattice FP64
-// work arrays (one thread per node, 256 threads per block):
-//   a_macro    rho, j, psi of the stored state (FP64), block mass partials
-//   a_force    forces (Eqs. (7), (9), (22)), Q, velocity (Eq. (6)), grad rho
-//   a_divv     div v seen by the temperature equation
-//   a_stage    RK4 stage inputs T_2, T_3, T_4 (Eqs. (19)-(20))
-//   a_tinit    adjoint of T^{t+1}: identity part and the RK4 weights
-//   a_tstage   one RK4 stage transposed: the Eq. (18) stencils gathered from
-//              the neighbours, pressure-work term differentiated in T and rho
-//   a_tstencil stencil transposes of grad rho and div v
-//   a_lb       push streaming transposed (gather), MRT collision transposed
-//              in moment space, velocity transposed, per-node force parts
+// work arrays.  Each block covers a 64 x 4 patch of nodes (lane = column,
+// wave = row), so no thread divides to find its node.  Ten launches per
+// reverse step of state t -> t+1:
+//   a_force    forces (Eqs. (7), (9), (22)), Q, velocity (Eq. (6)), grad rho;
+//              rho_ave from the mass partials of the state
+//   a_divv0    div v seen by the temperature equation, the per-node
+//              coefficients of Eq. (18), and the first RK4 stage input T_2
+//   a_stage    RK4 stage inputs T_3, T_4 (Eqs. (19)-(20))
+//   a_tstage   one RK4 stage transposed (four launches, last stage first):
+//              the Eq. (18) stencils gathered from the neighbours, the
+//              pressure-work term differentiated in T and rho
+//   a_lb       stencil transposes of grad rho and div v (gather), push
+//              streaming transposed (gather), MRT collision transposed in
+//              moment space, velocity transposed, per-node force parts
 //   a_final    interaction-force stencil transposed (gather), EOS transposed,
-//              rho = sum f, Zou-He completion transposed
-//   a_hf       the heat-flux sample of a state transposed (source term)
-// The state of a node is its stored populations: wall-row populations that
-// arrive from outside are completions of the stored ones (Zou-He), so their
-// adjoint is folded into the stored ones.
+//              rho = sum f, Zou-He completion transposed, the heat-flux sample
+//              of state t transposed, and rho, j, psi of state t-1 for the
+//              next reverse step
+// a_macro forms rho, j, psi of a state where no a_final precedes it, and
+// a_hf the heat-flux source of the last state.  The state of a node is its
+// stored populations: wall-row populations that arrive from outside are
+// completions of the stored ones (Zou-He), so their adjoint is folded into
+// the stored ones.  The adjoint covers lattices with walls (periodic x).
 #pragma once
 
 #include "lbb_device.hpp"
 
 namespace lbb {
 
-constexpr int NTA = 256;
+constexpr int NTA = 256;          // threads per adjoint block
+constexpr int AXB = 64, AYB = 4;  // node patch of one block
 
 struct AdjW {
-    double *rho, *jx, *jy, *psi, *sx, *sy, *Fx, *Fy, *Q, *vx, *vy, *vTx, *vTy, *Drx, *Dry, *divv;
-    double *Tk[4];   // RK4 stage inputs T_1 (= T^t) .. T_4
-    double *gh[4];   // adjoints of the stage slopes h_1 .. h_4
-    double *gDrx, *gDry, *gdiv, *grho, *gvx, *gvy, *gFx, *gFy, *gQ, *gsx, *gsy, *gpsi;
-    double *part;    // block partials: [2b] d/d rho_ave, [2b+1] d/d G_w
-    double *scal;    // [0] rho_ave, [1] dJ/d rho_ave of this step, [2] dJ/dG_w (accumulated)
+    // rho, j, psi and T of the state being reversed; a_final replaces them
+    // by those of the state before it
+    double *rho, *jx, *jy, *psi, *T1;
+    double *sx, *sy, *Fx, *Fy, *Q, *vx, *vy, *vTx, *vTy, *Drx, *Dry;
+    // Eq. (18) as K(T) = AX d_x T + AY d_y T + chi lap T - IA divv T + IB divv T phi'(T)
+    // with AX = -vx + chi d_x rho / rho, IA = R / ((1 - b rho) c_v),
+    // IB = a rho / ((1 + 2 b rho - b^2 rho^2) c_v); E1, E2 give the rho
+    // derivative of the pressure-work factor; RI = 1 / rho
+    double *divv, *AX, *AY, *IA, *IB, *E1, *E2, *RI;
+    double *Tk[4];   // T_1 (= T1) .. T_4, the RK4 stage inputs
+    double *gh[3];   // adjoints of the slopes h_1 .. h_3 (that of h_4 is lT^{t+1}/6)
+    double *gDrx, *gDry, *gdiv, *grho, *gvx, *gvy, *gpsi, *gsx, *gsy;
+    double *mpart;   // block mass partials of the state being reversed
+    double *fpart;   // block partials of the force adjoint: [2b] rho_ave, [2b+1] G_w
+    double *scal;    // [2] dJ/dG_w, accumulated over the steps
 };
 
-__device__ __forceinline__ bool a_wall(const DevParams &P, int j) { return !P.periodic_y && (j == 0 || j == P.ny - 1); }
+#define A_NODE                                                 \
+    const int gi = blockIdx.x * AXB + (threadIdx.x & 63);      \
+    const int gj = blockIdx.y * AYB + (threadIdx.x >> 6);      \
+    const bool on = gi < P.nx && gj < P.ny;                    \
+    const size_t N = (size_t)P.nx * P.ny;                      \
+    const size_t c = (size_t)gj * P.nx + gi;                   \
+    (void)N;
 
-// neighbour of node (i, j) along e_a (false when beyond a wall)
-__device__ __forceinline__ bool a_nbr(const DevParams &P, int i, int j, int dx, int dy, size_t &cn)
+__device__ __forceinline__ bool a_int(const DevParams &P, int j) { return j > 0 && j < P.ny - 1; }
+
+// index of node (gi + dx, gj + dy) for a row known to lie in the lattice
+__device__ __forceinline__ size_t a_at(const DevParams &P, int gi, int gj, int dx, int dy)
 {
-    int ii = i + dx, jj = j + dy;
+    int ii = gi + dx;
     ii = ii < 0 ? ii + P.nx : (ii >= P.nx ? ii - P.nx : ii);
-    if (P.periodic_y) jj = jj < 0 ? jj + P.ny : (jj >= P.ny ? jj - P.ny : jj);
-    else if (jj < 0 || jj >= P.ny) return false;
-    cn = (size_t)jj * P.nx + ii;
-    return true;
+    return (size_t)(gj + dy) * P.nx + ii;
+}
+
+// Neighbour c' = c - e_a of node (gi, gj) when it is an interior node (ok),
+// else c itself: gathers load every neighbour without branching and weight
+// the missing ones by zero.
+__device__ __forceinline__ size_t a_src(const DevParams &P, int gi, int gj, int a, size_t c, bool &ok)
+{
+    const int jj = gj - kEY[a];
+    ok = a_int(P, jj);
+    return ok ? a_at(P, gi, gj, -kEX[a], -kEY[a]) : c;
 }
 
 __constant__ const double kW[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
 __constant__ const double kWpsi[9] = {0.0, 1.0 / 3, 1.0 / 3, 1.0 / 3, 1.0 / 3, 1.0 / 12, 1.0 / 12, 1.0 / 12, 1.0 / 12};
 
+// Fixed-order sum of a[k * stride + off], k < n, returned to every thread of
+// the block (every block forms the same value); all threads must call it.
+__device__ __forceinline__ double block_sum_all(const double *__restrict__ a, int n, int stride, int off,
+                                                double *red /* [NTA / 64 + 1] */)
+{
+    double s = 0.0;
+    for (int k = threadIdx.x; k < n; k += NTA) s += a[(size_t)k * stride + off];
+    s = block_sum<NTA>(s, red);
+    if (threadIdx.x == 0) red[NTA / 64] = s;
+    __syncthreads();
+    return red[NTA / 64];
+}
+
 // phi'(T) and phi''(T) of the Peng-Robinson alpha function (Eq. (21))
 __device__ __forceinline__ void phi_derivs(const DevParams &P, double T, double &d1, double &d2)
 {
     const double u = sqrt(T * P.inv_Tc);
-    d1 = -P.kappa * (1.0 + P.kappa * (1.0 - u)) / (P.Tc * u);
-    d2 = P.kappa * (1.0 + P.kappa) / (2.0 * P.Tc * P.Tc * u * u * u);
+    const double iu = 1.0 / (P.Tc * u);
+    d1 = -P.kappa * (1.0 + P.kappa * (1.0 - u)) * iu;
+    d2 = 0.5 * P.kappa * (1.0 + P.kappa) * iu * iu * iu * P.Tc;
 }
 
 // (dp/drho)_T and (dp/dT)_rho of Eq. (21)
@@ -95,65 +140,60 @@ __device__ __forceinline__ void zou_he_T(double g[9], int bottom)
     }
 }
 
-#define A_NODE                                                          \
-    const size_t N = (size_t)P.nx * P.ny;                               \
-    const size_t c = (size_t)blockIdx.x * NTA + threadIdx.x;            \
-    const bool on = c < N;                                              \
-    const int gi = on ? (int)(c % P.nx) : 0, gj = on ? (int)(c / P.nx) : 0; \
-    (void)gi;
+// rho, j, psi and T of a stored state at node c; returns rho
+template <typename S>
+__device__ __forceinline__ double a_macro_node(const DevParams &P, const S *__restrict__ f, const S *__restrict__ T,
+                                               size_t N, size_t c, int gj, const AdjW &w)
+{
+    double fl[9];
+    load_node(P, f, N, c, gj, fl);
+    double r = 0.0;
+    for (int a = 0; a < 9; ++a) r += fl[a];
+    const double Tv = P.T_ref + (double)T[c];
+    w.rho[c] = r;
+    w.jx[c] = fl[1] - fl[3] + fl[5] - fl[6] - fl[7] + fl[8];
+    w.jy[c] = fl[2] - fl[4] + fl[5] + fl[6] - fl[7] - fl[8];
+    w.T1[c] = Tv;
+    w.psi[c] = pseudopotential(P, r, Tv);
+    return r;
+}
 
 template <typename S>
 __global__ __launch_bounds__(NTA) void a_macro(DevParams P, const S *__restrict__ f, const S *__restrict__ T, AdjW w)
 {
     __shared__ double red[NTA / 64];
     A_NODE
-    double m = 0.0;
-    if (on) {
-        double fl[9];
-        load_node(P, f, N, c, gj, fl);
-        double r = 0.0;
-        for (int a = 0; a < 9; ++a) r += fl[a];
-        w.rho[c] = r;
-        w.jx[c] = fl[1] - fl[3] + fl[5] - fl[6] - fl[7] + fl[8];
-        w.jy[c] = fl[2] - fl[4] + fl[5] + fl[6] - fl[7] - fl[8];
-        const double Tv = P.T_ref + (double)T[c];
-        w.Tk[0][c] = Tv;
-        w.psi[c] = pseudopotential(P, r, Tv);
-        m = r;
-    }
+    const double m = on ? a_macro_node(P, f, T, N, c, gj, w) : 0.0;
     const double s = block_sum<NTA>(m, red);
-    if (threadIdx.x == 0) w.part[blockIdx.x] = s;
+    if (threadIdx.x == 0) w.mpart[blockIdx.y * gridDim.x + blockIdx.x] = s;
 }
 
-__global__ void a_reduce_mass(DevParams P, AdjW w, int nb)
+__global__ __launch_bounds__(NTA) void a_force(DevParams P, AdjW w, int nbm)
 {
-    __shared__ double red[NTA / 64];
-    const double s = block_sum_array<NTA>(w.part, nb, red);
-    if (threadIdx.x == 0) w.scal[0] = s / ((double)P.nx * (double)P.ny);
-}
-
-__global__ __launch_bounds__(NTA) void a_force(DevParams P, AdjW w)
-{
+    __shared__ double red[NTA / 64 + 1];
+    const double rho_ave = block_sum_all(w.mpart, nbm, 1, 0, red) / ((double)P.nx * (double)P.ny);
     A_NODE
     if (!on) return;
     double sx = 0.0, sy = 0.0, Fx = 0.0, Fy = 0.0, Q = 0.0, rx = 0.0, ry = 0.0;
     const double r = w.rho[c];
-    if (!a_wall(P, gj)) {
+    const bool in = a_int(P, gj);
+    if (in) {
+#pragma unroll
         for (int a = 1; a < 9; ++a) {
-            size_t cn;
-            a_nbr(P, gi, gj, kEX[a], kEY[a], cn);
-            sx += kWpsi[a] * w.psi[cn] * kEX[a];
-            sy += kWpsi[a] * w.psi[cn] * kEY[a];
-            rx += 3.0 * kW[a] * kEX[a] * w.rho[cn];
-            ry += 3.0 * kW[a] * kEY[a] * w.rho[cn];
+            const size_t cn = a_at(P, gi, gj, kEX[a], kEY[a]);
+            const double pn = w.psi[cn], rn = w.rho[cn];
+            sx += kWpsi[a] * pn * kEX[a];
+            sy += kWpsi[a] * pn * kEY[a];
+            rx += 3.0 * kW[a] * kEX[a] * rn;
+            ry += 3.0 * kW[a] * kEY[a] * rn;
         }
         const double ps = w.psi[c];
         Fx = -P.G * ps * sx;
         Fy = -P.G * ps * sy;
         Q = P.G * P.G * (sx * sx + sy * sy);
-        if (!P.periodic_y && gj == 1) Fy += P.Gw_bottom * ps * ps / 6.0;
-        if (!P.periodic_y && gj == P.ny - 2) Fy -= P.Gw_top * ps * ps / 6.0;
-        Fy -= (r - w.scal[0]) * P.g;
+        if (gj == 1) Fy += P.Gw_bottom * ps * ps / 6.0;
+        if (gj == P.ny - 2) Fy -= P.Gw_top * ps * ps / 6.0;
+        Fy -= (r - rho_ave) * P.g;
     }
     w.sx[c] = sx;
     w.sy[c] = sy;
@@ -165,43 +205,61 @@ __global__ __launch_bounds__(NTA) void a_force(DevParams P, AdjW w)
     const double vx = (w.jx[c] + 0.5 * Fx) / r, vy = (w.jy[c] + 0.5 * Fy) / r;
     w.vx[c] = vx;
     w.vy[c] = vy;
-    w.vTx[c] = a_wall(P, gj) ? 0.0 : vx;
-    w.vTy[c] = a_wall(P, gj) ? 0.0 : vy;
+    w.vTx[c] = in ? vx : 0.0;
+    w.vTy[c] = in ? vy : 0.0;
 }
 
-__global__ __launch_bounds__(NTA) void a_divv(DevParams P, AdjW w)
+// Eq. (18) at interior node c for the stage field Tf, with its stencils and
+// phi'(T), phi''(T) at the node
+__device__ __forceinline__ double a_K(const DevParams &P, const AdjW &w, const double *__restrict__ Tf, int gi, int gj,
+                                      size_t c, double &dTx, double &dTy, double &lap, double &d1, double &d2)
+{
+    const double tc = Tf[c];
+    dTx = dTy = lap = 0.0;
+#pragma unroll
+    for (int a = 1; a < 9; ++a) {
+        const double t = Tf[a_at(P, gi, gj, kEX[a], kEY[a])];
+        dTx += 3.0 * kW[a] * kEX[a] * t;
+        dTy += 3.0 * kW[a] * kEY[a] * t;
+        lap += 6.0 * kW[a] * (t - tc);
+    }
+    phi_derivs(P, tc, d1, d2);
+    const double dv = w.divv[c];
+    return w.AX[c] * dTx + w.AY[c] * dTy + P.chi * lap - w.IA[c] * dv * tc + w.IB[c] * dv * tc * d1;
+}
+
+// div v, the coefficients of Eq. (18), and T_2 = T_1 + K(T_1)/2
+__global__ __launch_bounds__(NTA) void a_divv0(DevParams P, AdjW w)
 {
     A_NODE
     if (!on) return;
-    double d = 0.0;
-    if (!a_wall(P, gj))
-        for (int a = 1; a < 9; ++a) {
-            size_t cn;
-            a_nbr(P, gi, gj, kEX[a], kEY[a], cn);
-            d += 3.0 * kW[a] * (kEX[a] * w.vTx[cn] + kEY[a] * w.vTy[cn]);
-        }
-    w.divv[c] = d;
-}
-
-// Eq. (18) at node c for the stage field Tf (with its stencils returned)
-__device__ __forceinline__ double a_K(const DevParams &P, const AdjW &w, const double *Tf, int gi, int gj, size_t c,
-                                      double &dTx, double &dTy, double &lap)
-{
-    dTx = dTy = lap = 0.0;
-    const double tc = Tf[c];
+    if (!a_int(P, gj)) {
+        w.divv[c] = w.AX[c] = w.AY[c] = w.IA[c] = w.IB[c] = w.E1[c] = w.E2[c] = w.RI[c] = 0.0;
+        w.Tk[1][c] = w.T1[c];
+        return;
+    }
+    double dv = 0.0;
+#pragma unroll
     for (int a = 1; a < 9; ++a) {
-        size_t cn;
-        a_nbr(P, gi, gj, kEX[a], kEY[a], cn);
-        dTx += 3.0 * kW[a] * kEX[a] * Tf[cn];
-        dTy += 3.0 * kW[a] * kEY[a] * Tf[cn];
-        lap += 6.0 * kW[a] * (Tf[cn] - tc);
+        const size_t cn = a_at(P, gi, gj, kEX[a], kEY[a]);
+        dv += 3.0 * kW[a] * (kEX[a] * w.vTx[cn] + kEY[a] * w.vTy[cn]);
     }
     const double r = w.rho[c];
-    double d1, d2;
-    phi_derivs(P, tc, d1, d2);
-    const double Pt = r * P.R / (1.0 - P.b * r) - P.a * r * r * d1 / (1.0 + 2.0 * P.b * r - P.b * P.b * r * r);
-    return -(w.vTx[c] * dTx + w.vTy[c] * dTy) + P.chi * (lap + (w.Drx[c] * dTx + w.Dry[c] * dTy) / r) -
-           tc * Pt * w.divv[c] / (r * P.cv);
+    const double D1 = 1.0 - P.b * r, D2 = 1.0 + 2.0 * P.b * r - P.b * P.b * r * r;
+    const double inv = 1.0 / (r * D1 * D2);
+    const double ri = D1 * D2 * inv, i1 = r * D2 * inv, i2 = r * D1 * inv;
+    const double icv = 1.0 / P.cv;
+    w.divv[c] = dv;
+    w.RI[c] = ri;
+    w.AX[c] = -w.vTx[c] + P.chi * w.Drx[c] * ri;
+    w.AY[c] = -w.vTy[c] + P.chi * w.Dry[c] * ri;
+    w.IA[c] = P.R * i1 * icv;
+    w.IB[c] = P.a * r * i2 * icv;
+    w.E1[c] = P.R * P.b * i1 * i1 * icv;
+    w.E2[c] = P.a * (1.0 + P.b * P.b * r * r) * i2 * i2 * icv;
+    double dTx, dTy, lap, d1, d2;
+    const double h = a_K(P, w, w.T1, gi, gj, c, dTx, dTy, lap, d1, d2);
+    w.Tk[1][c] = w.T1[c] + 0.5 * h;
 }
 
 // T_{k+1} = T_1 + c_k K(T_k) on interior rows (T_1 on wall rows)
@@ -210,102 +268,77 @@ __global__ __launch_bounds__(NTA) void a_stage(DevParams P, AdjW w, int k, doubl
     A_NODE
     if (!on) return;
     double h = 0.0;
-    if (!a_wall(P, gj)) {
-        double dx, dy, lp;
-        h = a_K(P, w, w.Tk[k], gi, gj, c, dx, dy, lp);
+    if (a_int(P, gj)) {
+        double dTx, dTy, lap, d1, d2;
+        h = a_K(P, w, w.Tk[k], gi, gj, c, dTx, dTy, lap, d1, d2);
     }
-    w.Tk[k + 1][c] = w.Tk[0][c] + ck * h;
+    w.Tk[k + 1][c] = w.T1[c] + ck * h;
 }
 
-// Start of a reverse step: lT0 = lT1 (identity part of T^{t+1} = T^t + ...),
-// slope adjoints from T^{t+1} = T^t + (h1 + 2 h2 + 2 h3 + h4)/6, the
-// per-node accumulators cleared.
-__global__ __launch_bounds__(NTA) void a_tinit(DevParams P, AdjW w, const double *__restrict__ lT1, double *__restrict__ lT0)
-{
-    A_NODE
-    if (!on) return;
-    const double g = a_wall(P, gj) ? 0.0 : lT1[c] / 6.0;
-    w.gh[0][c] = g;
-    w.gh[1][c] = 2.0 * g;
-    w.gh[2][c] = 2.0 * g;
-    w.gh[3][c] = g;
-    lT0[c] = lT1[c];
-    w.gDrx[c] = w.gDry[c] = w.gdiv[c] = w.grho[c] = w.gvx[c] = w.gvy[c] = 0.0;
-}
-
-// One RK4 stage transposed: gather the adjoint of T_k at c from the slope
-// adjoints of c and its neighbours; accumulate the rho and v parts at c.
-__global__ __launch_bounds__(NTA) void a_tstage(DevParams P, AdjW w, int k, double ck, double *__restrict__ lT0)
+// RK4 stage k (slope h_{k+1} = K(T_{k+1})) transposed.  Gathers the adjoint
+// of the stage input at c from the slope adjoints of c and its neighbours,
+// accumulates the rho and v parts at c, hands c_k times it to the slope of
+// the stage before (whose adjoint is w_k lT^{t+1}/6 plus that, with the RK4
+// weights w = (1, 2, 2, 1)), and adds it to the adjoint of T^t, which starts
+// from lT^{t+1} (identity part).  The last stage's slope adjoint is
+// lT^{t+1}/6 on interior nodes.
+__global__ __launch_bounds__(NTA) void a_tstage(DevParams P, AdjW w, int k, double ck, const double *__restrict__ lT1,
+                                                double *__restrict__ lT0)
 {
     A_NODE
     if (!on) return;
     const double *Tf = w.Tk[k];
-    const double *gh = w.gh[k];
+    const double *gk = k < 3 ? w.gh[k] : lT1;
+    const double sk = k < 3 ? 1.0 : 1.0 / 6.0;
     double gT = 0.0;
     // neighbours c' = c - e_a whose stencils read T(c) with weight e_a
+#pragma unroll
     for (int a = 1; a < 9; ++a) {
-        size_t cp;
-        if (!a_nbr(P, gi, gj, -kEX[a], -kEY[a], cp)) continue;
-        const int jp = (int)(cp / P.nx);
-        if (a_wall(P, jp)) continue;
-        const double g = gh[cp];
-        if (g == 0.0) continue;
-        const double rp = w.rho[cp];
-        const double ax = -w.vTx[cp] + P.chi * w.Drx[cp] / rp, ay = -w.vTy[cp] + P.chi * w.Dry[cp] / rp;
-        gT += g * (3.0 * kW[a] * (ax * kEX[a] + ay * kEY[a]) + 6.0 * kW[a] * P.chi);
+        bool ok;
+        const size_t cp = a_src(P, gi, gj, a, c, ok);
+        const double g = (ok ? sk : 0.0) * gk[cp];
+        gT += g * (3.0 * kW[a] * (w.AX[cp] * kEX[a] + w.AY[cp] * kEY[a]) + 6.0 * kW[a] * P.chi);
     }
-    if (!a_wall(P, gj)) {
-        const double g = gh[c];
-        double dTx, dTy, lap;
-        (void)a_K(P, w, Tf, gi, gj, c, dTx, dTy, lap);
-        const double r = w.rho[c], Tv = Tf[c], dv = w.divv[c];
-        double d1, d2;
-        phi_derivs(P, Tv, d1, d2);
-        const double D1 = 1.0 - P.b * r, D2 = 1.0 + 2.0 * P.b * r - P.b * P.b * r * r;
-        const double Pt = r * P.R / D1 - P.a * r * r * d1 / D2;
-        const double dPdT = -P.a * r * r * d2 / D2;
-        gT += g * (-(10.0 / 3.0) * P.chi - dv / (r * P.cv) * (Pt + Tv * dPdT));
-        w.gDrx[c] += g * P.chi * dTx / r;
-        w.gDry[c] += g * P.chi * dTy / r;
-        w.gvx[c] += -g * dTx;
-        w.gvy[c] += -g * dTy;
-        w.gdiv[c] += -g * Tv * Pt / (r * P.cv);
-        const double dPr = P.R * P.b / (D1 * D1) - P.a * d1 * (1.0 + P.b * P.b * r * r) / (D2 * D2);
-        w.grho[c] += g * (-P.chi * (w.Drx[c] * dTx + w.Dry[c] * dTy) / (r * r) - Tv * dv / P.cv * dPr);
-        if (k > 0) w.gh[k - 1][c] += ck * gT;
+    if (a_int(P, gj)) {
+        const double g = sk * gk[c];
+        double dTx, dTy, lap, d1, d2;
+        (void)a_K(P, w, Tf, gi, gj, c, dTx, dTy, lap, d1, d2);
+        const double Tv = Tf[c], dv = w.divv[c], ri = w.RI[c], IA = w.IA[c], IB = w.IB[c];
+        gT += g * (-(10.0 / 3.0) * P.chi - dv * (IA - IB * (d1 + Tv * d2)));
+        const double aDrx = g * P.chi * dTx * ri, aDry = g * P.chi * dTy * ri;
+        const double avx = -g * dTx, avy = -g * dTy;
+        const double adiv = -g * Tv * (IA - IB * d1);
+        const double arho = g * (-P.chi * (w.Drx[c] * dTx + w.Dry[c] * dTy) * ri * ri -
+                                 Tv * dv * (w.E1[c] - w.E2[c] * d1));
+        if (k == 3) {
+            w.gDrx[c] = aDrx;
+            w.gDry[c] = aDry;
+            w.gvx[c] = avx;
+            w.gvy[c] = avy;
+            w.gdiv[c] = adiv;
+            w.grho[c] = arho;
+        } else {
+            w.gDrx[c] += aDrx;
+            w.gDry[c] += aDry;
+            w.gvx[c] += avx;
+            w.gvy[c] += avy;
+            w.gdiv[c] += adiv;
+            w.grho[c] += arho;
+        }
+        if (k > 0) {
+            const double wk = (k == 1) ? 1.0 : 2.0;
+            w.gh[k - 1][c] = wk * lT1[c] / 6.0 + ck * gT;
+        }
+    } else if (k == 3) {
+        w.gDrx[c] = w.gDry[c] = w.gvx[c] = w.gvy[c] = w.gdiv[c] = w.grho[c] = 0.0;
     }
-    lT0[c] += gT;
+    if (k == 3) lT0[c] = lT1[c] + gT;
+    else lT0[c] += gT;
 }
 
-// Stencil transposes of grad rho and div v (the velocity seen by the
-// temperature equation is zero on the wall rows, so only interior nodes
-// receive the div v part); the temperature velocity adjoint joins v.
-__global__ __launch_bounds__(NTA) void a_tstencil(DevParams P, AdjW w)
-{
-    A_NODE
-    if (!on) return;
-    double gr = 0.0, gu = 0.0, gv = 0.0;
-    for (int a = 1; a < 9; ++a) {
-        size_t cp;
-        if (!a_nbr(P, gi, gj, -kEX[a], -kEY[a], cp)) continue;
-        if (a_wall(P, (int)(cp / P.nx))) continue;
-        gr += 3.0 * kW[a] * (kEX[a] * w.gDrx[cp] + kEY[a] * w.gDry[cp]);
-        gu += 3.0 * kW[a] * kEX[a] * w.gdiv[cp];
-        gv += 3.0 * kW[a] * kEY[a] * w.gdiv[cp];
-    }
-    w.grho[c] += gr;
-    if (!a_wall(P, gj)) {
-        w.gvx[c] += gu;
-        w.gvy[c] += gv;
-    } else {
-        w.gvx[c] = 0.0;
-        w.gvy[c] = 0.0;
-    }
-}
-
-// Streaming and collision transposed at node c; writes the adjoint of the
-// completed populations (before the density and completion parts), and the
-// per-node force adjoints.
+// Stencil transposes of grad rho and div v, then streaming and collision
+// transposed at node c; writes the adjoint of the completed populations
+// (before the density and completion parts), and the per-node force adjoints.
 template <typename S>
 __global__ __launch_bounds__(NTA) void a_lb(DevParams P, AdjW w, const S *__restrict__ f,
                                             const double *__restrict__ lf1, double *__restrict__ lf0)
@@ -314,11 +347,36 @@ __global__ __launch_bounds__(NTA) void a_lb(DevParams P, AdjW w, const S *__rest
     A_NODE
     double pr = 0.0, pg = 0.0;
     if (on) {
+        const bool in = a_int(P, gj);
+        // grad rho and div v of the temperature equation transposed (only
+        // interior nodes carry them; the velocity it sees is zero on walls)
+        double gr = w.grho[c], gvx = 0.0, gvy = 0.0;
+        {
+            double tr = 0.0, tu = 0.0, tv = 0.0;
+#pragma unroll
+            for (int a = 1; a < 9; ++a) {
+                bool ok;
+                const size_t cp = a_src(P, gi, gj, a, c, ok);
+                const double m = ok ? 3.0 * kW[a] : 0.0;
+                tr += m * (kEX[a] * w.gDrx[cp] + kEY[a] * w.gDry[cp]);
+                const double gd = w.gdiv[cp];
+                tu += m * kEX[a] * gd;
+                tv += m * kEY[a] * gd;
+            }
+            gr += tr;
+            if (in) {
+                gvx = w.gvx[c] + tu;
+                gvy = w.gvy[c] + tv;
+            }
+        }
         // push streaming transposed: f'(c + e_a, a) = f*(c, a)
         double gfs[9];
+#pragma unroll
         for (int a = 0; a < 9; ++a) {
-            size_t ct;
-            gfs[a] = a_nbr(P, gi, gj, kEX[a], kEY[a], ct) ? lf1[(size_t)a * N + ct] : 0.0;
+            const int jj = gj + kEY[a];
+            const bool ok = jj >= 0 && jj < P.ny;
+            const double v = lf1[(size_t)a * N + (ok ? a_at(P, gi, gj, kEX[a], kEY[a]) : c)];
+            gfs[a] = ok ? v : 0.0;
         }
         double fl[9];
         load_node(P, f, N, c, gj, fl);
@@ -335,7 +393,7 @@ __global__ __launch_bounds__(NTA) void a_lb(DevParams P, AdjW w, const S *__rest
         m[6] = -2.0 * fl[2] + 2.0 * fl[4] + fl[5] + fl[6] - fl[7] - fl[8];
         m[7] = fl[1] - fl[2] + fl[3] - fl[4];
         m[8] = fl[5] - fl[6] + fl[7] - fl[8];
-        const double v2 = vx * vx + vy * vy, vF = vx * Fx + vy * Fy;
+        const double v2 = vx * vx + vy * vy;
         const double meq7 = r * (vx * vx - vy * vy), meq8 = r * vx * vy;
         const double S7 = 2.0 * (vx * Fx - vy * Fy), S8 = vx * Fy + vy * Fx;
         const double tau = P.tau_V + (r - P.rho_V) * P.tau_slope, s_nu = 1.0 / tau;
@@ -376,10 +434,10 @@ __global__ __launch_bounds__(NTA) void a_lb(DevParams P, AdjW w, const S *__rest
         gf[7] = gm[0] + 2.0 * gm[1] + gm[2] - gm[3] - gm[4] - gm[5] - gm[6] + gm[8];
         gf[8] = gm[0] + 2.0 * gm[1] + gm[2] + gm[3] + gm[4] - gm[5] - gm[6] - gm[8];
         // m_eq(rho, v) of Eq. (5)
-        double gr = gq[0] + gq[1] * (-2.0 + 3.0 * v2) + gq[2] * (1.0 - 3.0 * v2) + gq[3] * vx - gq[4] * vx +
-                    gq[5] * vy - gq[6] * vy + gq[7] * (vx * vx - vy * vy) + gq[8] * vx * vy;
-        double gvx = r * (6.0 * vx * (gq[1] - gq[2]) + gq[3] - gq[4] + 2.0 * vx * gq[7] + vy * gq[8]);
-        double gvy = r * (6.0 * vy * (gq[1] - gq[2]) + gq[5] - gq[6] - 2.0 * vy * gq[7] + vx * gq[8]);
+        gr += gq[0] + gq[1] * (-2.0 + 3.0 * v2) + gq[2] * (1.0 - 3.0 * v2) + gq[3] * vx - gq[4] * vx +
+              gq[5] * vy - gq[6] * vy + gq[7] * (vx * vx - vy * vy) + gq[8] * vx * vy;
+        gvx += r * (6.0 * vx * (gq[1] - gq[2]) + gq[3] - gq[4] + 2.0 * vx * gq[7] + vy * gq[8]);
+        gvy += r * (6.0 * vy * (gq[1] - gq[2]) + gq[5] - gq[6] - 2.0 * vy * gq[7] + vx * gq[8]);
         // S(v, F, Q) of Eq. (8)
         const double a6 = gS[1] - gS[2];
         double gFx = 6.0 * a6 * vx + gS[3] - gS[4] + 2.0 * vx * gS[7] + vy * gS[8];
@@ -387,12 +445,9 @@ __global__ __launch_bounds__(NTA) void a_lb(DevParams P, AdjW w, const S *__rest
         gvx += 6.0 * a6 * Fx + 2.0 * Fx * gS[7] + Fy * gS[8];
         gvy += 6.0 * a6 * Fy - 2.0 * Fy * gS[7] + Fx * gS[8];
         const double gQ = P.sig_e * gS[1] - P.sig_z * gS[2];
-        (void)vF;
         // s_nu = 1 / tau(rho)
         gr += gsnu * (-P.tau_slope / (tau * tau));
-        // v = (j + F/2)/rho, with what the temperature equation saw of v
-        gvx += w.gvx[c];
-        gvy += w.gvy[c];
+        // v = (j + F/2)/rho
         const double gjx = gvx / r, gjy = gvy / r;
         gFx += 0.5 * gvx / r;
         gFy += 0.5 * gvy / r;
@@ -400,105 +455,143 @@ __global__ __launch_bounds__(NTA) void a_lb(DevParams P, AdjW w, const S *__rest
         for (int a = 0; a < 9; ++a) lf0[(size_t)a * N + c] = gf[a] + kEX[a] * gjx + kEY[a] * gjy;
         // per-node force parts (no force on the wall rows)
         double gpsi = 0.0, gsx = 0.0, gsy = 0.0;
-        if (!a_wall(P, gj)) {
+        if (in) {
             const double ps = w.psi[c];
             gr += -P.g * gFy;
             pr = P.g * gFy;
-            if (!P.periodic_y && gj == 1) {
+            if (gj == 1) {
                 gpsi += gFy * P.Gw_bottom * ps / 3.0;
                 pg = gFy * ps * ps / 6.0;
             }
-            if (!P.periodic_y && gj == P.ny - 2) gpsi += -gFy * P.Gw_top * ps / 3.0;
+            if (gj == P.ny - 2) gpsi += -gFy * P.Gw_top * ps / 3.0;
             gpsi += -P.G * (w.sx[c] * gFx + w.sy[c] * gFy);
             gsx = -P.G * ps * gFx + 2.0 * P.G * P.G * w.sx[c] * gQ;
             gsy = -P.G * ps * gFy + 2.0 * P.G * P.G * w.sy[c] * gQ;
         }
-        w.grho[c] += gr;
+        w.grho[c] = gr;
         w.gpsi[c] = gpsi;
         w.gsx[c] = gsx;
         w.gsy[c] = gsy;
     }
+    const int blk = blockIdx.y * gridDim.x + blockIdx.x;
     const double sr = block_sum<NTA>(pr, red);
     __syncthreads();
     const double sg = block_sum<NTA>(pg, red);
     if (threadIdx.x == 0) {
-        w.part[2 * blockIdx.x] = sr;
-        w.part[2 * blockIdx.x + 1] = sg;
+        w.fpart[2 * blk] = sr;
+        w.fpart[2 * blk + 1] = sg;
     }
 }
 
-__global__ void a_reduce_force(AdjW w, int nb)
+// Heat-flux sample q = -(c_v chi / nx) sum_i rho(i,0) (-3 T0 + 4 T1 - T2)/2
+// of a stored state, transposed with weight wq, at node (gi, gj) of rows
+// 0..2: the population part (row 0, Zou-He folded) and the temperature part.
+template <typename S>
+__device__ __forceinline__ void hf_source(const DevParams &P, const S *__restrict__ f, const S *__restrict__ T,
+                                          double wq, size_t N, int gi, int gj, double gpop[9], double &gtem)
 {
-    __shared__ double red[NTA / 64];
-    double sr = 0.0, sg = 0.0;
-    for (int k = threadIdx.x; k < nb; k += NTA) {
-        sr += w.part[2 * k];
-        sg += w.part[2 * k + 1];
+    const double k = -P.cv_chi / P.nx * wq;
+    for (int a = 0; a < 9; ++a) gpop[a] = 0.0;
+    gtem = 0.0;
+    if (gj > 2) return;
+    double fl[9];
+    load_node(P, f, N, (size_t)gi, 0, fl);
+    double r0 = 0.0;
+    for (int a = 0; a < 9; ++a) r0 += fl[a];
+    if (gj == 0) {
+        const double t0 = (double)T[gi], t1 = (double)T[P.nx + gi], t2 = (double)T[2 * P.nx + gi];
+        for (int a = 0; a < 9; ++a) gpop[a] = k * (-3.0 * t0 + 4.0 * t1 - t2) / 2.0;
+        zou_he_T(gpop, 1);
     }
-    const double a = block_sum<NTA>(sr, red);
-    __syncthreads();
-    const double b = block_sum<NTA>(sg, red);
-    if (threadIdx.x == 0) {
-        w.scal[1] = a;
-        w.scal[2] += b;
-    }
+    gtem = k * r0 * (gj == 0 ? -1.5 : (gj == 1 ? 2.0 : -0.5));
 }
 
 // Interaction-force stencil transposed (gather of s over the neighbours),
-// EOS transposed, rho = sum f, Zou-He completion transposed.
+// EOS transposed, rho = sum f, Zou-He completion transposed; the heat-flux
+// source of state t (when it is a sample, wq > 0), and rho, j, psi of the
+// state before (fp, Tp when given) with its mass partials.
 template <typename S>
-__global__ __launch_bounds__(NTA) void a_final(DevParams P, AdjW w, const S *__restrict__ T, double *__restrict__ lf0,
-                                               double *__restrict__ lT0)
+__global__ __launch_bounds__(NTA) void a_final(DevParams P, AdjW w, const S *__restrict__ f, const S *__restrict__ T,
+                                               double wq, const S *__restrict__ fp, const S *__restrict__ Tp,
+                                               int nbf, double *__restrict__ lf0, double *__restrict__ lT0)
 {
+    __shared__ double red[NTA / 64 + 1];
+    const double sr = block_sum_all(w.fpart, nbf, 2, 0, red);
+    const int blk = blockIdx.y * gridDim.x + blockIdx.x;
+    if (blk == 0) {
+        const double sg = block_sum_all(w.fpart, nbf, 2, 1, red);
+        if (threadIdx.x == 0) w.scal[2] += sg;
+    }
     A_NODE
-    if (!on) return;
-    double gpsi = w.gpsi[c];
-    for (int a = 1; a < 9; ++a) {
-        size_t cp;
-        if (!a_nbr(P, gi, gj, -kEX[a], -kEY[a], cp)) continue;
-        if (a_wall(P, (int)(cp / P.nx))) continue;
-        gpsi += kWpsi[a] * (kEX[a] * w.gsx[cp] + kEY[a] * w.gsy[cp]);
-    }
-    double gr = w.grho[c] + w.scal[1] / ((double)P.nx * (double)P.ny);
-    if (gpsi != 0.0) {
-        const double r = w.rho[c], Tv = P.T_ref + (double)T[c];
-        double dpdr, dpdT;
-        eos_derivs(P, r, Tv, dpdr, dpdT);
-        const double gq = gpsi / (2.0 * w.psi[c]) * P.two_over_G;
-        gr += gq * (dpdr - 1.0 / 3.0);
-        lT0[c] += gq * dpdT;
-    }
-    double g[9];
-    for (int a = 0; a < 9; ++a) g[a] = lf0[(size_t)a * N + c] + gr;
-    if (!P.periodic_y && P.mode != MODE_THERMAL_ONLY) {
+    double m = 0.0;
+    if (on) {
+        double gpsi = w.gpsi[c];
+#pragma unroll
+        for (int a = 1; a < 9; ++a) {
+            bool ok;
+            const size_t cp = a_src(P, gi, gj, a, c, ok);
+            const double m = ok ? kWpsi[a] : 0.0;
+            gpsi += m * (kEX[a] * w.gsx[cp] + kEY[a] * w.gsy[cp]);
+        }
+        double gr = w.grho[c] + sr / ((double)P.nx * (double)P.ny);
+        double gT = 0.0;
+        if (gpsi != 0.0) {
+            const double r = w.rho[c], Tv = w.T1[c];
+            double dpdr, dpdT;
+            eos_derivs(P, r, Tv, dpdr, dpdT);
+            const double gq = gpsi / (2.0 * w.psi[c]) * P.two_over_G;
+            gr += gq * (dpdr - 1.0 / 3.0);
+            gT = gq * dpdT;
+        }
+        double g[9];
+        for (int a = 0; a < 9; ++a) g[a] = lf0[(size_t)a * N + c] + gr;
         if (gj == 0) zou_he_T(g, 1);
         else if (gj == P.ny - 1) zou_he_T(g, 0);
+        if (wq != 0.0 && gj <= 2) {
+            double gpop[9], gtem;
+            hf_source(P, f, T, wq, N, gi, gj, gpop, gtem);
+            for (int a = 0; a < 9; ++a) g[a] += gpop[a];
+            gT += gtem;
+        }
+        for (int a = 0; a < 9; ++a) lf0[(size_t)a * N + c] = g[a];
+        lT0[c] += gT;
+        // this thread's reads of the state-t values at c are done
+        if (fp) m = a_macro_node(P, fp, Tp, N, c, gj, w);
     }
-    for (int a = 0; a < 9; ++a) lf0[(size_t)a * N + c] = g[a];
+    if (fp) {
+        const double s = block_sum<NTA>(m, red);
+        if (threadIdx.x == 0) w.mpart[blk] = s;
+    }
 }
 
-// The heat-flux sample of a state transposed, weight wq (= 1/N), added to
-// the adjoint of that state.  One thread per bottom-wall node.
+// T of a state copied into the T part of each of `slots` stored states
+// (layout per state: 9 population planes, then T), so that every slot holds
+// the Dirichlet wall rows the thermal launch does not rewrite.
+template <typename S>
+__global__ void a_bcast_T(const S *__restrict__ T, S *__restrict__ seg, size_t n, int slots)
+{
+    const size_t total = n * (size_t)slots;
+    for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < total; k += (size_t)gridDim.x * blockDim.x) {
+        const size_t s = k / n, c = k - s * n;
+        seg[s * 10 * n + 9 * n + c] = T[c];
+    }
+}
+
+// The heat-flux sample of a state transposed, weight wq, added to the
+// adjoint of that state.  One thread per node of rows 0..2 (blockIdx.y = row).
 template <typename S>
 __global__ void a_hf(DevParams P, const S *__restrict__ f, const S *__restrict__ T, double wq,
                      double *__restrict__ lf, double *__restrict__ lT)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= P.nx || P.periodic_y) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
+    if (i >= P.nx || j > 2) return;
     const size_t N = (size_t)P.nx * P.ny;
-    double fl[9];
-    load_node(P, f, N, (size_t)i, 0, fl);
-    double r0 = 0.0;
-    for (int a = 0; a < 9; ++a) r0 += fl[a];
-    const double t0 = (double)T[i], t1 = (double)T[P.nx + i], t2 = (double)T[2 * P.nx + i];
-    const double k = -P.cv_chi / P.nx * wq;
-    double g[9];
-    for (int a = 0; a < 9; ++a) g[a] = k * (-3.0 * t0 + 4.0 * t1 - t2) / 2.0;
-    zou_he_T(g, 1);
-    for (int a = 0; a < 9; ++a) lf[(size_t)a * N + i] += g[a];
-    lT[i] += k * r0 * (-1.5);
-    lT[P.nx + i] += k * r0 * 2.0;
-    lT[2 * P.nx + i] += k * r0 * (-0.5);
+    double gpop[9], gtem;
+    hf_source(P, f, T, wq, N, i, j, gpop, gtem);
+    const size_t c = (size_t)j * P.nx + i;
+    if (j == 0)
+        for (int a = 0; a < 9; ++a) lf[(size_t)a * N + c] += gpop[a];
+    lT[c] += gtem;
 }
 
 }  // namespace lbb

@@ -112,6 +112,18 @@ struct Inst {
     int blkA0, blkB0;  // first block of this lattice in the LB / thermal grids
 };
 
+// Tile of a lattice's q-th block (0 <= q < nb).  Workgroups are dispatched
+// to the 8 XCDs round-robin, so blocks q, q+8, q+16, ... share an XCD and its
+// L2; they get one contiguous run of tiles (row-major), so halo rows and the
+// cache lines straddling tile edges are fetched once per XCD instead of once
+// per tile.  With nb = 8m + r the XCD class x = q mod 8 owns m (+1 if x < r)
+// tiles starting at x m + min(x, r).
+__device__ __forceinline__ int xcd_tile(int q, int nb)
+{
+    const int x = q & 7, k = q >> 3, m = nb >> 3, r = nb & 7;
+    return x * m + (x < r ? x : r) + k;
+}
+
 __device__ __forceinline__ int wrapi(int i, int n)
 {
     int r = i % n;
@@ -378,7 +390,8 @@ __global__ __launch_bounds__(64 * NWA) void k_lb(const Inst *__restrict__ insts,
         if (threadIdx.x == 0) sc->tB = t;  // the thermal launch of this step
         return;
     }
-    const int bx = blk % nbx, by = blk / nbx;
+    const int tile = xcd_tile(blk, nbx * nby);
+    const int bx = tile % nbx, by = tile / nbx;
     const int x0 = bx * TXA, y0 = by * TYA;
     const size_t N = (size_t)P.nx * P.ny;
     const bool walls = !P.periodic_y;
@@ -567,7 +580,8 @@ __global__ __launch_bounds__(64 * NWB) void k_thermal(const Inst *__restrict__ i
         }
         return;
     }
-    const int bx = blk % nbx, by = blk / nbx;
+    const int tile = xcd_tile(blk, nbx * nby);
+    const int bx = tile % nbx, by = tile / nbx;
     const int x0 = bx * TXB, y0 = by * TY;
     const bool walls = !P.periodic_y;
     const bool run = P.mode != MODE_ISOTHERMAL;

@@ -8,6 +8,7 @@
 #include "lbb_adjoint.hpp"
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cmath>
 #include <cstdio>
@@ -157,6 +158,8 @@ struct lbb_domain {
     hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     std::vector<double> Tb;
     int64_t dev_bytes = 0;
+    void *adj_mem = nullptr;             // adjoint workspace, kept between calls
+    size_t adj_bytes = 0;
 };
 
 namespace {
@@ -226,28 +229,39 @@ int push_inst(lbb_domain *d)
     return LBB_OK;
 }
 
+// The optional events are recorded by the dispatch itself (start and end of
+// the kernel), so their interval is the kernel's own duration.
 template <typename S>
-void launch_lb(hipStream_t st, const lbb::Inst *insts, const int *blk, int nblocks, int cf, int cT)
+void launch_lb(hipStream_t st, const lbb::Inst *insts, const int *blk, int nblocks, int cf, int cT,
+               hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr)
 {
-    hipLaunchKernelGGL(lbb::k_lb<S>, dim3(nblocks), dim3(64 * lbb::NWA), 0, st, insts, blk, cf, cT);
+    if (ev0)
+        hipExtLaunchKernelGGL(lbb::k_lb<S>, dim3(nblocks), dim3(64 * lbb::NWA), 0, st, ev0, ev1, 0, insts, blk, cf, cT);
+    else
+        hipLaunchKernelGGL(lbb::k_lb<S>, dim3(nblocks), dim3(64 * lbb::NWA), 0, st, insts, blk, cf, cT);
 }
 
 template <typename S>
-void launch_thermal(hipStream_t st, const lbb::Inst *insts, const int *blk, int nblocks, int cf, int cT)
+void launch_thermal(hipStream_t st, const lbb::Inst *insts, const int *blk, int nblocks, int cf, int cT,
+                    hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr)
 {
-    hipLaunchKernelGGL(lbb::k_thermal<S>, dim3(nblocks), dim3(64 * lbb::NWB), 0, st, insts, blk, cf, cT);
+    if (ev0)
+        hipExtLaunchKernelGGL(lbb::k_thermal<S>, dim3(nblocks), dim3(64 * lbb::NWB), 0, st, ev0, ev1, 0, insts, blk,
+                              cf, cT);
+    else
+        hipLaunchKernelGGL(lbb::k_thermal<S>, dim3(nblocks), dim3(64 * lbb::NWB), 0, st, insts, blk, cf, cT);
 }
 
 template <typename S>
-void launch_lb(lbb_domain *d)
+void launch_lb(lbb_domain *d, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr)
 {
-    launch_lb<S>(d->stream, d->d_inst, d->d_blkA, d->nbxA * d->nbyA + 1, d->cf, d->cT);
+    launch_lb<S>(d->stream, d->d_inst, d->d_blkA, d->nbxA * d->nbyA + 1, d->cf, d->cT, ev0, ev1);
 }
 
 template <typename S>
-void launch_thermal(lbb_domain *d)
+void launch_thermal(lbb_domain *d, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr)
 {
-    launch_thermal<S>(d->stream, d->d_inst, d->d_blkB, d->nbxB * d->nbyB + 1, d->cf, d->cT);
+    launch_thermal<S>(d->stream, d->d_inst, d->d_blkB, d->nbxB * d->nbyB + 1, d->cf, d->cT, ev0, ev1);
 }
 
 void advance_buffers(lbb_domain *d)
@@ -394,7 +408,7 @@ void release(lbb_domain *d)
     for (void *q : {d->f[0], d->f[1], d->T[0], d->T[1], d->rho, d->vx, d->vy})
         if (q) (void)hipFree(q);
     for (void *q : {(void *)d->mass_part, (void *)d->hf_part, (void *)d->Tb_dev, (void *)d->sc,
-                    (void *)d->d_inst, (void *)d->d_blkA, (void *)d->d_blkB})
+                    (void *)d->d_inst, (void *)d->d_blkA, (void *)d->d_blkB, d->adj_mem})
         if (q) (void)hipFree(q);
     if (d->stream) (void)hipStreamDestroy(d->stream);
     delete d;
@@ -652,30 +666,32 @@ int lbb_time_kernels(lbb_domain *d, int64_t n, double *ms_lb, double *ms_thermal
     if (!d) return fail(LBB_EINVAL, "domain is NULL");
     if (n < 1) return fail(LBB_EINVAL, "n must be >= 1");
     if (d->poisoned) return fail(LBB_ESTATE, "domain poisoned by an earlier invalid state; load a state first");
-    std::vector<hipEvent_t> ev(3 * (size_t)n + 1, nullptr);
+    // per step: kernel start/end events of both launches, plus the ends of the run
+    std::vector<hipEvent_t> ev(4 * (size_t)n + 2, nullptr);
     for (auto &e : ev) LBB_HIP(hipEventCreate(&e));
     const bool fp64 = d->p.precision == LBB_FP64;
     LBB_HIP(hipEventRecord(ev[0], d->stream));
     for (int64_t k = 0; k < n; ++k) {
-        LBB_HIP(hipEventRecord(ev[3 * k + 1], d->stream));
-        if (fp64) launch_lb<double>(d); else launch_lb<float>(d);
-        LBB_HIP(hipEventRecord(ev[3 * k + 2], d->stream));
-        if (fp64) launch_thermal<double>(d); else launch_thermal<float>(d);
-        LBB_HIP(hipEventRecord(ev[3 * k + 3], d->stream));
+        hipEvent_t *e = &ev[4 * k + 1];
+        if (fp64) launch_lb<double>(d, e[0], e[1]); else launch_lb<float>(d, e[0], e[1]);
+        LBB_HIP(hipGetLastError());
+        if (fp64) launch_thermal<double>(d, e[2], e[3]); else launch_thermal<float>(d, e[2], e[3]);
+        LBB_HIP(hipGetLastError());
         advance_buffers(d);
     }
+    LBB_HIP(hipEventRecord(ev[4 * n + 1], d->stream));
     hipLaunchKernelGGL(lbb::k_flush_heat_flux, dim3(1), dim3(lbb::NT), 0, d->stream, d->d_inst);
     LBB_HIP(hipGetLastError());
     LBB_HIP(hipStreamSynchronize(d->stream));
     double a = 0, b = 0;
     float ms = 0;
     for (int64_t k = 0; k < n; ++k) {
-        LBB_HIP(hipEventElapsedTime(&ms, ev[3 * k + 1], ev[3 * k + 2]));
+        LBB_HIP(hipEventElapsedTime(&ms, ev[4 * k + 1], ev[4 * k + 2]));
         a += ms;
-        LBB_HIP(hipEventElapsedTime(&ms, ev[3 * k + 2], ev[3 * k + 3]));
+        LBB_HIP(hipEventElapsedTime(&ms, ev[4 * k + 3], ev[4 * k + 4]));
         b += ms;
     }
-    LBB_HIP(hipEventElapsedTime(&ms, ev[0], ev[3 * n]));
+    LBB_HIP(hipEventElapsedTime(&ms, ev[0], ev[4 * n + 1]));
     for (auto &e : ev) (void)hipEventDestroy(e);
     if (ms_lb) *ms_lb = a / (double)n;
     if (ms_thermal) *ms_thermal = b / (double)n;
@@ -1081,20 +1097,16 @@ extern "C" int lbb_batch_destroy(lbb_batch *b)
 
 namespace {
 
-struct DevBuf {
-    std::vector<void *> ptrs;
-    ~DevBuf()
-    {
-        for (void *q : ptrs) (void)hipFree(q);
-    }
+// Carves 256-byte aligned pieces out of one device allocation.
+struct Carver {
+    unsigned char *base;
+    size_t off = 0;
     template <typename T>
-    bool get(T **out, size_t n)
+    T *take(size_t n)
     {
-        void *q = nullptr;
-        if (hipMalloc(&q, n * sizeof(T)) != hipSuccess) return false;
-        ptrs.push_back(q);
-        *out = static_cast<T *>(q);
-        return hipMemset(q, 0, n * sizeof(T)) == hipSuccess;
+        T *p = reinterpret_cast<T *>(base ? base + off : nullptr);
+        off += (n * sizeof(T) + 255) & ~(size_t)255;
+        return p;
     }
 };
 
@@ -1105,34 +1117,54 @@ int adjoint_impl(lbb_domain *d, int64_t N, int64_t K, double *J, double *dJ_dTb,
     const size_t n = d->N, es = sizeof(S);
     const size_t state_bytes = 10 * n * es;  // f (9) and T
     const int64_t nck = (N + K - 1) / K;
-    DevBuf mem;
-    unsigned char *backup = nullptr, *ck = nullptr, *seg = nullptr;
-    Scalars *ck_sc = nullptr;
-    double *hf_backup = nullptr;
+    const dim3 ag((d->p.nx + AXB - 1) / AXB, (d->p.ny + AYB - 1) / AYB);
+    const int nb = (int)(ag.x * ag.y);
+    // workspace layout (a dry run with a null base sizes it)
+    unsigned char *backup, *ck, *seg;
+    Inst *inst_seg;  // step k of a segment: reads stored state k, writes state k+1
+    Scalars *ck_sc;
+    double *hf_backup, *lf[2], *lT[2];
     AdjW w{};
-    double *lf[2], *lT[2];
-    double *arrs[29];
-    bool ok = mem.get(&backup, state_bytes) && mem.get(&ck, (size_t)nck * state_bytes) &&
-              mem.get(&seg, (size_t)K * state_bytes) && mem.get(&ck_sc, (size_t)nck + 1) &&
-              mem.get(&hf_backup, (size_t)d->nbxB) && mem.get(&lf[0], 9 * n) && mem.get(&lf[1], 9 * n) &&
-              mem.get(&lT[0], n) && mem.get(&lT[1], n);
-    for (int k = 0; k < 29 && ok; ++k) ok = mem.get(&arrs[k], n);
-    const int nb = (int)((n + NTA - 1) / NTA);
-    ok = ok && mem.get(&w.part, 2 * (size_t)nb) && mem.get(&w.scal, 4);
-    if (!ok) return fail(LBB_ENOMEM, "adjoint work memory could not be allocated");
-    {
-        double **dst[] = {&w.rho, &w.jx, &w.jy, &w.psi, &w.sx, &w.sy, &w.Fx, &w.Fy, &w.Q, &w.vx, &w.vy, &w.vTx,
-                          &w.vTy, &w.Drx, &w.Dry, &w.divv, &w.gDrx, &w.gDry, &w.gdiv, &w.grho, &w.gvx, &w.gvy,
-                          &w.gFx, &w.gFy, &w.gQ, &w.gsx, &w.gsy, &w.gpsi};
-        for (int k = 0; k < 28; ++k) *dst[k] = arrs[k];
+    auto carve = [&](unsigned char *base) -> size_t {
+        Carver cv{base};
+        backup = cv.take<unsigned char>(state_bytes);
+        ck = cv.take<unsigned char>((size_t)nck * state_bytes);
+        seg = cv.take<unsigned char>((size_t)(K + 1) * state_bytes);
+        inst_seg = cv.take<Inst>((size_t)K);
+        ck_sc = cv.take<Scalars>((size_t)nck + 1);
+        hf_backup = cv.take<double>(d->nbxB);
+        for (int k = 0; k < 2; ++k) {
+            lf[k] = cv.take<double>(9 * n);
+            lT[k] = cv.take<double>(n);
+        }
+        double **arr[] = {&w.rho, &w.jx, &w.jy, &w.psi, &w.T1, &w.sx, &w.sy, &w.Fx, &w.Fy, &w.Q, &w.vx,
+                          &w.vy, &w.vTx, &w.vTy, &w.Drx, &w.Dry, &w.divv, &w.AX, &w.AY, &w.IA, &w.IB, &w.E1,
+                          &w.E2, &w.RI, &w.Tk[1], &w.Tk[2], &w.Tk[3], &w.gh[0], &w.gh[1], &w.gh[2], &w.gDrx,
+                          &w.gDry, &w.gdiv, &w.grho, &w.gvx, &w.gvy, &w.gpsi, &w.gsx, &w.gsy};
+        for (double **a : arr) *a = cv.take<double>(n);
+        w.Tk[0] = w.T1;
+        w.mpart = cv.take<double>(nb);
+        w.fpart = cv.take<double>(2 * (size_t)nb);
+        w.scal = cv.take<double>(4);
+        return cv.off;
+    };
+    const size_t need = carve(nullptr);
+    if (d->adj_bytes < need) {
+        if (d->adj_mem) {
+            (void)hipStreamSynchronize(d->stream);
+            (void)hipFree(d->adj_mem);
+            d->dev_bytes -= (int64_t)d->adj_bytes;
+            d->adj_mem = nullptr;
+            d->adj_bytes = 0;
+        }
+        if (hipMalloc(&d->adj_mem, need) != hipSuccess) {
+            d->adj_mem = nullptr;
+            return fail(LBB_ENOMEM, "adjoint work memory could not be allocated");
+        }
+        d->adj_bytes = need;
+        d->dev_bytes += (int64_t)need;
     }
-    double *tk = nullptr, *ghs = nullptr;
-    if (!mem.get(&tk, 4 * n) || !mem.get(&ghs, 4 * n)) return fail(LBB_ENOMEM, "adjoint work memory could not be allocated");
-    for (int k = 0; k < 4; ++k) {
-        w.Tk[k] = tk + k * n;
-        w.gh[k] = ghs + k * n;
-    }
-    (void)arrs[28];
+    carve(static_cast<unsigned char *>(d->adj_mem));
     hipStream_t st = d->stream;
     auto copy_state_out = [&](unsigned char *dst) -> hipError_t {
         hipError_t e = hipMemcpyAsync(dst, d->f[d->cf], 9 * n * es, hipMemcpyDeviceToDevice, st);
@@ -1150,19 +1182,42 @@ int adjoint_impl(lbb_domain *d, int64_t N, int64_t K, double *J, double *dJ_dTb,
     LBB_HIP(copy_state_out(backup));
     LBB_HIP(hipMemcpyAsync(&ck_sc[nck], d->sc, sizeof(Scalars), hipMemcpyDeviceToDevice, st));
     LBB_HIP(hipMemcpyAsync(hf_backup, d->hf_part, d->nbxB * sizeof(double), hipMemcpyDeviceToDevice, st));
-    // forward with the average restarted: J = q_sum / N afterwards
+    // launch tables of the stored-state steps, and the wall rows of T in every slot
+    std::vector<Inst> hinst(K);
+    for (int64_t k = 0; k < K; ++k) {
+        Inst I = make_inst(d);
+        S *a = reinterpret_cast<S *>(seg + (size_t)k * state_bytes), *b = reinterpret_cast<S *>(seg + (size_t)(k + 1) * state_bytes);
+        I.f[0] = a;
+        I.f[1] = b;
+        I.T[0] = a + 9 * n;
+        I.T[1] = b + 9 * n;
+        hinst[k] = I;
+    }
+    LBB_HIP(hipMemcpyAsync(inst_seg, hinst.data(), K * sizeof(Inst), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(a_bcast_T<S>, dim3(256), dim3(256), 0, st, static_cast<const S *>(d->T[d->cT]),
+                       reinterpret_cast<S *>(seg), n, (int)(K + 1));
+    auto slot_step = [&](int64_t k) {
+        launch_lb<S>(st, inst_seg + k, d->d_blkA, d->nbxA * d->nbyA + 1, 0, 0);
+        launch_thermal<S>(st, inst_seg + k, d->d_blkB, d->nbxB * d->nbyB + 1, 0, 0);
+    };
+    auto slot_f = [&](int64_t k) { return reinterpret_cast<const S *>(seg + (size_t)k * state_bytes); };
+    // forward with the average restarted: J = q_sum / N afterwards.  States
+    // of the last segment go straight into the slots (no recompute later).
     Scalars s0;
     LBB_HIP(hipMemcpyAsync(&s0, d->sc, sizeof s0, hipMemcpyDeviceToHost, st));
     LBB_HIP(hipStreamSynchronize(st));
     s0.q_sum = 0.0;
     s0.n_samples = 0;
     LBB_HIP(hipMemcpyAsync(d->sc, &s0, sizeof s0, hipMemcpyHostToDevice, st));
+    const int64_t tL = (nck - 1) * K;
     for (int64_t t = 0; t < N; ++t) {
         if (t % K == 0) {
-            LBB_HIP(copy_state_out(ck + (size_t)(t / K) * state_bytes));
+            LBB_HIP(copy_state_out(t < tL ? ck + (size_t)(t / K) * state_bytes : seg));
             LBB_HIP(hipMemcpyAsync(&ck_sc[t / K], d->sc, sizeof(Scalars), hipMemcpyDeviceToDevice, st));
         }
-        enqueue_step<S>(d);
+        if (t < tL) enqueue_step<S>(d);
+        else slot_step(t - tL);
+        LBB_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_flush_heat_flux, dim3(1), dim3(NT), 0, st, d->d_inst);
     int rc = check_errors(d);
@@ -1172,36 +1227,45 @@ int adjoint_impl(lbb_domain *d, int64_t N, int64_t K, double *J, double *dJ_dTb,
     LBB_HIP(hipStreamSynchronize(st));
     *J = s1.q_sum / (double)N;
 
-    // reverse sweep
+    // reverse sweep: the adjoint of the final state starts from its heat-flux sample
     const DevParams P = d->dp;
     const double wq = 1.0 / (double)N;
-    const unsigned nbx_hf = (unsigned)((d->p.nx + 255) / 256);
-    hipLaunchKernelGGL(a_hf<S>, dim3(nbx_hf), dim3(256), 0, st, P, static_cast<const S *>(d->f[d->cf]),
-                       static_cast<const S *>(d->T[d->cT]), wq, lf[1], lT[1]);
-    const double cst[4] = {0.0, 0.5, 0.5, 1.0};
+    LBB_HIP(hipMemsetAsync(lf[1], 0, 9 * n * sizeof(double), st));
+    LBB_HIP(hipMemsetAsync(lT[1], 0, n * sizeof(double), st));
+    LBB_HIP(hipMemsetAsync(w.scal, 0, 4 * sizeof(double), st));
+    {
+        const S *fN = slot_f(N - tL);
+        hipLaunchKernelGGL(a_hf<S>, dim3((d->p.nx + 255) / 256, 3), dim3(256), 0, st, P, fN, fN + 9 * n, wq, lf[1],
+                           lT[1]);
+    }
     for (int64_t sg = nck - 1; sg >= 0; --sg) {
         const int64_t t0 = sg * K, t1 = (t0 + K < N) ? t0 + K : N;
-        LBB_HIP(copy_state_in(ck + (size_t)sg * state_bytes));
-        LBB_HIP(hipMemcpyAsync(d->sc, &ck_sc[sg], sizeof(Scalars), hipMemcpyDeviceToDevice, st));
-        for (int64_t t = t0; t < t1; ++t) {
-            LBB_HIP(copy_state_out(seg + (size_t)(t - t0) * state_bytes));
-            if (t + 1 < t1) enqueue_step<S>(d);
+        if (sg < nck - 1) {
+            // recompute the segment's states from its checkpoint into the slots
+            LBB_HIP(hipMemcpyAsync(seg, ck + (size_t)sg * state_bytes, state_bytes, hipMemcpyDeviceToDevice, st));
+            LBB_HIP(hipMemcpyAsync(d->sc, &ck_sc[sg], sizeof(Scalars), hipMemcpyDeviceToDevice, st));
+            for (int64_t t = t0; t + 1 < t1; ++t) slot_step(t - t0);
+        }
+        {
+            const S *fs = slot_f(t1 - 1 - t0);
+            hipLaunchKernelGGL(a_macro<S>, ag, dim3(NTA), 0, st, P, fs, fs + 9 * n, w);
         }
         for (int64_t t = t1 - 1; t >= t0; --t) {
-            const S *fs = reinterpret_cast<const S *>(seg + (size_t)(t - t0) * state_bytes);
+            const S *fs = slot_f(t - t0);
             const S *Ts = fs + 9 * n;
-            hipLaunchKernelGGL(a_macro<S>, dim3(nb), dim3(NTA), 0, st, P, fs, Ts, w);
-            hipLaunchKernelGGL(a_reduce_mass, dim3(1), dim3(NTA), 0, st, P, w, nb);
-            hipLaunchKernelGGL(a_force, dim3(nb), dim3(NTA), 0, st, P, w);
-            hipLaunchKernelGGL(a_divv, dim3(nb), dim3(NTA), 0, st, P, w);
-            for (int k = 0; k < 3; ++k) hipLaunchKernelGGL(a_stage, dim3(nb), dim3(NTA), 0, st, P, w, k, cst[k + 1]);
-            hipLaunchKernelGGL(a_tinit, dim3(nb), dim3(NTA), 0, st, P, w, lT[1], lT[0]);
-            for (int k = 3; k >= 0; --k) hipLaunchKernelGGL(a_tstage, dim3(nb), dim3(NTA), 0, st, P, w, k, cst[k], lT[0]);
-            hipLaunchKernelGGL(a_tstencil, dim3(nb), dim3(NTA), 0, st, P, w);
-            hipLaunchKernelGGL(a_lb<S>, dim3(nb), dim3(NTA), 0, st, P, w, fs, lf[1], lf[0]);
-            hipLaunchKernelGGL(a_reduce_force, dim3(1), dim3(NTA), 0, st, w, nb);
-            hipLaunchKernelGGL(a_final<S>, dim3(nb), dim3(NTA), 0, st, P, w, Ts, lf[0], lT[0]);
-            if (t >= 1) hipLaunchKernelGGL(a_hf<S>, dim3(nbx_hf), dim3(256), 0, st, P, fs, Ts, wq, lf[0], lT[0]);
+            const S *fp = t > t0 ? slot_f(t - 1 - t0) : nullptr;
+            const S *Tp = fp ? fp + 9 * n : nullptr;
+            hipLaunchKernelGGL(a_force, ag, dim3(NTA), 0, st, P, w, nb);
+            hipLaunchKernelGGL(a_divv0, ag, dim3(NTA), 0, st, P, w);
+            hipLaunchKernelGGL(a_stage, ag, dim3(NTA), 0, st, P, w, 1, 0.5);
+            hipLaunchKernelGGL(a_stage, ag, dim3(NTA), 0, st, P, w, 2, 1.0);
+            hipLaunchKernelGGL(a_tstage, ag, dim3(NTA), 0, st, P, w, 3, 1.0, lT[1], lT[0]);
+            hipLaunchKernelGGL(a_tstage, ag, dim3(NTA), 0, st, P, w, 2, 0.5, lT[1], lT[0]);
+            hipLaunchKernelGGL(a_tstage, ag, dim3(NTA), 0, st, P, w, 1, 0.5, lT[1], lT[0]);
+            hipLaunchKernelGGL(a_tstage, ag, dim3(NTA), 0, st, P, w, 0, 0.0, lT[1], lT[0]);
+            hipLaunchKernelGGL(a_lb<S>, ag, dim3(NTA), 0, st, P, w, fs, lf[1], lf[0]);
+            hipLaunchKernelGGL(a_final<S>, ag, dim3(NTA), 0, st, P, w, fs, Ts, t >= 1 ? wq : 0.0, fp, Tp, nb, lf[0],
+                               lT[0]);
             std::swap(lf[0], lf[1]);
             std::swap(lT[0], lT[1]);
         }
