@@ -27,11 +27,30 @@ ALG_BYTES_STEP = {"f32": 80, "f64": 160}
 # The LB launch's share of it: the nine populations read and written.
 ALG_BYTES_LB = {"f32": 72, "f64": 144}
 
-# HBM traffic of the LB launch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
-# (KiB per dispatch, scaled by the same counters on a plain copy kernel), taken
-# on the kernel sources whose hash is recorded here; reported as null once the
-# sources change.
-MEASURED_TRAFFIC = None
+# HBM traffic of the LB launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
+# (KiB per dispatch, mean over the dispatches of a --profile run), each scaled
+# by what the same counter reads for an elementwise kernel that reads 1 GiB
+# and writes 1 GiB (FETCH_SIZE 524296 KiB -> factor 2.0, WRITE_SIZE 1048576
+# KiB -> factor 1.0).  Valid for the kernel sources whose hash is recorded;
+# reported as null once the sources change.
+MEASURED_TRAFFIC = {
+    "source_hash": "8720d6075d3cad7b",
+    "fetch_factor": 1048576.0 / 524296.2,
+    "write_factor": 1048576.0 / 1048576.0,
+    "k_lb": {
+        "large_1024x512_fp32": {"fetch_kib": 10833.2, "write_kib": 24628.5},
+        "large_4096x2048_fp32": {"fetch_kib": 179043.7, "write_kib": 394597.5},
+    },
+}
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per LB launch from the recorded counters, or None."""
+    m = MEASURED_TRAFFIC
+    if not m or m.get("source_hash") != source_hash() or workload not in m["k_lb"]:
+        return None
+    c = m["k_lb"][workload]
+    return int(round((c["fetch_kib"] * m["fetch_factor"] + c["write_kib"] * m["write_factor"]) * 1024))
 
 
 def source_hash() -> str:
@@ -153,6 +172,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=100, help="oracle steps for the CPU baseline (0: skip)")
     ap.add_argument("--sweep-steps", type=int, default=2000, help="steps of the 48-lattice sweep comparison (0: skip)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost measurement")
+    ap.add_argument("--adjoint-only", action="store_true", help="only the adjoint/forward cost measurement (profiling)")
     ap.add_argument("--profile", action="store_true", help="timed region only (for rocprofv3 runs)")
     ap.add_argument("--copy-probe", action="store_true", help="run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -175,6 +195,10 @@ def main():
             torch.neg(a, out=b)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "launches": 5}))
+        return
+
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": adjoint_bench()}), flush=True)
         return
 
     from paper_1501_03857_amd import lbboil as L
@@ -215,10 +239,7 @@ def main():
 
     ms_lb, ms_th, ms_seq = d.time_kernels(args.kernel_steps)
     achieved = ALG_BYTES_LB[store] * cells / (ms_lb * 1e-3) / 1e9
-    traffic = None
-    if MEASURED_TRAFFIC and MEASURED_TRAFFIC.get("source_hash") == source_hash() \
-            and MEASURED_TRAFFIC.get("workload") == w.name:
-        traffic = MEASURED_TRAFFIC["bytes_per_launch"]
+    traffic = measured_traffic(w.name)
     step_bytes = ALG_BYTES_STEP[store] * cells
     sweep = sweep_bench(args.sweep_steps) if args.sweep_steps > 0 else None
     if sweep:
@@ -247,6 +268,8 @@ def main():
                    "parallelism": "none", "launches_per_step": 2, "graph_steps": 32},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_unit": "bytes per launch",
+                     "traffic_gbs": None if traffic is None else round(traffic / (ms_lb * 1e-3) / 1e9, 1),
                      "kernel": "k_lb", "kernel_ms": round(ms_lb, 6),
                      "alg_bytes_per_update": ALG_BYTES_LB[store]},
         "step_roofline": {"achieved": round(step_bytes / (ms_step * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
