@@ -17,6 +17,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -162,6 +164,51 @@ def adjoint_bench():
     return out
 
 
+def batch_adjoint_bench(steps=600):
+    """Batched adjoint: 16 lattices of 384x192 (FP32), 600 steps, checkpoint
+    interval chosen by the library.  Forward = the same 600 steps of the batch
+    (graph replays); adjoint = one lbb_batch_adjoint call; device memory as
+    the library's own count and the drop of hipMemGetInfo's free bytes."""
+    import torch
+    from paper_1501_03857_amd import lbboil as L
+    from paper_1501_03857_amd import workloads as WL
+
+    ws = WL.batch_adjoint_workloads(steps)
+    params, tbs, rhos = [], [], []
+    for w in ws:
+        Tc, _ = L.eos_constants(w.a, w.b, w.R, w.omega)
+        rv, rl = L.coexistence(w.a, w.b, w.R, w.omega, w.Ts_over_Tc * Tc)
+        params.append(L.Params(nx=w.nx, ny=w.ny, precision=L.FP32, liquid_rows=w.liquid_rows, a=w.a, b=w.b,
+                               R=w.R, omega=w.omega, Ts_over_Tc=w.Ts_over_Tc, sigma=w.sigma, g=w.g,
+                               Gw_bottom=w.Gw_bottom, rho_L=rl, rho_V=rv))
+        tbs.append(w.heater_T(Tc))
+        rhos.append(w.density(rl, rv))
+    b = L.Batch(params, tbs, rhos)
+    b.step(64)  # graph instantiation and first launches
+    free0 = torch.cuda.mem_get_info()[0]
+    blob = [b.domain(i).save() for i in range(len(ws))]
+    t0 = time.perf_counter()
+    b.step(steps)
+    fwd = time.perf_counter() - t0
+    for i, x in enumerate(blob):
+        b.domain(i).load(x)
+    t0 = time.perf_counter()
+    J, g, gw = b.adjoint(steps, 0)
+    first = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    J2, g2, gw2 = b.adjoint(steps, 0)
+    adj = time.perf_counter() - t0
+    free1 = torch.cuda.mem_get_info()[0]
+    dev = b.device_bytes()
+    b.close()
+    return {"instances": len(ws), "nx": 384, "ny": 192, "storage": "f32", "steps": steps, "K": "auto",
+            "forward_ms": round(fwd * 1e3, 3), "adjoint_ms": round(adj * 1e3, 3),
+            "adjoint_first_call_ms": round(first * 1e3, 3), "ratio": round(adj / fwd, 2),
+            "repeat_bitwise": bool(np.array_equal(J, J2) and all(np.array_equal(a, c) for a, c in zip(g, g2))),
+            "J_range": [float(J.min()), float(J.max())], "dJ_dGw_range": [float(gw.min()), float(gw.max())],
+            "library_device_bytes": int(dev), "hip_free_bytes_drop": int(free0 - free1)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,7 +245,7 @@ def main():
         return
 
     if args.adjoint_only:
-        print(json.dumps({"adjoint": adjoint_bench()}), flush=True)
+        print(json.dumps({"adjoint": adjoint_bench(), "batch_adjoint": batch_adjoint_bench()}), flush=True)
         return
 
     from paper_1501_03857_amd import lbboil as L
@@ -246,9 +293,10 @@ def main():
         print(f"[bench] sweep: batched {sweep['batched_mlups']} MLUPS vs sequential {sweep['plain_sequential_mlups']} "
               f"MLUPS ({sweep['speedup']}x)", file=sys.stderr, flush=True)
     adj = None if args.no_adjoint else adjoint_bench()
+    badj = None if args.no_adjoint else batch_adjoint_bench()
     if adj:
-        print(f"[bench] adjoint/forward: f64 {adj['f64']['ratio']}x, f32 {adj['f32']['ratio']}x",
-              file=sys.stderr, flush=True)
+        print(f"[bench] adjoint/forward: f64 {adj['f64']['ratio']}x, f32 {adj['f32']['ratio']}x; "
+              f"batch of {badj['instances']}: {badj['ratio']}x", file=sys.stderr, flush=True)
     cpu = cpu_baseline(w, args.cpu_steps) if args.cpu_steps > 0 else None
 
     line = {
@@ -279,6 +327,7 @@ def main():
         "heat_flux_mean": hf["q_mean"],
         "batched_sweep": sweep,
         "adjoint": adj,
+        "batch_adjoint": badj,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -202,12 +202,29 @@ int lbb_batch_destroy(lbb_batch *b);
  * respect to the bottom-wall temperatures T_b(x) (all nx nodes, FP64 [nx])
  * and the bottom wall strength G_w (Eq. (22)), by a hand-written discrete
  * adjoint of the whole coupled step (FP64 arithmetic, FP64 adjoint fields).
- * States are checkpointed every K steps (K <= 0: K = min(N, 50)) and each
- * segment is recomputed before its reverse sweep.  The domain's state, step
- * count and heat-flux average are restored afterwards.  Device memory:
- * about (N/K + K) * 10 * nx*ny * sizeof(real) + 75 * nx*ny * 8 bytes.
- * EUNSUPPORTED for periodic_y or a test mode; EINVAL for N < 1. */
+ * J is required; dJ_dTb and dJ_dGw may be NULL.  States are checkpointed
+ * every K steps and each segment but the last is recomputed before its
+ * reverse sweep.  K <= 0 lets the library choose: every state kept (K = N,
+ * no recompute) when N + 2 states take at most a quarter of the free device
+ * memory, else K = ceil(sqrt(N)).  The domain's state, step count and
+ * heat-flux average are restored afterwards.  Device memory, allocated on
+ * the first call and kept by the domain (reported by lbb_info): about
+ * (N/K + K + 2) * 10 * nx*ny * sizeof(real) + 55 * nx*ny * 8 bytes.
+ * EUNSUPPORTED for periodic_y or a test mode; EINVAL for N < 1; ENOMEM when
+ * the workspace cannot be allocated. */
 int lbb_adjoint(lbb_domain *d, int64_t N, int64_t K, double *J, double *dJ_dTb, double *dJ_dGw);
+
+/* The adjoint of every batch member at once (the same N and K for all),
+ * each lattice's forward, recompute and reverse steps sharing the batch's
+ * launches.  Outputs: J[n], dJ_dTb[sum of the members' nx] (member after
+ * member), dJ_dGw[n]; J required, the others may be NULL.  Results equal
+ * lbb_adjoint on each member alone.  Members are restored and left in phase;
+ * EINVAL if the members are out of phase, the member's error code (with its
+ * index in the message) if one cannot be differentiated. */
+int lbb_batch_adjoint(lbb_batch *b, int64_t N, int64_t K, double *J, double *dJ_dTb, double *dJ_dGw);
+
+/* Device bytes held by the batch: its members and its adjoint workspace. */
+int lbb_batch_info(lbb_batch *b, int64_t *device_bytes);
 
 /* Current step count, grid shape and device bytes held by the domain. */
 int lbb_info(lbb_domain *d, int64_t *t, int32_t *nx, int32_t *ny, int64_t *device_bytes);

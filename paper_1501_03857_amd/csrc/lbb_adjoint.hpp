@@ -3,8 +3,9 @@
 // bottom-wall temperatures T_b(x) (Sec. 3.1) and the wall strength G_w
 // (Eq. (22)).  One reverse step transposes the forward step of
 // lbb_device.hpp stage by stage, in reverse order, over whole-lattice FP64
-// work arrays.  Each block covers a 64 x 4 patch of nodes (lane = column,
-// wave = row), so no thread divides to find its node.  Ten launches per
+// work arrays.  A launch covers any number of lattices through a lattice
+// table (one lattice, or every member of a batch); each block covers a
+// 64 x 4 patch of one lattice (lane = column, wave = row).  Ten launches per
 // reverse step of state t -> t+1:
 //   a_force    forces (Eqs. (7), (9), (22)), Q, velocity (Eq. (6)), grad rho;
 //              rho_ave from the mass partials of the state
@@ -53,13 +54,43 @@ struct AdjW {
     double *scal;    // [2] dJ/dG_w, accumulated over the steps
 };
 
+// One lattice of an adjoint launch: its parameters, work arrays, stored
+// states and adjoint buffers, and its place in the launch grid.  A launch
+// covers any number of lattices; a block finds its lattice through a block ->
+// lattice table and its 64 x 4 patch from its index within the lattice.
+struct AdjInst {
+    DevParams P;
+    AdjW w;
+    const void *seg;          // stored states of the segment: slot k at 10 k nx ny elements
+    double *lf[2], *lT[2];    // adjoints of f and T: [cur] the later state, [cur ^ 1] the earlier
+    int gx;                   // patches per lattice row
+    int blk0;                 // first block of this lattice in the grid
+    int nb;                   // blocks of this lattice
+};
+
+#define A_INST                                            \
+    const AdjInst &I = ai[amap[blockIdx.x]];              \
+    const DevParams P = I.P;                              \
+    const AdjW &w = I.w;                                  \
+    const int q = (int)blockIdx.x - I.blk0;               \
+    (void)w;
+
 #define A_NODE                                                 \
-    const int gi = blockIdx.x * AXB + (threadIdx.x & 63);      \
-    const int gj = blockIdx.y * AYB + (threadIdx.x >> 6);      \
+    const int gi = (q % I.gx) * AXB + (threadIdx.x & 63);      \
+    const int gj = (q / I.gx) * AYB + (threadIdx.x >> 6);      \
     const bool on = gi < P.nx && gj < P.ny;                    \
     const size_t N = (size_t)P.nx * P.ny;                      \
     const size_t c = (size_t)gj * P.nx + gi;                   \
     (void)N;
+
+// stored state k of lattice I (populations; T follows at 9 nx ny)
+template <typename S>
+__device__ __forceinline__ const S *a_slot(const AdjInst &I, int k)
+{
+    return static_cast<const S *>(I.seg) + (size_t)k * 10 * (size_t)I.P.nx * I.P.ny;
+}
+
+#define A_ARGS const AdjInst *__restrict__ ai, const int *__restrict__ amap
 
 __device__ __forceinline__ bool a_int(const DevParams &P, int j) { return j > 0 && j < P.ny - 1; }
 
@@ -159,19 +190,22 @@ __device__ __forceinline__ double a_macro_node(const DevParams &P, const S *__re
 }
 
 template <typename S>
-__global__ __launch_bounds__(NTA) void a_macro(DevParams P, const S *__restrict__ f, const S *__restrict__ T, AdjW w)
+__global__ __launch_bounds__(NTA) void a_macro(A_ARGS, int k)
 {
     __shared__ double red[NTA / 64];
+    A_INST
     A_NODE
-    const double m = on ? a_macro_node(P, f, T, N, c, gj, w) : 0.0;
+    const S *f = a_slot<S>(I, k);
+    const double m = on ? a_macro_node(P, f, f + 9 * N, N, c, gj, w) : 0.0;
     const double s = block_sum<NTA>(m, red);
-    if (threadIdx.x == 0) w.mpart[blockIdx.y * gridDim.x + blockIdx.x] = s;
+    if (threadIdx.x == 0) w.mpart[q] = s;
 }
 
-__global__ __launch_bounds__(NTA) void a_force(DevParams P, AdjW w, int nbm)
+__global__ __launch_bounds__(NTA) void a_force(A_ARGS)
 {
     __shared__ double red[NTA / 64 + 1];
-    const double rho_ave = block_sum_all(w.mpart, nbm, 1, 0, red) / ((double)P.nx * (double)P.ny);
+    A_INST
+    const double rho_ave = block_sum_all(w.mpart, I.nb, 1, 0, red) / ((double)P.nx * (double)P.ny);
     A_NODE
     if (!on) return;
     double sx = 0.0, sy = 0.0, Fx = 0.0, Fy = 0.0, Q = 0.0, rx = 0.0, ry = 0.0;
@@ -229,8 +263,9 @@ __device__ __forceinline__ double a_K(const DevParams &P, const AdjW &w, const d
 }
 
 // div v, the coefficients of Eq. (18), and T_2 = T_1 + K(T_1)/2
-__global__ __launch_bounds__(NTA) void a_divv0(DevParams P, AdjW w)
+__global__ __launch_bounds__(NTA) void a_divv0(A_ARGS)
 {
+    A_INST
     A_NODE
     if (!on) return;
     if (!a_int(P, gj)) {
@@ -263,8 +298,9 @@ __global__ __launch_bounds__(NTA) void a_divv0(DevParams P, AdjW w)
 }
 
 // T_{k+1} = T_1 + c_k K(T_k) on interior rows (T_1 on wall rows)
-__global__ __launch_bounds__(NTA) void a_stage(DevParams P, AdjW w, int k, double ck)
+__global__ __launch_bounds__(NTA) void a_stage(A_ARGS, int k, double ck)
 {
+    A_INST
     A_NODE
     if (!on) return;
     double h = 0.0;
@@ -282,10 +318,12 @@ __global__ __launch_bounds__(NTA) void a_stage(DevParams P, AdjW w, int k, doubl
 // weights w = (1, 2, 2, 1)), and adds it to the adjoint of T^t, which starts
 // from lT^{t+1} (identity part).  The last stage's slope adjoint is
 // lT^{t+1}/6 on interior nodes.
-__global__ __launch_bounds__(NTA) void a_tstage(DevParams P, AdjW w, int k, double ck, const double *__restrict__ lT1,
-                                                double *__restrict__ lT0)
+__global__ __launch_bounds__(NTA) void a_tstage(A_ARGS, int k, double ck, int cur)
 {
+    A_INST
     A_NODE
+    const double *__restrict__ lT1 = I.lT[cur];
+    double *__restrict__ lT0 = I.lT[cur ^ 1];
     if (!on) return;
     const double *Tf = w.Tk[k];
     const double *gk = k < 3 ? w.gh[k] : lT1;
@@ -340,11 +378,14 @@ __global__ __launch_bounds__(NTA) void a_tstage(DevParams P, AdjW w, int k, doub
 // transposed at node c; writes the adjoint of the completed populations
 // (before the density and completion parts), and the per-node force adjoints.
 template <typename S>
-__global__ __launch_bounds__(NTA) void a_lb(DevParams P, AdjW w, const S *__restrict__ f,
-                                            const double *__restrict__ lf1, double *__restrict__ lf0)
+__global__ __launch_bounds__(NTA) void a_lb(A_ARGS, int k, int cur)
 {
     __shared__ double red[NTA / 64];
+    A_INST
     A_NODE
+    const S *__restrict__ f = a_slot<S>(I, k);
+    const double *__restrict__ lf1 = I.lf[cur];
+    double *__restrict__ lf0 = I.lf[cur ^ 1];
     double pr = 0.0, pg = 0.0;
     if (on) {
         const bool in = a_int(P, gj);
@@ -473,13 +514,12 @@ __global__ __launch_bounds__(NTA) void a_lb(DevParams P, AdjW w, const S *__rest
         w.gsx[c] = gsx;
         w.gsy[c] = gsy;
     }
-    const int blk = blockIdx.y * gridDim.x + blockIdx.x;
     const double sr = block_sum<NTA>(pr, red);
     __syncthreads();
     const double sg = block_sum<NTA>(pg, red);
     if (threadIdx.x == 0) {
-        w.fpart[2 * blk] = sr;
-        w.fpart[2 * blk + 1] = sg;
+        w.fpart[2 * q] = sr;
+        w.fpart[2 * q + 1] = sg;
     }
 }
 
@@ -511,18 +551,22 @@ __device__ __forceinline__ void hf_source(const DevParams &P, const S *__restric
 // source of state t (when it is a sample, wq > 0), and rho, j, psi of the
 // state before (fp, Tp when given) with its mass partials.
 template <typename S>
-__global__ __launch_bounds__(NTA) void a_final(DevParams P, AdjW w, const S *__restrict__ f, const S *__restrict__ T,
-                                               double wq, const S *__restrict__ fp, const S *__restrict__ Tp,
-                                               int nbf, double *__restrict__ lf0, double *__restrict__ lT0)
+__global__ __launch_bounds__(NTA) void a_final(A_ARGS, int k, int cur, double wq, int prev)
 {
     __shared__ double red[NTA / 64 + 1];
-    const double sr = block_sum_all(w.fpart, nbf, 2, 0, red);
-    const int blk = blockIdx.y * gridDim.x + blockIdx.x;
-    if (blk == 0) {
-        const double sg = block_sum_all(w.fpart, nbf, 2, 1, red);
+    A_INST
+    const double sr = block_sum_all(w.fpart, I.nb, 2, 0, red);
+    if (q == 0) {
+        const double sg = block_sum_all(w.fpart, I.nb, 2, 1, red);
         if (threadIdx.x == 0) w.scal[2] += sg;
     }
     A_NODE
+    const S *__restrict__ f = a_slot<S>(I, k);
+    const S *__restrict__ T = f + 9 * N;
+    const S *__restrict__ fp = prev ? a_slot<S>(I, k - 1) : nullptr;
+    const S *__restrict__ Tp = prev ? fp + 9 * N : nullptr;
+    double *__restrict__ lf0 = I.lf[cur ^ 1];
+    double *__restrict__ lT0 = I.lT[cur ^ 1];
     double m = 0.0;
     if (on) {
         double gpsi = w.gpsi[c];
@@ -558,9 +602,9 @@ __global__ __launch_bounds__(NTA) void a_final(DevParams P, AdjW w, const S *__r
         // this thread's reads of the state-t values at c are done
         if (fp) m = a_macro_node(P, fp, Tp, N, c, gj, w);
     }
-    if (fp) {
+    if (prev) {
         const double s = block_sum<NTA>(m, red);
-        if (threadIdx.x == 0) w.mpart[blk] = s;
+        if (threadIdx.x == 0) w.mpart[q] = s;
     }
 }
 
@@ -577,21 +621,20 @@ __global__ void a_bcast_T(const S *__restrict__ T, S *__restrict__ seg, size_t n
     }
 }
 
-// The heat-flux sample of a state transposed, weight wq, added to the
-// adjoint of that state.  One thread per node of rows 0..2 (blockIdx.y = row).
+// The heat-flux sample of stored state k transposed, weight wq, added to the
+// adjoint [cur] of that state (nodes of rows 0..2 act).
 template <typename S>
-__global__ void a_hf(DevParams P, const S *__restrict__ f, const S *__restrict__ T, double wq,
-                     double *__restrict__ lf, double *__restrict__ lT)
+__global__ __launch_bounds__(NTA) void a_hf(A_ARGS, int k, double wq, int cur)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
-    if (i >= P.nx || j > 2) return;
-    const size_t N = (size_t)P.nx * P.ny;
+    A_INST
+    A_NODE
+    if (!on || gj > 2) return;
+    const S *f = a_slot<S>(I, k);
     double gpop[9], gtem;
-    hf_source(P, f, T, wq, N, i, j, gpop, gtem);
-    const size_t c = (size_t)j * P.nx + i;
-    if (j == 0)
-        for (int a = 0; a < 9; ++a) lf[(size_t)a * N + c] += gpop[a];
-    lT[c] += gtem;
+    hf_source(P, f, f + 9 * N, wq, N, gi, gj, gpop, gtem);
+    if (gj == 0)
+        for (int a = 0; a < 9; ++a) I.lf[cur][(size_t)a * N + c] += gpop[a];
+    I.lT[cur][c] += gtem;
 }
 
 }  // namespace lbb

@@ -900,6 +900,8 @@ struct lbb_batch {
     int cf = 0, cT = 0;
     int precision = 0, mode = 0;
     hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    void *adj_mem = nullptr;             // adjoint workspace, kept between calls
+    size_t adj_bytes = 0;
 };
 
 static void batch_release(lbb_batch *b)
@@ -908,7 +910,7 @@ static void batch_release(lbb_batch *b)
     for (auto &row : b->graph)
         for (auto &g : row)
             if (g) (void)hipGraphExecDestroy(g);
-    for (void *q : {(void *)b->d_insts, (void *)b->d_blkA, (void *)b->d_blkB})
+    for (void *q : {(void *)b->d_insts, (void *)b->d_blkA, (void *)b->d_blkB, b->adj_mem})
         if (q) (void)hipFree(q);
     if (b->stream) (void)hipStreamDestroy(b->stream);
     for (lbb_domain *d : b->doms) release(d);
@@ -1110,181 +1112,296 @@ struct Carver {
     }
 };
 
+// The lattices of one adjoint run (a domain, or the members of a batch) and
+// the forward launch tables that step them together on their own buffers.
+struct AdjGroup {
+    std::vector<lbb_domain *> doms;
+    hipStream_t st = nullptr;
+    const lbb::Inst *fwd_insts = nullptr;
+    const int *blkA = nullptr, *blkB = nullptr;
+    int totA = 0, totB = 0;
+    std::vector<int> blkA0, blkB0;  // member offsets in the forward grids
+    int *cf = nullptr, *cT = nullptr;
+    void **mem = nullptr;           // cached workspace of the owner
+    size_t *bytes = nullptr;
+};
+
+// Per-lattice pieces of the workspace.
+struct AdjMember {
+    unsigned char *backup, *ck, *seg;
+    lbb::Scalars *ck_sc;
+    double *hf_backup, *lf[2], *lT[2];
+    lbb::AdjW w;
+    int gx, nb;
+    size_t n, state_bytes;
+};
+
+// Checkpoint interval when the caller leaves it open (K <= 0): every state
+// kept (no recompute) when N + 2 stored states of all lattices take at most a
+// quarter of the free device memory, else sqrt(N).
+int64_t auto_K(const AdjGroup &g, int64_t N, size_t es)
+{
+    size_t per_state = 0;
+    for (lbb_domain *d : g.doms) per_state += 10 * d->N * es;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
+    if ((double)(N + 2) * (double)per_state <= 0.25 * (double)free_b) return N;
+    int64_t K = (int64_t)std::ceil(std::sqrt((double)N));
+    return K < 1 ? 1 : K;
+}
+
 template <typename S>
-int adjoint_impl(lbb_domain *d, int64_t N, int64_t K, double *J, double *dJ_dTb, double *dJ_dGw)
+int adjoint_run(AdjGroup &g, int64_t N, int64_t K, double *J, double *dJ_dTb, double *dJ_dGw)
 {
     using namespace lbb;
-    const size_t n = d->N, es = sizeof(S);
-    const size_t state_bytes = 10 * n * es;  // f (9) and T
+    const int nm = (int)g.doms.size();
+    const size_t es = sizeof(S);
     const int64_t nck = (N + K - 1) / K;
-    const dim3 ag((d->p.nx + AXB - 1) / AXB, (d->p.ny + AYB - 1) / AYB);
-    const int nb = (int)(ag.x * ag.y);
-    // workspace layout (a dry run with a null base sizes it)
-    unsigned char *backup, *ck, *seg;
-    Inst *inst_seg;  // step k of a segment: reads stored state k, writes state k+1
-    Scalars *ck_sc;
-    double *hf_backup, *lf[2], *lT[2];
-    AdjW w{};
+    hipStream_t st = g.st;
+    std::vector<AdjMember> m(nm);
+    Inst *inst_seg = nullptr;  // [K][nm]: step k of a segment reads stored state k, writes k+1
+    AdjInst *d_ai = nullptr;
+    int *d_amap = nullptr;
+    int tot = 0;
+    for (int i = 0; i < nm; ++i) {
+        const lbb_domain *d = g.doms[i];
+        m[i].n = d->N;
+        m[i].state_bytes = 10 * d->N * es;
+        m[i].gx = (d->p.nx + AXB - 1) / AXB;
+        m[i].nb = m[i].gx * ((d->p.ny + AYB - 1) / AYB);
+        tot += m[i].nb;
+    }
     auto carve = [&](unsigned char *base) -> size_t {
         Carver cv{base};
-        backup = cv.take<unsigned char>(state_bytes);
-        ck = cv.take<unsigned char>((size_t)nck * state_bytes);
-        seg = cv.take<unsigned char>((size_t)(K + 1) * state_bytes);
-        inst_seg = cv.take<Inst>((size_t)K);
-        ck_sc = cv.take<Scalars>((size_t)nck + 1);
-        hf_backup = cv.take<double>(d->nbxB);
-        for (int k = 0; k < 2; ++k) {
-            lf[k] = cv.take<double>(9 * n);
-            lT[k] = cv.take<double>(n);
+        for (int i = 0; i < nm; ++i) {
+            AdjMember &a = m[i];
+            const size_t n = a.n;
+            a.backup = cv.take<unsigned char>(a.state_bytes);
+            a.ck = cv.take<unsigned char>((size_t)nck * a.state_bytes);
+            a.seg = cv.take<unsigned char>((size_t)(K + 1) * a.state_bytes);
+            a.ck_sc = cv.take<Scalars>((size_t)nck + 1);
+            a.hf_backup = cv.take<double>(g.doms[i]->nbxB);
+            for (int k = 0; k < 2; ++k) {
+                a.lf[k] = cv.take<double>(9 * n);
+                a.lT[k] = cv.take<double>(n);
+            }
+            AdjW &w = a.w;
+            double **arr[] = {&w.rho, &w.jx, &w.jy, &w.psi, &w.T1, &w.sx, &w.sy, &w.Fx, &w.Fy, &w.Q, &w.vx,
+                              &w.vy, &w.vTx, &w.vTy, &w.Drx, &w.Dry, &w.divv, &w.AX, &w.AY, &w.IA, &w.IB, &w.E1,
+                              &w.E2, &w.RI, &w.Tk[1], &w.Tk[2], &w.Tk[3], &w.gh[0], &w.gh[1], &w.gh[2], &w.gDrx,
+                              &w.gDry, &w.gdiv, &w.grho, &w.gvx, &w.gvy, &w.gpsi, &w.gsx, &w.gsy};
+            for (double **p : arr) *p = cv.take<double>(n);
+            w.Tk[0] = w.T1;
+            w.mpart = cv.take<double>(a.nb);
+            w.fpart = cv.take<double>(2 * (size_t)a.nb);
+            w.scal = cv.take<double>(4);
         }
-        double **arr[] = {&w.rho, &w.jx, &w.jy, &w.psi, &w.T1, &w.sx, &w.sy, &w.Fx, &w.Fy, &w.Q, &w.vx,
-                          &w.vy, &w.vTx, &w.vTy, &w.Drx, &w.Dry, &w.divv, &w.AX, &w.AY, &w.IA, &w.IB, &w.E1,
-                          &w.E2, &w.RI, &w.Tk[1], &w.Tk[2], &w.Tk[3], &w.gh[0], &w.gh[1], &w.gh[2], &w.gDrx,
-                          &w.gDry, &w.gdiv, &w.grho, &w.gvx, &w.gvy, &w.gpsi, &w.gsx, &w.gsy};
-        for (double **a : arr) *a = cv.take<double>(n);
-        w.Tk[0] = w.T1;
-        w.mpart = cv.take<double>(nb);
-        w.fpart = cv.take<double>(2 * (size_t)nb);
-        w.scal = cv.take<double>(4);
+        inst_seg = cv.take<Inst>((size_t)K * nm);
+        d_ai = cv.take<AdjInst>(nm);
+        d_amap = cv.take<int>(tot);
         return cv.off;
     };
     const size_t need = carve(nullptr);
-    if (d->adj_bytes < need) {
-        if (d->adj_mem) {
-            (void)hipStreamSynchronize(d->stream);
-            (void)hipFree(d->adj_mem);
-            d->dev_bytes -= (int64_t)d->adj_bytes;
-            d->adj_mem = nullptr;
-            d->adj_bytes = 0;
+    if (*g.bytes < need) {
+        if (*g.mem) {
+            (void)hipStreamSynchronize(st);
+            (void)hipFree(*g.mem);
+            *g.mem = nullptr;
+            *g.bytes = 0;
         }
-        if (hipMalloc(&d->adj_mem, need) != hipSuccess) {
-            d->adj_mem = nullptr;
+        if (hipMalloc(g.mem, need) != hipSuccess) {
+            *g.mem = nullptr;
             return fail(LBB_ENOMEM, "adjoint work memory could not be allocated");
         }
-        d->adj_bytes = need;
-        d->dev_bytes += (int64_t)need;
+        *g.bytes = need;
     }
-    carve(static_cast<unsigned char *>(d->adj_mem));
-    hipStream_t st = d->stream;
-    auto copy_state_out = [&](unsigned char *dst) -> hipError_t {
-        hipError_t e = hipMemcpyAsync(dst, d->f[d->cf], 9 * n * es, hipMemcpyDeviceToDevice, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(dst + 9 * n * es, d->T[d->cT], n * es, hipMemcpyDeviceToDevice, st);
+    carve(static_cast<unsigned char *>(*g.mem));
+
+    auto own_f = [&](int i) { return g.doms[i]->f[*g.cf]; };
+    auto own_T = [&](int i) { return g.doms[i]->T[*g.cT]; };
+    auto copy_state_out = [&](int i, unsigned char *dst) -> hipError_t {
+        const size_t n = m[i].n;
+        hipError_t e = hipMemcpyAsync(dst, own_f(i), 9 * n * es, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(dst + 9 * n * es, own_T(i), n * es, hipMemcpyDeviceToDevice, st);
         return e;
     };
-    auto copy_state_in = [&](const unsigned char *src) -> hipError_t {
-        d->cf = d->cT = 0;
-        hipError_t e = hipMemcpyAsync(d->f[0], src, 9 * n * es, hipMemcpyDeviceToDevice, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(d->T[0], src + 9 * n * es, n * es, hipMemcpyDeviceToDevice, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(d->T[1], src + 9 * n * es, n * es, hipMemcpyDeviceToDevice, st);
-        return e;
+    auto own_step = [&]() {
+        launch_lb<S>(st, g.fwd_insts, g.blkA, g.totA, *g.cf, *g.cT);
+        launch_thermal<S>(st, g.fwd_insts, g.blkB, g.totB, *g.cf, *g.cT);
+        *g.cf ^= 1;
+        *g.cT ^= 1;
     };
-    // keep the caller's state, counters and heat-flux partials
-    LBB_HIP(copy_state_out(backup));
-    LBB_HIP(hipMemcpyAsync(&ck_sc[nck], d->sc, sizeof(Scalars), hipMemcpyDeviceToDevice, st));
-    LBB_HIP(hipMemcpyAsync(hf_backup, d->hf_part, d->nbxB * sizeof(double), hipMemcpyDeviceToDevice, st));
-    // launch tables of the stored-state steps, and the wall rows of T in every slot
-    std::vector<Inst> hinst(K);
-    for (int64_t k = 0; k < K; ++k) {
-        Inst I = make_inst(d);
-        S *a = reinterpret_cast<S *>(seg + (size_t)k * state_bytes), *b = reinterpret_cast<S *>(seg + (size_t)(k + 1) * state_bytes);
-        I.f[0] = a;
-        I.f[1] = b;
-        I.T[0] = a + 9 * n;
-        I.T[1] = b + 9 * n;
-        hinst[k] = I;
-    }
-    LBB_HIP(hipMemcpyAsync(inst_seg, hinst.data(), K * sizeof(Inst), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(a_bcast_T<S>, dim3(256), dim3(256), 0, st, static_cast<const S *>(d->T[d->cT]),
-                       reinterpret_cast<S *>(seg), n, (int)(K + 1));
     auto slot_step = [&](int64_t k) {
-        launch_lb<S>(st, inst_seg + k, d->d_blkA, d->nbxA * d->nbyA + 1, 0, 0);
-        launch_thermal<S>(st, inst_seg + k, d->d_blkB, d->nbxB * d->nbyB + 1, 0, 0);
+        launch_lb<S>(st, inst_seg + k * nm, g.blkA, g.totA, 0, 0);
+        launch_thermal<S>(st, inst_seg + k * nm, g.blkB, g.totB, 0, 0);
     };
-    auto slot_f = [&](int64_t k) { return reinterpret_cast<const S *>(seg + (size_t)k * state_bytes); };
-    // forward with the average restarted: J = q_sum / N afterwards.  States
+
+    // keep each lattice's state, counters and heat-flux partials
+    for (int i = 0; i < nm; ++i) {
+        lbb_domain *d = g.doms[i];
+        LBB_HIP(copy_state_out(i, m[i].backup));
+        LBB_HIP(hipMemcpyAsync(&m[i].ck_sc[nck], d->sc, sizeof(Scalars), hipMemcpyDeviceToDevice, st));
+        LBB_HIP(hipMemcpyAsync(m[i].hf_backup, d->hf_part, d->nbxB * sizeof(double), hipMemcpyDeviceToDevice, st));
+    }
+    // launch tables: stored-state steps and the adjoint grid
+    std::vector<Inst> hinst((size_t)K * nm);
+    std::vector<AdjInst> hai(nm);
+    std::vector<int> hamap;
+    hamap.reserve(tot);
+    for (int i = 0; i < nm; ++i) {
+        lbb_domain *d = g.doms[i];
+        const size_t n = m[i].n;
+        for (int64_t k = 0; k < K; ++k) {
+            Inst I = make_inst(d);
+            S *a = reinterpret_cast<S *>(m[i].seg + (size_t)k * m[i].state_bytes);
+            S *b = reinterpret_cast<S *>(m[i].seg + (size_t)(k + 1) * m[i].state_bytes);
+            I.f[0] = a;
+            I.f[1] = b;
+            I.T[0] = a + 9 * n;
+            I.T[1] = b + 9 * n;
+            I.blkA0 = g.blkA0[i];
+            I.blkB0 = g.blkB0[i];
+            hinst[(size_t)k * nm + i] = I;
+        }
+        AdjInst A{};
+        A.P = d->dp;
+        A.w = m[i].w;
+        A.seg = m[i].seg;
+        for (int k = 0; k < 2; ++k) {
+            A.lf[k] = m[i].lf[k];
+            A.lT[k] = m[i].lT[k];
+        }
+        A.gx = m[i].gx;
+        A.blk0 = (int)hamap.size();
+        A.nb = m[i].nb;
+        hai[i] = A;
+        hamap.insert(hamap.end(), m[i].nb, i);
+        hipLaunchKernelGGL(a_bcast_T<S>, dim3(256), dim3(256), 0, st, static_cast<const S *>(own_T(i)),
+                           reinterpret_cast<S *>(m[i].seg), n, (int)(K + 1));
+    }
+    LBB_HIP(hipMemcpyAsync(inst_seg, hinst.data(), hinst.size() * sizeof(Inst), hipMemcpyHostToDevice, st));
+    LBB_HIP(hipMemcpyAsync(d_ai, hai.data(), nm * sizeof(AdjInst), hipMemcpyHostToDevice, st));
+    LBB_HIP(hipMemcpyAsync(d_amap, hamap.data(), tot * sizeof(int), hipMemcpyHostToDevice, st));
+
+    // forward with the averages restarted: J = q_sum / N afterwards.  States
     // of the last segment go straight into the slots (no recompute later).
-    Scalars s0;
-    LBB_HIP(hipMemcpyAsync(&s0, d->sc, sizeof s0, hipMemcpyDeviceToHost, st));
+    std::vector<Scalars> s0(nm);
+    for (int i = 0; i < nm; ++i)
+        LBB_HIP(hipMemcpyAsync(&s0[i], g.doms[i]->sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
     LBB_HIP(hipStreamSynchronize(st));
-    s0.q_sum = 0.0;
-    s0.n_samples = 0;
-    LBB_HIP(hipMemcpyAsync(d->sc, &s0, sizeof s0, hipMemcpyHostToDevice, st));
+    for (int i = 0; i < nm; ++i) {
+        s0[i].q_sum = 0.0;
+        s0[i].n_samples = 0;
+        LBB_HIP(hipMemcpyAsync(g.doms[i]->sc, &s0[i], sizeof(Scalars), hipMemcpyHostToDevice, st));
+    }
     const int64_t tL = (nck - 1) * K;
     for (int64_t t = 0; t < N; ++t) {
-        if (t % K == 0) {
-            LBB_HIP(copy_state_out(t < tL ? ck + (size_t)(t / K) * state_bytes : seg));
-            LBB_HIP(hipMemcpyAsync(&ck_sc[t / K], d->sc, sizeof(Scalars), hipMemcpyDeviceToDevice, st));
-        }
-        if (t < tL) enqueue_step<S>(d);
+        if (t % K == 0)
+            for (int i = 0; i < nm; ++i) {
+                LBB_HIP(copy_state_out(i, t < tL ? m[i].ck + (size_t)(t / K) * m[i].state_bytes : m[i].seg));
+                LBB_HIP(hipMemcpyAsync(&m[i].ck_sc[t / K], g.doms[i]->sc, sizeof(Scalars), hipMemcpyDeviceToDevice,
+                                       st));
+            }
+        if (t < tL) own_step();
         else slot_step(t - tL);
         LBB_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_flush_heat_flux, dim3(1), dim3(NT), 0, st, d->d_inst);
-    int rc = check_errors(d);
-    if (rc) return rc;
-    Scalars s1;
-    LBB_HIP(hipMemcpyAsync(&s1, d->sc, sizeof s1, hipMemcpyDeviceToHost, st));
+    hipLaunchKernelGGL(k_flush_heat_flux, dim3(nm), dim3(NT), 0, st, g.fwd_insts);
     LBB_HIP(hipStreamSynchronize(st));
-    *J = s1.q_sum / (double)N;
+    std::vector<Scalars> s1(nm);
+    for (int i = 0; i < nm; ++i) {
+        int rc = check_errors(g.doms[i]);
+        if (rc) return nm > 1 ? fail(rc, "batch member " + std::to_string(i) + ": " + g_err) : rc;
+        LBB_HIP(hipMemcpyAsync(&s1[i], g.doms[i]->sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+    }
+    LBB_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < nm; ++i) J[i] = s1[i].q_sum / (double)N;
 
     // reverse sweep: the adjoint of the final state starts from its heat-flux sample
-    const DevParams P = d->dp;
     const double wq = 1.0 / (double)N;
-    LBB_HIP(hipMemsetAsync(lf[1], 0, 9 * n * sizeof(double), st));
-    LBB_HIP(hipMemsetAsync(lT[1], 0, n * sizeof(double), st));
-    LBB_HIP(hipMemsetAsync(w.scal, 0, 4 * sizeof(double), st));
-    {
-        const S *fN = slot_f(N - tL);
-        hipLaunchKernelGGL(a_hf<S>, dim3((d->p.nx + 255) / 256, 3), dim3(256), 0, st, P, fN, fN + 9 * n, wq, lf[1],
-                           lT[1]);
+    for (int i = 0; i < nm; ++i) {
+        LBB_HIP(hipMemsetAsync(m[i].lf[0], 0, 9 * m[i].n * sizeof(double), st));
+        LBB_HIP(hipMemsetAsync(m[i].lT[0], 0, m[i].n * sizeof(double), st));
+        LBB_HIP(hipMemsetAsync(m[i].w.scal, 0, 4 * sizeof(double), st));
     }
+    const dim3 grid(tot), blk(NTA);
+    int cur = 0;
+    hipLaunchKernelGGL(a_hf<S>, grid, blk, 0, st, d_ai, d_amap, (int)(N - tL), wq, cur);
     for (int64_t sg = nck - 1; sg >= 0; --sg) {
         const int64_t t0 = sg * K, t1 = (t0 + K < N) ? t0 + K : N;
         if (sg < nck - 1) {
             // recompute the segment's states from its checkpoint into the slots
-            LBB_HIP(hipMemcpyAsync(seg, ck + (size_t)sg * state_bytes, state_bytes, hipMemcpyDeviceToDevice, st));
-            LBB_HIP(hipMemcpyAsync(d->sc, &ck_sc[sg], sizeof(Scalars), hipMemcpyDeviceToDevice, st));
+            for (int i = 0; i < nm; ++i) {
+                LBB_HIP(hipMemcpyAsync(m[i].seg, m[i].ck + (size_t)sg * m[i].state_bytes, m[i].state_bytes,
+                                       hipMemcpyDeviceToDevice, st));
+                LBB_HIP(hipMemcpyAsync(g.doms[i]->sc, &m[i].ck_sc[sg], sizeof(Scalars), hipMemcpyDeviceToDevice, st));
+            }
             for (int64_t t = t0; t + 1 < t1; ++t) slot_step(t - t0);
         }
-        {
-            const S *fs = slot_f(t1 - 1 - t0);
-            hipLaunchKernelGGL(a_macro<S>, ag, dim3(NTA), 0, st, P, fs, fs + 9 * n, w);
-        }
+        hipLaunchKernelGGL(a_macro<S>, grid, blk, 0, st, d_ai, d_amap, (int)(t1 - 1 - t0));
         for (int64_t t = t1 - 1; t >= t0; --t) {
-            const S *fs = slot_f(t - t0);
-            const S *Ts = fs + 9 * n;
-            const S *fp = t > t0 ? slot_f(t - 1 - t0) : nullptr;
-            const S *Tp = fp ? fp + 9 * n : nullptr;
-            hipLaunchKernelGGL(a_force, ag, dim3(NTA), 0, st, P, w, nb);
-            hipLaunchKernelGGL(a_divv0, ag, dim3(NTA), 0, st, P, w);
-            hipLaunchKernelGGL(a_stage, ag, dim3(NTA), 0, st, P, w, 1, 0.5);
-            hipLaunchKernelGGL(a_stage, ag, dim3(NTA), 0, st, P, w, 2, 1.0);
-            hipLaunchKernelGGL(a_tstage, ag, dim3(NTA), 0, st, P, w, 3, 1.0, lT[1], lT[0]);
-            hipLaunchKernelGGL(a_tstage, ag, dim3(NTA), 0, st, P, w, 2, 0.5, lT[1], lT[0]);
-            hipLaunchKernelGGL(a_tstage, ag, dim3(NTA), 0, st, P, w, 1, 0.5, lT[1], lT[0]);
-            hipLaunchKernelGGL(a_tstage, ag, dim3(NTA), 0, st, P, w, 0, 0.0, lT[1], lT[0]);
-            hipLaunchKernelGGL(a_lb<S>, ag, dim3(NTA), 0, st, P, w, fs, lf[1], lf[0]);
-            hipLaunchKernelGGL(a_final<S>, ag, dim3(NTA), 0, st, P, w, fs, Ts, t >= 1 ? wq : 0.0, fp, Tp, nb, lf[0],
-                               lT[0]);
-            std::swap(lf[0], lf[1]);
-            std::swap(lT[0], lT[1]);
+            const int k = (int)(t - t0);
+            hipLaunchKernelGGL(a_force, grid, blk, 0, st, d_ai, d_amap);
+            hipLaunchKernelGGL(a_divv0, grid, blk, 0, st, d_ai, d_amap);
+            hipLaunchKernelGGL(a_stage, grid, blk, 0, st, d_ai, d_amap, 1, 0.5);
+            hipLaunchKernelGGL(a_stage, grid, blk, 0, st, d_ai, d_amap, 2, 1.0);
+            hipLaunchKernelGGL(a_tstage, grid, blk, 0, st, d_ai, d_amap, 3, 1.0, cur);
+            hipLaunchKernelGGL(a_tstage, grid, blk, 0, st, d_ai, d_amap, 2, 0.5, cur);
+            hipLaunchKernelGGL(a_tstage, grid, blk, 0, st, d_ai, d_amap, 1, 0.5, cur);
+            hipLaunchKernelGGL(a_tstage, grid, blk, 0, st, d_ai, d_amap, 0, 0.0, cur);
+            hipLaunchKernelGGL(a_lb<S>, grid, blk, 0, st, d_ai, d_amap, k, cur);
+            hipLaunchKernelGGL(a_final<S>, grid, blk, 0, st, d_ai, d_amap, k, cur, t >= 1 ? wq : 0.0,
+                               t > t0 ? 1 : 0);
+            cur ^= 1;
         }
         LBB_HIP(hipGetLastError());
     }
-    std::vector<double> g(d->p.nx);
-    double gGw = 0.0;
-    LBB_HIP(hipMemcpyAsync(g.data(), lT[1], d->p.nx * sizeof(double), hipMemcpyDeviceToHost, st));
-    LBB_HIP(hipMemcpyAsync(&gGw, w.scal + 2, sizeof(double), hipMemcpyDeviceToHost, st));
-    // restore the caller's state
-    LBB_HIP(copy_state_in(backup));
-    LBB_HIP(hipMemcpyAsync(d->sc, &ck_sc[nck], sizeof(Scalars), hipMemcpyDeviceToDevice, st));
-    LBB_HIP(hipMemcpyAsync(d->hf_part, hf_backup, d->nbxB * sizeof(double), hipMemcpyDeviceToDevice, st));
+    // gradients: row 0 of the adjoint of T^0, and the accumulated G_w part
+    std::vector<std::vector<double>> gT(nm);
+    std::vector<double> gGw(nm, 0.0);
+    for (int i = 0; i < nm; ++i) {
+        gT[i].resize(g.doms[i]->p.nx);
+        LBB_HIP(hipMemcpyAsync(gT[i].data(), m[i].lT[cur], gT[i].size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        LBB_HIP(hipMemcpyAsync(&gGw[i], m[i].w.scal + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+    }
+    // restore every lattice's state
+    for (int i = 0; i < nm; ++i) {
+        lbb_domain *d = g.doms[i];
+        const size_t n = m[i].n;
+        LBB_HIP(hipMemcpyAsync(d->f[0], m[i].backup, 9 * n * es, hipMemcpyDeviceToDevice, st));
+        LBB_HIP(hipMemcpyAsync(d->T[0], m[i].backup + 9 * n * es, n * es, hipMemcpyDeviceToDevice, st));
+        LBB_HIP(hipMemcpyAsync(d->T[1], m[i].backup + 9 * n * es, n * es, hipMemcpyDeviceToDevice, st));
+        LBB_HIP(hipMemcpyAsync(d->sc, &m[i].ck_sc[nck], sizeof(Scalars), hipMemcpyDeviceToDevice, st));
+        LBB_HIP(hipMemcpyAsync(d->hf_part, m[i].hf_backup, d->nbxB * sizeof(double), hipMemcpyDeviceToDevice, st));
+        d->cf = d->cT = 0;
+    }
+    *g.cf = *g.cT = 0;
     LBB_HIP(hipStreamSynchronize(st));
-    if (dJ_dTb) std::memcpy(dJ_dTb, g.data(), d->p.nx * sizeof(double));
-    if (dJ_dGw) *dJ_dGw = gGw;
-    for (double v : g)
-        if (!std::isfinite(v)) return fail(LBB_ENONFINITE, "adjoint produced a non-finite gradient");
+    size_t off = 0;
+    for (int i = 0; i < nm; ++i) {
+        for (double v : gT[i])
+            if (!std::isfinite(v)) return fail(LBB_ENONFINITE, "adjoint produced a non-finite gradient");
+        if (dJ_dTb) std::memcpy(dJ_dTb + off, gT[i].data(), gT[i].size() * sizeof(double));
+        if (dJ_dGw) dJ_dGw[i] = gGw[i];
+        off += gT[i].size();
+    }
     return LBB_OK;
+}
+
+int adjoint_checks(const lbb_domain *d)
+{
+    if (d->p.periodic_y || d->p.thermal_mode != LBB_COUPLED)
+        return fail(LBB_EUNSUPPORTED, "the adjoint covers the coupled model with walls");
+    if (d->poisoned) return fail(LBB_ESTATE, "domain poisoned by an earlier invalid state; load a state first");
+    return LBB_OK;
+}
+
+int adjoint_group(AdjGroup &g, int precision, int64_t N, int64_t K, double *J, double *dJ_dTb, double *dJ_dGw)
+{
+    if (K <= 0) K = auto_K(g, N, precision == LBB_FP64 ? 8 : 4);
+    if (K > N) K = N;
+    return precision == LBB_FP64 ? adjoint_run<double>(g, N, K, J, dJ_dTb, dJ_dGw)
+                                 : adjoint_run<float>(g, N, K, J, dJ_dTb, dJ_dGw);
 }
 
 }  // namespace
@@ -1293,13 +1410,71 @@ extern "C" int lbb_adjoint(lbb_domain *d, int64_t N, int64_t K, double *J, doubl
 {
     if (!d || !J) return fail(LBB_EINVAL, "domain and J are required");
     if (N < 1) return fail(LBB_EINVAL, "N must be >= 1");
-    if (d->p.periodic_y || d->p.thermal_mode != LBB_COUPLED)
-        return fail(LBB_EUNSUPPORTED, "the adjoint covers the coupled model with walls");
-    if (d->poisoned) return fail(LBB_ESTATE, "domain poisoned by an earlier invalid state; load a state first");
-    if (K <= 0) K = N < 50 ? N : 50;
-    if (K > N) K = N;
-    return d->p.precision == LBB_FP64 ? adjoint_impl<double>(d, N, K, J, dJ_dTb, dJ_dGw)
-                                      : adjoint_impl<float>(d, N, K, J, dJ_dTb, dJ_dGw);
+    int rc = adjoint_checks(d);
+    if (rc) return rc;
+    AdjGroup g;
+    g.doms = {d};
+    g.st = d->stream;
+    g.fwd_insts = d->d_inst;
+    g.blkA = d->d_blkA;
+    g.blkB = d->d_blkB;
+    g.totA = d->nbxA * d->nbyA + 1;
+    g.totB = d->nbxB * d->nbyB + 1;
+    g.blkA0 = {0};
+    g.blkB0 = {0};
+    g.cf = &d->cf;
+    g.cT = &d->cT;
+    const size_t before = d->adj_bytes;
+    g.mem = &d->adj_mem;
+    g.bytes = &d->adj_bytes;
+    rc = adjoint_group(g, d->p.precision, N, K, J, dJ_dTb, dJ_dGw);
+    d->dev_bytes += (int64_t)d->adj_bytes - (int64_t)before;
+    return rc;
+}
+
+extern "C" int lbb_batch_adjoint(lbb_batch *b, int64_t N, int64_t K, double *J, double *dJ_dTb, double *dJ_dGw)
+{
+    if (!b || !J) return fail(LBB_EINVAL, "batch and J are required");
+    if (N < 1) return fail(LBB_EINVAL, "N must be >= 1");
+    int rc = batch_phase(b);
+    if (rc) return rc;
+    for (size_t i = 0; i < b->doms.size(); ++i) {
+        rc = adjoint_checks(b->doms[i]);
+        if (rc) return fail(rc, "batch member " + std::to_string(i) + ": " + g_err);
+    }
+    rc = batch_push(b);
+    if (rc) return rc;
+    AdjGroup g;
+    g.doms = b->doms;
+    g.st = b->stream;
+    g.fwd_insts = b->d_insts;
+    g.blkA = b->d_blkA;
+    g.blkB = b->d_blkB;
+    g.totA = b->totA;
+    g.totB = b->totB;
+    int a0 = 0, b0 = 0;
+    for (lbb_domain *d : b->doms) {
+        g.blkA0.push_back(a0);
+        g.blkB0.push_back(b0);
+        a0 += d->nbxA * d->nbyA + 1;
+        b0 += d->nbxB * d->nbyB + 1;
+    }
+    g.cf = &b->cf;
+    g.cT = &b->cT;
+    g.mem = &b->adj_mem;
+    g.bytes = &b->adj_bytes;
+    return adjoint_group(g, b->precision, N, K, J, dJ_dTb, dJ_dGw);
+}
+
+extern "C" int lbb_batch_info(lbb_batch *b, int64_t *device_bytes)
+{
+    if (!b) return fail(LBB_EINVAL, "batch is NULL");
+    if (device_bytes) {
+        int64_t s = (int64_t)b->adj_bytes;
+        for (lbb_domain *d : b->doms) s += d->dev_bytes;
+        *device_bytes = s;
+    }
+    return LBB_OK;
 }
 
 extern "C" {

@@ -88,6 +88,8 @@ def lib():
             "lbb_batch_size": (C.c_int, [vp]),
             "lbb_batch_destroy": (C.c_int, [vp]),
             "lbb_adjoint": (C.c_int, [vp, _i64, _i64, _pd, _pd, _pd]),
+            "lbb_batch_adjoint": (C.c_int, [vp, _i64, _i64, _pd, _pd, _pd]),
+            "lbb_batch_info": (C.c_int, [vp, C.POINTER(_i64)]),
             "lbb_last_error": (C.c_char_p, []),
         }
         for name, (res, args) in sig.items():
@@ -366,6 +368,25 @@ class Batch:
         ns = (_i64 * n)()
         _check(lib().lbb_batch_heat_flux(self._h, _ptr(qn), _ptr(qm), ns))
         return dict(q_now=qn, q_mean=qm, n_samples=np.array(ns[:]))
+
+    def adjoint(self, n_steps: int, K: int = 0):
+        """Per member: J = mean bottom-wall heat flux over the next n_steps and
+        its gradient w.r.t. T_b (all nx of the member) and G_w, all members in
+        shared launches; every member's state is left unchanged."""
+        n = len(self)
+        J, gGw = np.zeros(n), np.zeros(n)
+        gTb = np.zeros(sum(p.nx for p in self.params))
+        _check(lib().lbb_batch_adjoint(self._h, int(n_steps), int(K), _ptr(J), _ptr(gTb), _ptr(gGw)))
+        out, off = [], 0
+        for p in self.params:
+            out.append(gTb[off:off + p.nx])
+            off += p.nx
+        return J, out, gGw
+
+    def device_bytes(self) -> int:
+        v = _i64()
+        _check(lib().lbb_batch_info(self._h, C.byref(v)))
+        return v.value
 
     def domain(self, i: int) -> Domain:
         h = lib().lbb_batch_domain(self._h, int(i))

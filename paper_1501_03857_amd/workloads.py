@@ -153,3 +153,18 @@ def sweep_workloads(steps: int = 10000):
                                 g=scaled_gravity(ny, 2.0 / 49.0), extra={"angle": ang}))
             i += 1
     return out
+
+
+def batch_adjoint_workloads(steps: int = 600):
+    """16 lattices of 384x192 (FP32) for the batched adjoint: superheats
+    0.04, 0.08, 0.12, 0.16 T_c times the four contact-angle labels, full-width
+    heaters, seeds 2000 + i, gravity scaled to the lattice height."""
+    out = []
+    i = 0
+    for dT in (0.04, 0.08, 0.12, 0.16):
+        for ang in (40, 60, 90, 120):
+            out.append(Workload(f"badj_{i:02d}", 384, 192, "fp32", steps, dT_over_Tc=dT, heater=(0, -1),
+                                Gw_bottom=CONTACT_ANGLE_GW[ang], seed=2000 + i,
+                                g=scaled_gravity(192, 2.0 / 49.0), extra={"angle": ang}))
+            i += 1
+    return out
