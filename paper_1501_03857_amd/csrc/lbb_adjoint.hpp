@@ -40,7 +40,7 @@ struct AdjW {
     // rho, j, psi and T of the state being reversed; a_final replaces them
     // by those of the state before it
     double *rho, *jx, *jy, *psi, *T1;
-    double *sx, *sy, *Fx, *Fy, *Q, *vx, *vy, *vTx, *vTy, *Drx, *Dry;
+    double *sx, *sy, *Fx, *Fy, *vx, *vy, *Drx, *Dry;
     // Eq. (18) as K(T) = AX d_x T + AY d_y T + chi lap T - IA divv T + IB divv T phi'(T)
     // with AX = -vx + chi d_x rho / rho, IA = R / ((1 - b rho) c_v),
     // IB = a rho / ((1 + 2 b rho - b^2 rho^2) c_v); E1, E2 give the rho
@@ -63,6 +63,7 @@ struct AdjInst {
     AdjW w;
     const void *seg;          // stored states of the segment: slot k at 10 k nx ny elements
     double *lf[2], *lT[2];    // adjoints of f and T: [cur] the later state, [cur ^ 1] the earlier
+    double *gr[2];            // density adjoint of interior nodes not yet added to lf (same parity)
     int gx;                   // patches per lattice row
     int blk0;                 // first block of this lattice in the grid
     int nb;                   // blocks of this lattice
@@ -208,7 +209,7 @@ __global__ __launch_bounds__(NTA) void a_force(A_ARGS)
     const double rho_ave = block_sum_all(w.mpart, I.nb, 1, 0, red) / ((double)P.nx * (double)P.ny);
     A_NODE
     if (!on) return;
-    double sx = 0.0, sy = 0.0, Fx = 0.0, Fy = 0.0, Q = 0.0, rx = 0.0, ry = 0.0;
+    double sx = 0.0, sy = 0.0, Fx = 0.0, Fy = 0.0, rx = 0.0, ry = 0.0;
     const double r = w.rho[c];
     const bool in = a_int(P, gj);
     if (in) {
@@ -224,7 +225,6 @@ __global__ __launch_bounds__(NTA) void a_force(A_ARGS)
         const double ps = w.psi[c];
         Fx = -P.G * ps * sx;
         Fy = -P.G * ps * sy;
-        Q = P.G * P.G * (sx * sx + sy * sy);
         if (gj == 1) Fy += P.Gw_bottom * ps * ps / 6.0;
         if (gj == P.ny - 2) Fy -= P.Gw_top * ps * ps / 6.0;
         Fy -= (r - rho_ave) * P.g;
@@ -233,14 +233,11 @@ __global__ __launch_bounds__(NTA) void a_force(A_ARGS)
     w.sy[c] = sy;
     w.Fx[c] = Fx;
     w.Fy[c] = Fy;
-    w.Q[c] = Q;
     w.Drx[c] = rx;
     w.Dry[c] = ry;
     const double vx = (w.jx[c] + 0.5 * Fx) / r, vy = (w.jy[c] + 0.5 * Fy) / r;
     w.vx[c] = vx;
     w.vy[c] = vy;
-    w.vTx[c] = in ? vx : 0.0;
-    w.vTy[c] = in ? vy : 0.0;
 }
 
 // Eq. (18) at interior node c for the stage field Tf, with its stencils and
@@ -276,8 +273,10 @@ __global__ __launch_bounds__(NTA) void a_divv0(A_ARGS)
     double dv = 0.0;
 #pragma unroll
     for (int a = 1; a < 9; ++a) {
+        // the velocity the temperature equation sees is zero on the wall rows
         const size_t cn = a_at(P, gi, gj, kEX[a], kEY[a]);
-        dv += 3.0 * kW[a] * (kEX[a] * w.vTx[cn] + kEY[a] * w.vTy[cn]);
+        const double m = a_int(P, gj + kEY[a]) ? 3.0 * kW[a] : 0.0;
+        dv += m * (kEX[a] * w.vx[cn] + kEY[a] * w.vy[cn]);
     }
     const double r = w.rho[c];
     const double D1 = 1.0 - P.b * r, D2 = 1.0 + 2.0 * P.b * r - P.b * P.b * r * r;
@@ -286,8 +285,8 @@ __global__ __launch_bounds__(NTA) void a_divv0(A_ARGS)
     const double icv = 1.0 / P.cv;
     w.divv[c] = dv;
     w.RI[c] = ri;
-    w.AX[c] = -w.vTx[c] + P.chi * w.Drx[c] * ri;
-    w.AY[c] = -w.vTy[c] + P.chi * w.Dry[c] * ri;
+    w.AX[c] = -w.vx[c] + P.chi * w.Drx[c] * ri;
+    w.AY[c] = -w.vy[c] + P.chi * w.Dry[c] * ri;
     w.IA[c] = P.R * i1 * icv;
     w.IB[c] = P.a * r * i2 * icv;
     w.E1[c] = P.R * P.b * i1 * i1 * icv;
@@ -311,13 +310,28 @@ __global__ __launch_bounds__(NTA) void a_stage(A_ARGS, int k, double ck)
     w.Tk[k + 1][c] = w.T1[c] + ck * h;
 }
 
+// Stencils of the stage field Tf at interior node c: d_x, d_y (isotropic,
+// the lattice weights of the gradient)
+__device__ __forceinline__ void a_grad(const DevParams &P, const double *__restrict__ Tf, int gi, int gj,
+                                       double &dTx, double &dTy)
+{
+    dTx = dTy = 0.0;
+#pragma unroll
+    for (int a = 1; a < 9; ++a) {
+        const double t = Tf[a_at(P, gi, gj, kEX[a], kEY[a])];
+        dTx += 3.0 * kW[a] * kEX[a] * t;
+        dTy += 3.0 * kW[a] * kEY[a] * t;
+    }
+}
+
 // RK4 stage k (slope h_{k+1} = K(T_{k+1})) transposed.  Gathers the adjoint
 // of the stage input at c from the slope adjoints of c and its neighbours,
-// accumulates the rho and v parts at c, hands c_k times it to the slope of
-// the stage before (whose adjoint is w_k lT^{t+1}/6 plus that, with the RK4
-// weights w = (1, 2, 2, 1)), and adds it to the adjoint of T^t, which starts
-// from lT^{t+1} (identity part).  The last stage's slope adjoint is
-// lT^{t+1}/6 on interior nodes.
+// hands c_k times it to the slope of the stage before (whose adjoint is
+// w_k lT^{t+1}/6 plus that, with the RK4 weights w = (1, 2, 2, 1)), and adds
+// it to the adjoint of T^t, which starts from lT^{t+1} (identity part).  The
+// last stage's slope adjoint is lT^{t+1}/6 on interior nodes.  The first
+// stage's launch (k = 0), when every slope adjoint at c is known, also forms
+// the rho, grad rho, v and div v parts of all four stages at c.
 __global__ __launch_bounds__(NTA) void a_tstage(A_ARGS, int k, double ck, int cur)
 {
     A_INST
@@ -325,7 +339,6 @@ __global__ __launch_bounds__(NTA) void a_tstage(A_ARGS, int k, double ck, int cu
     const double *__restrict__ lT1 = I.lT[cur];
     double *__restrict__ lT0 = I.lT[cur ^ 1];
     if (!on) return;
-    const double *Tf = w.Tk[k];
     const double *gk = k < 3 ? w.gh[k] : lT1;
     const double sk = k < 3 ? 1.0 : 1.0 / 6.0;
     double gT = 0.0;
@@ -337,41 +350,47 @@ __global__ __launch_bounds__(NTA) void a_tstage(A_ARGS, int k, double ck, int cu
         const double g = (ok ? sk : 0.0) * gk[cp];
         gT += g * (3.0 * kW[a] * (w.AX[cp] * kEX[a] + w.AY[cp] * kEY[a]) + 6.0 * kW[a] * P.chi);
     }
-    if (a_int(P, gj)) {
+    const bool in = a_int(P, gj);
+    if (in) {
         const double g = sk * gk[c];
-        double dTx, dTy, lap, d1, d2;
-        (void)a_K(P, w, Tf, gi, gj, c, dTx, dTy, lap, d1, d2);
-        const double Tv = Tf[c], dv = w.divv[c], ri = w.RI[c], IA = w.IA[c], IB = w.IB[c];
+        const double Tv = w.Tk[k][c], dv = w.divv[c], IA = w.IA[c], IB = w.IB[c];
+        double d1, d2;
+        phi_derivs(P, Tv, d1, d2);
         gT += g * (-(10.0 / 3.0) * P.chi - dv * (IA - IB * (d1 + Tv * d2)));
-        const double aDrx = g * P.chi * dTx * ri, aDry = g * P.chi * dTy * ri;
-        const double avx = -g * dTx, avy = -g * dTy;
-        const double adiv = -g * Tv * (IA - IB * d1);
-        const double arho = g * (-P.chi * (w.Drx[c] * dTx + w.Dry[c] * dTy) * ri * ri -
-                                 Tv * dv * (w.E1[c] - w.E2[c] * d1));
-        if (k == 3) {
-            w.gDrx[c] = aDrx;
-            w.gDry[c] = aDry;
-            w.gvx[c] = avx;
-            w.gvy[c] = avy;
-            w.gdiv[c] = adiv;
-            w.grho[c] = arho;
-        } else {
-            w.gDrx[c] += aDrx;
-            w.gDry[c] += aDry;
-            w.gvx[c] += avx;
-            w.gvy[c] += avy;
-            w.gdiv[c] += adiv;
-            w.grho[c] += arho;
-        }
         if (k > 0) {
             const double wk = (k == 1) ? 1.0 : 2.0;
             w.gh[k - 1][c] = wk * lT1[c] / 6.0 + ck * gT;
         }
-    } else if (k == 3) {
-        w.gDrx[c] = w.gDry[c] = w.gvx[c] = w.gvy[c] = w.gdiv[c] = w.grho[c] = 0.0;
     }
-    if (k == 3) lT0[c] = lT1[c] + gT;
-    else lT0[c] += gT;
+    lT0[c] = (k == 3 ? lT1[c] : lT0[c]) + gT;
+    if (k != 0) return;
+    double aDrx = 0.0, aDry = 0.0, avx = 0.0, avy = 0.0, adiv = 0.0, arho = 0.0;
+    if (in) {
+        const double dv = w.divv[c], ri = w.RI[c], IA = w.IA[c], IB = w.IB[c], E1 = w.E1[c], E2 = w.E2[c];
+        const double Drx = w.Drx[c], Dry = w.Dry[c];
+        const double gs[4] = {w.gh[0][c], w.gh[1][c], w.gh[2][c], lT1[c] / 6.0};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const double *Tf = w.Tk[j];
+            double dTx, dTy, d1, d2;
+            a_grad(P, Tf, gi, gj, dTx, dTy);
+            const double Tv = Tf[c];
+            phi_derivs(P, Tv, d1, d2);
+            const double g = gs[j];
+            aDrx += g * P.chi * dTx * ri;
+            aDry += g * P.chi * dTy * ri;
+            avx += -g * dTx;
+            avy += -g * dTy;
+            adiv += -g * Tv * (IA - IB * d1);
+            arho += g * (-P.chi * (Drx * dTx + Dry * dTy) * ri * ri - Tv * dv * (E1 - E2 * d1));
+        }
+    }
+    w.gDrx[c] = aDrx;
+    w.gDry[c] = aDry;
+    w.gvx[c] = avx;
+    w.gvy[c] = avy;
+    w.gdiv[c] = adiv;
+    w.grho[c] = arho;
 }
 
 // Stencil transposes of grad rho and div v, then streaming and collision
@@ -416,7 +435,10 @@ __global__ __launch_bounds__(NTA) void a_lb(A_ARGS, int k, int cur)
         for (int a = 0; a < 9; ++a) {
             const int jj = gj + kEY[a];
             const bool ok = jj >= 0 && jj < P.ny;
-            const double v = lf1[(size_t)a * N + (ok ? a_at(P, gi, gj, kEX[a], kEY[a]) : c)];
+            // interior nodes keep their density adjoint apart (added here);
+            // wall nodes hold the complete adjoint (Zou-He transposed)
+            const size_t ct = ok ? a_at(P, gi, gj, kEX[a], kEY[a]) : c;
+            const double v = lf1[(size_t)a * N + ct] + (a_int(P, jj) ? I.gr[cur][ct] : 0.0);
             gfs[a] = ok ? v : 0.0;
         }
         double fl[9];
@@ -587,18 +609,21 @@ __global__ __launch_bounds__(NTA) void a_final(A_ARGS, int k, int cur, double wq
             gr += gq * (dpdr - 1.0 / 3.0);
             gT = gq * dpdT;
         }
-        double g[9];
-        for (int a = 0; a < 9; ++a) g[a] = lf0[(size_t)a * N + c] + gr;
-        if (gj == 0) zou_he_T(g, 1);
-        else if (gj == P.ny - 1) zou_he_T(g, 0);
-        if (wq != 0.0 && gj <= 2) {
-            double gpop[9], gtem;
-            hf_source(P, f, T, wq, N, gi, gj, gpop, gtem);
-            for (int a = 0; a < 9; ++a) g[a] += gpop[a];
-            gT += gtem;
+        double gpop[9], gtem = 0.0;
+        if (wq != 0.0 && gj <= 2) hf_source(P, f, T, wq, N, gi, gj, gpop, gtem);
+        if (a_int(P, gj)) {
+            // rho = sum f: the density adjoint joins every population of the
+            // node; kept apart and added where the next step gathers lf
+            I.gr[cur ^ 1][c] = gr;
+        } else {
+            double g[9];
+            for (int a = 0; a < 9; ++a) g[a] = lf0[(size_t)a * N + c] + gr;
+            zou_he_T(g, gj == 0);
+            if (wq != 0.0 && gj == 0)
+                for (int a = 0; a < 9; ++a) g[a] += gpop[a];
+            for (int a = 0; a < 9; ++a) lf0[(size_t)a * N + c] = g[a];
         }
-        for (int a = 0; a < 9; ++a) lf0[(size_t)a * N + c] = g[a];
-        lT0[c] += gT;
+        lT0[c] += gT + gtem;
         // this thread's reads of the state-t values at c are done
         if (fp) m = a_macro_node(P, fp, Tp, N, c, gj, w);
     }

@@ -1130,7 +1130,7 @@ struct AdjGroup {
 struct AdjMember {
     unsigned char *backup, *ck, *seg;
     lbb::Scalars *ck_sc;
-    double *hf_backup, *lf[2], *lT[2];
+    double *hf_backup, *lf[2], *lT[2], *gr[2];
     lbb::AdjW w;
     int gx, nb;
     size_t n, state_bytes;
@@ -1184,10 +1184,11 @@ int adjoint_run(AdjGroup &g, int64_t N, int64_t K, double *J, double *dJ_dTb, do
             for (int k = 0; k < 2; ++k) {
                 a.lf[k] = cv.take<double>(9 * n);
                 a.lT[k] = cv.take<double>(n);
+                a.gr[k] = cv.take<double>(n);
             }
             AdjW &w = a.w;
-            double **arr[] = {&w.rho, &w.jx, &w.jy, &w.psi, &w.T1, &w.sx, &w.sy, &w.Fx, &w.Fy, &w.Q, &w.vx,
-                              &w.vy, &w.vTx, &w.vTy, &w.Drx, &w.Dry, &w.divv, &w.AX, &w.AY, &w.IA, &w.IB, &w.E1,
+            double **arr[] = {&w.rho, &w.jx, &w.jy, &w.psi, &w.T1, &w.sx, &w.sy, &w.Fx, &w.Fy, &w.vx,
+                              &w.vy, &w.Drx, &w.Dry, &w.divv, &w.AX, &w.AY, &w.IA, &w.IB, &w.E1,
                               &w.E2, &w.RI, &w.Tk[1], &w.Tk[2], &w.Tk[3], &w.gh[0], &w.gh[1], &w.gh[2], &w.gDrx,
                               &w.gDry, &w.gdiv, &w.grho, &w.gvx, &w.gvy, &w.gpsi, &w.gsx, &w.gsy};
             for (double **p : arr) *p = cv.take<double>(n);
@@ -1270,6 +1271,7 @@ int adjoint_run(AdjGroup &g, int64_t N, int64_t K, double *J, double *dJ_dTb, do
         for (int k = 0; k < 2; ++k) {
             A.lf[k] = m[i].lf[k];
             A.lT[k] = m[i].lT[k];
+            A.gr[k] = m[i].gr[k];
         }
         A.gx = m[i].gx;
         A.blk0 = (int)hamap.size();
@@ -1322,6 +1324,7 @@ int adjoint_run(AdjGroup &g, int64_t N, int64_t K, double *J, double *dJ_dTb, do
     for (int i = 0; i < nm; ++i) {
         LBB_HIP(hipMemsetAsync(m[i].lf[0], 0, 9 * m[i].n * sizeof(double), st));
         LBB_HIP(hipMemsetAsync(m[i].lT[0], 0, m[i].n * sizeof(double), st));
+        LBB_HIP(hipMemsetAsync(m[i].gr[0], 0, m[i].n * sizeof(double), st));
         LBB_HIP(hipMemsetAsync(m[i].w.scal, 0, 4 * sizeof(double), st));
     }
     const dim3 grid(tot), blk(NTA);
