@@ -226,6 +226,35 @@ int lbb_batch_adjoint(lbb_batch *b, int64_t N, int64_t K, double *J, double *dJ_
 /* Device bytes held by the batch: its members and its adjoint workspace. */
 int lbb_batch_info(lbb_batch *b, int64_t *device_bytes);
 
+/* ---- Tile shapes and autotuning ---------------------------------------
+ * The LB launch works on tiles 62 nodes wide and the thermal launch on tiles
+ * 56 wide (plus their halos, one wave64 wide); their heights and waves per
+ * block come from small tables of shapes.  lbb_tile_shapes reports them:
+ * n_lb and n_thermal entries of (width, height, waves) in lb[3 n_lb] and
+ * thermal[3 n_thermal] (any pointer may be NULL).  Shape 0 of each is the
+ * default of a new domain or batch.  Results do not depend on the shapes
+ * beyond the summation order of the domain-mean density (ulp level). */
+int lbb_tile_shapes(int32_t *n_lb, int32_t *n_thermal, int32_t *lb, int32_t *thermal);
+int lbb_get_tiles(lbb_domain *d, int32_t *shape_lb, int32_t *shape_thermal);
+/* Select the shapes (indices into the tables); EINVAL for an unknown index.
+ * A batch member takes its batch's shapes when the batch next steps. */
+int lbb_set_tiles(lbb_domain *d, int32_t shape_lb, int32_t shape_thermal);
+/* Time every LB shape, then every thermal shape with the best LB shape, for
+ * `steps` steps each on the domain's own state (per-kernel durations from
+ * events recorded by the dispatches), keep the fastest of each, and restore
+ * the state, step count and heat-flux average.  Outputs (may be NULL): the
+ * chosen shapes and the mean durations in ms per shape (ms_lb[n_lb],
+ * ms_thermal[n_thermal]).  EINVAL for steps < 1; ESTATE on a poisoned
+ * domain; ENONFINITE if a trial step produces an invalid state (the state is
+ * restored all the same). */
+int lbb_autotune(lbb_domain *d, int32_t steps, int32_t *shape_lb, int32_t *shape_thermal, double *ms_lb,
+                 double *ms_thermal);
+int lbb_batch_set_tiles(lbb_batch *b, int32_t shape_lb, int32_t shape_thermal);
+/* As lbb_autotune, for the batch's shared launches (one shape pair for all
+ * members). */
+int lbb_batch_autotune(lbb_batch *b, int32_t steps, int32_t *shape_lb, int32_t *shape_thermal, double *ms_lb,
+                       double *ms_thermal);
+
 /* Current step count, grid shape and device bytes held by the domain. */
 int lbb_info(lbb_domain *d, int64_t *t, int32_t *nx, int32_t *ny, int64_t *device_bytes);
 

@@ -15,7 +15,7 @@
 //   partials         per-block FP64 partial sums of mass and heat flux.
 //
 // One step t -> t+1 is two launches:
-//   k_lb      : per tile (62x12, halo 1; 4 waves): rho and psi (FP64 EOS, Eq. (21)) of
+//   k_lb      : per tile (62 x 12 by default, halo 1): rho and psi (FP64 EOS, Eq. (21)) of
 //               the tile and its halo into LDS; per interior node the forces
 //               (Eqs. (7), (9), (22)), velocity (Eq. (6)), MRT collision with
 //               the improved forcing (Eqs. (2), (4), (5), (8)) and push
@@ -23,7 +23,7 @@
 //               of the streamed state (exact identity, so the next step's
 //               rho_ave needs no extra pass).  One extra block reduces the
 //               heat-flux partials of the previous thermal launch.
-//   k_thermal: per tile (56x24, halo 4; 16 waves): RK4 (Eqs. (19)-(20)) of Eq. (18) in
+//   k_thermal: per tile (56 x 24 by default, halo 4): RK4 (Eqs. (19)-(20)) of Eq. (18) in
 //               LDS with the region shrinking by one node per stage; FP64
 //               heat-flux partials of the new state on the bottom tile row.
 //               One extra block reduces the mass partials of k_lb into
@@ -40,17 +40,22 @@ constexpr int NT = 256;   // threads per block of the small kernels (4 waves)
 constexpr int TXR = 64;   // read-back tile
 constexpr int TYR = 8;
 constexpr int TXA = 62;   // LB tile width: tile + halo of one is one wave wide
-constexpr int TYA = 12;   // LB tile height
-constexpr int NWA = 4;    // waves per LB block
-constexpr int IPW_A = TYA / NWA;  // interior rows per LB wave
-static_assert(TYA % NWA == 0, "LB rows must split evenly over the waves");
 constexpr int HB = 4;     // thermal halo (RK4 has four stencil stages)
 constexpr int TXB = 64 - 2 * HB;  // thermal tile width: tile + halo is one wave wide
-constexpr int NWB = 16;   // waves per thermal block
 
-// Thermal tile height and the type of the RK4 stage arithmetic: FP64 storage
-// keeps FP64; FP32 storage runs the stages in FP32 on T - T_s (rounding
-// ~4e-10 absolute) with the EOS coefficients formed in FP64.
+// Tile shapes the launches can take (height, waves per block); the host picks
+// one of each per lattice or batch, by default or by timing them on the
+// lattice (autotune).  Index 0 is the default.
+struct TileShape {
+    int ty, nw;
+};
+constexpr int NSHAPE_A = 4, NSHAPE_B = 4;
+constexpr TileShape kShapeA[NSHAPE_A] = {{12, 4}, {8, 4}, {6, 2}, {4, 2}};
+constexpr TileShape kShapeB[NSHAPE_B] = {{24, 16}, {40, 16}, {16, 16}, {8, 8}};
+
+// Type of the RK4 stage arithmetic: FP64 storage keeps FP64; FP32 storage
+// runs the stages in FP32 on T - T_s (rounding ~4e-10 absolute) with the EOS
+// coefficients formed in FP64.
 template <typename S> struct ThermalCfg;
 // sqrt of the stage arithmetic: correctly rounded in FP64, the hardware
 // instruction (1 ulp) in FP32
@@ -58,11 +63,9 @@ __device__ __forceinline__ double stage_sqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float stage_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 template <> struct ThermalCfg<float> {
     using C = float;
-    static constexpr int TY = 24;
 };
 template <> struct ThermalCfg<double> {
     using C = double;
-    static constexpr int TY = 24;
 };
 
 enum : int { MODE_COUPLED = 0, MODE_ISOTHERMAL = 1, MODE_THERMAL_ONLY = 2 };
@@ -365,7 +368,7 @@ __device__ __forceinline__ void tile_psi(const DevParams &P, const S *__restrict
 // lane = column, and each of the NWA waves owns every NWA-th row.  Phase 1
 // forms rho and psi (FP64 EOS) on the tile and halo, keeping each node's
 // populations in registers; phase 2 collides the interior nodes and pushes.
-template <typename S>
+template <typename S, int TYA, int NWA>
 __global__ __launch_bounds__(64 * NWA) void k_lb(const Inst *__restrict__ insts, const int *__restrict__ blk2inst,
                                                  int cf, int cT)
 {
@@ -381,6 +384,8 @@ __global__ __launch_bounds__(64 * NWA) void k_lb(const Inst *__restrict__ insts,
     Scalars *__restrict__ sc = I.sc;
     const int nbx = I.nbxA, nby = I.nbyA;
     const int blk = (int)blockIdx.x - I.blkA0;
+    static_assert(TYA % NWA == 0, "LB rows must split evenly over the waves");
+    constexpr int IPW_A = TYA / NWA;             // interior rows per wave
     constexpr int H = TYA + 2;                   // region rows (halo rows 0 and H-1)
     __shared__ double psi_s[H * 64];
     __shared__ double red[NWA];
@@ -548,7 +553,7 @@ __global__ __launch_bounds__(64 * NWA) void k_lb(const Inst *__restrict__ insts,
 // region; stage k is evaluated on the region shrunk by k+1 nodes, with the
 // stage values updated in place between barriers and the RK4 sums in
 // registers.
-template <typename S>
+template <typename S, int TY, int NWB>
 __global__ __launch_bounds__(64 * NWB) void k_thermal(const Inst *__restrict__ insts,
                                                       const int *__restrict__ blk2inst, int cf, int cT)
 {
@@ -564,7 +569,6 @@ __global__ __launch_bounds__(64 * NWB) void k_thermal(const Inst *__restrict__ i
     const int nbx = I.nbxB, nby = I.nbyB;
     const int blk = (int)blockIdx.x - I.blkB0;
     using C = typename ThermalCfg<S>::C;
-    constexpr int TY = ThermalCfg<S>::TY;
     constexpr int H = TY + 2 * HB;               // region rows
     constexpr int RPW = (H + NWB - 1) / NWB;     // region rows per wave
     __shared__ C T0[H][64];

@@ -151,6 +151,7 @@ struct lbb_domain {
     double *mass_part = nullptr, *hf_part = nullptr, *Tb_dev = nullptr;
     lbb::Scalars *sc = nullptr;
     int nbxA = 0, nbyA = 0, nbxB = 0, nbyB = 0;
+    int shA = 0, shB = 0;                // tile shapes (indices into kShapeA, kShapeB)
     int cf = 0, cT = 0;
     lbb::Inst *d_inst = nullptr;         // this lattice as a one-entry launch table
     int *d_blkA = nullptr, *d_blkB = nullptr;
@@ -160,6 +161,10 @@ struct lbb_domain {
     int64_t dev_bytes = 0;
     void *adj_mem = nullptr;             // adjoint workspace, kept between calls
     size_t adj_bytes = 0;
+};
+
+struct lbb_param_dims {
+    int nx, ny;
 };
 
 namespace {
@@ -231,37 +236,78 @@ int push_inst(lbb_domain *d)
 
 // The optional events are recorded by the dispatch itself (start and end of
 // the kernel), so their interval is the kernel's own duration.
-template <typename S>
-void launch_lb(hipStream_t st, const lbb::Inst *insts, const int *blk, int nblocks, int cf, int cT,
-               hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr)
+template <typename K, typename... A>
+void launch_kernel(K kern, int nblocks, int nthreads, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1, A... args)
 {
     if (ev0)
-        hipExtLaunchKernelGGL(lbb::k_lb<S>, dim3(nblocks), dim3(64 * lbb::NWA), 0, st, ev0, ev1, 0, insts, blk, cf, cT);
+        hipExtLaunchKernelGGL(kern, dim3(nblocks), dim3(nthreads), 0, st, ev0, ev1, 0, args...);
     else
-        hipLaunchKernelGGL(lbb::k_lb<S>, dim3(nblocks), dim3(64 * lbb::NWA), 0, st, insts, blk, cf, cT);
+        hipLaunchKernelGGL(kern, dim3(nblocks), dim3(nthreads), 0, st, args...);
+}
+
+// LB and thermal launches in tile shape `sh` (an index into kShapeA or
+// kShapeB).  The optional events are recorded by the dispatch itself (start
+// and end of the kernel), so their interval is the kernel's own duration.
+template <typename S>
+void launch_lb(hipStream_t st, const lbb::Inst *insts, const int *blk, int nblocks, int cf, int cT, int sh,
+               hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr)
+{
+    using namespace lbb;
+    switch (sh) {
+    case 1: launch_kernel(k_lb<S, kShapeA[1].ty, kShapeA[1].nw>, nblocks, 64 * kShapeA[1].nw, st, ev0, ev1, insts, blk, cf, cT); break;
+    case 2: launch_kernel(k_lb<S, kShapeA[2].ty, kShapeA[2].nw>, nblocks, 64 * kShapeA[2].nw, st, ev0, ev1, insts, blk, cf, cT); break;
+    case 3: launch_kernel(k_lb<S, kShapeA[3].ty, kShapeA[3].nw>, nblocks, 64 * kShapeA[3].nw, st, ev0, ev1, insts, blk, cf, cT); break;
+    default: launch_kernel(k_lb<S, kShapeA[0].ty, kShapeA[0].nw>, nblocks, 64 * kShapeA[0].nw, st, ev0, ev1, insts, blk, cf, cT); break;
+    }
 }
 
 template <typename S>
-void launch_thermal(hipStream_t st, const lbb::Inst *insts, const int *blk, int nblocks, int cf, int cT,
+void launch_thermal(hipStream_t st, const lbb::Inst *insts, const int *blk, int nblocks, int cf, int cT, int sh,
                     hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr)
 {
-    if (ev0)
-        hipExtLaunchKernelGGL(lbb::k_thermal<S>, dim3(nblocks), dim3(64 * lbb::NWB), 0, st, ev0, ev1, 0, insts, blk,
-                              cf, cT);
-    else
-        hipLaunchKernelGGL(lbb::k_thermal<S>, dim3(nblocks), dim3(64 * lbb::NWB), 0, st, insts, blk, cf, cT);
+    using namespace lbb;
+    switch (sh) {
+    case 1: launch_kernel(k_thermal<S, kShapeB[1].ty, kShapeB[1].nw>, nblocks, 64 * kShapeB[1].nw, st, ev0, ev1, insts, blk, cf, cT); break;
+    case 2: launch_kernel(k_thermal<S, kShapeB[2].ty, kShapeB[2].nw>, nblocks, 64 * kShapeB[2].nw, st, ev0, ev1, insts, blk, cf, cT); break;
+    case 3: launch_kernel(k_thermal<S, kShapeB[3].ty, kShapeB[3].nw>, nblocks, 64 * kShapeB[3].nw, st, ev0, ev1, insts, blk, cf, cT); break;
+    default: launch_kernel(k_thermal<S, kShapeB[0].ty, kShapeB[0].nw>, nblocks, 64 * kShapeB[0].nw, st, ev0, ev1, insts, blk, cf, cT); break;
+    }
 }
 
 template <typename S>
 void launch_lb(lbb_domain *d, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr)
 {
-    launch_lb<S>(d->stream, d->d_inst, d->d_blkA, d->nbxA * d->nbyA + 1, d->cf, d->cT, ev0, ev1);
+    launch_lb<S>(d->stream, d->d_inst, d->d_blkA, d->nbxA * d->nbyA + 1, d->cf, d->cT, d->shA, ev0, ev1);
 }
 
 template <typename S>
 void launch_thermal(lbb_domain *d, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr)
 {
-    launch_thermal<S>(d->stream, d->d_inst, d->d_blkB, d->nbxB * d->nbyB + 1, d->cf, d->cT, ev0, ev1);
+    launch_thermal<S>(d->stream, d->d_inst, d->d_blkB, d->nbxB * d->nbyB + 1, d->cf, d->cT, d->shB, ev0, ev1);
+}
+
+// Grid of the domain's launches for its tile shapes.
+void set_grid(lbb_domain *d)
+{
+    d->nbxA = (d->p.nx + lbb::TXA - 1) / lbb::TXA;
+    d->nbyA = (d->p.ny + lbb::kShapeA[d->shA].ty - 1) / lbb::kShapeA[d->shA].ty;
+    d->nbxB = (d->p.nx + lbb::TXB - 1) / lbb::TXB;
+    d->nbyB = (d->p.ny + lbb::kShapeB[d->shB].ty - 1) / lbb::kShapeB[d->shB].ty;
+}
+
+// Largest block counts over all tile shapes (sizes of the partial-sum and
+// block-table buffers).
+int max_blocks_A(const lbb_param_dims &g)
+{
+    int m = 0;
+    for (const auto &t : lbb::kShapeA) m = std::max(m, ((g.nx + lbb::TXA - 1) / lbb::TXA) * ((g.ny + t.ty - 1) / t.ty));
+    return m;
+}
+int max_blocks_B(const lbb_param_dims &g)
+{
+    int m = 0;
+    for (const auto &t : lbb::kShapeB) m = std::max(m, ((g.nx + lbb::TXB - 1) / lbb::TXB) * ((g.ny + t.ty - 1) / t.ty));
+    return m;
 }
 
 void advance_buffers(lbb_domain *d)
@@ -582,11 +628,9 @@ int lbb_init_domain(const lbb_params *pin, const double *T_bottom, const double 
     q.sig_z = p.sigma / (1.0 / p.s_zeta - 0.5);
     q.inv_Tc = 1.0 / Tc;
     q.two_over_G = 2.0 / p.G;
-    d->nbxA = (p.nx + lbb::TXA - 1) / lbb::TXA;
-    d->nbyA = (p.ny + lbb::TYA - 1) / lbb::TYA;
-    d->nbxB = (p.nx + lbb::TXB - 1) / lbb::TXB;
-    const int tyB = p.precision == LBB_FP64 ? lbb::ThermalCfg<double>::TY : lbb::ThermalCfg<float>::TY;
-    d->nbyB = (p.ny + tyB - 1) / tyB;
+    set_grid(d);
+    const lbb_param_dims dims{p.nx, p.ny};
+    const int mbA = max_blocks_A(dims), mbB = max_blocks_B(dims);
 
     auto alloc = [&](void **ptr, size_t bytes) -> bool {
         if (hipMalloc(ptr, bytes) != hipSuccess) return false;
@@ -598,13 +642,13 @@ int lbb_init_domain(const lbb_params *pin, const double *T_bottom, const double 
     ok = ok && alloc(&d->f[0], 9 * N * es) && alloc(&d->f[1], 9 * N * es);
     ok = ok && alloc(&d->T[0], N * es) && alloc(&d->T[1], N * es);
     ok = ok && alloc(&d->rho, N * es) && alloc(&d->vx, N * es) && alloc(&d->vy, N * es);
-    ok = ok && alloc((void **)&d->mass_part, (size_t)d->nbxA * d->nbyA * sizeof(double));
+    ok = ok && alloc((void **)&d->mass_part, (size_t)mbA * sizeof(double));
     ok = ok && alloc((void **)&d->hf_part, (size_t)d->nbxB * sizeof(double));
     ok = ok && alloc((void **)&d->Tb_dev, (size_t)p.nx * sizeof(double));
     ok = ok && alloc((void **)&d->sc, sizeof(lbb::Scalars));
     ok = ok && alloc((void **)&d->d_inst, sizeof(lbb::Inst));
-    ok = ok && alloc((void **)&d->d_blkA, (size_t)(d->nbxA * d->nbyA + 1) * sizeof(int));
-    ok = ok && alloc((void **)&d->d_blkB, (size_t)(d->nbxB * d->nbyB + 1) * sizeof(int));
+    ok = ok && alloc((void **)&d->d_blkA, (size_t)(mbA + 1) * sizeof(int));
+    ok = ok && alloc((void **)&d->d_blkB, (size_t)(mbB + 1) * sizeof(int));
     if (!ok) {
         (void)hipGetLastError();
         release(d);
@@ -899,6 +943,7 @@ struct lbb_batch {
     int totA = 0, totB = 0;
     int cf = 0, cT = 0;
     int precision = 0, mode = 0;
+    int shA = 0, shB = 0;                // tile shapes of the batch's launches
     hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     void *adj_mem = nullptr;             // adjoint workspace, kept between calls
     size_t adj_bytes = 0;
@@ -917,9 +962,54 @@ static void batch_release(lbb_batch *b)
     delete b;
 }
 
-// Upload the launch table (all members, with their block offsets).
+static void batch_drop_graphs(lbb_batch *b)
+{
+    for (auto &row : b->graph)
+        for (auto &g : row)
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
+}
+
+// Block -> member tables of the batch's launches for its tile shapes (the
+// buffers are sized for the largest block counts).
+static int batch_tables(lbb_batch *b)
+{
+    std::vector<int> ta, tb;
+    b->totA = b->totB = 0;
+    for (size_t i = 0; i < b->doms.size(); ++i) {
+        lbb_domain *d = b->doms[i];
+        ta.insert(ta.end(), d->nbxA * d->nbyA + 1, (int)i);
+        tb.insert(tb.end(), d->nbxB * d->nbyB + 1, (int)i);
+        b->totA += d->nbxA * d->nbyA + 1;
+        b->totB += d->nbxB * d->nbyB + 1;
+    }
+    LBB_HIP(hipMemcpy(b->d_blkA, ta.data(), ta.size() * sizeof(int), hipMemcpyHostToDevice));
+    LBB_HIP(hipMemcpy(b->d_blkB, tb.data(), tb.size() * sizeof(int), hipMemcpyHostToDevice));
+    return LBB_OK;
+}
+
+// Upload the launch table (all members, with their block offsets); members
+// take the batch's tile shapes.
 static int batch_push(lbb_batch *b)
 {
+    bool regrid = false;
+    for (lbb_domain *d : b->doms)
+        if (d->shA != b->shA || d->shB != b->shB) {
+            d->shA = b->shA;
+            d->shB = b->shB;
+            set_grid(d);
+            drop_graphs(d);
+            int rc = push_inst(d);
+            if (rc) return rc;
+            regrid = true;
+        }
+    if (regrid) {
+        int rc = batch_tables(b);
+        if (rc) return rc;
+        batch_drop_graphs(b);
+    }
     std::vector<lbb::Inst> insts;
     int a0 = 0, b0 = 0;
     for (lbb_domain *d : b->doms) {
@@ -939,11 +1029,11 @@ static int batch_push(lbb_batch *b)
 static void batch_enqueue_step(lbb_batch *b)
 {
     if (b->precision == LBB_FP64) {
-        launch_lb<double>(b->stream, b->d_insts, b->d_blkA, b->totA, b->cf, b->cT);
-        launch_thermal<double>(b->stream, b->d_insts, b->d_blkB, b->totB, b->cf, b->cT);
+        launch_lb<double>(b->stream, b->d_insts, b->d_blkA, b->totA, b->cf, b->cT, b->shA);
+        launch_thermal<double>(b->stream, b->d_insts, b->d_blkB, b->totB, b->cf, b->cT, b->shB);
     } else {
-        launch_lb<float>(b->stream, b->d_insts, b->d_blkA, b->totA, b->cf, b->cT);
-        launch_thermal<float>(b->stream, b->d_insts, b->d_blkB, b->totB, b->cf, b->cT);
+        launch_lb<float>(b->stream, b->d_insts, b->d_blkA, b->totA, b->cf, b->cT, b->shA);
+        launch_thermal<float>(b->stream, b->d_insts, b->d_blkB, b->totB, b->cf, b->cT, b->shB);
     }
     if (b->mode != LBB_THERMAL_ONLY) b->cf ^= 1;
     if (b->mode != LBB_ISOTHERMAL) b->cT ^= 1;
@@ -971,20 +1061,17 @@ extern "C" int lbb_batch_init(const lbb_params *ps, int n, const double *const *
             return fail(rc, m);
         }
         b->doms.push_back(d);
-        b->totA += d->nbxA * d->nbyA + 1;
-        b->totB += d->nbxB * d->nbyB + 1;
     }
-    std::vector<int> ta, tb;
-    for (int i = 0; i < n; ++i) {
-        ta.insert(ta.end(), b->doms[i]->nbxA * b->doms[i]->nbyA + 1, i);
-        tb.insert(tb.end(), b->doms[i]->nbxB * b->doms[i]->nbyB + 1, i);
+    size_t capA = 0, capB = 0;
+    for (lbb_domain *d : b->doms) {
+        const lbb_param_dims dims{d->p.nx, d->p.ny};
+        capA += max_blocks_A(dims) + 1;
+        capB += max_blocks_B(dims) + 1;
     }
     bool ok = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) == hipSuccess &&
               hipMalloc(&b->d_insts, n * sizeof(lbb::Inst)) == hipSuccess &&
-              hipMalloc(&b->d_blkA, ta.size() * sizeof(int)) == hipSuccess &&
-              hipMalloc(&b->d_blkB, tb.size() * sizeof(int)) == hipSuccess &&
-              hipMemcpy(b->d_blkA, ta.data(), ta.size() * sizeof(int), hipMemcpyHostToDevice) == hipSuccess &&
-              hipMemcpy(b->d_blkB, tb.data(), tb.size() * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+              hipMalloc(&b->d_blkA, capA * sizeof(int)) == hipSuccess &&
+              hipMalloc(&b->d_blkB, capB * sizeof(int)) == hipSuccess && batch_tables(b) == LBB_OK;
     if (!ok || batch_push(b) != LBB_OK) {
         (void)hipGetLastError();
         batch_release(b);
@@ -1095,6 +1182,256 @@ extern "C" int lbb_batch_destroy(lbb_batch *b)
 
 }  // extern "C"
 
+// ---- tile shapes and autotuning -------------------------------------------
+
+namespace {
+
+// Device copy of a lattice's current state, counters and heat-flux partials.
+struct SavedState {
+    void *f = nullptr, *T = nullptr;
+    lbb::Scalars *sc = nullptr;
+    double *hf = nullptr;
+    ~SavedState()
+    {
+        for (void *q : {f, T, (void *)sc, (void *)hf})
+            if (q) (void)hipFree(q);
+    }
+};
+
+int save_state_dev(lbb_domain *d, int cf, int cT, SavedState &s, hipStream_t st)
+{
+    const size_t n = d->N, es = d->esz;
+    LBB_HIP(hipMalloc(&s.f, 9 * n * es));
+    LBB_HIP(hipMalloc(&s.T, n * es));
+    LBB_HIP(hipMalloc((void **)&s.sc, sizeof(lbb::Scalars)));
+    LBB_HIP(hipMalloc((void **)&s.hf, d->nbxB * sizeof(double)));
+    LBB_HIP(hipMemcpyAsync(s.f, d->f[cf], 9 * n * es, hipMemcpyDeviceToDevice, st));
+    LBB_HIP(hipMemcpyAsync(s.T, d->T[cT], n * es, hipMemcpyDeviceToDevice, st));
+    LBB_HIP(hipMemcpyAsync(s.sc, d->sc, sizeof(lbb::Scalars), hipMemcpyDeviceToDevice, st));
+    LBB_HIP(hipMemcpyAsync(s.hf, d->hf_part, d->nbxB * sizeof(double), hipMemcpyDeviceToDevice, st));
+    return LBB_OK;
+}
+
+int restore_state_dev(lbb_domain *d, const SavedState &s, hipStream_t st)
+{
+    const size_t n = d->N, es = d->esz;
+    LBB_HIP(hipMemcpyAsync(d->f[0], s.f, 9 * n * es, hipMemcpyDeviceToDevice, st));
+    LBB_HIP(hipMemcpyAsync(d->T[0], s.T, n * es, hipMemcpyDeviceToDevice, st));
+    LBB_HIP(hipMemcpyAsync(d->T[1], s.T, n * es, hipMemcpyDeviceToDevice, st));
+    LBB_HIP(hipMemcpyAsync(d->sc, s.sc, sizeof(lbb::Scalars), hipMemcpyDeviceToDevice, st));
+    LBB_HIP(hipMemcpyAsync(d->hf_part, s.hf, d->nbxB * sizeof(double), hipMemcpyDeviceToDevice, st));
+    d->cf = d->cT = 0;
+    d->poisoned = false;
+    return LBB_OK;
+}
+
+int domain_set_tiles(lbb_domain *d, int a, int b)
+{
+    d->shA = a;
+    d->shB = b;
+    set_grid(d);
+    drop_graphs(d);
+    return push_inst(d);
+}
+
+bool valid_shapes(int a, int b) { return a >= 0 && a < lbb::NSHAPE_A && b >= 0 && b < lbb::NSHAPE_B; }
+
+// Mean kernel durations (ms) of n batch steps, each launch carrying events
+// that its dispatch records; the batch advances n steps.
+template <typename S>
+int batch_time_kernels(lbb_batch *b, int64_t n, double *ms_lb, double *ms_thermal)
+{
+    std::vector<hipEvent_t> ev(4 * (size_t)n, nullptr);
+    for (auto &e : ev) LBB_HIP(hipEventCreate(&e));
+    for (int64_t k = 0; k < n; ++k) {
+        hipEvent_t *e = &ev[4 * k];
+        launch_lb<S>(b->stream, b->d_insts, b->d_blkA, b->totA, b->cf, b->cT, b->shA, e[0], e[1]);
+        launch_thermal<S>(b->stream, b->d_insts, b->d_blkB, b->totB, b->cf, b->cT, b->shB, e[2], e[3]);
+        LBB_HIP(hipGetLastError());
+        if (b->mode != LBB_THERMAL_ONLY) b->cf ^= 1;
+        if (b->mode != LBB_ISOTHERMAL) b->cT ^= 1;
+    }
+    hipLaunchKernelGGL(lbb::k_flush_heat_flux, dim3((unsigned)b->doms.size()), dim3(lbb::NT), 0, b->stream, b->d_insts);
+    LBB_HIP(hipStreamSynchronize(b->stream));
+    double a = 0, c = 0;
+    float ms = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        LBB_HIP(hipEventElapsedTime(&ms, ev[4 * k], ev[4 * k + 1]));
+        a += ms;
+        LBB_HIP(hipEventElapsedTime(&ms, ev[4 * k + 2], ev[4 * k + 3]));
+        c += ms;
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    for (lbb_domain *d : b->doms) {
+        d->cf = b->cf;
+        d->cT = b->cT;
+    }
+    *ms_lb = a / (double)n;
+    *ms_thermal = c / (double)n;
+    for (size_t i = 0; i < b->doms.size(); ++i) {
+        int rc = check_errors(b->doms[i]);
+        if (rc) return fail(rc, "batch member " + std::to_string(i) + ": " + g_err);
+    }
+    return LBB_OK;
+}
+
+// Time every LB shape (thermal shape fixed), then every thermal shape (LB
+// shape at its best), on the lattice's own state; keep the fastest of each.
+// `set` applies a shape pair, `time` advances n steps and returns the mean
+// kernel durations.
+template <typename Set, typename Time>
+int tune_shapes(int steps, Set set, Time time, int a0, int b0, int *best_a, int *best_b, double *ms_lb,
+                double *ms_thermal)
+{
+    double best = 1e300;
+    int ba = a0, bb = b0;
+    for (int a = 0; a < lbb::NSHAPE_A; ++a) {
+        double ta, tb;
+        int rc = set(a, b0);
+        if (!rc) rc = time(1, &ta, &tb);  // first launches of the variant
+        if (!rc) rc = time(steps, &ta, &tb);
+        if (rc) return rc;
+        if (ms_lb) ms_lb[a] = ta;
+        if (ta < best) {
+            best = ta;
+            ba = a;
+        }
+    }
+    best = 1e300;
+    for (int t = 0; t < lbb::NSHAPE_B; ++t) {
+        double ta, tb;
+        int rc = set(ba, t);
+        if (!rc) rc = time(1, &ta, &tb);
+        if (!rc) rc = time(steps, &ta, &tb);
+        if (rc) return rc;
+        if (ms_thermal) ms_thermal[t] = tb;
+        if (tb < best) {
+            best = tb;
+            bb = t;
+        }
+    }
+    *best_a = ba;
+    *best_b = bb;
+    return LBB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbb_tile_shapes(int32_t *n_lb, int32_t *n_thermal, int32_t *lb, int32_t *thermal)
+{
+    if (n_lb) *n_lb = lbb::NSHAPE_A;
+    if (n_thermal) *n_thermal = lbb::NSHAPE_B;
+    for (int i = 0; i < lbb::NSHAPE_A && lb; ++i) {
+        lb[3 * i] = lbb::TXA;
+        lb[3 * i + 1] = lbb::kShapeA[i].ty;
+        lb[3 * i + 2] = lbb::kShapeA[i].nw;
+    }
+    for (int i = 0; i < lbb::NSHAPE_B && thermal; ++i) {
+        thermal[3 * i] = lbb::TXB;
+        thermal[3 * i + 1] = lbb::kShapeB[i].ty;
+        thermal[3 * i + 2] = lbb::kShapeB[i].nw;
+    }
+    return LBB_OK;
+}
+
+int lbb_get_tiles(lbb_domain *d, int32_t *shape_lb, int32_t *shape_thermal)
+{
+    if (!d) return fail(LBB_EINVAL, "domain is NULL");
+    if (shape_lb) *shape_lb = d->shA;
+    if (shape_thermal) *shape_thermal = d->shB;
+    return LBB_OK;
+}
+
+int lbb_set_tiles(lbb_domain *d, int32_t shape_lb, int32_t shape_thermal)
+{
+    if (!d) return fail(LBB_EINVAL, "domain is NULL");
+    if (!valid_shapes(shape_lb, shape_thermal)) return fail(LBB_EINVAL, "unknown tile shape");
+    LBB_HIP(hipStreamSynchronize(d->stream));
+    return domain_set_tiles(d, shape_lb, shape_thermal);
+}
+
+int lbb_autotune(lbb_domain *d, int32_t steps, int32_t *shape_lb, int32_t *shape_thermal, double *ms_lb,
+                 double *ms_thermal)
+{
+    if (!d) return fail(LBB_EINVAL, "domain is NULL");
+    if (steps < 1) return fail(LBB_EINVAL, "steps must be >= 1");
+    if (d->poisoned) return fail(LBB_ESTATE, "domain poisoned by an earlier invalid state; load a state first");
+    SavedState sv;
+    int rc = save_state_dev(d, d->cf, d->cT, sv, d->stream);
+    if (rc) return rc;
+    int ba = d->shA, bb = d->shB;
+    rc = tune_shapes(
+        steps, [&](int a, int b) { return domain_set_tiles(d, a, b); },
+        [&](int64_t n, double *ta, double *tb) {
+            double tt;
+            return lbb_time_kernels(d, n, ta, tb, &tt);
+        },
+        d->shA, d->shB, &ba, &bb, ms_lb, ms_thermal);
+    const std::string err = rc ? g_err : std::string();
+    const int rc2 = domain_set_tiles(d, ba, bb);
+    const int rc3 = restore_state_dev(d, sv, d->stream);
+    LBB_HIP(hipStreamSynchronize(d->stream));
+    if (rc) return fail(rc, err);
+    if (rc2) return rc2;
+    if (rc3) return rc3;
+    if (shape_lb) *shape_lb = ba;
+    if (shape_thermal) *shape_thermal = bb;
+    return LBB_OK;
+}
+
+int lbb_batch_set_tiles(lbb_batch *b, int32_t shape_lb, int32_t shape_thermal)
+{
+    if (!b) return fail(LBB_EINVAL, "batch is NULL");
+    if (!valid_shapes(shape_lb, shape_thermal)) return fail(LBB_EINVAL, "unknown tile shape");
+    LBB_HIP(hipStreamSynchronize(b->stream));
+    b->shA = shape_lb;
+    b->shB = shape_thermal;
+    return batch_push(b);
+}
+
+int lbb_batch_autotune(lbb_batch *b, int32_t steps, int32_t *shape_lb, int32_t *shape_thermal, double *ms_lb,
+                       double *ms_thermal)
+{
+    if (!b) return fail(LBB_EINVAL, "batch is NULL");
+    if (steps < 1) return fail(LBB_EINVAL, "steps must be >= 1");
+    int rc = batch_phase(b);
+    if (rc) return rc;
+    rc = batch_push(b);
+    if (rc) return rc;
+    std::vector<SavedState> sv(b->doms.size());
+    for (size_t i = 0; i < b->doms.size() && !rc; ++i) rc = save_state_dev(b->doms[i], b->cf, b->cT, sv[i], b->stream);
+    if (rc) return rc;
+    int ba = b->shA, bb = b->shB;
+    rc = tune_shapes(
+        steps,
+        [&](int a, int t) {
+            b->shA = a;
+            b->shB = t;
+            return batch_push(b);
+        },
+        [&](int64_t n, double *ta, double *tb) {
+            return b->precision == LBB_FP64 ? batch_time_kernels<double>(b, n, ta, tb)
+                                            : batch_time_kernels<float>(b, n, ta, tb);
+        },
+        b->shA, b->shB, &ba, &bb, ms_lb, ms_thermal);
+    const std::string err = rc ? g_err : std::string();
+    b->shA = ba;
+    b->shB = bb;
+    int rc2 = batch_push(b);
+    for (size_t i = 0; i < b->doms.size() && !rc2; ++i) rc2 = restore_state_dev(b->doms[i], sv[i], b->stream);
+    b->cf = b->cT = 0;
+    LBB_HIP(hipStreamSynchronize(b->stream));
+    if (rc) return fail(rc, err);
+    if (rc2) return rc2;
+    if (shape_lb) *shape_lb = ba;
+    if (shape_thermal) *shape_thermal = bb;
+    return LBB_OK;
+}
+
+}  // extern "C"
+
 // ---- adjoint --------------------------------------------------------------
 
 namespace {
@@ -1122,6 +1459,7 @@ struct AdjGroup {
     int totA = 0, totB = 0;
     std::vector<int> blkA0, blkB0;  // member offsets in the forward grids
     int *cf = nullptr, *cT = nullptr;
+    int shA = 0, shB = 0;           // tile shapes of the forward launches
     void **mem = nullptr;           // cached workspace of the owner
     size_t *bytes = nullptr;
 };
@@ -1227,14 +1565,14 @@ int adjoint_run(AdjGroup &g, int64_t N, int64_t K, double *J, double *dJ_dTb, do
         return e;
     };
     auto own_step = [&]() {
-        launch_lb<S>(st, g.fwd_insts, g.blkA, g.totA, *g.cf, *g.cT);
-        launch_thermal<S>(st, g.fwd_insts, g.blkB, g.totB, *g.cf, *g.cT);
+        launch_lb<S>(st, g.fwd_insts, g.blkA, g.totA, *g.cf, *g.cT, g.shA);
+        launch_thermal<S>(st, g.fwd_insts, g.blkB, g.totB, *g.cf, *g.cT, g.shB);
         *g.cf ^= 1;
         *g.cT ^= 1;
     };
     auto slot_step = [&](int64_t k) {
-        launch_lb<S>(st, inst_seg + k * nm, g.blkA, g.totA, 0, 0);
-        launch_thermal<S>(st, inst_seg + k * nm, g.blkB, g.totB, 0, 0);
+        launch_lb<S>(st, inst_seg + k * nm, g.blkA, g.totA, 0, 0, g.shA);
+        launch_thermal<S>(st, inst_seg + k * nm, g.blkB, g.totB, 0, 0, g.shB);
     };
 
     // keep each lattice's state, counters and heat-flux partials
@@ -1427,6 +1765,8 @@ extern "C" int lbb_adjoint(lbb_domain *d, int64_t N, int64_t K, double *J, doubl
     g.blkB0 = {0};
     g.cf = &d->cf;
     g.cT = &d->cT;
+    g.shA = d->shA;
+    g.shB = d->shB;
     const size_t before = d->adj_bytes;
     g.mem = &d->adj_mem;
     g.bytes = &d->adj_bytes;
@@ -1464,6 +1804,8 @@ extern "C" int lbb_batch_adjoint(lbb_batch *b, int64_t N, int64_t K, double *J, 
     }
     g.cf = &b->cf;
     g.cT = &b->cT;
+    g.shA = b->shA;
+    g.shB = b->shB;
     g.mem = &b->adj_mem;
     g.bytes = &b->adj_bytes;
     return adjoint_group(g, b->precision, N, K, J, dJ_dTb, dJ_dGw);

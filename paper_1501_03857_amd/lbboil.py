@@ -31,6 +31,7 @@ _d = C.c_double
 _pd = C.POINTER(C.c_double)
 _i32 = C.c_int32
 _i64 = C.c_int64
+_pi32 = C.POINTER(C.c_int32)
 
 
 class CParams(C.Structure):
@@ -89,6 +90,12 @@ def lib():
             "lbb_batch_destroy": (C.c_int, [vp]),
             "lbb_adjoint": (C.c_int, [vp, _i64, _i64, _pd, _pd, _pd]),
             "lbb_batch_adjoint": (C.c_int, [vp, _i64, _i64, _pd, _pd, _pd]),
+            "lbb_tile_shapes": (C.c_int, [_pi32, _pi32, _pi32, _pi32]),
+            "lbb_get_tiles": (C.c_int, [vp, _pi32, _pi32]),
+            "lbb_set_tiles": (C.c_int, [vp, C.c_int32, C.c_int32]),
+            "lbb_autotune": (C.c_int, [vp, C.c_int32, _pi32, _pi32, _pd, _pd]),
+            "lbb_batch_set_tiles": (C.c_int, [vp, C.c_int32, C.c_int32]),
+            "lbb_batch_autotune": (C.c_int, [vp, C.c_int32, _pi32, _pi32, _pd, _pd]),
             "lbb_batch_info": (C.c_int, [vp, C.POINTER(_i64)]),
             "lbb_last_error": (C.c_char_p, []),
         }
@@ -243,6 +250,22 @@ class Domain:
     def stream(self) -> int:
         return lib().lbb_stream(self._h)
 
+    @property
+    def tiles(self):
+        """(LB shape, thermal shape) indices into tile_shapes()."""
+        a, b = C.c_int32(), C.c_int32()
+        _check(lib().lbb_get_tiles(self._h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def set_tiles(self, shape_lb: int, shape_thermal: int):
+        _check(lib().lbb_set_tiles(self._h, int(shape_lb), int(shape_thermal)))
+        return self
+
+    def autotune(self, steps: int = 20):
+        """Time every tile shape on this lattice, keep the fastest; the state
+        is left unchanged.  Returns the choice and the per-shape times (ms)."""
+        return _autotune(lib().lbb_autotune, self._h, steps)
+
     def adjoint(self, n_steps: int, K: int = 0):
         """J = mean bottom-wall heat flux over the next n_steps and its
         gradient w.r.t. T_b (all nx) and G_w; the state is left unchanged."""
@@ -302,6 +325,24 @@ class Domain:
     @property
     def t(self) -> int:
         return self.info()["t"]
+
+
+def tile_shapes():
+    """(lb, thermal): lists of (width, height, waves) of the tile shapes."""
+    na, nb = C.c_int32(), C.c_int32()
+    _check(lib().lbb_tile_shapes(C.byref(na), C.byref(nb), None, None))
+    a, b = (C.c_int32 * (3 * na.value))(), (C.c_int32 * (3 * nb.value))()
+    _check(lib().lbb_tile_shapes(None, None, a, b))
+    return ([tuple(a[3 * i:3 * i + 3]) for i in range(na.value)],
+            [tuple(b[3 * i:3 * i + 3]) for i in range(nb.value)])
+
+
+def _autotune(fn, h, steps):
+    na, nb = len(tile_shapes()[0]), len(tile_shapes()[1])
+    sa, sb = C.c_int32(), C.c_int32()
+    ma, mb = np.zeros(na), np.zeros(nb)
+    _check(fn(h, int(steps), C.byref(sa), C.byref(sb), _ptr(ma), _ptr(mb)))
+    return dict(shape_lb=sa.value, shape_thermal=sb.value, ms_lb=ma, ms_thermal=mb)
 
 
 class Batch:
@@ -387,6 +428,14 @@ class Batch:
         v = _i64()
         _check(lib().lbb_batch_info(self._h, C.byref(v)))
         return v.value
+
+    def set_tiles(self, shape_lb: int, shape_thermal: int):
+        _check(lib().lbb_batch_set_tiles(self._h, int(shape_lb), int(shape_thermal)))
+        return self
+
+    def autotune(self, steps: int = 20):
+        """As Domain.autotune, for the batch's shared launches."""
+        return _autotune(lib().lbb_batch_autotune, self._h, steps)
 
     def domain(self, i: int) -> Domain:
         h = lib().lbb_batch_domain(self._h, int(i))

@@ -101,3 +101,24 @@ def test_batch_rejects_mixed_precision_and_empty():
     assert e.value.code == L.LBB_EINVAL
     with pytest.raises(L.LbbError):
         L.Batch([])
+
+
+def test_tile_shape_tables():
+    """The tile shapes: each tile plus its halo is one wave64 wide, heights
+    split evenly over the waves of the LB launch."""
+    lb, th = L.tile_shapes()
+    assert len(lb) >= 2 and len(th) >= 2
+    for w, h, nw in lb:
+        assert w + 2 == 64 and h % nw == 0 and 1 <= nw <= 16
+    for w, h, nw in th:
+        assert w + 8 == 64 and h >= 1 and 1 <= nw <= 16
+    assert lb[0] == (62, 12, 4) and th[0] == (56, 24, 16)
+
+
+def test_tile_calls_reject_bad_arguments():
+    lib = L.lib()
+    assert lib.lbb_set_tiles(None, 0, 0) == L.LBB_EINVAL
+    assert lib.lbb_get_tiles(None, None, None) == L.LBB_EINVAL
+    assert lib.lbb_autotune(None, 5, None, None, None, None) == L.LBB_EINVAL
+    assert lib.lbb_batch_set_tiles(None, 0, 0) == L.LBB_EINVAL
+    assert lib.lbb_batch_autotune(None, 5, None, None, None, None) == L.LBB_EINVAL

@@ -1,0 +1,111 @@
+"""Every tile shape of the LB and thermal launches against the oracle, and
+the autotuner: it may only change speed, never the state it was given."""
+import itertools
+
+import numpy as np
+import pytest
+
+from paper_1501_03857_amd import lbboil as L
+from paper_1501_03857_amd import workloads as WL
+from parity_utils import compare, make_pair
+
+pytestmark = pytest.mark.gpu
+
+NA, NB = (len(x) for x in L.tile_shapes())
+COMBOS = list(itertools.product(range(NA), range(NB)))
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ragged_walls():
+    w = WL.PLAIN_128x64.resized(100, 37, heater=(25, 51), Gw_bottom=0.05)
+    o, _, _ = make_pair(w, Gw_top=-0.03)
+    o.step(60)
+    return w, o
+
+
+@pytest.fixture(scope="module")
+def ragged_periodic():
+    w = WL.PLAIN_128x64.resized(70, 37, heater=(10, 30))
+    o, _, _ = make_pair(w, periodic_y=1)
+    o.step(60)
+    return w, o
+
+
+@pytest.mark.parametrize("shape_lb,shape_thermal", COMBOS)
+def test_every_tile_shape_matches_oracle_walls(ragged_walls, shape_lb, shape_thermal):
+    _say("tiles walls", shape_lb, shape_thermal)
+    w, o = ragged_walls
+    _, d, _ = make_pair(w, Gw_top=-0.03)
+    d.set_tiles(shape_lb, shape_thermal)
+    assert d.tiles == (shape_lb, shape_thermal)
+    d.step(60)
+    errs, bad = compare(o, d, 1e-12)
+    assert not bad, errs
+
+
+@pytest.mark.parametrize("shape_lb,shape_thermal", COMBOS)
+def test_every_tile_shape_matches_oracle_periodic(ragged_periodic, shape_lb, shape_thermal):
+    _say("tiles periodic", shape_lb, shape_thermal)
+    w, o = ragged_periodic
+    _, d, _ = make_pair(w, periodic_y=1)
+    d.set_tiles(shape_lb, shape_thermal)
+    d.step(60)
+    errs, bad = compare(o, d, 1e-12)
+    assert not bad, errs
+
+
+@pytest.mark.parametrize("shape", range(max(NA, NB)))
+def test_tile_shapes_fp32(shape):
+    _say("tiles fp32", shape)
+    o, d, _ = make_pair(WL.PLAIN_128x64, precision=L.FP32)
+    d.set_tiles(shape % NA, shape % NB)
+    o.step(100)
+    d.step(100)
+    errs, bad = compare(o, d, 1e-5)
+    assert not bad, errs
+
+
+def test_autotune_leaves_state_and_keeps_parity():
+    _say("autotune domain")
+    o, d, _ = make_pair(WL.PLAIN_128x64)
+    o.step(40)
+    d.step(20)
+    before, hf0 = d.fields(), d.heat_flux()
+    r = d.autotune(6)
+    assert 0 <= r["shape_lb"] < NA and 0 <= r["shape_thermal"] < NB
+    assert d.tiles == (r["shape_lb"], r["shape_thermal"])
+    assert np.all(r["ms_lb"] > 0) and np.all(r["ms_thermal"] > 0)
+    after, hf1 = d.fields(), d.heat_flux()
+    for k in ("f", "T", "rho", "ux", "uy"):
+        assert np.array_equal(before[k], after[k]), k
+    assert hf0["n_samples"] == hf1["n_samples"] == 20 and hf0["q_mean"] == hf1["q_mean"]
+    d.step(20)
+    errs, bad = compare(o, d, 1e-12)
+    assert not bad, errs
+
+
+def test_batch_tiles_and_autotune():
+    _say("batch tiles")
+    ws = [WL.PLAIN_128x64, WL.PLAIN_128x64.resized(100, 37, heater=(10, 60), Gw_bottom=0.065, seed=5)]
+    pairs = [make_pair(w) for w in ws]
+    b = L.Batch([L.Params(nx=w.nx, ny=w.ny, liquid_rows=w.liquid_rows, sigma=w.sigma, g=w.g, Gw_bottom=w.Gw_bottom,
+                          rho_L=x[2]["rho_L"], rho_V=x[2]["rho_V"]) for w, x in zip(ws, pairs)],
+                [x[2]["Tb"] for x in pairs], [w.density(x[2]["rho_L"], x[2]["rho_V"]) for w, x in zip(ws, pairs)])
+    b.set_tiles(2, 3)
+    b.step(33)
+    for i, (_, d, _) in enumerate(pairs):
+        d.set_tiles(2, 3).step(33)
+        assert np.array_equal(b.domain(i).fields()["f"], d.fields()["f"]), i
+    before = [b.domain(i).fields() for i in range(2)]
+    r = b.autotune(4)
+    assert 0 <= r["shape_lb"] < NA and 0 <= r["shape_thermal"] < NB
+    for i in range(2):
+        assert np.array_equal(before[i]["f"], b.domain(i).fields()["f"]), i
+    b.step(7)
+    for i, (_, d, _) in enumerate(pairs):
+        d.set_tiles(r["shape_lb"], r["shape_thermal"]).step(7)
+        assert np.array_equal(b.domain(i).fields()["f"], d.fields()["f"]), i
