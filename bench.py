@@ -82,10 +82,12 @@ def cpu_baseline(w, steps):
                       f"({w.nx * w.ny * steps:.3g} lattice updates, {dt:.1f} s)"}
 
 
-def sweep_bench(steps, warmup=50):
+def sweep_bench(steps, warmup=50, tune_steps=10):
     """The 48-lattice boiling-curve sweep: aggregate MLUPS of one batch
-    (shared launches) against the same lattices run one after another through
-    the single-lattice path, each timed with HIP events on its stream."""
+    (shared launches, autotuned) against the same lattices run one after
+    another through the single-lattice path with its default tiles ("plain"),
+    and again with each lattice autotuned; each timed with HIP events on its
+    stream."""
     import torch
     from paper_1501_03857_amd import lbboil as L
     from paper_1501_03857_amd import workloads as WL
@@ -112,31 +114,41 @@ def sweep_bench(steps, warmup=50):
         return e0.elapsed_time(e1)
 
     b = L.Batch(params, tbs, rhos)
+    tb_tiles = b.autotune(tune_steps)
     b.step(warmup)
     ms_batch = timed(b, steps)
     q_batch = b.heat_flux()["q_mean"]
     b.close()
-    ms_plain = 0.0
+    ms_plain = ms_tuned = 0.0
     for p, tb, rho in zip(params, tbs, rhos):
         d = L.Domain(p, T_bottom=tb, rho0=rho)
         d.step(warmup)
         ms_plain += timed(d, steps)
         d.close()
+        d = L.Domain(p, T_bottom=tb, rho0=rho)
+        d.autotune(tune_steps)
+        d.step(warmup)
+        ms_tuned += timed(d, steps)
+        d.close()
     mb = cells * steps / (ms_batch * 1e-3) / 1e6
     mp = cells * steps / (ms_plain * 1e-3) / 1e6
+    mt = cells * steps / (ms_tuned * 1e-3) / 1e6
     sizes = {}
     for w in ws:
         sizes[f"{w.nx}x{w.ny}"] = sizes.get(f"{w.nx}x{w.ny}", 0) + 1
     return {"instances": len(ws), "cells": cells, "steps": steps, "sizes": sizes,
             "batched_mlups": round(mb, 1), "plain_sequential_mlups": round(mp, 1),
             "speedup": round(mb / mp, 2), "batched_ms": round(ms_batch, 3), "plain_ms": round(ms_plain, 3),
+            "sequential_autotuned_mlups": round(mt, 1), "speedup_vs_autotuned": round(mb / mt, 2),
+            "batch_tiles": [tb_tiles["shape_lb"], tb_tiles["shape_thermal"]],
             "q_mean_range": [float(min(q_batch)), float(max(q_batch))]}
 
 
 def adjoint_bench():
     """Cost of the adjoint against the forward on the adjoint workload
-    (256x128, heater i in [96, 160) at 0.10 T_c, G_w = 0.065, 400 steps,
-    checkpoints every 50), wall time of synchronous calls."""
+    (256x128, heater i in [96, 160) at 0.10 T_c, G_w = 0.065, 400 steps),
+    autotuned tiles, wall time of synchronous calls: checkpoints every 50
+    with recompute, and with the interval the library picks (K <= 0)."""
     from paper_1501_03857_amd import lbboil as L
     from paper_1501_03857_amd import workloads as WL
 
@@ -148,6 +160,7 @@ def adjoint_bench():
         p = L.Params(nx=w.nx, ny=w.ny, precision=prec, liquid_rows=w.liquid_rows, sigma=w.sigma, g=w.g,
                      Gw_bottom=w.Gw_bottom, rho_L=rl, rho_V=rv)
         d = L.Domain(p, T_bottom=w.heater_T(Tc), rho0=w.density(rl, rv))
+        d.autotune(20)
         d.adjoint(8, 4)  # warm-up (allocations, first launches)
         d.step(8)
         blob = d.save()
@@ -158,8 +171,14 @@ def adjoint_bench():
         t0 = time.perf_counter()
         J, g, gw = d.adjoint(w.steps, 50)
         adj = time.perf_counter() - t0
+        d.adjoint(8, 0)
+        t0 = time.perf_counter()
+        d.adjoint(w.steps, 0)
+        adj_auto = time.perf_counter() - t0
         out[name] = {"forward_ms": round(fwd * 1e3, 3), "adjoint_ms": round(adj * 1e3, 3),
-                     "ratio": round(adj / fwd, 2), "J": J, "dJ_dGw": gw}
+                     "ratio": round(adj / fwd, 2), "adjoint_auto_K_ms": round(adj_auto * 1e3, 3),
+                     "ratio_auto_K": round(adj_auto / fwd, 2), "J": J, "dJ_dGw": gw,
+                     "tiles": list(d.tiles)}
         d.close()
     return out
 
@@ -184,6 +203,7 @@ def batch_adjoint_bench(steps=600):
         tbs.append(w.heater_T(Tc))
         rhos.append(w.density(rl, rv))
     b = L.Batch(params, tbs, rhos)
+    b.autotune(10)
     b.step(64)  # graph instantiation and first launches
     free0 = torch.cuda.mem_get_info()[0]
     blob = [b.domain(i).save() for i in range(len(ws))]
@@ -216,6 +236,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="large", choices=["large", "large4096", "plain"])
     ap.add_argument("--kernel-steps", type=int, default=400, help="steps timed per launch for the roofline")
+    ap.add_argument("--tune-steps", type=int, default=30,
+                    help="steps per tile shape for the autotuner before timing (0: default shapes)")
     ap.add_argument("--cpu-steps", type=int, default=100, help="oracle steps for the CPU baseline (0: skip)")
     ap.add_argument("--sweep-steps", type=int, default=2000, help="steps of the 48-lattice sweep comparison (0: skip)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost measurement")
@@ -260,8 +282,12 @@ def main():
                  Gw_bottom=w.Gw_bottom, rho_L=rl, rho_V=rv)
     d = L.Domain(p, T_bottom=w.heater_T(Tc), rho0=w.density(rl, rv))
     cells = w.nx * w.ny
-    print(f"[bench] {w.name}: {w.nx}x{w.ny} {store} storage, warmup {args.warmup}, timed {args.steps}",
-          file=sys.stderr, flush=True)
+    tune = d.autotune(args.tune_steps) if args.tune_steps > 0 else None
+    shapes_lb, shapes_th = L.tile_shapes()
+    tiles = {"lb": list(shapes_lb[d.tiles[0]]), "thermal": list(shapes_th[d.tiles[1]]),
+             "autotuned": tune is not None}
+    print(f"[bench] {w.name}: {w.nx}x{w.ny} {store} storage, tiles {tiles}, warmup {args.warmup}, "
+          f"timed {args.steps}", file=sys.stderr, flush=True)
 
     d.step(args.warmup)
     stream = torch.cuda.ExternalStream(d.stream)
@@ -313,7 +339,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "storage": store, "global_batch": 1,
-                   "parallelism": "none", "launches_per_step": 2, "graph_steps": 32},
+                   "parallelism": "none", "launches_per_step": 2, "graph_steps": 32, "tiles": tiles},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "traffic_unit": "bytes per launch",

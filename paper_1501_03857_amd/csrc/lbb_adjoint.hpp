@@ -4,17 +4,16 @@
 // (Eq. (22)).  One reverse step transposes the forward step of
 // lbb_device.hpp stage by stage, in reverse order, over whole-lattice FP64
 // work arrays.  A launch covers any number of lattices through a lattice
-// table (one lattice, or every member of a batch); each block covers a
-// 64 x 4 patch of one lattice (lane = column, wave = row).  Ten launches per
-// reverse step of state t -> t+1:
-//   a_force    forces (Eqs. (7), (9), (22)), Q, velocity (Eq. (6)), grad rho;
+// table (one lattice, or every member of a batch); the per-node kernels work
+// on 64 x 4 patches (lane = column, wave = row), the temperature kernel on
+// tiles with a halo in LDS.  Five launches per reverse step of state
+// t -> t+1:
+//   a_force    forces (Eqs. (7), (9), (22)), velocity (Eq. (6)), grad rho;
 //              rho_ave from the mass partials of the state
-//   a_divv0    div v seen by the temperature equation, the per-node
-//              coefficients of Eq. (18), and the first RK4 stage input T_2
-//   a_stage    RK4 stage inputs T_3, T_4 (Eqs. (19)-(20))
-//   a_tstage   one RK4 stage transposed (four launches, last stage first):
-//              the Eq. (18) stencils gathered from the neighbours, the
-//              pressure-work term differentiated in T and rho
+//   a_divv0    div v seen by the temperature equation and the per-node
+//              coefficients of Eq. (18)
+//   a_theradj  the RK4 temperature step (Eqs. (18)-(20)) transposed: stage
+//              inputs recomputed and the four stages transposed in one tile
 //   a_lb       stencil transposes of grad rho and div v (gather), push
 //              streaming transposed (gather), MRT collision transposed in
 //              moment space, velocity transposed, per-node force parts
@@ -46,8 +45,6 @@ struct AdjW {
     // IB = a rho / ((1 + 2 b rho - b^2 rho^2) c_v); E1, E2 give the rho
     // derivative of the pressure-work factor; RI = 1 / rho
     double *divv, *AX, *AY, *IA, *IB, *E1, *E2, *RI;
-    double *Tk[4];   // T_1 (= T1) .. T_4, the RK4 stage inputs
-    double *gh[3];   // adjoints of the slopes h_1 .. h_3 (that of h_4 is lT^{t+1}/6)
     double *gDrx, *gDry, *gdiv, *grho, *gvx, *gvy, *gpsi, *gsx, *gsy;
     double *mpart;   // block mass partials of the state being reversed
     double *fpart;   // block partials of the force adjoint: [2b] rho_ave, [2b+1] G_w
@@ -67,6 +64,7 @@ struct AdjInst {
     int gx;                   // patches per lattice row
     int blk0;                 // first block of this lattice in the grid
     int nb;                   // blocks of this lattice
+    int tgx, tblk0;           // temperature-adjoint tiles per row, first tile in its grid
 };
 
 #define A_INST                                            \
@@ -240,26 +238,7 @@ __global__ __launch_bounds__(NTA) void a_force(A_ARGS)
     w.vy[c] = vy;
 }
 
-// Eq. (18) at interior node c for the stage field Tf, with its stencils and
-// phi'(T), phi''(T) at the node
-__device__ __forceinline__ double a_K(const DevParams &P, const AdjW &w, const double *__restrict__ Tf, int gi, int gj,
-                                      size_t c, double &dTx, double &dTy, double &lap, double &d1, double &d2)
-{
-    const double tc = Tf[c];
-    dTx = dTy = lap = 0.0;
-#pragma unroll
-    for (int a = 1; a < 9; ++a) {
-        const double t = Tf[a_at(P, gi, gj, kEX[a], kEY[a])];
-        dTx += 3.0 * kW[a] * kEX[a] * t;
-        dTy += 3.0 * kW[a] * kEY[a] * t;
-        lap += 6.0 * kW[a] * (t - tc);
-    }
-    phi_derivs(P, tc, d1, d2);
-    const double dv = w.divv[c];
-    return w.AX[c] * dTx + w.AY[c] * dTy + P.chi * lap - w.IA[c] * dv * tc + w.IB[c] * dv * tc * d1;
-}
-
-// div v, the coefficients of Eq. (18), and T_2 = T_1 + K(T_1)/2
+// div v and the coefficients of Eq. (18) at the node (zero on wall rows).
 __global__ __launch_bounds__(NTA) void a_divv0(A_ARGS)
 {
     A_INST
@@ -267,7 +246,6 @@ __global__ __launch_bounds__(NTA) void a_divv0(A_ARGS)
     if (!on) return;
     if (!a_int(P, gj)) {
         w.divv[c] = w.AX[c] = w.AY[c] = w.IA[c] = w.IB[c] = w.E1[c] = w.E2[c] = w.RI[c] = 0.0;
-        w.Tk[1][c] = w.T1[c];
         return;
     }
     double dv = 0.0;
@@ -291,106 +269,201 @@ __global__ __launch_bounds__(NTA) void a_divv0(A_ARGS)
     w.IB[c] = P.a * r * i2 * icv;
     w.E1[c] = P.R * P.b * i1 * i1 * icv;
     w.E2[c] = P.a * (1.0 + P.b * P.b * r * r) * i2 * i2 * icv;
-    double dTx, dTy, lap, d1, d2;
-    const double h = a_K(P, w, w.T1, gi, gj, c, dTx, dTy, lap, d1, d2);
-    w.Tk[1][c] = w.T1[c] + 0.5 * h;
 }
 
-// T_{k+1} = T_1 + c_k K(T_k) on interior rows (T_1 on wall rows)
-__global__ __launch_bounds__(NTA) void a_stage(A_ARGS, int k, double ck)
-{
-    A_INST
-    A_NODE
-    if (!on) return;
-    double h = 0.0;
-    if (a_int(P, gj)) {
-        double dTx, dTy, lap, d1, d2;
-        h = a_K(P, w, w.Tk[k], gi, gj, c, dTx, dTy, lap, d1, d2);
-    }
-    w.Tk[k + 1][c] = w.T1[c] + ck * h;
-}
+// ---------------------------------------------------------------------------
+// The temperature step transposed in one launch: the RK4 stage inputs
+// T_2..T_4 recomputed (Eqs. (19)-(20)) and the four stages transposed, last
+// first, on one tile with a halo of 7 (three forward stencil stages, four
+// reverse ones), in LDS.  Lane = column (tile TAX = 50 wide, one wave64 with
+// the halo), each of the TAW waves owns fixed region rows; tiles are TAY rows
+// high (16, or 8 where 16-row tiles would leave the chip underfilled).  Stage k's slope
+// adjoint is g_k = w_k lT^{t+1}/6 + c_{k+1} gT_{k+1} (RK4 weights w = (1, 2,
+// 2, 1), g_3 = lT^{t+1}/6), gT_k being the adjoint of the stage input T_k,
+// gathered from the slope adjoints of the node and its neighbours.  Outputs
+// on the tile: the adjoint of T^t (lT^{t+1} plus the four gT_k) and the
+// rho, grad rho, v and div v parts of the four stages.
+constexpr int TAH = 7;
+constexpr int TAX = 64 - 2 * TAH;
 
-// Stencils of the stage field Tf at interior node c: d_x, d_y (isotropic,
-// the lattice weights of the gradient)
-__device__ __forceinline__ void a_grad(const DevParams &P, const double *__restrict__ Tf, int gi, int gj,
-                                       double &dTx, double &dTy)
+template <int TAY, int TAW>
+__global__ __launch_bounds__(64 * TAW) void a_theradj(const AdjInst *__restrict__ ai, const int *__restrict__ tmap,
+                                                      int cur)
 {
-    dTx = dTy = 0.0;
-#pragma unroll
-    for (int a = 1; a < 9; ++a) {
-        const double t = Tf[a_at(P, gi, gj, kEX[a], kEY[a])];
-        dTx += 3.0 * kW[a] * kEX[a] * t;
-        dTy += 3.0 * kW[a] * kEY[a] * t;
-    }
-}
-
-// RK4 stage k (slope h_{k+1} = K(T_{k+1})) transposed.  Gathers the adjoint
-// of the stage input at c from the slope adjoints of c and its neighbours,
-// hands c_k times it to the slope of the stage before (whose adjoint is
-// w_k lT^{t+1}/6 plus that, with the RK4 weights w = (1, 2, 2, 1)), and adds
-// it to the adjoint of T^t, which starts from lT^{t+1} (identity part).  The
-// last stage's slope adjoint is lT^{t+1}/6 on interior nodes.  The first
-// stage's launch (k = 0), when every slope adjoint at c is known, also forms
-// the rho, grad rho, v and div v parts of all four stages at c.
-__global__ __launch_bounds__(NTA) void a_tstage(A_ARGS, int k, double ck, int cur)
-{
-    A_INST
-    A_NODE
+    constexpr int H = TAY + 2 * TAH;          // region rows
+    constexpr int RPW = (H + TAW - 1) / TAW;  // region rows per wave
+    // planes 0..3: T_1..T_4; 4: lT^{t+1}; 5: g_2.  g_1 reuses plane 3 once
+    // T_4 is dead, g_0 plane 2 once T_3 is.
+    __shared__ double sb[6][H][64];
+    __shared__ double sAX[H][64], sAY[H][64];
+    const AdjInst &I = ai[tmap[blockIdx.x]];
+    const DevParams P = I.P;
+    const AdjW &w = I.w;
+    const int q = (int)blockIdx.x - I.tblk0;
+    const int x0 = (q % I.tgx) * TAX, y0 = (q / I.tgx) * TAY;
+    static_assert(RPW * TAW >= H, "every region row has a wave");
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int gx = wrapi(x0 + lane - TAH, P.nx);
     const double *__restrict__ lT1 = I.lT[cur];
     double *__restrict__ lT0 = I.lT[cur ^ 1];
-    if (!on) return;
-    const double *gk = k < 3 ? w.gh[k] : lT1;
-    const double sk = k < 3 ? 1.0 : 1.0 / 6.0;
-    double gT = 0.0;
-    // neighbours c' = c - e_a whose stencils read T(c) with weight e_a
+    const double chi = P.chi;
+
+    // region row r of this wave's m-th slot: lattice row, in lattice, interior
+    int gyr[RPW];
+    bool inl[RPW], inr[RPW];
+    double cdv[RPW], cIA[RPW], cIB[RPW];
 #pragma unroll
-    for (int a = 1; a < 9; ++a) {
-        bool ok;
-        const size_t cp = a_src(P, gi, gj, a, c, ok);
-        const double g = (ok ? sk : 0.0) * gk[cp];
-        gT += g * (3.0 * kW[a] * (w.AX[cp] * kEX[a] + w.AY[cp] * kEY[a]) + 6.0 * kW[a] * P.chi);
-    }
-    const bool in = a_int(P, gj);
-    if (in) {
-        const double g = sk * gk[c];
-        const double Tv = w.Tk[k][c], dv = w.divv[c], IA = w.IA[c], IB = w.IB[c];
-        double d1, d2;
-        phi_derivs(P, Tv, d1, d2);
-        gT += g * (-(10.0 / 3.0) * P.chi - dv * (IA - IB * (d1 + Tv * d2)));
-        if (k > 0) {
-            const double wk = (k == 1) ? 1.0 : 2.0;
-            w.gh[k - 1][c] = wk * lT1[c] / 6.0 + ck * gT;
+    for (int m = 0; m < RPW; ++m) {
+        const int r = wv + TAW * m;
+        const int gy = y0 + r - TAH;
+        gyr[m] = gy;
+        inl[m] = r < H && gy >= 0 && gy < P.ny;
+        inr[m] = inl[m] && gy > 0 && gy < P.ny - 1;
+        double t1 = 0.0, ax = 0.0, ay = 0.0, l1 = 0.0;
+        cdv[m] = cIA[m] = cIB[m] = 0.0;
+        if (inl[m]) {
+            const size_t c = (size_t)gy * P.nx + gx;
+            t1 = w.T1[c];
+            ax = w.AX[c];
+            ay = w.AY[c];
+            l1 = lT1[c];
+            cdv[m] = w.divv[c];
+            cIA[m] = w.IA[c];
+            cIB[m] = w.IB[c];
+        }
+        if (r < H) {
+            sb[0][r][lane] = t1;
+            sb[4][r][lane] = l1;
+            sAX[r][lane] = ax;
+            sAY[r][lane] = ay;
         }
     }
-    lT0[c] = (k == 3 ? lT1[c] : lT0[c]) + gT;
-    if (k != 0) return;
-    double aDrx = 0.0, aDry = 0.0, avx = 0.0, avy = 0.0, adiv = 0.0, arho = 0.0;
-    if (in) {
-        const double dv = w.divv[c], ri = w.RI[c], IA = w.IA[c], IB = w.IB[c], E1 = w.E1[c], E2 = w.E2[c];
-        const double Drx = w.Drx[c], Dry = w.Dry[c];
-        const double gs[4] = {w.gh[0][c], w.gh[1][c], w.gh[2][c], lT1[c] / 6.0};
+    __syncthreads();
+
+    // forward stages: T_{s+1} = T_1 + c_s K(T_s) on the region shrunk by s
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const double *Tf = w.Tk[j];
-            double dTx, dTy, d1, d2;
-            a_grad(P, Tf, gi, gj, dTx, dTy);
-            const double Tv = Tf[c];
-            phi_derivs(P, Tv, d1, d2);
-            const double g = gs[j];
-            aDrx += g * P.chi * dTx * ri;
-            aDry += g * P.chi * dTy * ri;
-            avx += -g * dTx;
-            avy += -g * dTy;
-            adiv += -g * Tv * (IA - IB * d1);
-            arho += g * (-P.chi * (Drx * dTx + Dry * dTy) * ri * ri - Tv * dv * (E1 - E2 * d1));
+    for (int s = 1; s <= 3; ++s) {
+        const double cs = s == 3 ? 1.0 : 0.5;
+#pragma unroll
+        for (int m = 0; m < RPW; ++m) {
+            const int r = wv + TAW * m;
+            if (r < s || r >= H - s || lane < s || lane >= 64 - s) continue;
+            double v = sb[0][r][lane];
+            if (inr[m]) {
+                const double(*F)[64] = sb[s - 1];
+                const int l = lane;
+                const double tc = F[r][l];
+                const double tE = F[r][l + 1], tW = F[r][l - 1], tN = F[r + 1][l], tS = F[r - 1][l];
+                const double tNE = F[r + 1][l + 1], tNW = F[r + 1][l - 1], tSW = F[r - 1][l - 1], tSE = F[r - 1][l + 1];
+                const double dTx = (tE - tW) * (1.0 / 3.0) + (tNE - tNW + tSE - tSW) * (1.0 / 12.0);
+                const double dTy = (tN - tS) * (1.0 / 3.0) + (tNE + tNW - tSE - tSW) * (1.0 / 12.0);
+                const double lap = (tE + tW + tN + tS) * (2.0 / 3.0) + (tNE + tNW + tSE + tSW) * (1.0 / 6.0) -
+                                   (10.0 / 3.0) * tc;
+                double d1, d2;
+                phi_derivs(P, tc, d1, d2);
+                const double h = sAX[r][l] * dTx + sAY[r][l] * dTy + chi * lap - cIA[m] * cdv[m] * tc +
+                                 cIB[m] * cdv[m] * tc * d1;
+                v += cs * h;
+            }
+            sb[s][r][lane] = v;
         }
+        __syncthreads();
     }
-    w.gDrx[c] = aDrx;
-    w.gDry[c] = aDry;
-    w.gvx[c] = avx;
-    w.gvy[c] = avy;
-    w.gdiv[c] = adiv;
-    w.grho[c] = arho;
+
+    // reverse stages k = 3..0 on the region shrunk by 7 - k
+    double lt[RPW], acc[RPW][6];
+#pragma unroll
+    for (int m = 0; m < RPW; ++m) {
+        lt[m] = 0.0;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) acc[m][j] = 0.0;
+    }
+    const bool tile_col = lane >= TAH && lane < TAH + TAX;
+#pragma unroll
+    for (int k = 3; k >= 0; --k) {
+        const int R = 7 - k;
+        // slope adjoint of stage k at region nodes: plane and scale
+        const int gp = k == 3 ? 4 : (k == 2 ? 5 : (k == 1 ? 3 : 2));
+        const double gs = k == 3 ? 1.0 / 6.0 : 1.0;
+        const int op = k == 3 ? 5 : (k == 2 ? 3 : 2);  // plane of the next slope adjoint
+        const double ck = k == 3 ? 1.0 : 0.5;
+        const double wk = (k == 1) ? 1.0 : 2.0;        // RK4 weight of slope k-1
+        double gnext[RPW];
+#pragma unroll
+        for (int m = 0; m < RPW; ++m) {
+            const int r = wv + TAW * m;
+            gnext[m] = 0.0;
+            if (r < R || r >= H - R || lane < R || lane >= 64 - R || !inl[m]) continue;
+            const double(*G)[64] = sb[gp];
+            const int l = lane;
+            double gT = 0.0;
+#pragma unroll
+            for (int a = 1; a < 9; ++a) {
+                const int rp = r - kEY[a], lp = l - kEX[a];
+                const int gyp = gyr[m] - kEY[a];
+                const double mk = (gyp > 0 && gyp < P.ny - 1) ? gs : 0.0;
+                gT += mk * G[rp][lp] * (3.0 * kW[a] * (sAX[rp][lp] * kEX[a] + sAY[rp][lp] * kEY[a]) + 6.0 * kW[a] * chi);
+            }
+            if (inr[m]) {
+                const double g = gs * G[r][l];
+                const double(*F)[64] = sb[k];
+                const double Tv = F[r][l];
+                double d1, d2;
+                phi_derivs(P, Tv, d1, d2);
+                gT += g * (-(10.0 / 3.0) * chi - cdv[m] * (cIA[m] - cIB[m] * (d1 + Tv * d2)));
+                if (k > 0) gnext[m] = wk * sb[4][r][l] / 6.0 + ck * gT;
+                const bool tile_row = r >= TAH && r < TAH + TAY;
+                if (tile_row && tile_col) {
+                    // this stage's part of the rho, grad rho, v, div v adjoints at the node
+                    const double dTx = (F[r][l + 1] - F[r][l - 1]) * (1.0 / 3.0) +
+                                       (F[r + 1][l + 1] - F[r + 1][l - 1] + F[r - 1][l + 1] - F[r - 1][l - 1]) * (1.0 / 12.0);
+                    const double dTy = (F[r + 1][l] - F[r - 1][l]) * (1.0 / 3.0) +
+                                       (F[r + 1][l + 1] + F[r + 1][l - 1] - F[r - 1][l + 1] - F[r - 1][l - 1]) * (1.0 / 12.0);
+                    acc[m][0] += g * dTx;       // chi RI applied at the end
+                    acc[m][1] += g * dTy;
+                    acc[m][2] += g * Tv;        // div v part: -g T (IA - IB d1)
+                    acc[m][3] += g * Tv * d1;
+                    acc[m][4] += g * (w.Drx[(size_t)gyr[m] * P.nx + gx] * dTx + w.Dry[(size_t)gyr[m] * P.nx + gx] * dTy);
+                    acc[m][5] += g * Tv * (w.E1[(size_t)gyr[m] * P.nx + gx] - w.E2[(size_t)gyr[m] * P.nx + gx] * d1);
+                }
+            }
+            lt[m] += gT;
+        }
+        if (k == 0) break;
+        __syncthreads();  // every read of the planes this stage overwrites is done
+#pragma unroll
+        for (int m = 0; m < RPW; ++m) {
+            const int r = wv + TAW * m;
+            if (r < R || r >= H - R || lane < R || lane >= 64 - R) continue;
+            sb[op][r][lane] = gnext[m];
+        }
+        __syncthreads();
+    }
+
+    // outputs on the tile
+#pragma unroll
+    for (int m = 0; m < RPW; ++m) {
+        const int r = wv + TAW * m;
+        if (r < TAH || r >= TAH + TAY || !tile_col || !inl[m] || x0 + lane - TAH >= P.nx) continue;
+        const size_t c = (size_t)gyr[m] * P.nx + gx;
+        lT0[c] = lT1[c] + lt[m];
+        double aDrx = 0.0, aDry = 0.0, avx = 0.0, avy = 0.0, adiv = 0.0, arho = 0.0;
+        if (inr[m]) {
+            const double ri = w.RI[c];
+            aDrx = chi * ri * acc[m][0];
+            aDry = chi * ri * acc[m][1];
+            avx = -acc[m][0];
+            avy = -acc[m][1];
+            adiv = -(cIA[m] * acc[m][2] - cIB[m] * acc[m][3]);
+            arho = -chi * ri * ri * acc[m][4] - cdv[m] * acc[m][5];
+        }
+        w.gDrx[c] = aDrx;
+        w.gDry[c] = aDry;
+        w.gvx[c] = avx;
+        w.gvy[c] = avy;
+        w.gdiv[c] = adiv;
+        w.grho[c] = arho;
+    }
 }
 
 // Stencil transposes of grad rho and div v, then streaming and collision

@@ -1276,40 +1276,43 @@ int batch_time_kernels(lbb_batch *b, int64_t n, double *ms_lb, double *ms_therma
 }
 
 // Time every LB shape (thermal shape fixed), then every thermal shape (LB
-// shape at its best), on the lattice's own state; keep the fastest of each.
-// `set` applies a shape pair, `time` advances n steps and returns the mean
-// kernel durations.
+// shape at its best), on the lattice's own state; keep the fastest of each
+// when it beats the shape in use by more than kTuneMargin (timing noise is a
+// few percent).  `set` applies a shape pair, `time` advances n steps and
+// returns the mean kernel durations.
+constexpr double kTuneMargin = 0.04;
+
 template <typename Set, typename Time>
 int tune_shapes(int steps, Set set, Time time, int a0, int b0, int *best_a, int *best_b, double *ms_lb,
                 double *ms_thermal)
 {
-    double best = 1e300;
-    int ba = a0, bb = b0;
+    double tA[lbb::NSHAPE_A], tB[lbb::NSHAPE_B];
     for (int a = 0; a < lbb::NSHAPE_A; ++a) {
         double ta, tb;
         int rc = set(a, b0);
         if (!rc) rc = time(1, &ta, &tb);  // first launches of the variant
         if (!rc) rc = time(steps, &ta, &tb);
         if (rc) return rc;
+        tA[a] = ta;
         if (ms_lb) ms_lb[a] = ta;
-        if (ta < best) {
-            best = ta;
-            ba = a;
-        }
     }
-    best = 1e300;
+    int ba = 0;
+    for (int a = 1; a < lbb::NSHAPE_A; ++a)
+        if (tA[a] < tA[ba]) ba = a;
+    if (!(tA[ba] < tA[a0] * (1.0 - kTuneMargin))) ba = a0;
     for (int t = 0; t < lbb::NSHAPE_B; ++t) {
         double ta, tb;
         int rc = set(ba, t);
         if (!rc) rc = time(1, &ta, &tb);
         if (!rc) rc = time(steps, &ta, &tb);
         if (rc) return rc;
+        tB[t] = tb;
         if (ms_thermal) ms_thermal[t] = tb;
-        if (tb < best) {
-            best = tb;
-            bb = t;
-        }
     }
+    int bb = 0;
+    for (int t = 1; t < lbb::NSHAPE_B; ++t)
+        if (tB[t] < tB[bb]) bb = t;
+    if (!(tB[bb] < tB[b0] * (1.0 - kTuneMargin))) bb = b0;
     *best_a = ba;
     *best_b = bb;
     return LBB_OK;
@@ -1470,7 +1473,7 @@ struct AdjMember {
     lbb::Scalars *ck_sc;
     double *hf_backup, *lf[2], *lT[2], *gr[2];
     lbb::AdjW w;
-    int gx, nb;
+    int gx, nb, tgx, tnb;
     size_t n, state_bytes;
 };
 
@@ -1499,8 +1502,8 @@ int adjoint_run(AdjGroup &g, int64_t N, int64_t K, double *J, double *dJ_dTb, do
     std::vector<AdjMember> m(nm);
     Inst *inst_seg = nullptr;  // [K][nm]: step k of a segment reads stored state k, writes k+1
     AdjInst *d_ai = nullptr;
-    int *d_amap = nullptr;
-    int tot = 0;
+    int *d_amap = nullptr, *d_tmap = nullptr;
+    int tot = 0, ttot = 0;
     for (int i = 0; i < nm; ++i) {
         const lbb_domain *d = g.doms[i];
         m[i].n = d->N;
@@ -1508,6 +1511,21 @@ int adjoint_run(AdjGroup &g, int64_t N, int64_t K, double *J, double *dJ_dTb, do
         m[i].gx = (d->p.nx + AXB - 1) / AXB;
         m[i].nb = m[i].gx * ((d->p.ny + AYB - 1) / AYB);
         tot += m[i].nb;
+    }
+    // temperature-adjoint tiles: 16 rows high unless that gives fewer than
+    // two tiles per compute unit, then 8
+    int tay = 16;
+    {
+        int t16 = 0;
+        for (int i = 0; i < nm; ++i)
+            t16 += ((g.doms[i]->p.nx + TAX - 1) / TAX) * ((g.doms[i]->p.ny + 15) / 16);
+        if (t16 < 2 * 256) tay = 8;
+    }
+    for (int i = 0; i < nm; ++i) {
+        const lbb_domain *d = g.doms[i];
+        m[i].tgx = (d->p.nx + TAX - 1) / TAX;
+        m[i].tnb = m[i].tgx * ((d->p.ny + tay - 1) / tay);
+        ttot += m[i].tnb;
     }
     auto carve = [&](unsigned char *base) -> size_t {
         Carver cv{base};
@@ -1527,10 +1545,9 @@ int adjoint_run(AdjGroup &g, int64_t N, int64_t K, double *J, double *dJ_dTb, do
             AdjW &w = a.w;
             double **arr[] = {&w.rho, &w.jx, &w.jy, &w.psi, &w.T1, &w.sx, &w.sy, &w.Fx, &w.Fy, &w.vx,
                               &w.vy, &w.Drx, &w.Dry, &w.divv, &w.AX, &w.AY, &w.IA, &w.IB, &w.E1,
-                              &w.E2, &w.RI, &w.Tk[1], &w.Tk[2], &w.Tk[3], &w.gh[0], &w.gh[1], &w.gh[2], &w.gDrx,
+                              &w.E2, &w.RI, &w.gDrx,
                               &w.gDry, &w.gdiv, &w.grho, &w.gvx, &w.gvy, &w.gpsi, &w.gsx, &w.gsy};
             for (double **p : arr) *p = cv.take<double>(n);
-            w.Tk[0] = w.T1;
             w.mpart = cv.take<double>(a.nb);
             w.fpart = cv.take<double>(2 * (size_t)a.nb);
             w.scal = cv.take<double>(4);
@@ -1538,6 +1555,7 @@ int adjoint_run(AdjGroup &g, int64_t N, int64_t K, double *J, double *dJ_dTb, do
         inst_seg = cv.take<Inst>((size_t)K * nm);
         d_ai = cv.take<AdjInst>(nm);
         d_amap = cv.take<int>(tot);
+        d_tmap = cv.take<int>(ttot);
         return cv.off;
     };
     const size_t need = carve(nullptr);
@@ -1585,8 +1603,9 @@ int adjoint_run(AdjGroup &g, int64_t N, int64_t K, double *J, double *dJ_dTb, do
     // launch tables: stored-state steps and the adjoint grid
     std::vector<Inst> hinst((size_t)K * nm);
     std::vector<AdjInst> hai(nm);
-    std::vector<int> hamap;
+    std::vector<int> hamap, htmap;
     hamap.reserve(tot);
+    htmap.reserve(ttot);
     for (int i = 0; i < nm; ++i) {
         lbb_domain *d = g.doms[i];
         const size_t n = m[i].n;
@@ -1614,14 +1633,18 @@ int adjoint_run(AdjGroup &g, int64_t N, int64_t K, double *J, double *dJ_dTb, do
         A.gx = m[i].gx;
         A.blk0 = (int)hamap.size();
         A.nb = m[i].nb;
+        A.tgx = m[i].tgx;
+        A.tblk0 = (int)htmap.size();
         hai[i] = A;
         hamap.insert(hamap.end(), m[i].nb, i);
+        htmap.insert(htmap.end(), m[i].tnb, i);
         hipLaunchKernelGGL(a_bcast_T<S>, dim3(256), dim3(256), 0, st, static_cast<const S *>(own_T(i)),
                            reinterpret_cast<S *>(m[i].seg), n, (int)(K + 1));
     }
     LBB_HIP(hipMemcpyAsync(inst_seg, hinst.data(), hinst.size() * sizeof(Inst), hipMemcpyHostToDevice, st));
     LBB_HIP(hipMemcpyAsync(d_ai, hai.data(), nm * sizeof(AdjInst), hipMemcpyHostToDevice, st));
     LBB_HIP(hipMemcpyAsync(d_amap, hamap.data(), tot * sizeof(int), hipMemcpyHostToDevice, st));
+    LBB_HIP(hipMemcpyAsync(d_tmap, htmap.data(), ttot * sizeof(int), hipMemcpyHostToDevice, st));
 
     // forward with the averages restarted: J = q_sum / N afterwards.  States
     // of the last segment go straight into the slots (no recompute later).
@@ -1684,12 +1707,8 @@ int adjoint_run(AdjGroup &g, int64_t N, int64_t K, double *J, double *dJ_dTb, do
             const int k = (int)(t - t0);
             hipLaunchKernelGGL(a_force, grid, blk, 0, st, d_ai, d_amap);
             hipLaunchKernelGGL(a_divv0, grid, blk, 0, st, d_ai, d_amap);
-            hipLaunchKernelGGL(a_stage, grid, blk, 0, st, d_ai, d_amap, 1, 0.5);
-            hipLaunchKernelGGL(a_stage, grid, blk, 0, st, d_ai, d_amap, 2, 1.0);
-            hipLaunchKernelGGL(a_tstage, grid, blk, 0, st, d_ai, d_amap, 3, 1.0, cur);
-            hipLaunchKernelGGL(a_tstage, grid, blk, 0, st, d_ai, d_amap, 2, 0.5, cur);
-            hipLaunchKernelGGL(a_tstage, grid, blk, 0, st, d_ai, d_amap, 1, 0.5, cur);
-            hipLaunchKernelGGL(a_tstage, grid, blk, 0, st, d_ai, d_amap, 0, 0.0, cur);
+            if (tay == 16) hipLaunchKernelGGL((a_theradj<16, 16>), dim3(ttot), dim3(64 * 16), 0, st, d_ai, d_tmap, cur);
+            else hipLaunchKernelGGL((a_theradj<8, 8>), dim3(ttot), dim3(64 * 8), 0, st, d_ai, d_tmap, cur);
             hipLaunchKernelGGL(a_lb<S>, grid, blk, 0, st, d_ai, d_amap, k, cur);
             hipLaunchKernelGGL(a_final<S>, grid, blk, 0, st, d_ai, d_amap, k, cur, t >= 1 ? wq : 0.0,
                                t > t0 ? 1 : 0);
