@@ -30,38 +30,40 @@ ALG_BYTES_STEP = {"f32": 80, "f64": 160}
 ALG_BYTES_LB = {"f32": 72, "f64": 144}
 
 # HBM traffic of the LB launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
-# (KiB per dispatch, mean over the dispatches of a --profile run), each scaled
-# by what the same counter reads for an elementwise kernel that reads 1 GiB
-# and writes 1 GiB (FETCH_SIZE 524296 KiB -> factor 2.0, WRITE_SIZE 1048576
-# KiB -> factor 1.0).  Valid for the kernel sources whose hash is recorded;
-# reported as null once the sources change.
+# (KiB per dispatch, mean over the dispatches of a --profile run with the
+# given tiles), each scaled by what the same counter reads for an elementwise
+# kernel that reads 1 GiB and writes 1 GiB (FETCH_SIZE 524298 KiB -> factor
+# 2.0, WRITE_SIZE 1048576 KiB -> factor 1.0).  Valid for the kernel source
+# whose hash is recorded and the same LB tile shape; null otherwise.
 MEASURED_TRAFFIC = {
-    "source_hash": "8720d6075d3cad7b",
-    "fetch_factor": 1048576.0 / 524296.2,
+    "source_hash": "cf4e990916084faf",
+    "fetch_factor": 1048576.0 / 524297.8,
     "write_factor": 1048576.0 / 1048576.0,
     "k_lb": {
-        "large_1024x512_fp32": {"fetch_kib": 10833.2, "write_kib": 24628.5},
-        "large_4096x2048_fp32": {"fetch_kib": 179043.7, "write_kib": 394597.5},
+        "large_1024x512_fp32": {"tiles_lb": [62, 12, 4], "fetch_kib": 10833.1, "write_kib": 24628.3},
+        "large_4096x2048_fp32": {"tiles_lb": [62, 8, 4], "fetch_kib": 174795.1, "write_kib": 394536.1},
     },
 }
 
 
-def measured_traffic(workload: str):
-    """HBM bytes per LB launch from the recorded counters, or None."""
+def measured_traffic(workload: str, tiles_lb):
+    """HBM bytes per LB launch from the recorded counters, or None when the
+    kernel source, the workload or the LB tile shape differ."""
     m = MEASURED_TRAFFIC
     if not m or m.get("source_hash") != source_hash() or workload not in m["k_lb"]:
         return None
     c = m["k_lb"][workload]
+    if list(c["tiles_lb"]) != list(tiles_lb):
+        return None
     return int(round((c["fetch_kib"] * m["fetch_factor"] + c["write_kib"] * m["write_factor"]) * 1024))
 
 
 def source_hash() -> str:
+    """Hash of the forward kernels' source (the counters below depend on it
+    and on the tile shape only)."""
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1501_03857_amd", "csrc")
-    for fn in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, fn), "rb") as fh:
-            h.update(fn.encode())
-            h.update(fh.read())
+    with open(os.path.join(ROOT, "paper_1501_03857_amd", "csrc", "lbb_device.hpp"), "rb") as fh:
+        h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -238,6 +240,8 @@ def main():
     ap.add_argument("--kernel-steps", type=int, default=400, help="steps timed per launch for the roofline")
     ap.add_argument("--tune-steps", type=int, default=30,
                     help="steps per tile shape for the autotuner before timing (0: default shapes)")
+    ap.add_argument("--tiles", default=None,
+                    help="LB,thermal tile shape indices to use instead of the autotuner (profiling runs)")
     ap.add_argument("--cpu-steps", type=int, default=100, help="oracle steps for the CPU baseline (0: skip)")
     ap.add_argument("--sweep-steps", type=int, default=2000, help="steps of the 48-lattice sweep comparison (0: skip)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost measurement")
@@ -282,7 +286,11 @@ def main():
                  Gw_bottom=w.Gw_bottom, rho_L=rl, rho_V=rv)
     d = L.Domain(p, T_bottom=w.heater_T(Tc), rho0=w.density(rl, rv))
     cells = w.nx * w.ny
-    tune = d.autotune(args.tune_steps) if args.tune_steps > 0 else None
+    tune = None
+    if args.tiles:
+        d.set_tiles(*(int(x) for x in args.tiles.split(",")))
+    elif args.tune_steps > 0:
+        tune = d.autotune(args.tune_steps)
     shapes_lb, shapes_th = L.tile_shapes()
     tiles = {"lb": list(shapes_lb[d.tiles[0]]), "thermal": list(shapes_th[d.tiles[1]]),
              "autotuned": tune is not None}
@@ -312,7 +320,7 @@ def main():
 
     ms_lb, ms_th, ms_seq = d.time_kernels(args.kernel_steps)
     achieved = ALG_BYTES_LB[store] * cells / (ms_lb * 1e-3) / 1e9
-    traffic = measured_traffic(w.name)
+    traffic = measured_traffic(w.name, tiles["lb"])
     step_bytes = ALG_BYTES_STEP[store] * cells
     sweep = sweep_bench(args.sweep_steps) if args.sweep_steps > 0 else None
     if sweep:
