@@ -145,6 +145,13 @@ int lbb_time_kernels(lbb_domain *d, int64_t n, double *ms_lb, double *ms_thermal
  * with the total force of the current state; T; and f (post-streaming, wall
  * rule applied).  Any pointer may be NULL. */
 int lbb_read_fields(lbb_domain *d, double *rho, double *ux, double *uy, double *T, double *f);
+/* The same fields into caller-owned device buffers (FP64, nx*ny each, f
+ * 9*nx*ny, layout [a][y][x]; NULL skipped), without a host wait.  The read
+ * is ordered after the library's earlier work on the domain, after the
+ * caller's earlier work on `stream` (a hipStream_t; NULL is the null stream)
+ * and before the caller's later work there.  EDEVICE if the launch or the
+ * stream ordering fails. */
+int lbb_read_fields_dev(lbb_domain *d, double *rho, double *ux, double *uy, double *T, double *f, void *stream);
 
 /* Bottom-wall heat flux (Sec. 3.2): q_now = q(t) of the current state, q_mean
  * = mean of the samples since creation or lbb_reset_average, n_samples their

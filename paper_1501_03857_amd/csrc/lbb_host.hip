@@ -743,6 +743,43 @@ int lbb_time_kernels(lbb_domain *d, int64_t n, double *ms_lb, double *ms_thermal
     return check_errors(d);
 }
 
+int lbb_read_fields_dev(lbb_domain *d, double *rho, double *ux, double *uy, double *T, double *f, void *stream)
+{
+    if (!d) return fail(LBB_EINVAL, "domain is NULL");
+    // the library stream does not synchronize with the null stream by
+    // itself, so the ordering is made explicit for any stream, NULL included
+    hipStream_t cs = static_cast<hipStream_t>(stream);
+    hipEvent_t ev = nullptr;
+    LBB_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    {
+        // the caller's earlier work on these buffers comes first
+        hipError_t e0 = hipEventRecord(ev, cs);
+        if (e0 == hipSuccess) e0 = hipStreamWaitEvent(d->stream, ev, 0);
+        if (e0 != hipSuccess) {
+            (void)hipEventDestroy(ev);
+            return fail(LBB_EDEVICE, std::string("read-back to device buffers: ") + hipGetErrorString(e0));
+        }
+    }
+    const int nbxR = (d->p.nx + lbb::TXR - 1) / lbb::TXR, nbyR = (d->p.ny + lbb::TYR - 1) / lbb::TYR;
+    if (d->p.precision == LBB_FP64)
+        hipLaunchKernelGGL(lbb::k_read<double>, dim3(nbxR * nbyR), dim3(lbb::NT), 0, d->stream, d->dp,
+                           static_cast<const double *>(d->f[d->cf]), static_cast<const double *>(d->T[d->cT]), rho,
+                           ux, uy, T, f, d->sc, nbxR);
+    else
+        hipLaunchKernelGGL(lbb::k_read<float>, dim3(nbxR * nbyR), dim3(lbb::NT), 0, d->stream, d->dp,
+                           static_cast<const float *>(d->f[d->cf]), static_cast<const float *>(d->T[d->cT]), rho,
+                           ux, uy, T, f, d->sc, nbxR);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) {
+        // and the caller's later work on its stream waits for the read
+        e = hipEventRecord(ev, d->stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(cs, ev, 0);
+    }
+    (void)hipEventDestroy(ev);
+    if (e != hipSuccess) return fail(LBB_EDEVICE, std::string("read-back to device buffers: ") + hipGetErrorString(e));
+    return LBB_OK;
+}
+
 int lbb_read_fields(lbb_domain *d, double *rho, double *ux, double *uy, double *T, double *f)
 {
     if (!d) return fail(LBB_EINVAL, "domain is NULL");

@@ -56,6 +56,15 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing; build it with python -m paper_1501_03857_amd.build")
+        # PyTorch ships its own HIP runtime under the same soname as the
+        # system one.  Loaded first, it is the one the library binds to, so
+        # the process holds a single runtime and torch streams, events and
+        # device buffers can be handed to the library; loaded after the
+        # library, it would start a second runtime that cannot see the GPU.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         _P = C.POINTER(CParams)
         vp = C.c_void_p
@@ -90,6 +99,7 @@ def lib():
             "lbb_batch_destroy": (C.c_int, [vp]),
             "lbb_adjoint": (C.c_int, [vp, _i64, _i64, _pd, _pd, _pd]),
             "lbb_batch_adjoint": (C.c_int, [vp, _i64, _i64, _pd, _pd, _pd]),
+            "lbb_read_fields_dev": (C.c_int, [vp, vp, vp, vp, vp, vp, vp]),
             "lbb_tile_shapes": (C.c_int, [_pi32, _pi32, _pi32, _pi32]),
             "lbb_get_tiles": (C.c_int, [vp, _pi32, _pi32]),
             "lbb_set_tiles": (C.c_int, [vp, C.c_int32, C.c_int32]),
@@ -283,6 +293,13 @@ class Domain:
         if f:
             out["f"] = ff
         return out
+
+    def read_into(self, rho=0, ux=0, uy=0, T=0, f=0, stream=0):
+        """Read the fields into device buffers given by address (FP64; 0 =
+        skip), ordered with the caller's `stream` (a hipStream_t address; 0 is
+        the null stream, e.g. torch's default stream)."""
+        _check(lib().lbb_read_fields_dev(self._h, rho or None, ux or None, uy or None, T or None, f or None,
+                                         stream or None))
 
     def bottom_temperature(self) -> np.ndarray:
         """The current bottom-wall temperatures T_b(x)."""

@@ -202,9 +202,11 @@ def test_invalid_state_is_reported_and_recoverable():
 @pytest.mark.slow
 def test_large_fp32_matches_oracle_200_steps():
     """The benchmarked workload (1024x512, FP32, full-width heater, G_w for
-    ~60 deg) over 200 steps through the same launch path as the benchmark."""
+    ~60 deg) over 200 steps through the same launch path as the benchmark
+    (tiles chosen by the autotuner, graph replays)."""
     _say("large 1024x512 fp32 200")
     o, d, _ = make_pair(WL.LARGE_1024x512)
+    d.autotune(10)
     d.step(200)
     o.step(200)
     errs, bad = compare(o, d, TOL32)
@@ -247,3 +249,61 @@ def test_large_fp32_long_run_heat_flux_within_2_percent_of_oracle():
     assert np.all(np.abs(np.log(np.array(trace) / q_ref)) < np.log(3.0))
     mass = float(np.sum(d.fields()["rho"]))
     assert abs(mass / ref["mass_final"] - 1.0) < 1e-4
+
+
+def test_largest_benchmark_lattice_matches_oracle():
+    """4096x2048 FP32 (the HBM-resident benchmark lattice) in the benchmark's
+    launch configuration (autotuned tiles), a few steps against the oracle."""
+    _say("4096x2048 fp32 6 steps")
+    o, d, _ = make_pair(WL.LARGE_4096x2048)
+    d.autotune(5)
+    d.step(6)
+    o.step(6)
+    errs, bad = compare(o, d, TOL32)
+    assert not bad, errs
+
+
+def test_large_x_invariant_state_stays_x_invariant():
+    """8192x4096 FP32 (33.5 M nodes): a liquid pool under vapour with no noise,
+    uniform heater and no wall strength is the same in every column; after
+    40 steps every column must still be identical bit for bit (no indexing or
+    wrap error anywhere in a lattice this size), and mass is conserved."""
+    _say("8192x4096 x-invariance")
+    w = WL.LARGE_1024x512.resized(8192, 4096, dT_over_Tc=0.0, Gw_bottom=0.0, noise_amp=0.0,
+                                  g=WL.scaled_gravity(4096, 2.0 / 49.0))
+    Tc, _ = L.eos_constants(w.a, w.b, w.R, w.omega)
+    rv, rl = L.coexistence(w.a, w.b, w.R, w.omega, w.Ts_over_Tc * Tc)
+    p = L.Params(nx=w.nx, ny=w.ny, precision=L.FP32, liquid_rows=w.liquid_rows, sigma=w.sigma, g=w.g,
+                 rho_L=rl, rho_V=rv, noise_amp=0.0)
+    d = L.Domain(p)
+    m0 = float(np.sum(d.fields(f=False)["rho"]))
+    d.step(40)
+    fl = d.fields(f=False)
+    for k in ("rho", "ux", "uy", "T"):
+        a = fl[k]
+        assert np.array_equal(a, np.repeat(a[:, :1], w.nx, axis=1)), k
+    assert np.max(np.abs(fl["ux"])) == 0.0
+    assert abs(float(np.sum(fl["rho"])) / m0 - 1.0) < 1e-6
+
+
+def test_read_into_device_buffers_matches_host_read():
+    """lbb_read_fields_dev into caller device buffers (torch tensors) on the
+    caller's stream, right after asynchronous steps: the same values as the
+    host read."""
+    import torch
+
+    _say("read into device buffers")
+    side = torch.cuda.Stream()
+    for prec, st in ((L.FP64, torch.cuda.current_stream()), (L.FP32, side)):
+        _, d, _ = make_pair(PLAIN, precision=prec)
+        n = PLAIN.nx * PLAIN.ny
+        with torch.cuda.stream(st):
+            bufs = {k: torch.full((n * (9 if k == "f" else 1),), -1.0, dtype=torch.float64, device="cuda")
+                    for k in ("rho", "ux", "uy", "T", "f")}
+            d.step_async(37)
+            d.read_into(**{k: v.data_ptr() for k, v in bufs.items()}, stream=st.cuda_stream)
+            host = {k: v.cpu().numpy() for k, v in bufs.items()}
+        ref = d.fields()
+        for k in ("rho", "ux", "uy", "T"):
+            assert np.array_equal(host[k].reshape(PLAIN.ny, PLAIN.nx), ref[k]), (prec, k)
+        assert np.array_equal(host["f"].reshape(9, PLAIN.ny, PLAIN.nx), ref["f"]), prec
