@@ -222,6 +222,25 @@ __device__ __forceinline__ double block_sum_array(const double *__restrict__ a, 
     return block_sum<NTH>(s, red);
 }
 
+// Fixed-order sum of n doubles by the first 256 threads of a block of at
+// least 256 threads (the others add nothing), the same for any block size;
+// result valid in thread 0.  All threads of the block must call it.
+__device__ __forceinline__ double fixed_sum(const double *__restrict__ a, int n, double *red /* [>= 4] */)
+{
+    double s = 0.0;
+    if (threadIdx.x < NT)
+        for (int k = threadIdx.x; k < n; k += NT) s += a[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0 && w < NT / 64) red[w] = s;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < NT / 64; ++k) t += red[k];
+    return t;
+}
+
 // Heat-flux bookkeeping: q of state t from the partial sums over x; counted
 // once per state index (t > last_counted), never for the initial state.
 __device__ __forceinline__ void reduce_heat_flux(const double *__restrict__ hf_part, int n_hf, int nx,
@@ -388,7 +407,6 @@ __global__ __launch_bounds__(64 * NWA) void k_lb(const Inst *__restrict__ insts,
     constexpr int IPW_A = TYA / NWA;             // interior rows per wave
     constexpr int H = TYA + 2;                   // region rows (halo rows 0 and H-1)
     __shared__ double psi_s[H * 64];
-    __shared__ double red[NWA];
     const long long t = sc->tA;
     if (blk == nbx * nby) {
         reduce_heat_flux(I.hf_part, I.nbxB, P.nx, sc, t);
@@ -466,11 +484,12 @@ __global__ __launch_bounds__(64 * NWA) void k_lb(const Inst *__restrict__ insts,
     __syncthreads();
     const double rho_ave = sc->rho_ave;
 
-    double mass = 0.0;
+    double mrow[IPW_A];
 #pragma unroll
     for (int m = 0; m < IPW_A; ++m) {
         const int r = 1 + wv + NWA * m;
         const int gy = gys[m];
+        mrow[m] = 0.0;
         if (!live[m] || lane < 1 || lane > TXA || x0 + lane - 1 >= P.nx) continue;
         const size_t c = (size_t)gy * P.nx + gx;
         double f[9];
@@ -487,7 +506,7 @@ __global__ __launch_bounds__(64 * NWA) void k_lb(const Inst *__restrict__ insts,
             double mm = 0.0;
 #pragma unroll
             for (int a = 0; a < 9; ++a) mm += f[a];
-            mass += mm;
+            mrow[m] = mm;
             continue;
         }
         double Fx, Fy, Q;
@@ -535,10 +554,17 @@ __global__ __launch_bounds__(64 * NWA) void k_lb(const Inst *__restrict__ insts,
         const double wu = !walls ? 1.0 : (gy == P.ny - 1 ? 0.0 : (gy == P.ny - 2 ? 2.0 : 1.0));
         const double wd = !walls ? 1.0 : (gy == 0 ? 0.0 : (gy == 1 ? 2.0 : 1.0));
         mm += wu * up + wd * dn;
-        mass += mm;
+        mrow[m] = mm;
     }
-    const double bm = block_sum<64 * NWA>(mass, red);
-    if (threadIdx.x == 0) I.mass_part[blk] = bm;
+    // mass partials per lattice row and 62-column chunk, summed over the wave
+    // by a fixed butterfly: the same grouping and order for every tile height
+#pragma unroll
+    for (int m = 0; m < IPW_A; ++m) {
+        double v = mrow[m];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (live[m] && lane == 0) I.mass_part[(size_t)gys[m] * nbx + bx] = v;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -577,7 +603,7 @@ __global__ __launch_bounds__(64 * NWB) void k_thermal(const Inst *__restrict__ i
     __shared__ double red[NWB];
     const long long t = sc->tB;
     if (blk == nbx * nby) {
-        const double m = block_sum_array<64 * NWB>(I.mass_part, I.nbxA * I.nbyA, red);
+        const double m = fixed_sum(I.mass_part, I.nbxA * P.ny, red);
         if (threadIdx.x == 0) {
             sc->rho_ave = m / ((double)P.nx * (double)P.ny);
             sc->tA = t + 1;

@@ -642,7 +642,9 @@ int lbb_init_domain(const lbb_params *pin, const double *T_bottom, const double 
     ok = ok && alloc(&d->f[0], 9 * N * es) && alloc(&d->f[1], 9 * N * es);
     ok = ok && alloc(&d->T[0], N * es) && alloc(&d->T[1], N * es);
     ok = ok && alloc(&d->rho, N * es) && alloc(&d->vx, N * es) && alloc(&d->vy, N * es);
-    ok = ok && alloc((void **)&d->mass_part, (size_t)mbA * sizeof(double));
+    // mass partials: one per lattice row and LB tile column (also holds the
+    // per-block partials of the set-up mass kernel, fewer)
+    ok = ok && alloc((void **)&d->mass_part, (size_t)std::max(mbA, d->nbxA * p.ny) * sizeof(double));
     ok = ok && alloc((void **)&d->hf_part, (size_t)d->nbxB * sizeof(double));
     ok = ok && alloc((void **)&d->Tb_dev, (size_t)p.nx * sizeof(double));
     ok = ok && alloc((void **)&d->sc, sizeof(lbb::Scalars));

@@ -1,5 +1,8 @@
-"""Every tile shape of the LB and thermal launches against the oracle, and
-the autotuner: it may only change speed, never the state it was given."""
+"""Every tile shape of the LB and thermal launches against the oracle and
+bitwise against the default shapes (the reductions group and order their
+partial sums the same way for every tile height, so any difference would be
+a race or an indexing error), and the autotuner: it may only change speed,
+never the state it was given."""
 import itertools
 
 import numpy as np
@@ -35,38 +38,68 @@ def ragged_periodic():
     return w, o
 
 
+def _gpu_run(w, shapes, steps, **kw):
+    _, d, _ = make_pair(w, **kw)
+    d.set_tiles(*shapes)
+    assert d.tiles == tuple(shapes)
+    d.step(steps)
+    return d
+
+
+@pytest.fixture(scope="module")
+def default_walls(ragged_walls):
+    w, _ = ragged_walls
+    d = _gpu_run(w, (0, 0), 60, Gw_top=-0.03)
+    return d.fields(), d.heat_flux()
+
+
+@pytest.fixture(scope="module")
+def default_periodic(ragged_periodic):
+    w, _ = ragged_periodic
+    return _gpu_run(w, (0, 0), 60, periodic_y=1).fields()
+
+
+@pytest.fixture(scope="module")
+def default_fp32():
+    return _gpu_run(WL.PLAIN_128x64, (0, 0), 100, precision=L.FP32).fields()
+
+
+def _same(a, b):
+    for k in ("f", "T", "rho", "ux", "uy"):
+        assert np.array_equal(a[k], b[k]), k
+
+
 @pytest.mark.parametrize("shape_lb,shape_thermal", COMBOS)
-def test_every_tile_shape_matches_oracle_walls(ragged_walls, shape_lb, shape_thermal):
+def test_every_tile_shape_matches_oracle_walls(ragged_walls, default_walls, shape_lb, shape_thermal):
     _say("tiles walls", shape_lb, shape_thermal)
     w, o = ragged_walls
-    _, d, _ = make_pair(w, Gw_top=-0.03)
-    d.set_tiles(shape_lb, shape_thermal)
-    assert d.tiles == (shape_lb, shape_thermal)
-    d.step(60)
+    d = _gpu_run(w, (shape_lb, shape_thermal), 60, Gw_top=-0.03)
     errs, bad = compare(o, d, 1e-12)
     assert not bad, errs
+    _same(d.fields(), default_walls[0])
+    hf = d.heat_flux()
+    assert hf["q_mean"] == default_walls[1]["q_mean"] and np.array_equal(hf["q_local"], default_walls[1]["q_local"])
 
 
 @pytest.mark.parametrize("shape_lb,shape_thermal", COMBOS)
-def test_every_tile_shape_matches_oracle_periodic(ragged_periodic, shape_lb, shape_thermal):
+def test_every_tile_shape_matches_oracle_periodic(ragged_periodic, default_periodic, shape_lb, shape_thermal):
     _say("tiles periodic", shape_lb, shape_thermal)
     w, o = ragged_periodic
-    _, d, _ = make_pair(w, periodic_y=1)
-    d.set_tiles(shape_lb, shape_thermal)
-    d.step(60)
+    d = _gpu_run(w, (shape_lb, shape_thermal), 60, periodic_y=1)
     errs, bad = compare(o, d, 1e-12)
     assert not bad, errs
+    _same(d.fields(), default_periodic)
 
 
-@pytest.mark.parametrize("shape", range(max(NA, NB)))
-def test_tile_shapes_fp32(shape):
-    _say("tiles fp32", shape)
-    o, d, _ = make_pair(WL.PLAIN_128x64, precision=L.FP32)
-    d.set_tiles(shape % NA, shape % NB)
+@pytest.mark.parametrize("shape_lb,shape_thermal", COMBOS)
+def test_tile_shapes_fp32(default_fp32, shape_lb, shape_thermal):
+    _say("tiles fp32", shape_lb, shape_thermal)
+    o, _, _ = make_pair(WL.PLAIN_128x64, precision=L.FP32)
+    d = _gpu_run(WL.PLAIN_128x64, (shape_lb, shape_thermal), 100, precision=L.FP32)
     o.step(100)
-    d.step(100)
     errs, bad = compare(o, d, 1e-5)
     assert not bad, errs
+    _same(d.fields(), default_fp32)
 
 
 def test_autotune_leaves_state_and_keeps_parity():
