@@ -262,6 +262,14 @@ int lbb_batch_set_tiles(lbb_batch *b, int32_t shape_lb, int32_t shape_thermal);
 int lbb_batch_autotune(lbb_batch *b, int32_t steps, int32_t *shape_lb, int32_t *shape_thermal, double *ms_lb,
                        double *ms_thermal);
 
+/* Device-memory budget of the process: the library refuses (ENOMEM, before
+ * touching the device) any domain, batch member or adjoint workspace that
+ * would take the bytes it holds over `bytes`; 0 (the default) means no
+ * budget.  EINVAL for bytes < 0.  lbb_device_bytes_held reports the bytes
+ * held against it (all live domains and adjoint workspaces). */
+int lbb_set_device_budget(int64_t bytes);
+int64_t lbb_device_bytes_held(void);
+
 /* Current step count, grid shape and device bytes held by the domain. */
 int lbb_info(lbb_domain *d, int64_t *t, int32_t *nx, int32_t *ny, int64_t *device_bytes);
 

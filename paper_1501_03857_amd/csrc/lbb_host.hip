@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -26,6 +27,25 @@ int fail(int code, const std::string &msg)
     g_err = msg;
     return code;
 }
+
+// Device-memory budget of the process (0: none) and the bytes the library
+// holds against it.
+std::atomic<int64_t> g_budget{0}, g_held{0};
+
+// Reserve `bytes` under the budget (ENOMEM, with nothing reserved, if it would
+// be exceeded); give back with release_bytes.
+int reserve_bytes(int64_t bytes, const char *what)
+{
+    const int64_t cap = g_budget.load();
+    const int64_t now = g_held.fetch_add(bytes) + bytes;
+    if (cap > 0 && now > cap) {
+        g_held.fetch_sub(bytes);
+        return fail(LBB_ENOMEM, std::string(what) + ": " + std::to_string(bytes) + " device bytes would exceed the budget of " +
+                                    std::to_string(cap) + " (" + std::to_string(now - bytes) + " held)");
+    }
+    return LBB_OK;
+}
+void release_bytes(int64_t bytes) { g_held.fetch_sub(bytes); }
 
 #define LBB_HIP(expr)                                                                          \
     do {                                                                                       \
@@ -161,6 +181,7 @@ struct lbb_domain {
     int64_t dev_bytes = 0;
     void *adj_mem = nullptr;             // adjoint workspace, kept between calls
     size_t adj_bytes = 0;
+    int64_t held = 0;                    // device bytes held against the budget
 };
 
 struct lbb_param_dims {
@@ -450,6 +471,7 @@ int set_state(lbb_domain *d, const double *rho, const double *ux, const double *
 void release(lbb_domain *d)
 {
     if (!d) return;
+    release_bytes(d->held);
     drop_graphs(d);
     for (void *q : {d->f[0], d->f[1], d->T[0], d->T[1], d->rho, d->vx, d->vy})
         if (q) (void)hipFree(q);
@@ -582,6 +604,16 @@ int lbb_init_domain(const lbb_params *pin, const double *T_bottom, const double 
             Tb[i] = T_bottom[i];
         }
 
+    // the device bytes this domain will hold, reserved under the budget first
+    const size_t esz = p.precision == LBB_FP64 ? 8 : 4;
+    const int64_t planned = (int64_t)(N * esz * (2 * 9 + 2 + 3)) + (int64_t)N * 8 + ((int64_t)1 << 20);
+    rc = reserve_bytes(planned, "domain");
+    if (rc) return rc;
+    struct Unreserve {
+        int64_t n;
+        ~Unreserve() { release_bytes(n); }
+    } unreserve{planned};
+
     int dev = 0;
     LBB_HIP(hipGetDevice(&dev));
     hipDeviceProp_t prop;
@@ -668,6 +700,8 @@ int lbb_init_domain(const lbb_params *pin, const double *T_bottom, const double 
         release(d);
         return fail(rc, m);
     }
+    g_held.fetch_add(d->dev_bytes);
+    d->held = d->dev_bytes;
     *out = d;
     return LBB_OK;
 }
@@ -986,11 +1020,13 @@ struct lbb_batch {
     hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
     void *adj_mem = nullptr;             // adjoint workspace, kept between calls
     size_t adj_bytes = 0;
+    int64_t held = 0;                    // device bytes held against the budget
 };
 
 static void batch_release(lbb_batch *b)
 {
     if (!b) return;
+    release_bytes(b->held);
     for (auto &row : b->graph)
         for (auto &g : row)
             if (g) (void)hipGraphExecDestroy(g);
@@ -1504,6 +1540,7 @@ struct AdjGroup {
     int shA = 0, shB = 0;           // tile shapes of the forward launches
     void **mem = nullptr;           // cached workspace of the owner
     size_t *bytes = nullptr;
+    int64_t *held = nullptr;        // the owner's bytes held against the budget
 };
 
 // Per-lattice pieces of the workspace.
@@ -1599,17 +1636,23 @@ int adjoint_run(AdjGroup &g, int64_t N, int64_t K, double *J, double *dJ_dTb, do
     };
     const size_t need = carve(nullptr);
     if (*g.bytes < need) {
+        int rc = reserve_bytes((int64_t)need, "adjoint workspace");
+        if (rc) return rc;
         if (*g.mem) {
             (void)hipStreamSynchronize(st);
             (void)hipFree(*g.mem);
+            release_bytes((int64_t)*g.bytes);
+            *g.held -= (int64_t)*g.bytes;
             *g.mem = nullptr;
             *g.bytes = 0;
         }
         if (hipMalloc(g.mem, need) != hipSuccess) {
             *g.mem = nullptr;
+            release_bytes((int64_t)need);
             return fail(LBB_ENOMEM, "adjoint work memory could not be allocated");
         }
         *g.bytes = need;
+        *g.held += (int64_t)need;
     }
     carve(static_cast<unsigned char *>(*g.mem));
 
@@ -1828,6 +1871,7 @@ extern "C" int lbb_adjoint(lbb_domain *d, int64_t N, int64_t K, double *J, doubl
     const size_t before = d->adj_bytes;
     g.mem = &d->adj_mem;
     g.bytes = &d->adj_bytes;
+    g.held = &d->held;
     rc = adjoint_group(g, d->p.precision, N, K, J, dJ_dTb, dJ_dGw);
     d->dev_bytes += (int64_t)d->adj_bytes - (int64_t)before;
     return rc;
@@ -1866,8 +1910,18 @@ extern "C" int lbb_batch_adjoint(lbb_batch *b, int64_t N, int64_t K, double *J, 
     g.shB = b->shB;
     g.mem = &b->adj_mem;
     g.bytes = &b->adj_bytes;
+    g.held = &b->held;
     return adjoint_group(g, b->precision, N, K, J, dJ_dTb, dJ_dGw);
 }
+
+extern "C" int lbb_set_device_budget(int64_t bytes)
+{
+    if (bytes < 0) return fail(LBB_EINVAL, "the budget must be >= 0 (0: none)");
+    g_budget.store(bytes);
+    return LBB_OK;
+}
+
+extern "C" int64_t lbb_device_bytes_held(void) { return g_held.load(); }
 
 extern "C" int lbb_batch_info(lbb_batch *b, int64_t *device_bytes)
 {

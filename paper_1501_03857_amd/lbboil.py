@@ -100,6 +100,8 @@ def lib():
             "lbb_adjoint": (C.c_int, [vp, _i64, _i64, _pd, _pd, _pd]),
             "lbb_batch_adjoint": (C.c_int, [vp, _i64, _i64, _pd, _pd, _pd]),
             "lbb_read_fields_dev": (C.c_int, [vp, vp, vp, vp, vp, vp, vp]),
+            "lbb_set_device_budget": (C.c_int, [_i64]),
+            "lbb_device_bytes_held": (_i64, []),
             "lbb_tile_shapes": (C.c_int, [_pi32, _pi32, _pi32, _pi32]),
             "lbb_get_tiles": (C.c_int, [vp, _pi32, _pi32]),
             "lbb_set_tiles": (C.c_int, [vp, C.c_int32, C.c_int32]),
@@ -342,6 +344,15 @@ class Domain:
     @property
     def t(self) -> int:
         return self.info()["t"]
+
+
+def set_device_budget(nbytes: int):
+    """Cap the device bytes the library may hold (0: no cap)."""
+    _check(lib().lbb_set_device_budget(int(nbytes)))
+
+
+def device_bytes_held() -> int:
+    return lib().lbb_device_bytes_held()
 
 
 def tile_shapes():

@@ -122,3 +122,18 @@ def test_tile_calls_reject_bad_arguments():
     assert lib.lbb_autotune(None, 5, None, None, None, None) == L.LBB_EINVAL
     assert lib.lbb_batch_set_tiles(None, 0, 0) == L.LBB_EINVAL
     assert lib.lbb_batch_autotune(None, 5, None, None, None, None) == L.LBB_EINVAL
+
+
+def test_device_budget_refuses_a_domain_before_touching_the_device():
+    """ENOMEM from the host-side budget, before any device call (this runs
+    on a host without a GPU); a negative budget is EINVAL."""
+    lib = L.lib()
+    assert lib.lbb_set_device_budget(-1) == L.LBB_EINVAL
+    assert lib.lbb_set_device_budget(1 << 20) == L.LBB_OK
+    try:
+        with pytest.raises(L.LbbError) as e:
+            L.Domain(L.Params(nx=512, ny=256))
+        assert e.value.code == L.LBB_ENOMEM and "budget" in str(e.value)
+        assert lib.lbb_device_bytes_held() == 0
+    finally:
+        assert lib.lbb_set_device_budget(0) == L.LBB_OK

@@ -83,3 +83,42 @@ def test_autograd_function_matches_library_gradient():
     assert float(J) == J2
     assert np.allclose(T_heater.grad.numpy(), 2.0 * g[idx], rtol=0, atol=0)
     assert float(Gw.grad) == 2.0 * gw
+
+
+def test_adjoint_refused_by_device_budget_leaves_domain_usable():
+    """A budget below what the adjoint workspace needs: ENOMEM, no partial
+    allocation held, the domain's state untouched and the adjoint working
+    again once the budget is lifted; all bytes given back on destruction."""
+    _say("adjoint budget")
+    import gc
+
+    gc.collect()  # earlier tests' domains are released now, not midway
+    gc.disable()
+    try:
+        _budget_case()
+    finally:
+        gc.enable()
+
+
+def _budget_case():
+    held0 = L.device_bytes_held()
+    _, d, _ = make_pair(SMALL)
+    d.step(5)
+    held1 = L.device_bytes_held()
+    assert held1 > held0
+    before = d.fields()
+    L.set_device_budget(held1 + 4096)
+    try:
+        with pytest.raises(L.LbbError) as e:
+            d.adjoint(24, K=6)
+        assert e.value.code == L.LBB_ENOMEM
+        assert L.device_bytes_held() == held1
+    finally:
+        L.set_device_budget(0)
+    after = d.fields()
+    assert np.array_equal(before["f"], after["f"]) and np.array_equal(before["T"], after["T"])
+    J, g, gw = d.adjoint(24, K=6)
+    assert np.isfinite(J) and np.all(np.isfinite(g))
+    assert L.device_bytes_held() > held1
+    d.close()
+    assert L.device_bytes_held() == held0
