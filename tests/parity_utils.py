@@ -43,8 +43,10 @@ def heat_flux_scale(o):
 
 
 def make_pair(w: WL.Workload, *, precision=None, mode=O.COUPLED, periodic_y=0, Gw_top=0.0, g=None,
-              rho0=None, T0=None, ux0=None, uy0=None):
-    """Oracle state and GPU domain of workload w with identical inputs."""
+              rho0=None, T0=None, ux0=None, uy0=None, **extra):
+    """Oracle state and GPU domain of workload w with identical inputs;
+    extra: further model parameters (relaxation rates, viscosities, c_v ...)
+    given to both sides."""
     tc = O.Tc(w.a, w.b, w.R)
     rv, rl, _ = O.maxwell(w.a, w.b, w.R, w.omega, w.Ts_over_Tc * tc)
     if rho0 is None:
@@ -53,7 +55,7 @@ def make_pair(w: WL.Workload, *, precision=None, mode=O.COUPLED, periodic_y=0, G
     g = w.g if g is None else g
     common = dict(nx=w.nx, ny=w.ny, a=w.a, b=w.b, R=w.R, omega=w.omega, Ts_over_Tc=w.Ts_over_Tc,
                   sigma=w.sigma, g=g, Gw_bottom=w.Gw_bottom, Gw_top=Gw_top, rho_L=rl, rho_V=rv,
-                  periodic_y=periodic_y, thermal_mode=mode)
+                  periodic_y=periodic_y, thermal_mode=mode, **extra)
     o = O.State(O.Params(**common), rho0, ux0=ux0, uy0=uy0, T0=T0, T_bottom=Tb)
     prec = {"fp64": L.FP64, "fp32": L.FP32}[w.precision] if precision is None else precision
     d = L.Domain(L.Params(precision=prec, liquid_rows=w.liquid_rows, **common), T_bottom=Tb, rho0=rho0)

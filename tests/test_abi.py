@@ -48,10 +48,13 @@ def test_default_params_match_binding_layout():
 @pytest.mark.parametrize("field,value", [
     ("nx", 2), ("ny", 3), ("precision", 7), ("thermal_mode", 3), ("G", 1.0), ("a", -1.0),
     ("s_e", 2.0), ("nu_L", 0.0), ("cv", float("nan")), ("liquid_rows", 65), ("noise_amp", -1.0),
+    ("nx", 1 << 16), ("Ts_over_Tc", 0.0),
 ])
 def test_init_rejects_invalid_parameters(field, value):
     p = L.Params()
     setattr(p, field, value)
+    if field == "nx" and value == 1 << 16:
+        p.ny = 1 << 16  # 2^32 nodes: beyond the 31-bit node index
     with pytest.raises(L.LbbError) as e:
         L.Domain(p)
     assert e.value.code == L.LBB_EINVAL

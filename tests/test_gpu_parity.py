@@ -307,3 +307,34 @@ def test_read_into_device_buffers_matches_host_read():
         for k in ("rho", "ux", "uy", "T"):
             assert np.array_equal(host[k].reshape(PLAIN.ny, PLAIN.nx), ref[k]), (prec, k)
         assert np.array_equal(host["f"].reshape(9, PLAIN.ny, PLAIN.nx), ref["f"]), prec
+
+
+PARAM_VARIANTS = [
+    dict(a=3.0 / 49.0),
+    dict(Ts_over_Tc=0.90),
+    dict(sigma=0.0),
+    dict(s_e=1.2, s_zeta=1.4, s_q=1.6),
+    dict(nu_L=0.05, nu_V=0.25),
+    dict(cv=4.0, cv_chi=0.05),
+    dict(omega=0.2),
+    dict(g=1e-4),
+]
+
+
+@pytest.mark.parametrize("variant", range(len(PARAM_VARIANTS)))
+def test_parameter_variants_match_oracle(variant):
+    """The model's parameters other than the defaults (EOS, relaxation rates,
+    viscosities, thermal constants, sigma, gravity), each on a ragged lattice
+    with a heater and both wall strengths: FP64 to 1e-12."""
+    kw = PARAM_VARIANTS[variant]
+    _say("parameter variant", kw)
+    w = PLAIN.resized(90, 41, heater=(20, 61), dT_over_Tc=0.08, Gw_bottom=0.07, seed=30 + variant,
+                      **{k: v for k, v in kw.items() if k in ("a", "Ts_over_Tc", "sigma", "omega", "g")})
+    extra = {k: v for k, v in kw.items() if k not in ("a", "Ts_over_Tc", "sigma", "omega", "g")}
+    o, d, _ = make_pair(w, Gw_top=-0.02, **extra)
+    o.step(150)
+    d.step(150)
+    errs, bad = compare(o, d, TOL64)
+    assert not bad, errs
+    ho, hd = o.heat_flux(), d.heat_flux()
+    assert abs(hd["q_mean"] - ho["q_mean"]) <= TOL64 * heat_flux_scale(o)

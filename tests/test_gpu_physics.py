@@ -1,0 +1,45 @@
+"""The paper's contact-angle experiment on the GPU path (Sec. 3.2, 3.3):
+sessile drops at T_s (a = 3/49, no gravity, isothermal) on walls of three
+strengths, run as one batch.  Each member's field must match the oracle and
+its cap angle the paper's (about 44.5, 50 and 55.5 deg)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1501_03857_amd import lbboil as L
+from parity_utils import normwise
+from physics_utils import cap_angle
+
+pytestmark = pytest.mark.gpu
+
+A3, B, R, OMEGA = 3.0 / 49.0, 2.0 / 21.0, 1.0, 0.344
+
+
+def test_sessile_drop_contact_angles_batched(golden):
+    print("[gpu-case] sessile drops, batch of 3, 3000 steps", flush=True)
+    ref = golden["contact_angles"]
+    tc = O.Tc(A3, B, R)
+    rv, rl, _ = O.maxwell(A3, B, R, OMEGA, 0.86 * tc)
+    nx, ny = 160, 60
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    rho0 = rv + (rl - rv) * 0.5 * (1 - np.tanh((np.hypot(x - nx / 2, y) - 22) / 2))
+    params = [L.Params(nx=nx, ny=ny, a=A3, rho_L=rl, rho_V=rv, g=0.0, Gw_bottom=Gw, thermal_mode=L.ISOTHERMAL,
+                       liquid_rows=1) for Gw in ref["Gw"]]
+    b = L.Batch(params, None, [rho0] * len(params))
+    m0 = rho0.sum()
+    b.step(3000)
+    angles = []
+    for i, theta in enumerate(ref["theta_deg"]):
+        rho = b.domain(i).fields(f=False)["rho"]
+        angles.append(cap_angle(rho, rl, rv))
+        assert abs(angles[-1] - theta) < 1.5, (ref["Gw"][i], angles[-1], theta)
+        assert abs(rho.sum() / m0 - 1) < 0.02
+    assert angles[0] < angles[1] < angles[2]
+    print(f"[gpu-case] angles {angles} vs {ref['theta_deg']}", flush=True)
+    # the middle member against the oracle's run of the same drop
+    o = O.State(O.Params(nx=nx, ny=ny, a=A3, rho_L=rl, rho_V=rv, g=0.0, Gw_bottom=ref["Gw"][1],
+                         thermal_mode=O.ISOTHERMAL), rho0)
+    o.step(3000)
+    got, want = b.domain(1).fields(), o.fields()
+    for k in ("rho", "f"):
+        assert normwise(got[k], want[k]) <= 1e-12, k

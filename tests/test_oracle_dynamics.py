@@ -18,6 +18,7 @@ import pytest
 from scipy import integrate, optimize
 
 import oracle as O
+from physics_utils import cap_angle
 from oracle import COUPLED, ISOTHERMAL, Params, State
 from paper_1501_03857_amd import workloads as WL
 
@@ -270,22 +271,6 @@ def test_liquid_droplet_falls_under_buoyancy():
     assert shift[0] < -3.0 and shift[1] > 3.0
 
 
-def _cap_angle(rho, rl, rv):
-    """Contact angle (liquid side) of a circular cap: base width w on row 1
-    (the first fluid row) and apex height h above it, tan(theta/2) = 2h/w."""
-    mid = 0.5 * (rl + rv)
-    nx = rho.shape[1]
-    c = rho[:, nx // 2]
-    j = np.where(c > mid)[0].max()
-    top = j + (c[j] - mid) / (c[j] - c[j + 1])
-    r1 = rho[1]
-    idx = np.where(r1 > mid)[0]
-    i0, i1 = idx.min(), idx.max()
-    assert 0 < i0 and i1 < nx - 1, "drop touches the periodic seam"
-    w = (i1 - i0) + (r1[i0] - mid) / (r1[i0] - r1[i0 - 1]) + (r1[i1] - mid) / (r1[i1] - r1[i1 + 1])
-    return 2 * np.degrees(np.arctan(2 * (top - 1) / w))
-
-
 @pytest.mark.slow
 def test_contact_angles_match_paper(golden):
     """Sessile drops at T_s with a = 3/49: G_w = 0 (fluid-fluid force off on
@@ -304,7 +289,7 @@ def test_contact_angles_match_paper(golden):
         s = State(p, rho0)
         m0 = s.fields()["rho"].sum()
         rho = s.step(3000).fields()["rho"]
-        angles.append(_cap_angle(rho, rl, rv))
+        angles.append(cap_angle(rho, rl, rv))
         assert abs(angles[-1] - theta) < 1.5, (Gw, angles[-1], theta)
         assert abs(rho.sum() / m0 - 1) < 0.02  # walls do not create mass
     assert angles[0] < angles[1] < angles[2]
