@@ -432,14 +432,14 @@ __global__ __launch_bounds__(64 * NWA) void k_lb(const Inst *__restrict__ insts,
         return gy >= 0 && gy < P.ny;
     };
     // rho and psi of node (r, lane) into LDS; returns rho
-    auto psi_node = [&](int r, int gy, const S fs[9]) -> double {
+    auto psi_node = [&](int r, int gy, const S fs[9], S Tn) -> double {
         double fl[9];
         complete_node(P, fs, gy, fl);
         double rr = fl[0];
 #pragma unroll
         for (int a = 1; a < 9; ++a) rr += fl[a];
         if (!frozen) {
-            const double T = P.T_ref + (double)Tin[(size_t)gy * P.nx + gx];
+            const double T = P.T_ref + (double)Tn;
             const double psi = pseudopotential(P, rr, T);
             if (!(rr > 0.0) || !(rr < 1e300)) flag_error(sc, t, ERR_RHO);
             if (!(psi >= 0.0) || !(psi < 1e300)) flag_error(sc, t, ERR_PSI);
@@ -449,38 +449,44 @@ __global__ __launch_bounds__(64 * NWA) void k_lb(const Inst *__restrict__ insts,
     };
 
     // phase 1: the wave's interior rows (populations kept in registers) and,
-    // for waves 0 and 1, the halo rows 0 and H-1 (psi only)
-    S fs[IPW_A][9];
+    // for waves 0 and 1, the halo rows 0 and H-1 (psi only).  Every global
+    // load of the phase is issued before the first arithmetic, so their
+    // latencies overlap.
+    S fs[IPW_A][9], Tv[IPW_A];
     double rho[IPW_A];
     int gys[IPW_A];
-    bool live[IPW_A];
+    bool live[IPW_A], inl[IPW_A];
 #pragma unroll
     for (int m = 0; m < IPW_A; ++m) {
         const int r = 1 + wv + NWA * m;
         int gy;
-        const bool in_lattice = row_of(r, gy);
+        inl[m] = row_of(r, gy);
         // a ragged last tile row beyond ny is not collided here, but with
         // periodic y it wraps onto a real row whose psi its neighbour needs
-        live[m] = in_lattice && y0 + r - 1 < P.ny;
+        live[m] = inl[m] && y0 + r - 1 < P.ny;
         gys[m] = gy;
-        rho[m] = 1.0;
-        if (!in_lattice) continue;
+        if (!inl[m]) continue;
         const size_t c = (size_t)gy * P.nx + gx;
 #pragma unroll
         for (int a = 0; a < 9; ++a) fs[m][a] = fin[(size_t)a * N + c];
-        rho[m] = psi_node(r, gy, fs[m]);
+        Tv[m] = frozen ? S(0) : Tin[c];
     }
-    if (wv < 2) {
-        const int r = wv == 0 ? 0 : H - 1;
-        int gy;
-        if (row_of(r, gy)) {
-            const size_t c = (size_t)gy * P.nx + gx;
-            S hs[9];
+    const int rh_ = wv == 0 ? 0 : H - 1;
+    int gyh = 0;
+    const bool halo = wv < 2 && row_of(rh_, gyh);
+    S hs[9], Th = S(0);
+    if (halo) {
+        const size_t c = (size_t)gyh * P.nx + gx;
 #pragma unroll
-            for (int a = 0; a < 9; ++a) hs[a] = fin[(size_t)a * N + c];
-            (void)psi_node(r, gy, hs);
-        }
+        for (int a = 0; a < 9; ++a) hs[a] = fin[(size_t)a * N + c];
+        Th = frozen ? S(0) : Tin[c];
     }
+#pragma unroll
+    for (int m = 0; m < IPW_A; ++m) {
+        rho[m] = 1.0;
+        if (inl[m]) rho[m] = psi_node(1 + wv + NWA * m, gys[m], fs[m], Tv[m]);
+    }
+    if (halo) (void)psi_node(rh_, gyh, hs, Th);
     __syncthreads();
     const double rho_ave = sc->rho_ave;
 
@@ -598,8 +604,8 @@ __global__ __launch_bounds__(64 * NWB) void k_thermal(const Inst *__restrict__ i
     constexpr int H = TY + 2 * HB;               // region rows
     constexpr int RPW = (H + NWB - 1) / NWB;     // region rows per wave
     __shared__ C T0[H][64];
-    __shared__ C X[4][H][64];   // rho, vx, vy after the load; then ax, ay, cw, cq
-    __shared__ C Ts[H][64];     // stage values T0 + c h; new T for the heat flux
+    __shared__ C X[3][H][64];   // rho, vx, vy
+    __shared__ C Ts[2][H][64];  // stage values T0 + c h (ping-pong); new T for the heat flux
     __shared__ double red[NWB];
     const long long t = sc->tB;
     if (blk == nbx * nby) {
@@ -648,14 +654,16 @@ __global__ __launch_bounds__(64 * NWB) void k_thermal(const Inst *__restrict__ i
 #pragma unroll
     for (int m = 0; m < RPW; ++m) acc[m] = C(0);
 
+    // Per-node coefficients of K on the region shrunk by one node, kept in
+    // registers (each wave evaluates K only at its own rows).
+    C cfr[4][RPW];
+#pragma unroll
+    for (int m = 0; m < RPW; ++m) cfr[0][m] = cfr[1][m] = cfr[2][m] = cfr[3][m] = C(0);
     if (run) {
-        // per-node coefficients on the region shrunk by one node
-        C cfr[4][RPW];
 #pragma unroll
         for (int m = 0; m < RPW; ++m) {
             const int r = wv + NWB * m;
             int gy;
-            cfr[0][m] = cfr[1][m] = cfr[2][m] = cfr[3][m] = C(0);
             if (r < 1 || r >= H - 1 || lane < 1 || lane >= 63 || !row_of(r, gy)) continue;
             if (walls && (gy == 0 || gy == P.ny - 1)) continue;
             const C(*rr)[64] = X[0];
@@ -684,61 +692,45 @@ __global__ __launch_bounds__(64 * NWB) void k_thermal(const Inst *__restrict__ i
             cfr[2][m] = (C)(P.R / P.cv * div * (rho * D2 * inv));
             cfr[3][m] = (C)(P.a / P.cv * rho * div * (rho * D1 * inv));
         }
-        __syncthreads();
-#pragma unroll
-        for (int m = 0; m < RPW; ++m) {
-            const int r = wv + NWB * m;
-            if (r >= H) continue;
-            X[0][r][lane] = cfr[0][m];
-            X[1][r][lane] = cfr[1][m];
-            X[2][r][lane] = cfr[2][m];
-            X[3][r][lane] = cfr[3][m];
-        }
-        __syncthreads();
 
         const C k1k = (C)(P.kappa * (1.0 + P.kappa)), k2 = (C)(P.kappa * P.kappa / P.Tc);
         const C inv_Tc = (C)(1.0 / P.Tc), Tref = (C)P.T_ref;
         const C cst[3] = {C(0.5), C(0.5), C(1.0)};
         const C wst[4] = {C(1), C(2), C(2), C(1)};
+        // stage st reads T0 (st = 0) or Ts[(st - 1) & 1] and writes Ts[st & 1]:
+        // one barrier per stage
 #pragma unroll
         for (int st = 0; st < 4; ++st) {
             const int rad = HB - 1 - st;
-            const C(*in)[64] = st == 0 ? T0 : Ts;
-            C h[RPW];
+            const C(*in)[64] = st == 0 ? T0 : Ts[(st - 1) & 1];
 #pragma unroll
             for (int m = 0; m < RPW; ++m) {
                 const int r = wv + NWB * m;
-                h[m] = C(0);
+                if (r >= H || r < HB - rad || r >= HB + TY + rad || lane < HB - rad || lane >= HB + TXB + rad) continue;
+                C h = C(0);
                 int gy;
-                if (r < HB - rad || r >= HB + TY + rad || lane < HB - rad || lane >= HB + TXB + rad) continue;
-                if (!row_of(r, gy) || (walls && (gy == 0 || gy == P.ny - 1))) continue;
-                const int l = lane;
-                const C tE = in[r][l + 1], tW = in[r][l - 1], tN = in[r + 1][l], tS = in[r - 1][l];
-                const C tNE = in[r + 1][l + 1], tNW = in[r + 1][l - 1], tSW = in[r - 1][l - 1], tSE = in[r - 1][l + 1];
-                const C tc = in[r][l];
-                const C dTx = (tE - tW) * C(1.0 / 3.0) + (tNE - tNW + tSE - tSW) * C(1.0 / 12.0);
-                const C dTy = (tN - tS) * C(1.0 / 3.0) + (tNE + tNW - tSE - tSW) * C(1.0 / 12.0);
-                const C lap = (tE + tW + tN + tS) * C(2.0 / 3.0) + (tNE + tNW + tSE + tSW) * C(1.0 / 6.0) - C(10.0 / 3.0) * tc;
-                const C T = Tref + tc;
-                const C Tphi = k2 * T - k1k * stage_sqrt(T * inv_Tc);
-                h[m] = -(X[0][r][l] * dTx + X[1][r][l] * dTy) + chi * lap - X[2][r][l] * T + X[3][r][l] * Tphi;
-                acc[m] += wst[st] * h[m];
-            }
-            if (st < 3) {
-                if (st > 0) __syncthreads();  // every read of the old stage values is done
-#pragma unroll
-                for (int m = 0; m < RPW; ++m) {
-                    const int r = wv + NWB * m;
-                    if (r >= H || r < HB - rad || r >= HB + TY + rad || lane < HB - rad || lane >= HB + TXB + rad) continue;
-                    Ts[r][lane] = T0[r][lane] + cst[st] * h[m];
+                if (row_of(r, gy) && !(walls && (gy == 0 || gy == P.ny - 1))) {
+                    const int l = lane;
+                    const C tE = in[r][l + 1], tW = in[r][l - 1], tN = in[r + 1][l], tS = in[r - 1][l];
+                    const C tNE = in[r + 1][l + 1], tNW = in[r + 1][l - 1], tSW = in[r - 1][l - 1], tSE = in[r - 1][l + 1];
+                    const C tc = in[r][l];
+                    const C dTx = (tE - tW) * C(1.0 / 3.0) + (tNE - tNW + tSE - tSW) * C(1.0 / 12.0);
+                    const C dTy = (tN - tS) * C(1.0 / 3.0) + (tNE + tNW - tSE - tSW) * C(1.0 / 12.0);
+                    const C lap = (tE + tW + tN + tS) * C(2.0 / 3.0) + (tNE + tNW + tSE + tSW) * C(1.0 / 6.0) - C(10.0 / 3.0) * tc;
+                    const C T = Tref + tc;
+                    const C Tphi = k2 * T - k1k * stage_sqrt(T * inv_Tc);
+                    h = -(cfr[0][m] * dTx + cfr[1][m] * dTy) + chi * lap - cfr[2][m] * T + cfr[3][m] * Tphi;
+                    acc[m] += wst[st] * h;
                 }
-                __syncthreads();
+                if (st < 3) Ts[st & 1][r][lane] = T0[r][lane] + cst[st] * h;
             }
+            if (st < 3) __syncthreads();
         }
     }
-    if (run) __syncthreads();  // the last stage read Ts; it is reused below
 
-    // new interior temperature (wall rows keep their Dirichlet values)
+    // new interior temperature (wall rows keep their Dirichlet values), into
+    // the stage plane the last stage did not read
+    C(*Tn_s)[64] = Ts[1];
 #pragma unroll
     for (int m = 0; m < RPW; ++m) {
         const int r = wv + NWB * m;
@@ -752,7 +744,7 @@ __global__ __launch_bounds__(64 * NWB) void k_thermal(const Inst *__restrict__ i
             if (!(Tabs > 0.0) || !(Tabs < 1e300)) flag_error(sc, t, ERR_T);
             Tout[(size_t)gy * P.nx + gx] = (S)Tn;
         }
-        Ts[r][lane] = Tn;
+        Tn_s[r][lane] = Tn;
     }
     __syncthreads();
 
@@ -766,7 +758,7 @@ __global__ __launch_bounds__(64 * NWB) void k_thermal(const Inst *__restrict__ i
             double r0 = fl[0];
 #pragma unroll
             for (int a = 1; a < 9; ++a) r0 += fl[a];
-            const double t0 = (double)T0[HB][lane], t1 = (double)Ts[HB + 1][lane], t2 = (double)Ts[HB + 2][lane];
+            const double t0 = (double)T0[HB][lane], t1 = (double)Tn_s[HB + 1][lane], t2 = (double)Tn_s[HB + 2][lane];
             qw = -P.cv_chi * r0 * (-3.0 * t0 + 4.0 * t1 - t2) / 2.0;
         }
 #pragma unroll
