@@ -21,13 +21,13 @@
 //               the improved forcing (Eqs. (2), (4), (5), (8)) and push
 //               streaming (Eq. (3)) into the other buffer; FP64 mass partials
 //               of the streamed state (exact identity, so the next step's
-//               rho_ave needs no extra pass).  One extra block reduces the
-//               heat-flux partials of the previous thermal launch.
+//               rho_ave needs no extra pass).  One extra block, first in the
+//               grid, reduces the heat-flux partials of the previous thermal launch.
 //   k_thermal: per tile (56 x 24 by default, halo 4): RK4 (Eqs. (19)-(20)) of Eq. (18) in
 //               LDS with the region shrinking by one node per stage; FP64
 //               heat-flux partials of the new state on the bottom tile row.
-//               One extra block reduces the mass partials of k_lb into
-//               rho_ave for the next step.
+//               One extra block, first in the grid, reduces the mass
+//               partials of k_lb into rho_ave for the next step.
 // All reductions run in a fixed order, so results are bitwise reproducible.
 #pragma once
 
@@ -225,11 +225,26 @@ __device__ __forceinline__ double block_sum_array(const double *__restrict__ a, 
 // Fixed-order sum of n doubles by the first 256 threads of a block of at
 // least 256 threads (the others add nothing), the same for any block size;
 // result valid in thread 0.  All threads of the block must call it.
+// s + a[k0] + a[k0 + stride] + ... (k < n), added in that order; the loads are
+// issued 16 at a time so a long sum waits for memory once per 16 terms.
+__device__ __forceinline__ double ordered_sum(const double *__restrict__ a, int k0, int n, int stride, double s)
+{
+    int k = k0;
+    for (; k + 15 * stride < n; k += 16 * stride) {
+        double v[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) v[j] = a[k + j * stride];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) s += v[j];
+    }
+    for (; k < n; k += stride) s += a[k];
+    return s;
+}
+
 __device__ __forceinline__ double fixed_sum(const double *__restrict__ a, int n, double *red /* [>= 4] */)
 {
     double s = 0.0;
-    if (threadIdx.x < NT)
-        for (int k = threadIdx.x; k < n; k += NT) s += a[k];
+    if (threadIdx.x < NT) s = ordered_sum(a, threadIdx.x, n, NT, 0.0);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -247,8 +262,7 @@ __device__ __forceinline__ void reduce_heat_flux(const double *__restrict__ hf_p
                                                  Scalars *sc, long long t)
 {
     if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int k = 0; k < n_hf; ++k) s += hf_part[k];
+        const double s = ordered_sum(hf_part, 0, n_hf, 1, 0.0);
         const double q = s / (double)nx;
         sc->q_now = q;
         if (t > sc->last_counted) {
@@ -408,12 +422,14 @@ __global__ __launch_bounds__(64 * NWA) void k_lb(const Inst *__restrict__ insts,
     constexpr int H = TYA + 2;                   // region rows (halo rows 0 and H-1)
     __shared__ double psi_s[H * 64];
     const long long t = sc->tA;
-    if (blk == nbx * nby) {
+    // block 0 of the lattice reduces the previous thermal launch's partials; it
+    // needs nothing from this launch, so it runs first, beside the tiles
+    if (blk == 0) {
         reduce_heat_flux(I.hf_part, I.nbxB, P.nx, sc, t);
         if (threadIdx.x == 0) sc->tB = t;  // the thermal launch of this step
         return;
     }
-    const int tile = xcd_tile(blk, nbx * nby);
+    const int tile = xcd_tile(blk - 1, nbx * nby);
     const int bx = tile % nbx, by = tile / nbx;
     const int x0 = bx * TXA, y0 = by * TYA;
     const size_t N = (size_t)P.nx * P.ny;
@@ -608,7 +624,7 @@ __global__ __launch_bounds__(64 * NWB) void k_thermal(const Inst *__restrict__ i
     __shared__ C Ts[2][H][64];  // stage values T0 + c h (ping-pong); new T for the heat flux
     __shared__ double red[NWB];
     const long long t = sc->tB;
-    if (blk == nbx * nby) {
+    if (blk == 0) {  // reduction of the LB launch's mass partials, first in the grid
         const double m = fixed_sum(I.mass_part, I.nbxA * P.ny, red);
         if (threadIdx.x == 0) {
             sc->rho_ave = m / ((double)P.nx * (double)P.ny);
@@ -616,7 +632,7 @@ __global__ __launch_bounds__(64 * NWB) void k_thermal(const Inst *__restrict__ i
         }
         return;
     }
-    const int tile = xcd_tile(blk, nbx * nby);
+    const int tile = xcd_tile(blk - 1, nbx * nby);
     const int bx = tile % nbx, by = tile / nbx;
     const int x0 = bx * TXB, y0 = by * TY;
     const bool walls = !P.periodic_y;
