@@ -163,17 +163,17 @@ def adjoint_bench():
                      Gw_bottom=w.Gw_bottom, rho_L=rl, rho_V=rv)
         d = L.Domain(p, T_bottom=w.heater_T(Tc), rho0=w.density(rl, rv))
         d.autotune(20)
-        d.adjoint(8, 4)  # warm-up (allocations, first launches)
         d.step(8)
         blob = d.save()
         t0 = time.perf_counter()
         d.step(w.steps)
         fwd = time.perf_counter() - t0
         d.load(blob)
+        d.adjoint(w.steps, 50)  # warm-up: the workspace for this interval, first launches
         t0 = time.perf_counter()
         J, g, gw = d.adjoint(w.steps, 50)
         adj = time.perf_counter() - t0
-        d.adjoint(8, 0)
+        d.adjoint(w.steps, 0)  # warm-up for the interval the library picks
         t0 = time.perf_counter()
         d.adjoint(w.steps, 0)
         adj_auto = time.perf_counter() - t0

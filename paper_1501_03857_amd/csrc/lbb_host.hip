@@ -1545,7 +1545,7 @@ struct AdjGroup {
 
 // Per-lattice pieces of the workspace.
 struct AdjMember {
-    unsigned char *backup, *ck, *seg;
+    unsigned char *backup, *ck, *seg[2];
     lbb::Scalars *ck_sc;
     double *hf_backup, *lf[2], *lT[2], *gr[2];
     lbb::AdjW w;
@@ -1567,6 +1567,34 @@ int64_t auto_K(const AdjGroup &g, int64_t N, size_t es)
     return K < 1 ? 1 : K;
 }
 
+// Second stream and its two events for the recompute of the next segment,
+// released on every return.
+struct RecomputeStream {
+    hipStream_t c = nullptr;
+    hipEvent_t done = nullptr, free_buf = nullptr;
+    hipError_t create()
+    {
+        hipError_t e = hipStreamCreateWithFlags(&c, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&free_buf, hipEventDisableTiming);
+        return e;
+    }
+    ~RecomputeStream()
+    {
+        if (c) {
+            (void)hipStreamSynchronize(c);
+            (void)hipStreamDestroy(c);
+        }
+        if (done) (void)hipEventDestroy(done);
+        if (free_buf) (void)hipEventDestroy(free_buf);
+    }
+};
+
+// Reverse sweep with checkpoints every K steps.  With more than one segment
+// the segment storage is doubled: while the reverse steps of segment s run on
+// the group's stream from one buffer, a second stream recomputes segment
+// s - 1 from its checkpoint into the other, so the recompute pass overlaps
+// the reverse pass instead of adding to it.
 template <typename S>
 int adjoint_run(AdjGroup &g, int64_t N, int64_t K, double *J, double *dJ_dTb, double *dJ_dGw)
 {
@@ -1574,9 +1602,10 @@ int adjoint_run(AdjGroup &g, int64_t N, int64_t K, double *J, double *dJ_dTb, do
     const int nm = (int)g.doms.size();
     const size_t es = sizeof(S);
     const int64_t nck = (N + K - 1) / K;
+    const int nbuf = nck > 1 ? 2 : 1;
     hipStream_t st = g.st;
     std::vector<AdjMember> m(nm);
-    Inst *inst_seg = nullptr;  // [K][nm]: step k of a segment reads stored state k, writes k+1
+    Inst *inst_seg = nullptr;  // [nbuf][K][nm]: step k of a segment reads stored state k, writes k+1
     AdjInst *d_ai = nullptr;
     int *d_amap = nullptr, *d_tmap = nullptr;
     int tot = 0, ttot = 0;
@@ -1610,7 +1639,8 @@ int adjoint_run(AdjGroup &g, int64_t N, int64_t K, double *J, double *dJ_dTb, do
             const size_t n = a.n;
             a.backup = cv.take<unsigned char>(a.state_bytes);
             a.ck = cv.take<unsigned char>((size_t)nck * a.state_bytes);
-            a.seg = cv.take<unsigned char>((size_t)(K + 1) * a.state_bytes);
+            for (int b = 0; b < 2; ++b)
+                a.seg[b] = b < nbuf ? cv.take<unsigned char>((size_t)(K + 1) * a.state_bytes) : nullptr;
             a.ck_sc = cv.take<Scalars>((size_t)nck + 1);
             a.hf_backup = cv.take<double>(g.doms[i]->nbxB);
             for (int k = 0; k < 2; ++k) {
@@ -1628,8 +1658,8 @@ int adjoint_run(AdjGroup &g, int64_t N, int64_t K, double *J, double *dJ_dTb, do
             w.fpart = cv.take<double>(2 * (size_t)a.nb);
             w.scal = cv.take<double>(4);
         }
-        inst_seg = cv.take<Inst>((size_t)K * nm);
-        d_ai = cv.take<AdjInst>(nm);
+        inst_seg = cv.take<Inst>((size_t)nbuf * K * nm);
+        d_ai = cv.take<AdjInst>((size_t)nbuf * nm);
         d_amap = cv.take<int>(tot);
         d_tmap = cv.take<int>(ttot);
         return cv.off;
@@ -1670,10 +1700,15 @@ int adjoint_run(AdjGroup &g, int64_t N, int64_t K, double *J, double *dJ_dTb, do
         *g.cf ^= 1;
         *g.cT ^= 1;
     };
-    auto slot_step = [&](int64_t k) {
-        launch_lb<S>(st, inst_seg + k * nm, g.blkA, g.totA, 0, 0, g.shA);
-        launch_thermal<S>(st, inst_seg + k * nm, g.blkB, g.totB, 0, 0, g.shB);
+    auto slot_step = [&](hipStream_t s, int b, int64_t k) {
+        const Inst *tab = inst_seg + ((size_t)b * K + k) * nm;
+        launch_lb<S>(s, tab, g.blkA, g.totA, 0, 0, g.shA);
+        launch_thermal<S>(s, tab, g.blkB, g.totB, 0, 0, g.shB);
     };
+    // buffer holding segment sg's states (the last segment uses buffer 0)
+    auto buf_of = [&](int64_t sg) { return (int)((nck - 1 - sg) & 1); };
+    RecomputeStream rs;
+    if (nbuf > 1) LBB_HIP(rs.create());
 
     // keep each lattice's state, counters and heat-flux partials
     for (int i = 0; i < nm; ++i) {
@@ -1683,30 +1718,30 @@ int adjoint_run(AdjGroup &g, int64_t N, int64_t K, double *J, double *dJ_dTb, do
         LBB_HIP(hipMemcpyAsync(m[i].hf_backup, d->hf_part, d->nbxB * sizeof(double), hipMemcpyDeviceToDevice, st));
     }
     // launch tables: stored-state steps and the adjoint grid
-    std::vector<Inst> hinst((size_t)K * nm);
-    std::vector<AdjInst> hai(nm);
+    std::vector<Inst> hinst((size_t)nbuf * K * nm);
+    std::vector<AdjInst> hai((size_t)nbuf * nm);
     std::vector<int> hamap, htmap;
     hamap.reserve(tot);
     htmap.reserve(ttot);
     for (int i = 0; i < nm; ++i) {
         lbb_domain *d = g.doms[i];
         const size_t n = m[i].n;
-        for (int64_t k = 0; k < K; ++k) {
-            Inst I = make_inst(d);
-            S *a = reinterpret_cast<S *>(m[i].seg + (size_t)k * m[i].state_bytes);
-            S *b = reinterpret_cast<S *>(m[i].seg + (size_t)(k + 1) * m[i].state_bytes);
-            I.f[0] = a;
-            I.f[1] = b;
-            I.T[0] = a + 9 * n;
-            I.T[1] = b + 9 * n;
-            I.blkA0 = g.blkA0[i];
-            I.blkB0 = g.blkB0[i];
-            hinst[(size_t)k * nm + i] = I;
-        }
+        for (int b = 0; b < nbuf; ++b)
+            for (int64_t k = 0; k < K; ++k) {
+                Inst I = make_inst(d);
+                S *x = reinterpret_cast<S *>(m[i].seg[b] + (size_t)k * m[i].state_bytes);
+                S *y = reinterpret_cast<S *>(m[i].seg[b] + (size_t)(k + 1) * m[i].state_bytes);
+                I.f[0] = x;
+                I.f[1] = y;
+                I.T[0] = x + 9 * n;
+                I.T[1] = y + 9 * n;
+                I.blkA0 = g.blkA0[i];
+                I.blkB0 = g.blkB0[i];
+                hinst[((size_t)b * K + k) * nm + i] = I;
+            }
         AdjInst A{};
         A.P = d->dp;
         A.w = m[i].w;
-        A.seg = m[i].seg;
         for (int k = 0; k < 2; ++k) {
             A.lf[k] = m[i].lf[k];
             A.lT[k] = m[i].lT[k];
@@ -1717,14 +1752,17 @@ int adjoint_run(AdjGroup &g, int64_t N, int64_t K, double *J, double *dJ_dTb, do
         A.nb = m[i].nb;
         A.tgx = m[i].tgx;
         A.tblk0 = (int)htmap.size();
-        hai[i] = A;
+        for (int b = 0; b < nbuf; ++b) {
+            A.seg = m[i].seg[b];
+            hai[(size_t)b * nm + i] = A;
+            hipLaunchKernelGGL(a_bcast_T<S>, dim3(256), dim3(256), 0, st, static_cast<const S *>(own_T(i)),
+                               reinterpret_cast<S *>(m[i].seg[b]), n, (int)(K + 1));
+        }
         hamap.insert(hamap.end(), m[i].nb, i);
         htmap.insert(htmap.end(), m[i].tnb, i);
-        hipLaunchKernelGGL(a_bcast_T<S>, dim3(256), dim3(256), 0, st, static_cast<const S *>(own_T(i)),
-                           reinterpret_cast<S *>(m[i].seg), n, (int)(K + 1));
     }
     LBB_HIP(hipMemcpyAsync(inst_seg, hinst.data(), hinst.size() * sizeof(Inst), hipMemcpyHostToDevice, st));
-    LBB_HIP(hipMemcpyAsync(d_ai, hai.data(), nm * sizeof(AdjInst), hipMemcpyHostToDevice, st));
+    LBB_HIP(hipMemcpyAsync(d_ai, hai.data(), hai.size() * sizeof(AdjInst), hipMemcpyHostToDevice, st));
     LBB_HIP(hipMemcpyAsync(d_amap, hamap.data(), tot * sizeof(int), hipMemcpyHostToDevice, st));
     LBB_HIP(hipMemcpyAsync(d_tmap, htmap.data(), ttot * sizeof(int), hipMemcpyHostToDevice, st));
 
@@ -1743,12 +1781,12 @@ int adjoint_run(AdjGroup &g, int64_t N, int64_t K, double *J, double *dJ_dTb, do
     for (int64_t t = 0; t < N; ++t) {
         if (t % K == 0)
             for (int i = 0; i < nm; ++i) {
-                LBB_HIP(copy_state_out(i, t < tL ? m[i].ck + (size_t)(t / K) * m[i].state_bytes : m[i].seg));
+                LBB_HIP(copy_state_out(i, t < tL ? m[i].ck + (size_t)(t / K) * m[i].state_bytes : m[i].seg[0]));
                 LBB_HIP(hipMemcpyAsync(&m[i].ck_sc[t / K], g.doms[i]->sc, sizeof(Scalars), hipMemcpyDeviceToDevice,
                                        st));
             }
         if (t < tL) own_step();
-        else slot_step(t - tL);
+        else slot_step(st, 0, t - tL);
         LBB_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_flush_heat_flux, dim3(nm), dim3(NT), 0, st, g.fwd_insts);
@@ -1773,26 +1811,39 @@ int adjoint_run(AdjGroup &g, int64_t N, int64_t K, double *J, double *dJ_dTb, do
     const dim3 grid(tot), blk(NTA);
     int cur = 0;
     hipLaunchKernelGGL(a_hf<S>, grid, blk, 0, st, d_ai, d_amap, (int)(N - tL), wq, cur);
+    // recompute of segment sg from its checkpoint into its buffer, on the
+    // second stream once the reverse steps that last read that buffer are done
+    auto recompute = [&](int64_t sg) -> hipError_t {
+        const int64_t t0 = sg * K, t1 = (t0 + K < N) ? t0 + K : N;
+        const int b = buf_of(sg);
+        hipError_t e = hipEventRecord(rs.free_buf, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(rs.c, rs.free_buf, 0);
+        for (int i = 0; i < nm && e == hipSuccess; ++i) {
+            e = hipMemcpyAsync(m[i].seg[b], m[i].ck + (size_t)sg * m[i].state_bytes, m[i].state_bytes,
+                               hipMemcpyDeviceToDevice, rs.c);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(g.doms[i]->sc, &m[i].ck_sc[sg], sizeof(Scalars), hipMemcpyDeviceToDevice, rs.c);
+        }
+        if (e != hipSuccess) return e;
+        for (int64_t t = t0; t + 1 < t1; ++t) slot_step(rs.c, b, t - t0);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipEventRecord(rs.done, rs.c);
+        return e;
+    };
     for (int64_t sg = nck - 1; sg >= 0; --sg) {
         const int64_t t0 = sg * K, t1 = (t0 + K < N) ? t0 + K : N;
-        if (sg < nck - 1) {
-            // recompute the segment's states from its checkpoint into the slots
-            for (int i = 0; i < nm; ++i) {
-                LBB_HIP(hipMemcpyAsync(m[i].seg, m[i].ck + (size_t)sg * m[i].state_bytes, m[i].state_bytes,
-                                       hipMemcpyDeviceToDevice, st));
-                LBB_HIP(hipMemcpyAsync(g.doms[i]->sc, &m[i].ck_sc[sg], sizeof(Scalars), hipMemcpyDeviceToDevice, st));
-            }
-            for (int64_t t = t0; t + 1 < t1; ++t) slot_step(t - t0);
-        }
-        hipLaunchKernelGGL(a_macro<S>, grid, blk, 0, st, d_ai, d_amap, (int)(t1 - 1 - t0));
+        const AdjInst *ai = d_ai + (size_t)buf_of(sg) * nm;
+        if (sg < nck - 1) LBB_HIP(hipStreamWaitEvent(st, rs.done, 0));  // segment sg recomputed
+        if (sg > 0) LBB_HIP(recompute(sg - 1));
+        hipLaunchKernelGGL(a_macro<S>, grid, blk, 0, st, ai, d_amap, (int)(t1 - 1 - t0));
         for (int64_t t = t1 - 1; t >= t0; --t) {
             const int k = (int)(t - t0);
-            hipLaunchKernelGGL(a_force, grid, blk, 0, st, d_ai, d_amap);
-            hipLaunchKernelGGL(a_divv0, grid, blk, 0, st, d_ai, d_amap);
-            if (tay == 16) hipLaunchKernelGGL((a_theradj<16, 16>), dim3(ttot), dim3(64 * 16), 0, st, d_ai, d_tmap, cur);
-            else hipLaunchKernelGGL((a_theradj<8, 8>), dim3(ttot), dim3(64 * 8), 0, st, d_ai, d_tmap, cur);
-            hipLaunchKernelGGL(a_lb<S>, grid, blk, 0, st, d_ai, d_amap, k, cur);
-            hipLaunchKernelGGL(a_final<S>, grid, blk, 0, st, d_ai, d_amap, k, cur, t >= 1 ? wq : 0.0,
+            hipLaunchKernelGGL(a_force, grid, blk, 0, st, ai, d_amap);
+            hipLaunchKernelGGL(a_divv0, grid, blk, 0, st, ai, d_amap);
+            if (tay == 16) hipLaunchKernelGGL((a_theradj<16, 16>), dim3(ttot), dim3(64 * 16), 0, st, ai, d_tmap, cur);
+            else hipLaunchKernelGGL((a_theradj<8, 8>), dim3(ttot), dim3(64 * 8), 0, st, ai, d_tmap, cur);
+            hipLaunchKernelGGL(a_lb<S>, grid, blk, 0, st, ai, d_amap, k, cur);
+            hipLaunchKernelGGL(a_final<S>, grid, blk, 0, st, ai, d_amap, k, cur, t >= 1 ? wq : 0.0,
                                t > t0 ? 1 : 0);
             cur ^= 1;
         }
