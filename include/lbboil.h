@@ -58,7 +58,8 @@ enum { LBB_COUPLED = 0, LBB_ISOTHERMAL = 1, LBB_THERMAL_ONLY = 2 };
 typedef struct lbb_params {
     int32_t nx, ny;          /* lattice nodes; rows 0 and ny-1 are the walls   */
     int32_t precision;       /* LBB_FP64, or LBB_FP32: f, T, rho, v stored in
-                                FP32; all arithmetic stays in FP64             */
+                                FP32; LB, EOS and reductions in FP64, the RK4
+                                stages in FP32 on T - T_s                      */
     int32_t periodic_y;      /* 1: no walls, periodic in y (test mode)         */
     int32_t thermal_mode;    /* LBB_COUPLED / LBB_ISOTHERMAL / LBB_THERMAL_ONLY */
     int32_t liquid_rows;     /* built-in initial state: rows j < liquid_rows
@@ -106,8 +107,10 @@ int lbb_coexistence(double a, double b, double R, double omega, double T,
  *                   of the (j*nx+i+1)-th output of the generator seeded with
  *                   seed, top 53 bits mapped to [0,1), amplitude noise_amp).
  * f starts at equilibrium at rest, T = T_s with the Dirichlet wall rows.
- * EINVAL: nx < 3, ny < 4 (ny < 3 when periodic_y), G >= 0, non-finite or
- * non-positive inputs, b*rho >= 1, rho_L == rho_V.  ENOMEM/EDEVICE on HIP
+ * EINVAL: nx < 3, ny < 4 (ny < 3 when periodic_y), a field plane of 2^32
+ * bytes or more (nx*ny*sizeof(real) >= 2^32: 2^30 nodes in FP32, 2^29 in
+ * FP64), G >= 0, non-finite or non-positive inputs, b*rho >= 1,
+ * rho_L == rho_V.  ENOMEM/EDEVICE on HIP
  * failures.  Device memory: about (20 + 5) * nx * ny * sizeof(real) bytes. */
 int lbb_init_domain(const lbb_params *p, const double *T_bottom, const double *rho0,
                     lbb_domain **out);

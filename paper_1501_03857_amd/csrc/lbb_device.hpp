@@ -133,6 +133,27 @@ __device__ __forceinline__ int wrapi(int i, int n)
     return r < 0 ? r + n : r;
 }
 
+// Plane-wise global memory access.  A field plane's base address is uniform
+// (scalar registers) and the lane adds a 32-bit byte offset, so each access
+// is one global load or store with no per-lane 64-bit address arithmetic.
+// The host keeps every plane below 4 GiB (nx ny sizeof(S) < 2^32), and the
+// cast to the global address space is free: lattice arrays are device
+// allocations.
+template <typename T>
+using gmem = __attribute__((address_space(1))) T;
+
+template <typename T>
+__device__ __forceinline__ T ld_at(const T *plane, unsigned byte_off)
+{
+    return *(const gmem<T> *)((const gmem<char> *)plane + byte_off);
+}
+
+template <typename T>
+__device__ __forceinline__ void st_at(T *plane, unsigned byte_off, T v)
+{
+    *(gmem<T> *)((gmem<char> *)plane + byte_off) = v;
+}
+
 // Zou-He completion of a wall node with zero wall velocity (Sec. 3.1): the
 // three populations arriving from outside follow from the known ones.
 __device__ __forceinline__ void zou_he(double f[9], int bottom)
@@ -406,7 +427,7 @@ __global__ __launch_bounds__(64 * NWA) void k_lb(const Inst *__restrict__ insts,
                                                  int cf, int cT)
 {
     const Inst &I = insts[blk2inst[blockIdx.x]];
-    const DevParams P = I.P;
+    const DevParams &P = I.P;
     const bool frozen = P.mode == MODE_THERMAL_ONLY;
     const S *__restrict__ fin = static_cast<const S *>(I.f[cf]);
     S *__restrict__ fout = static_cast<S *>(I.f[cf ^ 1]);
@@ -437,6 +458,7 @@ __global__ __launch_bounds__(64 * NWA) void k_lb(const Inst *__restrict__ insts,
     // the wave index is uniform over the wave: keep row logic on the scalar unit
     const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int gx = wrapi(x0 + lane - 1, P.nx);
+    const unsigned gxu = (unsigned)gx;
 
     // lattice row of region row r (wrapped when periodic); false beyond a wall
     auto row_of = [&](int r, int &gy) -> bool {
@@ -482,20 +504,20 @@ __global__ __launch_bounds__(64 * NWA) void k_lb(const Inst *__restrict__ insts,
         live[m] = inl[m] && y0 + r - 1 < P.ny;
         gys[m] = gy;
         if (!inl[m]) continue;
-        const size_t c = (size_t)gy * P.nx + gx;
+        const unsigned o = ((unsigned)gy * (unsigned)P.nx + gxu) * (unsigned)sizeof(S);
 #pragma unroll
-        for (int a = 0; a < 9; ++a) fs[m][a] = fin[(size_t)a * N + c];
-        Tv[m] = frozen ? S(0) : Tin[c];
+        for (int a = 0; a < 9; ++a) fs[m][a] = ld_at(fin + (size_t)a * N, o);
+        Tv[m] = frozen ? S(0) : ld_at(Tin, o);
     }
     const int rh_ = wv == 0 ? 0 : H - 1;
     int gyh = 0;
     const bool halo = wv < 2 && row_of(rh_, gyh);
     S hs[9], Th = S(0);
     if (halo) {
-        const size_t c = (size_t)gyh * P.nx + gx;
+        const unsigned o = ((unsigned)gyh * (unsigned)P.nx + gxu) * (unsigned)sizeof(S);
 #pragma unroll
-        for (int a = 0; a < 9; ++a) hs[a] = fin[(size_t)a * N + c];
-        Th = frozen ? S(0) : Tin[c];
+        for (int a = 0; a < 9; ++a) hs[a] = ld_at(fin + (size_t)a * N, o);
+        Th = frozen ? S(0) : ld_at(Tin, o);
     }
 #pragma unroll
     for (int m = 0; m < IPW_A; ++m) {
@@ -513,7 +535,8 @@ __global__ __launch_bounds__(64 * NWA) void k_lb(const Inst *__restrict__ insts,
         const int gy = gys[m];
         mrow[m] = 0.0;
         if (!live[m] || lane < 1 || lane > TXA || x0 + lane - 1 >= P.nx) continue;
-        const size_t c = (size_t)gy * P.nx + gx;
+        constexpr unsigned sz = (unsigned)sizeof(S);
+        const unsigned rowc = (unsigned)gy * (unsigned)P.nx, oc = (rowc + gxu) * sz;
         double f[9];
         complete_node(P, fs[m], gy, f);
         const double rh = rho[m];
@@ -522,9 +545,9 @@ __global__ __launch_bounds__(64 * NWA) void k_lb(const Inst *__restrict__ insts,
         const bool wall_row = walls && (gy == 0 || gy == P.ny - 1);
         if (frozen) {
             // THERMAL_ONLY: f is frozen, the temperature sees sum e f / rho
-            rho_o[c] = S(rh);
-            vx_o[c] = wall_row ? S(0) : S(jx / rh);
-            vy_o[c] = wall_row ? S(0) : S(jy / rh);
+            st_at(rho_o, oc, S(rh));
+            st_at(vx_o, oc, wall_row ? S(0) : S(jx / rh));
+            st_at(vy_o, oc, wall_row ? S(0) : S(jy / rh));
             double mm = 0.0;
 #pragma unroll
             for (int a = 0; a < 9; ++a) mm += f[a];
@@ -536,9 +559,9 @@ __global__ __launch_bounds__(64 * NWA) void k_lb(const Inst *__restrict__ insts,
         const double inv_rho = 1.0 / rh;
         const double vx = (jx + 0.5 * Fx) * inv_rho;
         const double vy = (jy + 0.5 * Fy) * inv_rho;
-        rho_o[c] = S(rh);
-        vx_o[c] = wall_row ? S(0) : S(vx);
-        vy_o[c] = wall_row ? S(0) : S(vy);
+        st_at(rho_o, oc, S(rh));
+        st_at(vx_o, oc, wall_row ? S(0) : S(vx));
+        st_at(vy_o, oc, wall_row ? S(0) : S(vy));
         collide(P, f, rh, vx, vy, Fx, Fy, Q);
         // round to the storage precision once; the mass partial sees what is stored
 #pragma unroll
@@ -556,19 +579,20 @@ __global__ __launch_bounds__(64 * NWA) void k_lb(const Inst *__restrict__ insts,
             if (ys < 0) ys = P.ny - 1;
         }
         const bool has_n = yn < P.ny, has_s = ys >= 0;
-        const size_t rowc = (size_t)gy * P.nx, rown = (size_t)yn * P.nx, rows = (size_t)ys * P.nx;
-        fout[0 * N + rowc + gx] = S(f[0]);
-        fout[1 * N + rowc + xe] = S(f[1]);
-        fout[3 * N + rowc + xw] = S(f[3]);
+        const unsigned rown = (unsigned)yn * (unsigned)P.nx, rows = (unsigned)ys * (unsigned)P.nx;
+        const unsigned xeu = (unsigned)xe, xwu = (unsigned)xw;
+        st_at(fout + 0 * N, oc, S(f[0]));
+        st_at(fout + 1 * N, (rowc + xeu) * sz, S(f[1]));
+        st_at(fout + 3 * N, (rowc + xwu) * sz, S(f[3]));
         if (has_n) {
-            fout[2 * N + rown + gx] = S(f[2]);
-            fout[5 * N + rown + xe] = S(f[5]);
-            fout[6 * N + rown + xw] = S(f[6]);
+            st_at(fout + 2 * N, (rown + gxu) * sz, S(f[2]));
+            st_at(fout + 5 * N, (rown + xeu) * sz, S(f[5]));
+            st_at(fout + 6 * N, (rown + xwu) * sz, S(f[6]));
         }
         if (has_s) {
-            fout[4 * N + rows + gx] = S(f[4]);
-            fout[7 * N + rows + xw] = S(f[7]);
-            fout[8 * N + rows + xe] = S(f[8]);
+            st_at(fout + 4 * N, (rows + gxu) * sz, S(f[4]));
+            st_at(fout + 7 * N, (rows + xwu) * sz, S(f[7]));
+            st_at(fout + 8 * N, (rows + xeu) * sz, S(f[8]));
         }
         const double up = f[2] + f[5] + f[6];
         const double dn = f[4] + f[7] + f[8];
@@ -606,7 +630,7 @@ __global__ __launch_bounds__(64 * NWB) void k_thermal(const Inst *__restrict__ i
                                                       const int *__restrict__ blk2inst, int cf, int cT)
 {
     const Inst &I = insts[blk2inst[blockIdx.x]];
-    const DevParams P = I.P;
+    const DevParams &P = I.P;
     const S *__restrict__ Tin = static_cast<const S *>(I.T[cT]);
     S *__restrict__ Tout = static_cast<S *>(I.T[cT ^ 1]);
     const S *__restrict__ rho_i = static_cast<const S *>(I.rho);
@@ -639,6 +663,7 @@ __global__ __launch_bounds__(64 * NWB) void k_thermal(const Inst *__restrict__ i
     const bool run = P.mode != MODE_ISOTHERMAL;
     const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int gx = wrapi(x0 + lane - HB, P.nx);
+    const unsigned gxu = (unsigned)gx;
 
     // lattice row of region row r; false beyond a wall
     auto row_of = [&](int r, int &gy) -> bool {
@@ -655,12 +680,12 @@ __global__ __launch_bounds__(64 * NWB) void k_thermal(const Inst *__restrict__ i
         const int r = wv + NWB * m;
         int gy;
         if (r >= H || !row_of(r, gy)) continue;
-        const size_t c = (size_t)gy * P.nx + gx;
-        T0[r][lane] = (C)Tin[c];
+        const unsigned o = ((unsigned)gy * (unsigned)P.nx + gxu) * (unsigned)sizeof(S);
+        T0[r][lane] = (C)ld_at(Tin, o);
         if (run) {
-            X[0][r][lane] = (C)rho_i[c];
-            X[1][r][lane] = (C)vx_i[c];
-            X[2][r][lane] = (C)vy_i[c];
+            X[0][r][lane] = (C)ld_at(rho_i, o);
+            X[1][r][lane] = (C)ld_at(vx_i, o);
+            X[2][r][lane] = (C)ld_at(vy_i, o);
         }
     }
     __syncthreads();
@@ -758,7 +783,7 @@ __global__ __launch_bounds__(64 * NWB) void k_thermal(const Inst *__restrict__ i
             Tn = (C)(S)(T0[r][lane] + acc[m] / C(6));
             const double Tabs = P.T_ref + (double)Tn;
             if (!(Tabs > 0.0) || !(Tabs < 1e300)) flag_error(sc, t, ERR_T);
-            Tout[(size_t)gy * P.nx + gx] = (S)Tn;
+            st_at(Tout, ((unsigned)gy * (unsigned)P.nx + gxu) * (unsigned)sizeof(S), (S)Tn);
         }
         Tn_s[r][lane] = Tn;
     }

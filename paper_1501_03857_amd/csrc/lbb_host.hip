@@ -195,8 +195,10 @@ int validate(const lbb_params *p)
     if (!p) return fail(LBB_EINVAL, "params is NULL");
     if (p->nx < 3) return fail(LBB_EINVAL, "nx must be >= 3");
     if (p->periodic_y ? p->ny < 3 : p->ny < 4) return fail(LBB_EINVAL, "ny must be >= 4 (>= 3 when periodic_y)");
-    if ((int64_t)p->nx * p->ny > 2147483647LL) return fail(LBB_EINVAL, "nx*ny must fit in 31 bits");
     if (p->precision != LBB_FP64 && p->precision != LBB_FP32) return fail(LBB_EINVAL, "unknown precision");
+    // the kernels address a field plane with 32-bit byte offsets
+    const int64_t plane = (int64_t)p->nx * p->ny * (p->precision == LBB_FP64 ? 8 : 4);
+    if (plane >= (int64_t)1 << 32) return fail(LBB_EINVAL, "nx*ny*sizeof(real) must stay below 2^32 bytes");
     if (p->thermal_mode < LBB_COUPLED || p->thermal_mode > LBB_THERMAL_ONLY) return fail(LBB_EINVAL, "unknown thermal_mode");
     const double v[] = {p->a, p->b, p->R, p->omega, p->Ts_over_Tc, p->G, p->sigma, p->s_rho, p->s_e, p->s_zeta,
                         p->s_j, p->s_q, p->nu_L, p->nu_V, p->rho_L, p->rho_V, p->cv, p->cv_chi, p->g,

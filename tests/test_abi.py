@@ -54,10 +54,20 @@ def test_init_rejects_invalid_parameters(field, value):
     p = L.Params()
     setattr(p, field, value)
     if field == "nx" and value == 1 << 16:
-        p.ny = 1 << 16  # 2^32 nodes: beyond the 31-bit node index
+        p.ny = 1 << 16  # 2^32 nodes: a field plane of 2^35 bytes
     with pytest.raises(L.LbbError) as e:
         L.Domain(p)
     assert e.value.code == L.LBB_EINVAL
+
+
+def test_init_rejects_fp64_plane_of_4_gib():
+    """2^29 nodes in FP64 make an 8-byte field plane of exactly 2^32 bytes,
+    one byte past the 32-bit offsets the kernels use: refused before any
+    device memory is touched."""
+    p = L.Params(nx=1 << 15, ny=1 << 14, precision=L.FP64)
+    with pytest.raises(L.LbbError) as e:
+        L.Domain(p)
+    assert e.value.code == L.LBB_EINVAL and "2^32" in str(e.value)
 
 
 def test_init_rejects_bad_initial_density():
