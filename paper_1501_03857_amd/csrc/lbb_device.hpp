@@ -196,20 +196,53 @@ __device__ __forceinline__ void complete_node(const DevParams &P, const S fs[9],
     }
 }
 
+// 1/x from the hardware reciprocal estimate (relative error near 2^-23)
+// refined by two Newton-Raphson steps, r <- r + r (1 - x r), each of which
+// squares the error: within a few ulp for finite nonzero normal x.  Cheaper
+// than the correctly rounded division sequence; the FP64 tolerances allow it.
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// sqrt(x) from the hardware reciprocal square root y ~ 1/sqrt(x):
+// Goldschmidt's coupled iteration on g ~ sqrt(x), h ~ 1/(2 sqrt(x))
+// (r = 1/2 - g h; g <- g + g r; h <- h + h r), twice, then one Newton
+// correction g <- g + h (x - g^2).  Within a few ulp for normal x > 0;
+// 0 for x = 0, NaN below.
+__device__ __forceinline__ double sqrt_nr(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    const double d = fma(-g, g, x);
+    g = fma(d, h, g);
+    return x > 0.0 ? g : (x == 0.0 ? 0.0 : __builtin_nan(""));
+}
+
 // psi = sqrt(2 (p_EOS - rho/3) / G) with the Peng-Robinson p_EOS (Eq. (21)),
 // always in FP64.  Returns a negative value on a negative radicand.
-// The two fractions of p_EOS share one division:
+// The two fractions of p_EOS share one reciprocal:
 //   p = [rho R T D2 - a phi rho^2 D1] / (D1 D2), D1 = 1 - b rho,
 //   D2 = 1 + 2 b rho - b^2 rho^2.
 __device__ __forceinline__ double pseudopotential(const DevParams &P, double rho, double T)
 {
-    const double s = 1.0 + P.kappa * (1.0 - sqrt(T * P.inv_Tc));
+    const double s = 1.0 + P.kappa * (1.0 - sqrt_nr(T * P.inv_Tc));
     const double phi = s * s;
     const double D1 = 1.0 - P.b * rho;
     const double D2 = 1.0 + 2.0 * P.b * rho - P.b * P.b * rho * rho;
-    const double p = (rho * P.R * T * D2 - P.a * phi * rho * rho * D1) / (D1 * D2);
+    const double p = (rho * P.R * T * D2 - P.a * phi * rho * rho * D1) * rcp_nr(D1 * D2);
     const double r = P.two_over_G * (p - rho * (1.0 / 3.0));
-    return (r >= 0.0) ? sqrt(r) : -1.0;
+    return (r >= 0.0) ? sqrt_nr(r) : -1.0;
 }
 
 __device__ __forceinline__ void flag_error(Scalars *sc, long long t, unsigned code)
@@ -346,7 +379,7 @@ __device__ __forceinline__ void collide(const DevParams &P, double f[9], double 
     const double v2 = vx * vx + vy * vy;
     const double vF = vx * Fx + vy * Fy;
     const double s_e = (P.s_e), s_z = (P.s_zeta), s_j = (P.s_j), s_q = (P.s_q);
-    const double s_nu = (1) / ((P.tau_V) + (rho - (P.rho_V)) * (P.tau_slope));
+    const double s_nu = rcp_nr((P.tau_V) + (rho - (P.rho_V)) * (P.tau_slope));
 
     // m* = m - L (m - m_eq) + (I - L/2) S
     const double e_s = m_e - s_e * (m_e - rho * ((-2) + (3) * v2)) + ((1) - (0.5) * s_e) * ((6) * vF + (P.sig_e) * Q);
@@ -556,7 +589,7 @@ __global__ __launch_bounds__(64 * NWA) void k_lb(const Inst *__restrict__ insts,
         }
         double Fx, Fy, Q;
         node_force<64>(P, psi_s, lane - 1, r - 1, gy, rh, rho_ave, Fx, Fy, Q);
-        const double inv_rho = 1.0 / rh;
+        const double inv_rho = rcp_nr(rh);
         const double vx = (jx + 0.5 * Fx) * inv_rho;
         const double vy = (jy + 0.5 * Fy) * inv_rho;
         st_at(rho_o, oc, S(rh));
