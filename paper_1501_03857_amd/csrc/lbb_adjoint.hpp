@@ -35,21 +35,34 @@ namespace lbb {
 constexpr int NTA = 256;          // threads per adjoint block
 constexpr int AXB = 64, AYB = 4;  // node patch of one block
 
-struct AdjW {
+// Work arrays of one lattice.  The host fills AdjW (= AdjWT<double>); the
+// kernels read the same pointers as AdjWT<gmem<double>>, so every access is
+// a global (not flat) memory instruction.
+template <typename D>
+struct AdjWT {
     // rho, j, psi and T of the state being reversed; a_final replaces them
     // by those of the state before it
-    double *rho, *jx, *jy, *psi, *T1;
-    double *sx, *sy, *Fx, *Fy, *vx, *vy, *Drx, *Dry;
+    D *rho, *jx, *jy, *psi, *T1;
+    D *sx, *sy, *Fx, *Fy, *vx, *vy, *Drx, *Dry;
     // Eq. (18) as K(T) = AX d_x T + AY d_y T + chi lap T - IA divv T + IB divv T phi'(T)
     // with AX = -vx + chi d_x rho / rho, IA = R / ((1 - b rho) c_v),
     // IB = a rho / ((1 + 2 b rho - b^2 rho^2) c_v); E1, E2 give the rho
     // derivative of the pressure-work factor; RI = 1 / rho
-    double *divv, *AX, *AY, *IA, *IB, *E1, *E2, *RI;
-    double *gDrx, *gDry, *gdiv, *grho, *gvx, *gvy, *gpsi, *gsx, *gsy;
-    double *mpart;   // block mass partials of the state being reversed
-    double *fpart;   // block partials of the force adjoint: [2b] rho_ave, [2b+1] G_w
-    double *scal;    // [2] dJ/dG_w, accumulated over the steps
+    D *divv, *AX, *AY, *IA, *IB, *E1, *E2, *RI;
+    D *gDrx, *gDry, *gdiv, *grho, *gvx, *gvy, *gpsi, *gsx, *gsy;
+    D *mpart;   // block mass partials of the state being reversed
+    D *fpart;   // block partials of the force adjoint: [2b] rho_ave, [2b+1] G_w
+    D *scal;    // [2] dJ/dG_w, accumulated over the steps
 };
+using AdjW = AdjWT<double>;
+using AdjWG = AdjWT<gmem<double>>;
+
+// a device array as a global-address-space pointer
+template <typename T>
+__device__ __forceinline__ gmem<T> *gp(T *p)
+{
+    return (gmem<T> *)p;
+}
 
 // One lattice of an adjoint launch: its parameters, work arrays, stored
 // states and adjoint buffers, and its place in the launch grid.  A launch
@@ -69,8 +82,8 @@ struct AdjInst {
 
 #define A_INST                                            \
     const AdjInst &I = ai[amap[blockIdx.x]];              \
-    const DevParams P = I.P;                              \
-    const AdjW &w = I.w;                                  \
+    const DevParams &P = I.P;                             \
+    const AdjWG &w = reinterpret_cast<const AdjWG &>(I.w); \
     const int q = (int)blockIdx.x - I.blk0;               \
     (void)w;
 
@@ -84,9 +97,9 @@ struct AdjInst {
 
 // stored state k of lattice I (populations; T follows at 9 nx ny)
 template <typename S>
-__device__ __forceinline__ const S *a_slot(const AdjInst &I, int k)
+__device__ __forceinline__ const gmem<S> *a_slot(const AdjInst &I, int k)
 {
-    return static_cast<const S *>(I.seg) + (size_t)k * 10 * (size_t)I.P.nx * I.P.ny;
+    return gp(static_cast<const S *>(I.seg)) + (size_t)k * 10 * (size_t)I.P.nx * I.P.ny;
 }
 
 #define A_ARGS const AdjInst *__restrict__ ai, const int *__restrict__ amap
@@ -116,7 +129,7 @@ __constant__ const double kWpsi[9] = {0.0, 1.0 / 3, 1.0 / 3, 1.0 / 3, 1.0 / 3, 1
 
 // Fixed-order sum of a[k * stride + off], k < n, returned to every thread of
 // the block (every block forms the same value); all threads must call it.
-__device__ __forceinline__ double block_sum_all(const double *__restrict__ a, int n, int stride, int off,
+__device__ __forceinline__ double block_sum_all(const gmem<double> *__restrict__ a, int n, int stride, int off,
                                                 double *red /* [NTA / 64 + 1] */)
 {
     double s = 0.0;
@@ -127,26 +140,36 @@ __device__ __forceinline__ double block_sum_all(const double *__restrict__ a, in
     return red[NTA / 64];
 }
 
-// phi'(T) and phi''(T) of the Peng-Robinson alpha function (Eq. (21))
-__device__ __forceinline__ void phi_derivs(const DevParams &P, double T, double &d1, double &d2)
+// phi'(T) and phi''(T) of the Peng-Robinson alpha function (Eq. (21)), and
+// u = sqrt(T / T_c).  One reciprocal square root y = 1/sqrt(T / T_c) gives
+// u = (T / T_c) y and 1/(T_c u) = y / T_c.
+__device__ __forceinline__ void phi_derivs(const DevParams &P, double T, double &d1, double &d2, double &u)
 {
-    const double u = sqrt(T * P.inv_Tc);
-    const double iu = 1.0 / (P.Tc * u);
+    const double x = T * P.inv_Tc;
+    const double y = rsq_nr(x);
+    u = x * y;
+    const double iu = y * P.inv_Tc;
     d1 = -P.kappa * (1.0 + P.kappa * (1.0 - u)) * iu;
     d2 = 0.5 * P.kappa * (1.0 + P.kappa) * iu * iu * iu * P.Tc;
 }
 
-// (dp/drho)_T and (dp/dT)_rho of Eq. (21)
+__device__ __forceinline__ void phi_derivs(const DevParams &P, double T, double &d1, double &d2)
+{
+    double u;
+    phi_derivs(P, T, d1, d2, u);
+}
+
+// (dp/drho)_T and (dp/dT)_rho of Eq. (21); 1/D1 and 1/D2 from one reciprocal
 __device__ __forceinline__ void eos_derivs(const DevParams &P, double r, double T, double &dpdr, double &dpdT)
 {
-    const double u = sqrt(T * P.inv_Tc);
+    double d1, d2, u;
+    phi_derivs(P, T, d1, d2, u);
     const double s = 1.0 + P.kappa * (1.0 - u);
     const double phi = s * s;
-    double d1, d2;
-    phi_derivs(P, T, d1, d2);
     const double D1 = 1.0 - P.b * r, D2 = 1.0 + 2.0 * P.b * r - P.b * P.b * r * r;
-    dpdr = P.R * T / (D1 * D1) - P.a * phi * 2.0 * r * (1.0 + P.b * r) / (D2 * D2);
-    dpdT = r * P.R / D1 - P.a * r * r * d1 / D2;
+    const double i12 = rcp_nr(D1 * D2), i1 = D2 * i12, i2 = D1 * i12;
+    dpdr = P.R * T * i1 * i1 - P.a * phi * 2.0 * r * (1.0 + P.b * r) * i2 * i2;
+    dpdT = r * P.R * i1 - P.a * r * r * d1 * i2;
 }
 
 // Zou-He completion transposed: the adjoint of the completed populations of
@@ -172,8 +195,9 @@ __device__ __forceinline__ void zou_he_T(double g[9], int bottom)
 
 // rho, j, psi and T of a stored state at node c; returns rho
 template <typename S>
-__device__ __forceinline__ double a_macro_node(const DevParams &P, const S *__restrict__ f, const S *__restrict__ T,
-                                               size_t N, size_t c, int gj, const AdjW &w)
+__device__ __forceinline__ double a_macro_node(const DevParams &P, const gmem<S> *__restrict__ f,
+                                               const gmem<S> *__restrict__ T, size_t N, size_t c, int gj,
+                                               const AdjWG &w)
 {
     double fl[9];
     load_node(P, f, N, c, gj, fl);
@@ -194,8 +218,8 @@ __global__ __launch_bounds__(NTA) void a_macro(A_ARGS, int k)
     __shared__ double red[NTA / 64];
     A_INST
     A_NODE
-    const S *f = a_slot<S>(I, k);
-    const double m = on ? a_macro_node(P, f, f + 9 * N, N, c, gj, w) : 0.0;
+    const gmem<S> *f = a_slot<S>(I, k);
+    const double m = on ? a_macro_node<S>(P, f, f + 9 * N, N, c, gj, w) : 0.0;
     const double s = block_sum<NTA>(m, red);
     if (threadIdx.x == 0) w.mpart[q] = s;
 }
@@ -233,7 +257,8 @@ __global__ __launch_bounds__(NTA) void a_force(A_ARGS)
     w.Fy[c] = Fy;
     w.Drx[c] = rx;
     w.Dry[c] = ry;
-    const double vx = (w.jx[c] + 0.5 * Fx) / r, vy = (w.jy[c] + 0.5 * Fy) / r;
+    const double ir = rcp_nr(r);
+    const double vx = (w.jx[c] + 0.5 * Fx) * ir, vy = (w.jy[c] + 0.5 * Fy) * ir;
     w.vx[c] = vx;
     w.vy[c] = vy;
 }
@@ -258,9 +283,9 @@ __global__ __launch_bounds__(NTA) void a_divv0(A_ARGS)
     }
     const double r = w.rho[c];
     const double D1 = 1.0 - P.b * r, D2 = 1.0 + 2.0 * P.b * r - P.b * P.b * r * r;
-    const double inv = 1.0 / (r * D1 * D2);
+    const double inv = rcp_nr(r * D1 * D2);
     const double ri = D1 * D2 * inv, i1 = r * D2 * inv, i2 = r * D1 * inv;
-    const double icv = 1.0 / P.cv;
+    const double icv = rcp_nr(P.cv);
     w.divv[c] = dv;
     w.RI[c] = ri;
     w.AX[c] = -w.vx[c] + P.chi * w.Drx[c] * ri;
@@ -298,14 +323,14 @@ __global__ __launch_bounds__(64 * TAW) void a_theradj(const AdjInst *__restrict_
     __shared__ double sAX[H][64], sAY[H][64];
     const AdjInst &I = ai[tmap[blockIdx.x]];
     const DevParams P = I.P;
-    const AdjW &w = I.w;
+    const AdjWG &w = reinterpret_cast<const AdjWG &>(I.w);
     const int q = (int)blockIdx.x - I.tblk0;
     const int x0 = (q % I.tgx) * TAX, y0 = (q / I.tgx) * TAY;
     static_assert(RPW * TAW >= H, "every region row has a wave");
     const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int gx = wrapi(x0 + lane - TAH, P.nx);
-    const double *__restrict__ lT1 = I.lT[cur];
-    double *__restrict__ lT0 = I.lT[cur ^ 1];
+    const gmem<double> *__restrict__ lT1 = gp(I.lT[cur]);
+    gmem<double> *__restrict__ lT0 = gp(I.lT[cur ^ 1]);
     const double chi = P.chi;
 
     // region row r of this wave's m-th slot: lattice row, in lattice, interior
@@ -411,7 +436,7 @@ __global__ __launch_bounds__(64 * TAW) void a_theradj(const AdjInst *__restrict_
                 double d1, d2;
                 phi_derivs(P, Tv, d1, d2);
                 gT += g * (-(10.0 / 3.0) * chi - cdv[m] * (cIA[m] - cIB[m] * (d1 + Tv * d2)));
-                if (k > 0) gnext[m] = wk * sb[4][r][l] / 6.0 + ck * gT;
+                if (k > 0) gnext[m] = wk * sb[4][r][l] * (1.0 / 6.0) + ck * gT;
                 const bool tile_row = r >= TAH && r < TAH + TAY;
                 if (tile_row && tile_col) {
                     // this stage's part of the rho, grad rho, v, div v adjoints at the node
@@ -475,9 +500,10 @@ __global__ __launch_bounds__(NTA) void a_lb(A_ARGS, int k, int cur)
     __shared__ double red[NTA / 64];
     A_INST
     A_NODE
-    const S *__restrict__ f = a_slot<S>(I, k);
-    const double *__restrict__ lf1 = I.lf[cur];
-    double *__restrict__ lf0 = I.lf[cur ^ 1];
+    const gmem<S> *__restrict__ f = a_slot<S>(I, k);
+    const gmem<double> *__restrict__ lf1 = gp(I.lf[cur]);
+    const gmem<double> *__restrict__ gr1 = gp(I.gr[cur]);
+    gmem<double> *__restrict__ lf0 = gp(I.lf[cur ^ 1]);
     double pr = 0.0, pg = 0.0;
     if (on) {
         const bool in = a_int(P, gj);
@@ -511,7 +537,7 @@ __global__ __launch_bounds__(NTA) void a_lb(A_ARGS, int k, int cur)
             // interior nodes keep their density adjoint apart (added here);
             // wall nodes hold the complete adjoint (Zou-He transposed)
             const size_t ct = ok ? a_at(P, gi, gj, kEX[a], kEY[a]) : c;
-            const double v = lf1[(size_t)a * N + ct] + (a_int(P, jj) ? I.gr[cur][ct] : 0.0);
+            const double v = lf1[(size_t)a * N + ct] + (a_int(P, jj) ? gr1[ct] : 0.0);
             gfs[a] = ok ? v : 0.0;
         }
         double fl[9];
@@ -532,7 +558,7 @@ __global__ __launch_bounds__(NTA) void a_lb(A_ARGS, int k, int cur)
         const double v2 = vx * vx + vy * vy;
         const double meq7 = r * (vx * vx - vy * vy), meq8 = r * vx * vy;
         const double S7 = 2.0 * (vx * Fx - vy * Fy), S8 = vx * Fy + vy * Fx;
-        const double tau = P.tau_V + (r - P.rho_V) * P.tau_slope, s_nu = 1.0 / tau;
+        const double tau = P.tau_V + (r - P.rho_V) * P.tau_slope, s_nu = rcp_nr(tau);
         const double L[9] = {P.s_rho, P.s_e, P.s_zeta, P.s_j, P.s_q, P.s_j, P.s_q, s_nu, s_nu};
         // f* = M^T diag(1/n) m*  ->  gm* = diag(1/n) M gf*
         double gms[9];
@@ -540,15 +566,15 @@ __global__ __launch_bounds__(NTA) void a_lb(A_ARGS, int k, int cur)
             const double g14 = gfs[1] + gfs[2] + gfs[3] + gfs[4], g58 = gfs[5] + gfs[6] + gfs[7] + gfs[8];
             double a0 = 0.0;
             for (int a = 0; a < 9; ++a) a0 += gfs[a];
-            gms[0] = a0 / 9.0;
-            gms[1] = (-4.0 * gfs[0] - g14 + 2.0 * g58) / 36.0;
-            gms[2] = (4.0 * gfs[0] - 2.0 * g14 + g58) / 36.0;
-            gms[3] = (gfs[1] - gfs[3] + gfs[5] - gfs[6] - gfs[7] + gfs[8]) / 6.0;
-            gms[4] = (-2.0 * gfs[1] + 2.0 * gfs[3] + gfs[5] - gfs[6] - gfs[7] + gfs[8]) / 12.0;
-            gms[5] = (gfs[2] - gfs[4] + gfs[5] + gfs[6] - gfs[7] - gfs[8]) / 6.0;
-            gms[6] = (-2.0 * gfs[2] + 2.0 * gfs[4] + gfs[5] + gfs[6] - gfs[7] - gfs[8]) / 12.0;
-            gms[7] = (gfs[1] - gfs[2] + gfs[3] - gfs[4]) / 4.0;
-            gms[8] = (gfs[5] - gfs[6] + gfs[7] - gfs[8]) / 4.0;
+            gms[0] = a0 * (1.0 / 9.0);
+            gms[1] = (-4.0 * gfs[0] - g14 + 2.0 * g58) * (1.0 / 36.0);
+            gms[2] = (4.0 * gfs[0] - 2.0 * g14 + g58) * (1.0 / 36.0);
+            gms[3] = (gfs[1] - gfs[3] + gfs[5] - gfs[6] - gfs[7] + gfs[8]) * (1.0 / 6.0);
+            gms[4] = (-2.0 * gfs[1] + 2.0 * gfs[3] + gfs[5] - gfs[6] - gfs[7] + gfs[8]) * (1.0 / 12.0);
+            gms[5] = (gfs[2] - gfs[4] + gfs[5] + gfs[6] - gfs[7] - gfs[8]) * (1.0 / 6.0);
+            gms[6] = (-2.0 * gfs[2] + 2.0 * gfs[4] + gfs[5] + gfs[6] - gfs[7] - gfs[8]) * (1.0 / 12.0);
+            gms[7] = (gfs[1] - gfs[2] + gfs[3] - gfs[4]) * 0.25;
+            gms[8] = (gfs[5] - gfs[6] + gfs[7] - gfs[8]) * 0.25;
         }
         // m* = m - L (m - m_eq) + (1 - L/2) S
         double gm[9], gq[9], gS[9];
@@ -582,12 +608,13 @@ __global__ __launch_bounds__(NTA) void a_lb(A_ARGS, int k, int cur)
         gvy += 6.0 * a6 * Fy - 2.0 * Fy * gS[7] + Fx * gS[8];
         const double gQ = P.sig_e * gS[1] - P.sig_z * gS[2];
         // s_nu = 1 / tau(rho)
-        gr += gsnu * (-P.tau_slope / (tau * tau));
+        gr += gsnu * (-P.tau_slope * s_nu * s_nu);
         // v = (j + F/2)/rho
-        const double gjx = gvx / r, gjy = gvy / r;
-        gFx += 0.5 * gvx / r;
-        gFy += 0.5 * gvy / r;
-        gr += -(gvx * vx + gvy * vy) / r;
+        const double ir = rcp_nr(r);
+        const double gjx = gvx * ir, gjy = gvy * ir;
+        gFx += 0.5 * gvx * ir;
+        gFy += 0.5 * gvy * ir;
+        gr += -(gvx * vx + gvy * vy) * ir;
         for (int a = 0; a < 9; ++a) lf0[(size_t)a * N + c] = gf[a] + kEX[a] * gjx + kEY[a] * gjy;
         // per-node force parts (no force on the wall rows)
         double gpsi = 0.0, gsx = 0.0, gsy = 0.0;
@@ -622,8 +649,9 @@ __global__ __launch_bounds__(NTA) void a_lb(A_ARGS, int k, int cur)
 // of a stored state, transposed with weight wq, at node (gi, gj) of rows
 // 0..2: the population part (row 0, Zou-He folded) and the temperature part.
 template <typename S>
-__device__ __forceinline__ void hf_source(const DevParams &P, const S *__restrict__ f, const S *__restrict__ T,
-                                          double wq, size_t N, int gi, int gj, double gpop[9], double &gtem)
+__device__ __forceinline__ void hf_source(const DevParams &P, const gmem<S> *__restrict__ f,
+                                          const gmem<S> *__restrict__ T, double wq, size_t N, int gi, int gj,
+                                          double gpop[9], double &gtem)
 {
     const double k = -P.cv_chi / P.nx * wq;
     for (int a = 0; a < 9; ++a) gpop[a] = 0.0;
@@ -656,12 +684,12 @@ __global__ __launch_bounds__(NTA) void a_final(A_ARGS, int k, int cur, double wq
         if (threadIdx.x == 0) w.scal[2] += sg;
     }
     A_NODE
-    const S *__restrict__ f = a_slot<S>(I, k);
-    const S *__restrict__ T = f + 9 * N;
-    const S *__restrict__ fp = prev ? a_slot<S>(I, k - 1) : nullptr;
-    const S *__restrict__ Tp = prev ? fp + 9 * N : nullptr;
-    double *__restrict__ lf0 = I.lf[cur ^ 1];
-    double *__restrict__ lT0 = I.lT[cur ^ 1];
+    const gmem<S> *__restrict__ f = a_slot<S>(I, k);
+    const gmem<S> *__restrict__ T = f + 9 * N;
+    const gmem<S> *__restrict__ fp = prev ? a_slot<S>(I, k - 1) : nullptr;
+    const gmem<S> *__restrict__ Tp = prev ? fp + 9 * N : nullptr;
+    gmem<double> *__restrict__ lf0 = gp(I.lf[cur ^ 1]);
+    gmem<double> *__restrict__ lT0 = gp(I.lT[cur ^ 1]);
     double m = 0.0;
     if (on) {
         double gpsi = w.gpsi[c];
@@ -678,16 +706,16 @@ __global__ __launch_bounds__(NTA) void a_final(A_ARGS, int k, int cur, double wq
             const double r = w.rho[c], Tv = w.T1[c];
             double dpdr, dpdT;
             eos_derivs(P, r, Tv, dpdr, dpdT);
-            const double gq = gpsi / (2.0 * w.psi[c]) * P.two_over_G;
+            const double gq = gpsi * 0.5 * rcp_nr(w.psi[c]) * P.two_over_G;
             gr += gq * (dpdr - 1.0 / 3.0);
             gT = gq * dpdT;
         }
         double gpop[9], gtem = 0.0;
-        if (wq != 0.0 && gj <= 2) hf_source(P, f, T, wq, N, gi, gj, gpop, gtem);
+        if (wq != 0.0 && gj <= 2) hf_source<S>(P, f, T, wq, N, gi, gj, gpop, gtem);
         if (a_int(P, gj)) {
             // rho = sum f: the density adjoint joins every population of the
             // node; kept apart and added where the next step gathers lf
-            I.gr[cur ^ 1][c] = gr;
+            gp(I.gr[cur ^ 1])[c] = gr;
         } else {
             double g[9];
             for (int a = 0; a < 9; ++a) g[a] = lf0[(size_t)a * N + c] + gr;
@@ -698,7 +726,7 @@ __global__ __launch_bounds__(NTA) void a_final(A_ARGS, int k, int cur, double wq
         }
         lT0[c] += gT + gtem;
         // this thread's reads of the state-t values at c are done
-        if (fp) m = a_macro_node(P, fp, Tp, N, c, gj, w);
+        if (fp) m = a_macro_node<S>(P, fp, Tp, N, c, gj, w);
     }
     if (prev) {
         const double s = block_sum<NTA>(m, red);
@@ -727,12 +755,12 @@ __global__ __launch_bounds__(NTA) void a_hf(A_ARGS, int k, double wq, int cur)
     A_INST
     A_NODE
     if (!on || gj > 2) return;
-    const S *f = a_slot<S>(I, k);
+    const gmem<S> *f = a_slot<S>(I, k);
     double gpop[9], gtem;
-    hf_source(P, f, f + 9 * N, wq, N, gi, gj, gpop, gtem);
+    hf_source<S>(P, f, f + 9 * N, wq, N, gi, gj, gpop, gtem);
     if (gj == 0)
-        for (int a = 0; a < 9; ++a) I.lf[cur][(size_t)a * N + c] += gpop[a];
-    I.lT[cur][c] += gtem;
+        for (int a = 0; a < 9; ++a) gp(I.lf[cur])[(size_t)a * N + c] += gpop[a];
+    gp(I.lT[cur])[c] += gtem;
 }
 
 }  // namespace lbb

@@ -53,13 +53,58 @@ constexpr int NSHAPE_A = 4, NSHAPE_B = 4;
 constexpr TileShape kShapeA[NSHAPE_A] = {{12, 4}, {8, 4}, {6, 2}, {4, 2}};
 constexpr TileShape kShapeB[NSHAPE_B] = {{24, 16}, {40, 16}, {16, 16}, {8, 8}};
 
+// 1/x from the hardware reciprocal estimate (relative error near 2^-23)
+// refined by two Newton-Raphson steps, r <- r + r (1 - x r), each of which
+// squares the error: within a few ulp for finite nonzero normal x.  Cheaper
+// than the correctly rounded division sequence; the FP64 tolerances allow it.
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// 1/sqrt(x) from the hardware estimate refined by two Newton-Raphson steps,
+// y <- y + y (1/2 - x y^2 / 2): within a few ulp for normal x > 0.
+__device__ __forceinline__ double rsq_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    double e = fma(-h * y, y, 0.5);
+    y = fma(y, e, y);
+    e = fma(-h * y, y, 0.5);
+    return fma(y, e, y);
+}
+
+// sqrt(x) from the hardware reciprocal square root y ~ 1/sqrt(x):
+// Goldschmidt's coupled iteration on g ~ sqrt(x), h ~ 1/(2 sqrt(x))
+// (r = 1/2 - g h; g <- g + g r; h <- h + h r), twice, then one Newton
+// correction g <- g + h (x - g^2).  Within a few ulp for normal x > 0;
+// 0 for x = 0, NaN below.
+__device__ __forceinline__ double sqrt_nr(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    const double d = fma(-g, g, x);
+    g = fma(d, h, g);
+    return x > 0.0 ? g : (x == 0.0 ? 0.0 : __builtin_nan(""));
+}
+
 // Type of the RK4 stage arithmetic: FP64 storage keeps FP64; FP32 storage
 // runs the stages in FP32 on T - T_s (rounding ~4e-10 absolute) with the EOS
 // coefficients formed in FP64.
 template <typename S> struct ThermalCfg;
-// sqrt of the stage arithmetic: correctly rounded in FP64, the hardware
-// instruction (1 ulp) in FP32
-__device__ __forceinline__ double stage_sqrt(double x) { return sqrt(x); }
+// sqrt of the stage arithmetic: the refined estimate (a few ulp) in FP64,
+// the hardware instruction (1 ulp) in FP32
+__device__ __forceinline__ double stage_sqrt(double x) { return sqrt_nr(x); }
 __device__ __forceinline__ float stage_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 template <> struct ThermalCfg<float> {
     using C = float;
@@ -172,9 +217,8 @@ __device__ __forceinline__ void zou_he(double f[9], int bottom)
 
 // Load the 9 populations of node c, completing wall nodes when the state
 // came from streaming (every mode but THERMAL_ONLY, where f is frozen).
-template <typename S>
-__device__ __forceinline__ void load_node(const DevParams &P, const S *__restrict__ f, size_t N, size_t c,
-                                          int gy, double fl[9])
+template <typename Ptr>
+__device__ __forceinline__ void load_node(const DevParams &P, Ptr f, size_t N, size_t c, int gy, double fl[9])
 {
 #pragma unroll
     for (int a = 0; a < 9; ++a) fl[a] = (double)f[(size_t)a * N + c];
@@ -194,39 +238,6 @@ __device__ __forceinline__ void complete_node(const DevParams &P, const S fs[9],
         if (gy == 0) zou_he(fl, 1);
         else if (gy == P.ny - 1) zou_he(fl, 0);
     }
-}
-
-// 1/x from the hardware reciprocal estimate (relative error near 2^-23)
-// refined by two Newton-Raphson steps, r <- r + r (1 - x r), each of which
-// squares the error: within a few ulp for finite nonzero normal x.  Cheaper
-// than the correctly rounded division sequence; the FP64 tolerances allow it.
-__device__ __forceinline__ double rcp_nr(double x)
-{
-    double r = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-x, r, 1.0);
-    return fma(r, e, r);
-}
-
-// sqrt(x) from the hardware reciprocal square root y ~ 1/sqrt(x):
-// Goldschmidt's coupled iteration on g ~ sqrt(x), h ~ 1/(2 sqrt(x))
-// (r = 1/2 - g h; g <- g + g r; h <- h + h r), twice, then one Newton
-// correction g <- g + h (x - g^2).  Within a few ulp for normal x > 0;
-// 0 for x = 0, NaN below.
-__device__ __forceinline__ double sqrt_nr(double x)
-{
-    const double y = __builtin_amdgcn_rsq(x);
-    double g = x * y, h = 0.5 * y;
-    double r = fma(-g, h, 0.5);
-    g = fma(g, r, g);
-    h = fma(h, r, h);
-    r = fma(-g, h, 0.5);
-    g = fma(g, r, g);
-    h = fma(h, r, h);
-    const double d = fma(-g, g, x);
-    g = fma(d, h, g);
-    return x > 0.0 ? g : (x == 0.0 ? 0.0 : __builtin_nan(""));
 }
 
 // psi = sqrt(2 (p_EOS - rho/3) / G) with the Peng-Robinson p_EOS (Eq. (21)),
@@ -758,7 +769,7 @@ __global__ __launch_bounds__(64 * NWB) void k_thermal(const Inst *__restrict__ i
             // 1/(rho D1 D2) gives 1/rho, 1/D1 and 1/D2
             const double D1 = 1.0 - P.b * rho;
             const double D2 = 1.0 + 2.0 * P.b * rho - P.b * P.b * rho * rho;
-            const double inv = 1.0 / (rho * D1 * D2);
+            const double inv = rcp_nr(rho * D1 * D2);
             const double div = (double)(dux + dvy);
             const C chi_rho = (C)(P.chi * D1 * D2 * inv);
             cfr[0][m] = uu[r][l] - chi_rho * drx;
@@ -813,7 +824,7 @@ __global__ __launch_bounds__(64 * NWB) void k_thermal(const Inst *__restrict__ i
         if (x0 + lane - HB >= P.nx || y0 + r - HB >= P.ny || !row_of(r, gy)) continue;
         C Tn = T0[r][lane];
         if (run && !(walls && (gy == 0 || gy == P.ny - 1))) {
-            Tn = (C)(S)(T0[r][lane] + acc[m] / C(6));
+            Tn = (C)(S)(T0[r][lane] + acc[m] * C(1.0 / 6.0));
             const double Tabs = P.T_ref + (double)Tn;
             if (!(Tabs > 0.0) || !(Tabs < 1e300)) flag_error(sc, t, ERR_T);
             st_at(Tout, ((unsigned)gy * (unsigned)P.nx + gxu) * (unsigned)sizeof(S), (S)Tn);
