@@ -32,16 +32,22 @@ ALG_BYTES_LB = {"f32": 72, "f64": 144}
 # HBM traffic of the LB launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
 # (KiB per dispatch, mean over the dispatches of a --profile run with the
 # given tiles), each scaled by what the same counter reads for an elementwise
-# kernel that reads 1 GiB and writes 1 GiB (FETCH_SIZE 524298 KiB -> factor
+# kernel that reads 1 GiB and writes 1 GiB (FETCH_SIZE 524294.5 KiB -> factor
 # 2.0, WRITE_SIZE 1048576 KiB -> factor 1.0).  Valid for the kernel source
 # whose hash is recorded and the same LB tile shape; null otherwise.
 MEASURED_TRAFFIC = {
-    "source_hash": "cf4e990916084faf",
-    "fetch_factor": 1048576.0 / 524297.8,
+    "source_hash": "2a5cc16241de89b6",
+    "fetch_factor": 1048576.0 / 524294.5,
     "write_factor": 1048576.0 / 1048576.0,
     "k_lb": {
-        "large_1024x512_fp32": {"tiles_lb": [62, 12, 4], "fetch_kib": 10833.1, "write_kib": 24628.3},
-        "large_4096x2048_fp32": {"tiles_lb": [62, 8, 4], "fetch_kib": 174795.1, "write_kib": 394536.1},
+        "large_1024x512_fp32": [
+            {"tiles_lb": [62, 12, 4], "fetch_kib": 10843.2, "write_kib": 24671.1},
+            {"tiles_lb": [62, 8, 4], "fetch_kib": 10660.8, "write_kib": 24629.3},
+        ],
+        "large_4096x2048_fp32": [
+            {"tiles_lb": [62, 6, 2], "fetch_kib": 169015.7, "write_kib": 396468.4},
+            {"tiles_lb": [62, 8, 4], "fetch_kib": 172978.3, "write_kib": 397380.7},
+        ],
     },
 }
 
@@ -50,12 +56,12 @@ def measured_traffic(workload: str, tiles_lb):
     """HBM bytes per LB launch from the recorded counters, or None when the
     kernel source, the workload or the LB tile shape differ."""
     m = MEASURED_TRAFFIC
-    if not m or m.get("source_hash") != source_hash() or workload not in m["k_lb"]:
+    if not m or m.get("source_hash") != source_hash():
         return None
-    c = m["k_lb"][workload]
-    if list(c["tiles_lb"]) != list(tiles_lb):
-        return None
-    return int(round((c["fetch_kib"] * m["fetch_factor"] + c["write_kib"] * m["write_factor"]) * 1024))
+    for c in m["k_lb"].get(workload, []):
+        if list(c["tiles_lb"]) == list(tiles_lb):
+            return int(round((c["fetch_kib"] * m["fetch_factor"] + c["write_kib"] * m["write_factor"]) * 1024))
+    return None
 
 
 def source_hash() -> str:
