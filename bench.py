@@ -2,7 +2,7 @@
 """Benchmark of the coupled LB + thermal time step on one MI355X.
 
 Workload: the 1024x512 boiling lattice (a = 2/49, T_s = 0.86 T_c,
-full-width heater at 0.10 T_c, G_w = 0.154 for ~60 deg), FP32 storage, inputs
+full-width heater at 0.10 T_c, G_w = 0.107 for a 60 deg contact angle), FP32 storage, inputs
 resident in HBM before the timed region.  A "step" is one time step of the
 whole hot path (LB launch + thermal launch, with the mass and heat-flux
 reductions) over the lattice.  --steps K steps are timed with HIP events on

@@ -100,6 +100,12 @@ int lbb_eos_constants(double a, double b, double R, double omega, double *Tc, do
 int lbb_coexistence(double a, double b, double R, double omega, double T,
                     double *rho_V, double *rho_L);
 
+/* Peng-Robinson pressure p_EOS(rho, T) of Eq. (21) (host arithmetic), the
+ * bulk pressure of the pseudopotential fluid (Sec. 2): the quantity the
+ * paper records at the centre of the top wall (Sec. 3.2, Fig. 3).
+ * EINVAL unless rho > 0, T > 0, b rho < 1 and p is non-NULL. */
+int lbb_eos_pressure(double a, double b, double R, double omega, double rho, double T, double *p);
+
 /* Create a domain on the current HIP device (Sec. 3.1 set-up).
  *   T_bottom [nx] : bottom-wall temperature T_b(x); NULL means T_s.
  *   rho0 [ny*nx]  : initial density; NULL builds the layered state

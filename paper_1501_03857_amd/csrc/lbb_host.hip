@@ -570,6 +570,18 @@ int lbb_coexistence(double a, double b, double R, double omega, double T, double
     return LBB_OK;
 }
 
+int lbb_eos_pressure(double a, double b, double R, double omega, double rho, double T, double *p)
+{
+    double Tc = 0, kap = 0;
+    int rc = lbb_eos_constants(a, b, R, omega, &Tc, &kap);
+    if (rc) return rc;
+    if (!p) return fail(LBB_EINVAL, "p is NULL");
+    if (!(finite_pos(rho) && finite_pos(T) && b * rho < 1.0)) return fail(LBB_EINVAL, "needs rho > 0, T > 0, b rho < 1");
+    const Eos e{a, b, R, Tc, kap, T};
+    *p = e.p(rho);
+    return LBB_OK;
+}
+
 int lbb_init_domain(const lbb_params *pin, const double *T_bottom, const double *rho0, lbb_domain **out)
 {
     if (!out) return fail(LBB_EINVAL, "out is NULL");

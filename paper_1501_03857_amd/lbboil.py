@@ -72,6 +72,7 @@ def lib():
             "lbb_default_params": (None, [_P]),
             "lbb_eos_constants": (C.c_int, [_d, _d, _d, _d, _pd, _pd]),
             "lbb_coexistence": (C.c_int, [_d, _d, _d, _d, _d, _pd, _pd]),
+            "lbb_eos_pressure": (C.c_int, [_d, _d, _d, _d, _d, _d, _pd]),
             "lbb_init_domain": (C.c_int, [_P, _pd, _pd, C.POINTER(vp)]),
             "lbb_set_fields": (C.c_int, [vp, _pd, _pd, _pd, _pd]),
             "lbb_step": (C.c_int, [vp, _i64]),
@@ -188,6 +189,13 @@ def coexistence(a, b, R, omega, T):
     rv, rl = _d(), _d()
     _check(lib().lbb_coexistence(a, b, R, omega, T, C.byref(rv), C.byref(rl)))
     return rv.value, rl.value
+
+
+def eos_pressure(a, b, R, omega, rho, T):
+    """p_EOS(rho, T) of the Peng-Robinson equation of state (Eq. (21))."""
+    p = _d()
+    _check(lib().lbb_eos_pressure(a, b, R, omega, float(rho), float(T), C.byref(p)))
+    return p.value
 
 
 class Domain:

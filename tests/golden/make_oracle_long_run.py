@@ -2,8 +2,8 @@
 """Write the oracle's long-horizon heat flux of the 1024x512 benchmark lattice.
 
 Runs the CPU oracle (FP64) on the 1024x512 workload (a = 2/49, T_s = 0.86 T_c,
-full-width heater at T_s + 0.10 T_c, G_w = 0.154, seed 2, gravity scaled to
-the lattice height) for 20000 steps, and stores:
+full-width heater at T_s + 0.10 T_c, G_w of the 60-degree label, seed 2,
+gravity scaled to the lattice height) for 20000 steps, and stores:
   * q (Sec. 3.2) of the state after every 1000th step,
   * the time average of q over steps 10001-20000 (average reset after step
     10000), the window the GPU test compares with,

@@ -1,0 +1,46 @@
+"""Host-side pieces of the boiling experiments (no GPU): the paper's pool
+set-up (Sec. 3.1) and the pressure read-out of the top-wall probe (Fig. 3),
+checked against the EOS's coexistence and the oracle's own p_EOS."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1501_03857_amd import experiments as E
+from paper_1501_03857_amd import lbboil as L
+
+
+def test_paper_pool_setup():
+    p, Tb, rho0 = E.paper_case(0.0165, Gw=0.065)
+    Ts, rv, rl = E.saturation()
+    assert (p.nx, p.ny, p.liquid_rows) == (600, 151, 90)
+    assert (p.a, p.b, p.sigma, p.g, p.Gw_bottom) == (3.0 / 49.0, 2.0 / 21.0, 1.2, 3e-5, 0.065)
+    assert Tb.shape == (600,) and np.all(Tb == Ts + 0.0165)
+    assert rho0.shape == (151, 600)
+    # liquid below y = 90, vapour above, at the Maxwell densities (Sec. 3.1: about 6.5 and 0.38)
+    assert abs(rho0[:90].mean() - rl) < 1e-3 and abs(rho0[90:].mean() - rv) < 1e-3
+    assert abs(rl - 6.5) < 0.01 and abs(rv - 0.38) < 0.001
+
+
+def test_eos_pressure_equal_at_coexistence():
+    """p_EOS(rho_V) = p_EOS(rho_L) = p_sat at the Maxwell densities (equal
+    pressures are one of the two Maxwell conditions), p_sat = 2.77368e-2 at
+    a = 3/49, T = 0.86 T_c."""
+    Ts, rv, rl = E.saturation()
+    pv = L.eos_pressure(E.PAPER_A, E.PAPER_B, E.PAPER_R, E.PAPER_OMEGA, rv, Ts)
+    pl = L.eos_pressure(E.PAPER_A, E.PAPER_B, E.PAPER_R, E.PAPER_OMEGA, rl, Ts)
+    assert abs(pv - pl) < 1e-12 and abs(pv - 2.77368e-2) < 1e-6
+
+
+@pytest.mark.parametrize("rho,T", [(0.4, 0.09), (3.0, 0.1), (6.5, 0.094), (8.0, 0.12)])
+def test_eos_pressure_matches_oracle(rho, T):
+    tc, kap = O.Tc(E.PAPER_A, E.PAPER_B), O.kappa(E.PAPER_OMEGA)
+    want = O.p_eos(rho, T, E.PAPER_A, E.PAPER_B, E.PAPER_R, tc, kap)
+    got = L.eos_pressure(E.PAPER_A, E.PAPER_B, E.PAPER_R, E.PAPER_OMEGA, rho, T)
+    assert abs(got - want) <= 1e-14 * max(1.0, abs(want))
+
+
+def test_eos_pressure_rejects_outside_domain():
+    for rho, T in ((-1.0, 0.1), (1.0, 0.0), (21.0 / 2.0, 0.1)):
+        with pytest.raises(L.LbbError) as e:
+            L.eos_pressure(E.PAPER_A, E.PAPER_B, E.PAPER_R, E.PAPER_OMEGA, rho, T)
+        assert e.value.code == L.LBB_EINVAL

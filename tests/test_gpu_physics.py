@@ -43,3 +43,30 @@ def test_sessile_drop_contact_angles_batched(golden):
     got, want = b.domain(1).fields(), o.fields()
     for k in ("rho", "f"):
         assert normwise(got[k], want[k]) <= 1e-12, k
+
+
+def test_calibration_harness_recovers_paper_wall_strengths():
+    """The contact-angle calibration (sessile drops over a G_w grid, one batch)
+    at the paper's a = 3/49 maps 50 and 55.5 deg to the paper's G_w = 0.065
+    and 0.105 (Sec. 3.3) within 0.01, and gives about 44.5 deg at G_w = 0."""
+    from paper_1501_03857_amd import experiments as E
+
+    print("[gpu-case] contact-angle calibration, a = 3/49", flush=True)
+    r = E.calibrate_wall_strength((50.0, 55.5), a=A3, grid=(0.0, 0.05, 0.1, 0.15))
+    print(f"[gpu-case] {r}", flush=True)
+    assert abs(r["angles"][0] - 44.5) < 2.0
+    assert abs(r["Gw"][50.0] - 0.065) < 0.01 and abs(r["Gw"][55.5] - 0.105) < 0.01
+
+
+def test_workload_angle_labels_match_their_wall_strengths():
+    """The G_w of each contact-angle label of the workloads (a = 2/49) gives
+    that angle on the GPU path."""
+    from paper_1501_03857_amd import experiments as E
+    from paper_1501_03857_amd import workloads as WL
+
+    print("[gpu-case] workload angle labels, a = 2/49", flush=True)
+    labels = sorted(WL.CONTACT_ANGLE_GW)
+    got = E.sessile_drops([WL.CONTACT_ANGLE_GW[k] for k in labels], a=2.0 / 49.0)
+    print(f"[gpu-case] {dict(zip(labels, got))}", flush=True)
+    for k, theta in zip(labels, got):
+        assert abs(theta - k) < 4.0, (k, theta)
