@@ -44,3 +44,28 @@ def test_eos_pressure_rejects_outside_domain():
         with pytest.raises(L.LbbError) as e:
             L.eos_pressure(E.PAPER_A, E.PAPER_B, E.PAPER_R, E.PAPER_OMEGA, rho, T)
         assert e.value.code == L.LBB_EINVAL
+
+
+@pytest.mark.parametrize("theta", [40.0, 60.0, 90.0, 120.0])
+def test_drop_angle_recovers_a_circular_cap(theta):
+    """A liquid region bounded by a circle that meets the first fluid row
+    (row 1) at angle theta: drop_angle measures theta from the base width and
+    apex height (geometry only), within the half-node resolution of the
+    sampled interface."""
+    nx, ny, rl, rv = 200, 90, 6.5, 0.38
+    base_half = 30.0
+    t = np.radians(theta)
+    R = base_half / np.sin(t)
+    yc = 1.0 - R * np.cos(t)          # centre height; the circle crosses row 1 at x = +-base_half
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    d = np.hypot(x - nx / 2, y - yc) - R
+    rho = rv + (rl - rv) * 0.5 * (1.0 - np.tanh(d / 1.0))
+    rho[0] = rho[1]
+    got = E.drop_angle(rho, rl, rv)
+    assert abs(got - theta) < 1.5, (theta, got)
+
+
+def test_drop_angle_is_nan_without_contact():
+    rho = np.full((40, 100), 0.38)
+    rho[20:30, 40:60] = 6.5           # a drop that does not touch row 1
+    assert np.isnan(E.drop_angle(rho, 6.5, 0.38))
