@@ -292,8 +292,9 @@ __device__ __forceinline__ double block_sum_array(const double *__restrict__ a, 
 // result valid in thread 0.  All threads of the block must call it.
 // s + a[k0] + a[k0 + stride] + ... (k < n), added in that order; the loads are
 // issued 16 at a time so a long sum waits for memory once per 16 terms.
-__device__ __forceinline__ double ordered_sum(const double *__restrict__ a, int k0, int n, int stride, double s)
+__device__ __forceinline__ double ordered_sum(const double *__restrict__ a_, int k0, int n, int stride, double s)
 {
+    const gmem<double> *__restrict__ a = (const gmem<double> *)a_;
     int k = k0;
     for (; k + 15 * stride < n; k += 16 * stride) {
         double v[16];
@@ -674,7 +675,7 @@ __global__ __launch_bounds__(64 * NWB) void k_thermal(const Inst *__restrict__ i
                                                       const int *__restrict__ blk2inst, int cf, int cT)
 {
     const Inst &I = insts[blk2inst[blockIdx.x]];
-    const DevParams &P = I.P;
+    const DevParams P = I.P;
     const S *__restrict__ Tin = static_cast<const S *>(I.T[cT]);
     S *__restrict__ Tout = static_cast<S *>(I.T[cT ^ 1]);
     const S *__restrict__ rho_i = static_cast<const S *>(I.rho);
@@ -739,6 +740,14 @@ __global__ __launch_bounds__(64 * NWB) void k_thermal(const Inst *__restrict__ i
 #pragma unroll
     for (int m = 0; m < RPW; ++m) acc[m] = C(0);
 
+    // rows where K acts: in the lattice and not a wall row
+    bool act[RPW];
+#pragma unroll
+    for (int m = 0; m < RPW; ++m) {
+        int gy;
+        act[m] = row_of(wv + NWB * m, gy) && !(walls && (gy == 0 || gy == P.ny - 1));
+    }
+
     // Per-node coefficients of K on the region shrunk by one node, kept in
     // registers (each wave evaluates K only at its own rows).
     C cfr[4][RPW];
@@ -748,9 +757,7 @@ __global__ __launch_bounds__(64 * NWB) void k_thermal(const Inst *__restrict__ i
 #pragma unroll
         for (int m = 0; m < RPW; ++m) {
             const int r = wv + NWB * m;
-            int gy;
-            if (r < 1 || r >= H - 1 || lane < 1 || lane >= 63 || !row_of(r, gy)) continue;
-            if (walls && (gy == 0 || gy == P.ny - 1)) continue;
+            if (r < 1 || r >= H - 1 || lane < 1 || lane >= 63 || !act[m]) continue;
             const C(*rr)[64] = X[0];
             const C(*uu)[64] = X[1];
             const C(*vv)[64] = X[2];
@@ -793,8 +800,7 @@ __global__ __launch_bounds__(64 * NWB) void k_thermal(const Inst *__restrict__ i
                 const int r = wv + NWB * m;
                 if (r >= H || r < HB - rad || r >= HB + TY + rad || lane < HB - rad || lane >= HB + TXB + rad) continue;
                 C h = C(0);
-                int gy;
-                if (row_of(r, gy) && !(walls && (gy == 0 || gy == P.ny - 1))) {
+                if (act[m]) {
                     const int l = lane;
                     const C tE = in[r][l + 1], tW = in[r][l - 1], tN = in[r + 1][l], tS = in[r - 1][l];
                     const C tNE = in[r + 1][l + 1], tNW = in[r + 1][l - 1], tSW = in[r - 1][l - 1], tSE = in[r - 1][l + 1];
@@ -839,7 +845,7 @@ __global__ __launch_bounds__(64 * NWB) void k_thermal(const Inst *__restrict__ i
         if (lane >= HB && lane < HB + TXB && x0 + lane - HB < P.nx) {
             const size_t N = (size_t)P.nx * P.ny;
             double fl[9];
-            load_node(P, fnew, N, (size_t)gx, 0, fl);
+            load_node(P, (const gmem<S> *)fnew, N, (size_t)gx, 0, fl);
             double r0 = fl[0];
 #pragma unroll
             for (int a = 1; a < 9; ++a) r0 += fl[a];
