@@ -465,8 +465,11 @@ __device__ __forceinline__ void tile_psi(const DevParams &P, const S *__restrict
 // LB step: forces, collision and push streaming; mass partials.
 // Layout: the tile (TXA x TYA) with its halo of one node is 64 columns wide,
 // lane = column, and each of the NWA waves owns every NWA-th row.  Phase 1
-// forms rho and psi (FP64 EOS) on the tile and halo, keeping each node's
-// populations in registers; phase 2 collides the interior nodes and pushes.
+// issues every population and temperature load of the wave's rows and halo
+// row, then forms rho and psi (FP64 EOS) on the tile and halo, keeping each
+// node's populations in registers; phase 2 collides the interior nodes and
+// pushes.  The parameters are read in place through the lattice table
+// (copied, they would not fit the scalar registers beside the plane bases).
 template <typename S, int TYA, int NWA>
 __global__ __launch_bounds__(64 * NWA) void k_lb(const Inst *__restrict__ insts, const int *__restrict__ blk2inst,
                                                  int cf, int cT)
@@ -667,9 +670,12 @@ __global__ __launch_bounds__(64 * NWA) void k_lb(const Inst *__restrict__ insts,
 // and T phi'(T) = kappa^2 T/T_c - kappa (1 + kappa) sqrt(T/T_c).
 // Layout: the tile (TXB x TY) with its halo of HB nodes is 64 columns wide,
 // so lane = column and each of the NWB waves owns every NWB-th row of the
-// region; stage k is evaluated on the region shrunk by k+1 nodes, with the
-// stage values updated in place between barriers and the RK4 sums in
-// registers.
+// region; stage k is evaluated on the region shrunk by k+1 nodes.  The
+// coefficients of K stay in registers (a wave evaluates K only at its own
+// rows), the stage inputs alternate between two LDS planes (one barrier per
+// stage) and the RK4 sums stay in registers.  The parameters are copied into
+// registers once: read through the lattice table they would be fetched again
+// after every barrier.
 template <typename S, int TY, int NWB>
 __global__ __launch_bounds__(64 * NWB) void k_thermal(const Inst *__restrict__ insts,
                                                       const int *__restrict__ blk2inst, int cf, int cT)
