@@ -9,6 +9,7 @@
 
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
+#include <functional>
 
 #include <atomic>
 #include <cmath>
@@ -1555,6 +1556,8 @@ struct AdjGroup {
     void **mem = nullptr;           // cached workspace of the owner
     size_t *bytes = nullptr;
     int64_t *held = nullptr;        // the owner's bytes held against the budget
+    // enqueue n forward steps of the owner on its stream (its graph path)
+    std::function<int(int64_t)> advance;
 };
 
 // Per-lattice pieces of the workspace.
@@ -1632,13 +1635,20 @@ int adjoint_run(AdjGroup &g, int64_t N, int64_t K, double *J, double *dJ_dTb, do
         tot += m[i].nb;
     }
     // temperature-adjoint tiles: 16 rows high unless that gives fewer than
-    // two tiles per compute unit, then 8
+    // two tiles per compute unit, then 8 (16 waves either way, 2-3 region
+    // rows each)
     int tay = 16;
     {
         int t16 = 0;
         for (int i = 0; i < nm; ++i)
             t16 += ((g.doms[i]->p.nx + TAX - 1) / TAX) * ((g.doms[i]->p.ny + 15) / 16);
         if (t16 < 2 * 256) tay = 8;
+        // 24-row tiles (LDS for one block per CU) cut the halo share where
+        // there are at least four tiles per CU
+        int t24 = 0;
+        for (int i = 0; i < nm; ++i)
+            t24 += ((g.doms[i]->p.nx + TAX - 1) / TAX) * ((g.doms[i]->p.ny + 23) / 24);
+        if (t24 >= 4 * 256) tay = 24;
     }
     for (int i = 0; i < nm; ++i) {
         const lbb_domain *d = g.doms[i];
@@ -1707,12 +1717,6 @@ int adjoint_run(AdjGroup &g, int64_t N, int64_t K, double *J, double *dJ_dTb, do
         hipError_t e = hipMemcpyAsync(dst, own_f(i), 9 * n * es, hipMemcpyDeviceToDevice, st);
         if (e == hipSuccess) e = hipMemcpyAsync(dst + 9 * n * es, own_T(i), n * es, hipMemcpyDeviceToDevice, st);
         return e;
-    };
-    auto own_step = [&]() {
-        launch_lb<S>(st, g.fwd_insts, g.blkA, g.totA, *g.cf, *g.cT, g.shA);
-        launch_thermal<S>(st, g.fwd_insts, g.blkB, g.totB, *g.cf, *g.cT, g.shB);
-        *g.cf ^= 1;
-        *g.cT ^= 1;
     };
     auto slot_step = [&](hipStream_t s, int b, int64_t k) {
         const Inst *tab = inst_seg + ((size_t)b * K + k) * nm;
@@ -1791,17 +1795,25 @@ int adjoint_run(AdjGroup &g, int64_t N, int64_t K, double *J, double *dJ_dTb, do
         s0[i].n_samples = 0;
         LBB_HIP(hipMemcpyAsync(g.doms[i]->sc, &s0[i], sizeof(Scalars), hipMemcpyHostToDevice, st));
     }
+    // Up to the last segment the owner steps through its own graphs, K steps
+    // from one checkpoint to the next (tL is a multiple of K).
     const int64_t tL = (nck - 1) * K;
-    for (int64_t t = 0; t < N; ++t) {
+    for (int64_t t = 0; t < N;) {
         if (t % K == 0)
             for (int i = 0; i < nm; ++i) {
                 LBB_HIP(copy_state_out(i, t < tL ? m[i].ck + (size_t)(t / K) * m[i].state_bytes : m[i].seg[0]));
                 LBB_HIP(hipMemcpyAsync(&m[i].ck_sc[t / K], g.doms[i]->sc, sizeof(Scalars), hipMemcpyDeviceToDevice,
                                        st));
             }
-        if (t < tL) own_step();
-        else slot_step(st, 0, t - tL);
-        LBB_HIP(hipGetLastError());
+        if (t < tL) {
+            const int rc = g.advance(K);
+            if (rc) return rc;
+            t += K;
+        } else {
+            slot_step(st, 0, t - tL);
+            LBB_HIP(hipGetLastError());
+            ++t;
+        }
     }
     hipLaunchKernelGGL(k_flush_heat_flux, dim3(nm), dim3(NT), 0, st, g.fwd_insts);
     LBB_HIP(hipStreamSynchronize(st));
@@ -1854,8 +1866,9 @@ int adjoint_run(AdjGroup &g, int64_t N, int64_t K, double *J, double *dJ_dTb, do
             const int k = (int)(t - t0);
             hipLaunchKernelGGL(a_force, grid, blk, 0, st, ai, d_amap);
             hipLaunchKernelGGL(a_divv0, grid, blk, 0, st, ai, d_amap);
-            if (tay == 16) hipLaunchKernelGGL((a_theradj<16, 16>), dim3(ttot), dim3(64 * 16), 0, st, ai, d_tmap, cur);
-            else hipLaunchKernelGGL((a_theradj<8, 8>), dim3(ttot), dim3(64 * 8), 0, st, ai, d_tmap, cur);
+            if (tay == 24) hipLaunchKernelGGL((a_theradj<24, 16>), dim3(ttot), dim3(64 * 16), 0, st, ai, d_tmap, cur);
+            else if (tay == 16) hipLaunchKernelGGL((a_theradj<16, 16>), dim3(ttot), dim3(64 * 16), 0, st, ai, d_tmap, cur);
+            else hipLaunchKernelGGL((a_theradj<8, 16>), dim3(ttot), dim3(64 * 16), 0, st, ai, d_tmap, cur);
             hipLaunchKernelGGL(a_lb<S>, grid, blk, 0, st, ai, d_amap, k, cur);
             hipLaunchKernelGGL(a_final<S>, grid, blk, 0, st, ai, d_amap, k, cur, t >= 1 ? wq : 0.0,
                                t > t0 ? 1 : 0);
@@ -1937,6 +1950,7 @@ extern "C" int lbb_adjoint(lbb_domain *d, int64_t N, int64_t K, double *J, doubl
     g.mem = &d->adj_mem;
     g.bytes = &d->adj_bytes;
     g.held = &d->held;
+    g.advance = [d](int64_t n) { return enqueue_steps(d, n); };
     rc = adjoint_group(g, d->p.precision, N, K, J, dJ_dTb, dJ_dGw);
     d->dev_bytes += (int64_t)d->adj_bytes - (int64_t)before;
     return rc;
@@ -1976,6 +1990,7 @@ extern "C" int lbb_batch_adjoint(lbb_batch *b, int64_t N, int64_t K, double *J, 
     g.mem = &b->adj_mem;
     g.bytes = &b->adj_bytes;
     g.held = &b->held;
+    g.advance = [b](int64_t n) { return lbb_batch_step_async(b, n); };
     return adjoint_group(g, b->precision, N, K, J, dJ_dTb, dJ_dGw);
 }
 
