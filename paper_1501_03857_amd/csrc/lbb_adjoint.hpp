@@ -6,14 +6,14 @@
 // work arrays.  A launch covers any number of lattices through a lattice
 // table (one lattice, or every member of a batch); the per-node kernels work
 // on 64 x 4 patches (lane = column, wave = row), the temperature kernel on
-// tiles with a halo in LDS.  Five launches per reverse step of state
+// tiles with a halo in LDS.  Four launches per reverse step of state
 // t -> t+1:
 //   a_force    forces (Eqs. (7), (9), (22)), velocity (Eq. (6)), grad rho;
 //              rho_ave from the mass partials of the state
-//   a_divv0    div v seen by the temperature equation and the per-node
-//              coefficients of Eq. (18)
-//   a_theradj  the RK4 temperature step (Eqs. (18)-(20)) transposed: stage
-//              inputs recomputed and the four stages transposed in one tile
+//   a_theradj  the RK4 temperature step (Eqs. (18)-(20)) transposed: div v
+//              and the coefficients of Eq. (18) formed on the tile and its
+//              halo, stage inputs recomputed and the four stages transposed
+//              in one tile
 //   a_lb       stencil transposes of grad rho and div v (gather), push
 //              streaming transposed (gather), MRT collision transposed in
 //              moment space, velocity transposed, per-node force parts
@@ -44,11 +44,6 @@ struct AdjWT {
     // by those of the state before it
     D *rho, *jx, *jy, *psi, *T1;
     D *sx, *sy, *Fx, *Fy, *vx, *vy, *Drx, *Dry;
-    // Eq. (18) as K(T) = AX d_x T + AY d_y T + chi lap T - IA divv T + IB divv T phi'(T)
-    // with AX = -vx + chi d_x rho / rho, IA = R / ((1 - b rho) c_v),
-    // IB = a rho / ((1 + 2 b rho - b^2 rho^2) c_v); E1, E2 give the rho
-    // derivative of the pressure-work factor; RI = 1 / rho
-    D *divv, *AX, *AY, *IA, *IB, *E1, *E2, *RI;
     D *gDrx, *gDry, *gdiv, *grho, *gvx, *gvy, *gpsi, *gsx, *gsy;
     D *mpart;   // block mass partials of the state being reversed
     D *fpart;   // block partials of the force adjoint: [2b] rho_ave, [2b+1] G_w
@@ -263,16 +258,18 @@ __global__ __launch_bounds__(NTA) void a_force(A_ARGS)
     w.vy[c] = vy;
 }
 
-// div v and the coefficients of Eq. (18) at the node (zero on wall rows).
-__global__ __launch_bounds__(NTA) void a_divv0(A_ARGS)
+// div v and the coefficients of Eq. (18) at interior node (gi, gj), formed
+// where the temperature adjoint needs them (wall rows carry none):
+// K(T) = AX d_x T + AY d_y T + chi lap T - IA divv T + IB divv T phi'(T) with
+// AX = -vx + chi d_x rho / rho, IA = R / ((1 - b rho) c_v),
+// IB = a rho / ((1 + 2 b rho - b^2 rho^2) c_v); E1, E2 give the rho
+// derivative of the pressure-work factor.
+struct DivCoef {
+    double dv, ax, ay, IA, IB;
+};
+
+__device__ __forceinline__ DivCoef div_coef(const DevParams &P, const AdjWG &w, int gi, int gj, size_t c)
 {
-    A_INST
-    A_NODE
-    if (!on) return;
-    if (!a_int(P, gj)) {
-        w.divv[c] = w.AX[c] = w.AY[c] = w.IA[c] = w.IB[c] = w.E1[c] = w.E2[c] = w.RI[c] = 0.0;
-        return;
-    }
     double dv = 0.0;
 #pragma unroll
     for (int a = 1; a < 9; ++a) {
@@ -286,14 +283,26 @@ __global__ __launch_bounds__(NTA) void a_divv0(A_ARGS)
     const double inv = rcp_nr(r * D1 * D2);
     const double ri = D1 * D2 * inv, i1 = r * D2 * inv, i2 = r * D1 * inv;
     const double icv = rcp_nr(P.cv);
-    w.divv[c] = dv;
-    w.RI[c] = ri;
-    w.AX[c] = -w.vx[c] + P.chi * w.Drx[c] * ri;
-    w.AY[c] = -w.vy[c] + P.chi * w.Dry[c] * ri;
-    w.IA[c] = P.R * i1 * icv;
-    w.IB[c] = P.a * r * i2 * icv;
-    w.E1[c] = P.R * P.b * i1 * i1 * icv;
-    w.E2[c] = P.a * (1.0 + P.b * P.b * r * r) * i2 * i2 * icv;
+    DivCoef k;
+    k.dv = dv;
+    k.ax = -w.vx[c] + P.chi * w.Drx[c] * ri;
+    k.ay = -w.vy[c] + P.chi * w.Dry[c] * ri;
+    k.IA = P.R * i1 * icv;
+    k.IB = P.a * r * i2 * icv;
+    return k;
+}
+
+// 1/rho and the rho derivatives E1 = R b i1^2 / c_v, E2 = a (1 + b^2 rho^2)
+// i2^2 / c_v of the pressure-work coefficients at a node of density r
+__device__ __forceinline__ void pw_derivs(const DevParams &P, double r, double &ri, double &E1, double &E2)
+{
+    const double D1 = 1.0 - P.b * r, D2 = 1.0 + 2.0 * P.b * r - P.b * P.b * r * r;
+    const double inv = rcp_nr(r * D1 * D2);
+    const double i1 = r * D2 * inv, i2 = r * D1 * inv;
+    const double icv = rcp_nr(P.cv);
+    ri = D1 * D2 * inv;
+    E1 = P.R * P.b * i1 * i1 * icv;
+    E2 = P.a * (1.0 + P.b * P.b * r * r) * i2 * i2 * icv;
 }
 
 // ---------------------------------------------------------------------------
@@ -336,7 +345,7 @@ __global__ __launch_bounds__(64 * TAW) void a_theradj(const AdjInst *__restrict_
     // region row r of this wave's m-th slot: lattice row, in lattice, interior
     int gyr[RPW];
     bool inl[RPW], inr[RPW];
-    double cdv[RPW], cIA[RPW], cIB[RPW];
+    double cdv[RPW], cIA[RPW], cIB[RPW], cE1[RPW], cE2[RPW];
 #pragma unroll
     for (int m = 0; m < RPW; ++m) {
         const int r = wv + TAW * m;
@@ -345,16 +354,23 @@ __global__ __launch_bounds__(64 * TAW) void a_theradj(const AdjInst *__restrict_
         inl[m] = r < H && gy >= 0 && gy < P.ny;
         inr[m] = inl[m] && gy > 0 && gy < P.ny - 1;
         double t1 = 0.0, ax = 0.0, ay = 0.0, l1 = 0.0;
-        cdv[m] = cIA[m] = cIB[m] = 0.0;
+        cdv[m] = cIA[m] = cIB[m] = cE1[m] = cE2[m] = 0.0;
         if (inl[m]) {
             const size_t c = (size_t)gy * P.nx + gx;
             t1 = w.T1[c];
-            ax = w.AX[c];
-            ay = w.AY[c];
             l1 = lT1[c];
-            cdv[m] = w.divv[c];
-            cIA[m] = w.IA[c];
-            cIB[m] = w.IB[c];
+            if (inr[m]) {
+                const DivCoef k = div_coef(P, w, gx, gy, c);
+                ax = k.ax;
+                ay = k.ay;
+                cdv[m] = k.dv;
+                cIA[m] = k.IA;
+                cIB[m] = k.IB;
+                if (r >= TAH && r < TAH + TAY) {
+                    double ri;
+                    pw_derivs(P, w.rho[c], ri, cE1[m], cE2[m]);
+                }
+            }
         }
         if (r < H) {
             sb[0][r][lane] = t1;
@@ -449,7 +465,7 @@ __global__ __launch_bounds__(64 * TAW) void a_theradj(const AdjInst *__restrict_
                     acc[m][2] += g * Tv;        // div v part: -g T (IA - IB d1)
                     acc[m][3] += g * Tv * d1;
                     acc[m][4] += g * (w.Drx[(size_t)gyr[m] * P.nx + gx] * dTx + w.Dry[(size_t)gyr[m] * P.nx + gx] * dTy);
-                    acc[m][5] += g * Tv * (w.E1[(size_t)gyr[m] * P.nx + gx] - w.E2[(size_t)gyr[m] * P.nx + gx] * d1);
+                    acc[m][5] += g * Tv * (cE1[m] - cE2[m] * d1);
                 }
             }
             lt[m] += gT;
@@ -474,7 +490,8 @@ __global__ __launch_bounds__(64 * TAW) void a_theradj(const AdjInst *__restrict_
         lT0[c] = lT1[c] + lt[m];
         double aDrx = 0.0, aDry = 0.0, avx = 0.0, avy = 0.0, adiv = 0.0, arho = 0.0;
         if (inr[m]) {
-            const double ri = w.RI[c];
+            double ri, e1, e2;
+            pw_derivs(P, w.rho[c], ri, e1, e2);
             aDrx = chi * ri * acc[m][0];
             aDry = chi * ri * acc[m][1];
             avx = -acc[m][0];
