@@ -282,7 +282,7 @@ __device__ __forceinline__ DivCoef div_coef(const DevParams &P, const AdjWG &w, 
     const double D1 = 1.0 - P.b * r, D2 = 1.0 + 2.0 * P.b * r - P.b * P.b * r * r;
     const double inv = rcp_nr(r * D1 * D2);
     const double ri = D1 * D2 * inv, i1 = r * D2 * inv, i2 = r * D1 * inv;
-    const double icv = rcp_nr(P.cv);
+    const double icv = P.inv_cv;
     DivCoef k;
     k.dv = dv;
     k.ax = -w.vx[c] + P.chi * w.Drx[c] * ri;
@@ -299,7 +299,7 @@ __device__ __forceinline__ void pw_derivs(const DevParams &P, double r, double &
     const double D1 = 1.0 - P.b * r, D2 = 1.0 + 2.0 * P.b * r - P.b * P.b * r * r;
     const double inv = rcp_nr(r * D1 * D2);
     const double i1 = r * D2 * inv, i2 = r * D1 * inv;
-    const double icv = rcp_nr(P.cv);
+    const double icv = P.inv_cv;
     ri = D1 * D2 * inv;
     E1 = P.R * P.b * i1 * i1 * icv;
     E2 = P.a * (1.0 + P.b * P.b * r * r) * i2 * i2 * icv;

@@ -129,6 +129,10 @@ struct DevParams {
     double g, Gw_bottom, Gw_top;
     double sig_e, sig_z;         // sigma/(tau_e - 1/2), sigma/(tau_zeta - 1/2)
     double inv_Tc, two_over_G;
+    // uniform factors of the thermal step, formed on the host (the GPU has no
+    // scalar FP64 unit, so each wave would otherwise divide in its vector ALU)
+    double R_cv, a_cv, inv_cv;    // R / c_v, a / c_v, 1 / c_v
+    double k1k, k2_Tc;            // kappa (1 + kappa), kappa^2 / T_c
 };
 
 // Device-resident scalars of one domain.  tA is the state index seen by the
@@ -787,12 +791,12 @@ __global__ __launch_bounds__(64 * NWB) void k_thermal(const Inst *__restrict__ i
             const C chi_rho = (C)(P.chi * D1 * D2 * inv);
             cfr[0][m] = uu[r][l] - chi_rho * drx;
             cfr[1][m] = vv[r][l] - chi_rho * dry;
-            cfr[2][m] = (C)(P.R / P.cv * div * (rho * D2 * inv));
-            cfr[3][m] = (C)(P.a / P.cv * rho * div * (rho * D1 * inv));
+            cfr[2][m] = (C)(P.R_cv * div * (rho * D2 * inv));
+            cfr[3][m] = (C)(P.a_cv * rho * div * (rho * D1 * inv));
         }
 
-        const C k1k = (C)(P.kappa * (1.0 + P.kappa)), k2 = (C)(P.kappa * P.kappa / P.Tc);
-        const C inv_Tc = (C)(1.0 / P.Tc), Tref = (C)P.T_ref;
+        const C k1k = (C)P.k1k, k2 = (C)P.k2_Tc;
+        const C inv_Tc = (C)P.inv_Tc, Tref = (C)P.T_ref;
         const C cst[3] = {C(0.5), C(0.5), C(1.0)};
         const C wst[4] = {C(1), C(2), C(2), C(1)};
         // stage st reads T0 (st = 0) or Ts[(st - 1) & 1] and writes Ts[st & 1]:

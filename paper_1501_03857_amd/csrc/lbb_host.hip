@@ -675,6 +675,11 @@ int lbb_init_domain(const lbb_params *pin, const double *T_bottom, const double 
     q.sig_z = p.sigma / (1.0 / p.s_zeta - 0.5);
     q.inv_Tc = 1.0 / Tc;
     q.two_over_G = 2.0 / p.G;
+    q.R_cv = p.R / p.cv;
+    q.a_cv = p.a / p.cv;
+    q.inv_cv = 1.0 / p.cv;
+    q.k1k = kap * (1.0 + kap);
+    q.k2_Tc = kap * kap / Tc;
     set_grid(d);
     const lbb_param_dims dims{p.nx, p.ny};
     const int mbA = max_blocks_A(dims), mbB = max_blocks_B(dims);
