@@ -36,17 +36,17 @@ ALG_BYTES_LB = {"f32": 72, "f64": 144}
 # 2.0, WRITE_SIZE 1048576 KiB -> factor 1.0).  Valid for the kernel source
 # whose hash is recorded and the same LB tile shape; null otherwise.
 MEASURED_TRAFFIC = {
-    "source_hash": "2a5cc16241de89b6",
+    "source_hash": "46f612879550aaad",
     "fetch_factor": 1048576.0 / 524294.5,
     "write_factor": 1048576.0 / 1048576.0,
     "k_lb": {
         "large_1024x512_fp32": [
-            {"tiles_lb": [62, 12, 4], "fetch_kib": 10843.2, "write_kib": 24671.1},
-            {"tiles_lb": [62, 8, 4], "fetch_kib": 10660.8, "write_kib": 24629.3},
+            {"tiles_lb": [62, 12, 4], "fetch_kib": 10836.9, "write_kib": 24671.2},
+            {"tiles_lb": [62, 8, 4], "fetch_kib": 10654.9, "write_kib": 24629.8},
         ],
         "large_4096x2048_fp32": [
-            {"tiles_lb": [62, 6, 2], "fetch_kib": 169015.7, "write_kib": 396468.4},
-            {"tiles_lb": [62, 8, 4], "fetch_kib": 172978.3, "write_kib": 397380.7},
+            {"tiles_lb": [62, 6, 2], "fetch_kib": 169040.2, "write_kib": 396494.9},
+            {"tiles_lb": [62, 8, 4], "fetch_kib": 173019.3, "write_kib": 397422.7},
         ],
     },
 }
