@@ -79,3 +79,31 @@ def test_adjoint_automatic_checkpoint_interval():
     for K in (17, 4):
         r = d.adjoint(17, K=K)
         assert a[0] == r[0] and np.array_equal(a[1], r[1]) and a[2] == r[2], K
+
+
+def test_temperature_adjoint_tile_height_does_not_change_the_gradient():
+    """16 lattices of 400x200 give the batch enough temperature-adjoint tiles
+    for 24-row tiles, while one lattice alone uses 8-row tiles: the gradients
+    must be bitwise equal (the per-node arithmetic of the transposed RK4 step
+    does not depend on the tiling)."""
+    _say("batch adjoint 16 x 400x200: 24-row vs 8-row temperature-adjoint tiles")
+    base = WL.PLAIN_128x64
+    mem = []
+    for i in range(16):
+        w = base.resized(400, 200, dT_over_Tc=0.04 + 0.01 * i, heater=(0, -1), Gw_bottom=0.065, seed=30 + i,
+                         g=WL.scaled_gravity(200, 2.0 / 49.0))
+        tc = O.Tc(w.a, w.b, w.R)
+        rv, rl, _ = O.maxwell(w.a, w.b, w.R, w.omega, w.Ts_over_Tc * tc)
+        p = L.Params(nx=w.nx, ny=w.ny, precision=L.FP32, liquid_rows=w.liquid_rows, sigma=w.sigma, g=w.g,
+                     Gw_bottom=w.Gw_bottom, rho_L=rl, rho_V=rv)
+        mem.append((p, w.heater_T(tc), w.density(rl, rv)))
+    b = L.Batch([m[0] for m in mem], [m[1] for m in mem], [m[2] for m in mem])
+    b.step(5)
+    J, g, gw = b.adjoint(8, K=4)  # two segments: the recompute stream and both buffers
+    b.close()
+    for i in (0, 9):
+        p, Tb, rho0 = mem[i]
+        d = L.Domain(p, T_bottom=Tb, rho0=rho0).step(5)
+        Js, gs, gws = d.adjoint(8, K=4)
+        assert J[i] == Js and np.array_equal(g[i], gs) and gw[i] == gws, i
+        d.close()
