@@ -8,7 +8,7 @@ whole hot path (LB launch + thermal launch, with the mass and heat-flux
 reductions) over the lattice.  --steps K steps are timed with HIP events on
 the library's stream around graph replays; value = nx*ny*K / time in MLUPS.
 
-Prints ONE JSON line.  --gpus N > 1 exits: this build runs on one GPU.
+Prints ONE JSON line.  --gpus N > 1 exits: the benchmark runs on one GPU.
 """
 import argparse
 import hashlib
@@ -73,6 +73,40 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def copy_bandwidth(nbytes=1 << 30, reps=10):
+    """HBM bandwidth a plain elementwise kernel reaches on this GPU: torch.neg
+    reading and writing nbytes each, timed with events over `reps` launches
+    after two untimed ones; GB/s of read + write traffic."""
+    import torch
+
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        torch.neg(a, out=b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        torch.neg(a, out=b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, steps):
     """The oracle, as it stands, on the host cores over a bounded sample."""
     import oracle as O
@@ -85,7 +119,7 @@ def cpu_baseline(w, steps):
     s.step(steps)
     dt = time.perf_counter() - t0
     return {"value": round(w.nx * w.ny * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": O.num_threads(),
-            "kind": "oracle",
+            "kind": "oracle", "cpu": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": f"first {steps} steps of the {w.nx}x{w.ny} workload in FP64 "
                       f"({w.nx * w.ny * steps:.3g} lattice updates, {dt:.1f} s)"}
 
@@ -248,7 +282,7 @@ def main():
                     help="steps per tile shape for the autotuner before timing (0: default shapes)")
     ap.add_argument("--tiles", default=None,
                     help="LB,thermal tile shape indices to use instead of the autotuner (profiling runs)")
-    ap.add_argument("--cpu-steps", type=int, default=100, help="oracle steps for the CPU baseline (0: skip)")
+    ap.add_argument("--cpu-steps", type=int, default=300, help="oracle steps for the CPU baseline (0: skip)")
     ap.add_argument("--sweep-steps", type=int, default=2000, help="steps of the 48-lattice sweep comparison (0: skip)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost measurement")
     ap.add_argument("--adjoint-only", action="store_true", help="only the adjoint/forward cost measurement (profiling)")
@@ -257,8 +291,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the path would shard by instances or x-slabs, see the design notes)", file=sys.stderr)
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(batches would shard by lattice, a single lattice by x-slabs with halo exchange)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -338,6 +372,7 @@ def main():
         print(f"[bench] adjoint/forward: f64 {adj['f64']['ratio']}x, f32 {adj['f32']['ratio']}x; "
               f"batch of {badj['instances']}: {badj['ratio']}x", file=sys.stderr, flush=True)
     cpu = cpu_baseline(w, args.cpu_steps) if args.cpu_steps > 0 else None
+    copy_gbs = copy_bandwidth()
 
     line = {
         "metric": "MLUPS of coupled LB+thermal step, % HBM peak; batched vs plain; adjoint/fwd",
@@ -359,7 +394,8 @@ def main():
                      "traffic_unit": "bytes per launch",
                      "traffic_gbs": None if traffic is None else round(traffic / (ms_lb * 1e-3) / 1e9, 1),
                      "kernel": "k_lb", "kernel_ms": round(ms_lb, 6),
-                     "alg_bytes_per_update": ALG_BYTES_LB[store]},
+                     "alg_bytes_per_update": ALG_BYTES_LB[store],
+                     "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
         "step_roofline": {"achieved": round(step_bytes / (ms_step * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
                           "unit": "GB/s", "frac": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                           "alg_bytes_per_update": ALG_BYTES_STEP[store]},

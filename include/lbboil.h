@@ -45,7 +45,7 @@ extern "C" {
 #define LBB_EDEVICE (-3)      /* HIP runtime error or no usable gfx950 device  */
 #define LBB_ENONFINITE (-4)   /* non-finite value, rho <= 0, T <= 0 or a
                                  negative pseudopotential radicand detected     */
-#define LBB_EUNSUPPORTED (-5) /* request not supported by this build           */
+#define LBB_EUNSUPPORTED (-5) /* request not supported by the library          */
 #define LBB_ESTATE (-6)       /* domain poisoned by an earlier LBB_ENONFINITE  */
 
 enum { LBB_FP64 = 0, LBB_FP32 = 1 };
