@@ -9,8 +9,7 @@
  * with the GPU library.
  *
  * Every routine follows the paper's equations in the paper's order; where the
- * paper is silent the reading adopted is stated next to the code (and listed
- * in the design notes of the repository).
+ * paper is silent the reading adopted is stated next to the code.
  */
 #ifndef LBB_ORACLE_H
 #define LBB_ORACLE_H
