@@ -106,6 +106,30 @@ template <typename S> struct ThermalCfg;
 // the hardware instruction (1 ulp) in FP32
 __device__ __forceinline__ double stage_sqrt(double x) { return sqrt_nr(x); }
 __device__ __forceinline__ float stage_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+// The value a lane's left (lane - 1) or right (lane + 1) neighbour holds,
+// through the wave-wide row shift of DPP (0 in the first and last lane).
+// Every lane of the wave must be active.
+__device__ __forceinline__ float lane_from_left(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138 /* wave_shr:1 */, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float lane_from_right(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130 /* wave_shl:1 */, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double lane_from_left(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_from_right(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
 template <> struct ThermalCfg<float> {
     using C = float;
 };
@@ -808,16 +832,23 @@ __global__ __launch_bounds__(64 * NWB) void k_thermal(const Inst *__restrict__ i
 #pragma unroll
             for (int m = 0; m < RPW; ++m) {
                 const int r = wv + NWB * m;
-                if (r >= H || r < HB - rad || r >= HB + TY + rad || lane < HB - rad || lane >= HB + TXB + rad) continue;
+                if (r >= H || r < HB - rad || r >= HB + TY + rad) continue;
+                // Column sums of the 3x3 stencil, formed by every lane for its
+                // own column and passed to the neighbouring columns:
+                // v = T_S + 4 T_c + T_N, w = T_N - T_S give
+                //   d_x T = (v_E - v_W)/12, d_y T = (w_W + 4 w + w_E)/12,
+                //   lap T = (v_W + v_E + 4 v - 36 T_c)/6,
+                // the isotropic stencils of the gradient and the Laplacian.
+                const C tc = in[r][lane], tN = in[r + 1][lane], tS = in[r - 1][lane];
+                const C v = (tN + tS) + C(4) * tc, w = tN - tS;
+                const C vW = lane_from_left(v), vE = lane_from_right(v);
+                const C wW = lane_from_left(w), wE = lane_from_right(w);
+                if (lane < HB - rad || lane >= HB + TXB + rad) continue;
                 C h = C(0);
                 if (act[m]) {
-                    const int l = lane;
-                    const C tE = in[r][l + 1], tW = in[r][l - 1], tN = in[r + 1][l], tS = in[r - 1][l];
-                    const C tNE = in[r + 1][l + 1], tNW = in[r + 1][l - 1], tSW = in[r - 1][l - 1], tSE = in[r - 1][l + 1];
-                    const C tc = in[r][l];
-                    const C dTx = (tE - tW) * C(1.0 / 3.0) + (tNE - tNW + tSE - tSW) * C(1.0 / 12.0);
-                    const C dTy = (tN - tS) * C(1.0 / 3.0) + (tNE + tNW - tSE - tSW) * C(1.0 / 12.0);
-                    const C lap = (tE + tW + tN + tS) * C(2.0 / 3.0) + (tNE + tNW + tSE + tSW) * C(1.0 / 6.0) - C(10.0 / 3.0) * tc;
+                    const C dTx = (vE - vW) * C(1.0 / 12.0);
+                    const C dTy = (wW + wE + C(4) * w) * C(1.0 / 12.0);
+                    const C lap = (vW + vE + C(4) * v - C(36) * tc) * C(1.0 / 6.0);
                     const C T = Tref + tc;
                     const C Tphi = k2 * T - k1k * stage_sqrt(T * inv_Tc);
                     h = -(cfr[0][m] * dTx + cfr[1][m] * dTy) + chi * lap - cfr[2][m] * T + cfr[3][m] * Tphi;
