@@ -791,20 +791,24 @@ __global__ __launch_bounds__(64 * NWB) void k_thermal(const Inst *__restrict__ i
 #pragma unroll
         for (int m = 0; m < RPW; ++m) {
             const int r = wv + NWB * m;
-            if (r < 1 || r >= H - 1 || lane < 1 || lane >= 63 || !act[m]) continue;
-            const C(*rr)[64] = X[0];
-            const C(*uu)[64] = X[1];
-            const C(*vv)[64] = X[2];
-            const int l = lane;
-            const double rho = (double)rr[r][l];
-            const C drx = (rr[r][l + 1] - rr[r][l - 1]) * C(1.0 / 3.0) +
-                          (rr[r + 1][l + 1] - rr[r + 1][l - 1] + rr[r - 1][l + 1] - rr[r - 1][l - 1]) * C(1.0 / 12.0);
-            const C dry = (rr[r + 1][l] - rr[r - 1][l]) * C(1.0 / 3.0) +
-                          (rr[r + 1][l + 1] + rr[r + 1][l - 1] - rr[r - 1][l + 1] - rr[r - 1][l - 1]) * C(1.0 / 12.0);
-            const C dux = (uu[r][l + 1] - uu[r][l - 1]) * C(1.0 / 3.0) +
-                          (uu[r + 1][l + 1] - uu[r + 1][l - 1] + uu[r - 1][l + 1] - uu[r - 1][l - 1]) * C(1.0 / 12.0);
-            const C dvy = (vv[r + 1][l] - vv[r - 1][l]) * C(1.0 / 3.0) +
-                          (vv[r + 1][l + 1] + vv[r + 1][l - 1] - vv[r - 1][l + 1] - vv[r - 1][l - 1]) * C(1.0 / 12.0);
+            if (r < 1 || r >= H - 1 || !act[m]) continue;
+            // column sums of the gradient stencils (see the stages below),
+            // every lane for its own column, passed to the neighbours
+            const C rc = X[0][r][lane], rN = X[0][r + 1][lane], rS = X[0][r - 1][lane];
+            const C uc = X[1][r][lane], uN = X[1][r + 1][lane], uS = X[1][r - 1][lane];
+            const C vN = X[2][r + 1][lane], vS = X[2][r - 1][lane];
+            const C sr = (rN + rS) + C(4) * rc, dr = rN - rS;
+            const C su = (uN + uS) + C(4) * uc, dv = vN - vS;
+            const C srW = lane_from_left(sr), srE = lane_from_right(sr);
+            const C drW = lane_from_left(dr), drE = lane_from_right(dr);
+            const C suW = lane_from_left(su), suE = lane_from_right(su);
+            const C dvW = lane_from_left(dv), dvE = lane_from_right(dv);
+            if (lane < 1 || lane >= 63) continue;
+            const double rho = (double)rc;
+            const C drx = (srE - srW) * C(1.0 / 12.0);
+            const C dry = (drW + drE + C(4) * dr) * C(1.0 / 12.0);
+            const C dux = (suE - suW) * C(1.0 / 12.0);
+            const C dvy = (dvW + dvE + C(4) * dv) * C(1.0 / 12.0);
             // A w = (R/c_v) div v / D1 and B w = (a/c_v) rho div v / D2 with
             // D1 = 1 - b rho, D2 = 1 + 2 b rho - b^2 rho^2; one reciprocal
             // 1/(rho D1 D2) gives 1/rho, 1/D1 and 1/D2
@@ -813,8 +817,8 @@ __global__ __launch_bounds__(64 * NWB) void k_thermal(const Inst *__restrict__ i
             const double inv = rcp_nr(rho * D1 * D2);
             const double div = (double)(dux + dvy);
             const C chi_rho = (C)(P.chi * D1 * D2 * inv);
-            cfr[0][m] = uu[r][l] - chi_rho * drx;
-            cfr[1][m] = vv[r][l] - chi_rho * dry;
+            cfr[0][m] = uc - chi_rho * drx;
+            cfr[1][m] = X[2][r][lane] - chi_rho * dry;
             cfr[2][m] = (C)(P.R_cv * div * (rho * D2 * inv));
             cfr[3][m] = (C)(P.a_cv * rho * div * (rho * D1 * inv));
         }
