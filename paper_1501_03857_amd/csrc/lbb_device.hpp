@@ -106,6 +106,31 @@ template <typename S> struct ThermalCfg;
 // the hardware instruction (1 ulp) in FP32
 __device__ __forceinline__ double stage_sqrt(double x) { return sqrt_nr(x); }
 __device__ __forceinline__ float stage_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+// DPP move of a double (two 32-bit moves) with control `ctl`; lanes the
+// pattern gives no source, or whose row `rmask` leaves out, read 0.
+template <int CTL, int RMASK>
+__device__ __forceinline__ double dpp_d(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTL, RMASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTL, RMASK, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum of one double per lane over the wave, valid in lane 63, in a fixed
+// order: an inclusive scan inside each row of 16 lanes (shifts by 1, 2, 4,
+// 8), then the total of row 0 added into row 1 and of row 2 into row 3, then
+// the total of rows 0-1 into rows 2-3.  Every lane must be active.
+__device__ __forceinline__ double wave_sum_to_last(double v)
+{
+    v += dpp_d<0x111 /* row_shr:1 */, 0xf>(v);
+    v += dpp_d<0x112 /* row_shr:2 */, 0xf>(v);
+    v += dpp_d<0x114 /* row_shr:4 */, 0xf>(v);
+    v += dpp_d<0x118 /* row_shr:8 */, 0xf>(v);
+    v += dpp_d<0x142 /* row_bcast:15 */, 0xa>(v);
+    v += dpp_d<0x143 /* row_bcast:31 */, 0xc>(v);
+    return v;
+}
+
 // The value a lane's left (lane - 1) or right (lane + 1) neighbour holds,
 // through the wave-wide row shift of DPP (0 in the first and last lane).
 // Every lane of the wave must be active.
@@ -679,13 +704,11 @@ __global__ __launch_bounds__(64 * NWA) void k_lb(const Inst *__restrict__ insts,
         mrow[m] = mm;
     }
     // mass partials per lattice row and 62-column chunk, summed over the wave
-    // by a fixed butterfly: the same grouping and order for every tile height
+    // in a fixed order (the same for every tile height)
 #pragma unroll
     for (int m = 0; m < IPW_A; ++m) {
-        double v = mrow[m];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        if (live[m] && lane == 0) I.mass_part[(size_t)gys[m] * nbx + bx] = v;
+        const double v = wave_sum_to_last(mrow[m]);
+        if (live[m] && lane == 63) I.mass_part[(size_t)gys[m] * nbx + bx] = v;
     }
 }
 
