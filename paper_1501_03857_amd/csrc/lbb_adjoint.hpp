@@ -388,18 +388,21 @@ __global__ __launch_bounds__(64 * TAW) void a_theradj(const AdjInst *__restrict_
 #pragma unroll
         for (int m = 0; m < RPW; ++m) {
             const int r = wv + TAW * m;
-            if (r < s || r >= H - s || lane < s || lane >= 64 - s) continue;
+            if (r < s || r >= H - s) continue;
+            // the gradient and Laplacian stencils from column sums shifted
+            // between lanes, as in the forward thermal step
+            const double(*F)[64] = sb[s - 1];
+            const double tc = F[r][lane], tN = F[r + 1][lane], tS = F[r - 1][lane];
+            const double cv = (tN + tS) + 4.0 * tc, cw = tN - tS;
+            const double vW = lane_from_left(cv), vE = lane_from_right(cv);
+            const double wW = lane_from_left(cw), wE = lane_from_right(cw);
+            if (lane < s || lane >= 64 - s) continue;
             double v = sb[0][r][lane];
             if (inr[m]) {
-                const double(*F)[64] = sb[s - 1];
                 const int l = lane;
-                const double tc = F[r][l];
-                const double tE = F[r][l + 1], tW = F[r][l - 1], tN = F[r + 1][l], tS = F[r - 1][l];
-                const double tNE = F[r + 1][l + 1], tNW = F[r + 1][l - 1], tSW = F[r - 1][l - 1], tSE = F[r - 1][l + 1];
-                const double dTx = (tE - tW) * (1.0 / 3.0) + (tNE - tNW + tSE - tSW) * (1.0 / 12.0);
-                const double dTy = (tN - tS) * (1.0 / 3.0) + (tNE + tNW - tSE - tSW) * (1.0 / 12.0);
-                const double lap = (tE + tW + tN + tS) * (2.0 / 3.0) + (tNE + tNW + tSE + tSW) * (1.0 / 6.0) -
-                                   (10.0 / 3.0) * tc;
+                const double dTx = (vE - vW) * (1.0 / 12.0);
+                const double dTy = (wW + wE + 4.0 * cw) * (1.0 / 12.0);
+                const double lap = (vW + vE + 4.0 * cv - 36.0 * tc) * (1.0 / 6.0);
                 double d1, d2;
                 phi_derivs(P, tc, d1, d2);
                 const double h = sAX[r][l] * dTx + sAY[r][l] * dTy + chi * lap - cIA[m] * cdv[m] * tc +
