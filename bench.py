@@ -32,21 +32,21 @@ ALG_BYTES_LB = {"f32": 72, "f64": 144}
 # HBM traffic of the LB launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
 # (KiB per dispatch, mean over the dispatches of a --profile run with the
 # given tiles), each scaled by what the same counter reads for an elementwise
-# kernel that reads 1 GiB and writes 1 GiB (FETCH_SIZE 524294.5 KiB -> factor
+# kernel that reads 1 GiB and writes 1 GiB (FETCH_SIZE 524297.8 KiB -> factor
 # 2.0, WRITE_SIZE 1048576 KiB -> factor 1.0).  Valid for the kernel source
 # whose hash is recorded and the same LB tile shape; null otherwise.
 MEASURED_TRAFFIC = {
-    "source_hash": "46f612879550aaad",
-    "fetch_factor": 1048576.0 / 524294.5,
+    "source_hash": "3fa9f92ea7d86a7b",
+    "fetch_factor": 1048576.0 / 524297.8,
     "write_factor": 1048576.0 / 1048576.0,
     "k_lb": {
         "large_1024x512_fp32": [
-            {"tiles_lb": [62, 12, 4], "fetch_kib": 10836.9, "write_kib": 24671.2},
-            {"tiles_lb": [62, 8, 4], "fetch_kib": 10654.9, "write_kib": 24629.8},
+            {"tiles_lb": [62, 12, 4], "fetch_kib": 10839.8, "write_kib": 24674.7},
+            {"tiles_lb": [62, 8, 4], "fetch_kib": 10657.6, "write_kib": 24627.8},
         ],
         "large_4096x2048_fp32": [
-            {"tiles_lb": [62, 6, 2], "fetch_kib": 169040.2, "write_kib": 396494.9},
-            {"tiles_lb": [62, 8, 4], "fetch_kib": 173019.3, "write_kib": 397422.7},
+            {"tiles_lb": [62, 6, 2], "fetch_kib": 169615.2, "write_kib": 398116.3},
+            {"tiles_lb": [62, 8, 4], "fetch_kib": 173336.0, "write_kib": 398156.8},
         ],
     },
 }
