@@ -39,6 +39,14 @@
  *    fluid-solid force of Eq. (22) acts on the fluid rows next to the walls
  *    with the wall rows as the solid; this reproduces the contact angles the
  *    paper reports for G_w = 0, 0.065 and 0.105.
+ *  - Ghost-layer variant (ghost_layer = 1, Sec. 3.2): F_m and Q of Eq. (7)
+ *    are also formed on the wall rows, with a ghost fluid layer beyond each
+ *    wall that mirrors the fluid about the wall row, psi(i, -1) = psi(i, 1)
+ *    and psi(i, ny) = psi(i, ny-2).  The wall row is then a symmetry line of
+ *    psi, so the normal component of F_m vanishes there (up to rounding) and
+ *    no body force pushes mass through the no-penetration wall; only the
+ *    tangential component acts.  Buoyancy still does not act on the wall
+ *    rows, and the fluid-solid force is applied as above.
  *  - rho_ave is recomputed every step over all nodes, wall rows included.
  *  - The temperature equation runs on rows 1..ny-2 with the wall rows held at
  *    their Dirichlet values in every RK stage; the velocity it sees is zero
@@ -360,7 +368,10 @@ void orc_grad_iso(int32_t nx, int32_t ny, int32_t periodic_y, const double *phi,
 
 /* O4: F_m = -G psi(x) sum_a w_a psi(x + e_a) e_a (Eq. (7)) and
  * Q = |F_m|^2/psi^2 = G^2 |sum_a w_a psi(x + e_a) e_a|^2 (Eq. (8)); zero on
- * the wall rows, where the paper does not apply the fluid-fluid force. */
+ * the wall rows, where the paper does not apply the fluid-fluid force,
+ * unless ghost_layer is set: then the wall rows get the same sum, with the
+ * neighbours beyond the wall taken from the ghost fluid layer, the mirror
+ * image of the first fluid row (Sec. 3.2). */
 void orc_interaction_force(const orc_params *p, const double *psi, double *Fx, double *Fy, double *Q)
 {
     const int nx = p->nx, ny = p->ny;
@@ -368,13 +379,15 @@ void orc_interaction_force(const orc_params *p, const double *psi, double *Fx, d
     for (int j = 0; j < ny; ++j) {
         for (int i = 0; i < nx; ++i) {
             size_t c = (size_t)j * nx + i;
-            if (!p->periodic_y && (j == 0 || j == ny - 1)) {
+            if (!p->periodic_y && (j == 0 || j == ny - 1) && !p->ghost_layer) {
                 Fx[c] = Fy[c] = Q[c] = 0.0;
                 continue;
             }
             double sx = 0.0, sy = 0.0;
             for (int a = 1; a < 9; ++a) {
                 int ii = wrap(i + EX[a], nx), jj = p->periodic_y ? wrap(j + EY[a], ny) : j + EY[a];
+                if (jj < 0) jj = -jj;                   /* ghost layer below the bottom wall */
+                if (jj > ny - 1) jj = 2 * (ny - 1) - jj; /* ghost layer above the top wall */
                 double v = psi[(size_t)jj * nx + ii];
                 sx += WPSI[a] * v * EX[a];
                 sy += WPSI[a] * v * EY[a];
@@ -450,6 +463,7 @@ static int params_ok(const orc_params *p)
     if (!(p->rho_L != p->rho_V)) return 0;
     if (!(p->s_e > 0 && p->s_zeta > 0 && p->s_e != 2.0 && p->s_zeta != 2.0)) return 0;
     if (p->thermal_mode < ORC_COUPLED || p->thermal_mode > ORC_THERMAL_ONLY) return 0;
+    if (p->ghost_layer != 0 && p->ghost_layer != 1) return 0;
     return 1;
 }
 

@@ -47,6 +47,9 @@ typedef struct orc_params {
     double Gw_bottom, Gw_top; /* fluid-solid strength, Eq. (22)          */
     int32_t periodic_y;     /* 1: no walls, periodic in y (test mode)    */
     int32_t thermal_mode;   /* ORC_COUPLED / ORC_ISOTHERMAL / ORC_THERMAL_ONLY */
+    int32_t ghost_layer;    /* 1: F_m of Eq. (7) also on the wall rows, with a
+                               ghost fluid layer beyond each wall mirroring
+                               the first fluid row (Sec. 3.2)              */
 } orc_params;
 
 typedef struct orc_state orc_state;

@@ -464,7 +464,7 @@ static void heat_flux_T(const orc_params *p, const double *f, const double *T, d
  * tests).  lf1 [9n], lT1 [n] in; lf0 [9n], lT0 [n] out; *gGw accumulates. */
 int orc_step_vjp(const orc_state *s, const double *lf1, const double *lT1, double *lf0, double *lT0, double *gGw)
 {
-    if (s->p.thermal_mode != ORC_COUPLED) return ORC_EINVAL;
+    if (s->p.thermal_mode != ORC_COUPLED || s->p.ghost_layer) return ORC_EINVAL;
     fwd_t w;
     if (!fwd_alloc(&w, s->p.nx, s->p.ny)) return ORC_ENOMEM;
     step_vjp(s, s->f, s->T, lf1, lT1, lf0, lT0, gGw, &w);
@@ -479,7 +479,7 @@ int orc_step_vjp(const orc_state *s, const double *lf1, const double *lT1, doubl
 int orc_adjoint(const orc_state *s, int64_t N, int64_t K, double *J, double *dJ_dTb, double *dJ_dGw)
 {
     const orc_params *p = &s->p;
-    if (p->thermal_mode != ORC_COUPLED || p->periodic_y || N < 1) return ORC_EINVAL;
+    if (p->thermal_mode != ORC_COUPLED || p->periodic_y || p->ghost_layer || N < 1) return ORC_EINVAL;
     if (K <= 0 || K > N) K = N;
     const int nx = p->nx;
     const size_t n = (size_t)nx * p->ny;

@@ -42,7 +42,7 @@ class _CParams(C.Structure):
         ("s_rho", _d), ("s_e", _d), ("s_zeta", _d), ("s_j", _d), ("s_q", _d),
         ("nu_L", _d), ("nu_V", _d), ("rho_L", _d), ("rho_V", _d),
         ("cv", _d), ("cv_chi", _d), ("g", _d), ("Gw_bottom", _d), ("Gw_top", _d),
-        ("periodic_y", C.c_int32), ("thermal_mode", C.c_int32),
+        ("periodic_y", C.c_int32), ("thermal_mode", C.c_int32), ("ghost_layer", C.c_int32),
     ]
 
 
@@ -75,6 +75,7 @@ class Params:
     Gw_top: float = 0.0
     periodic_y: int = 0
     thermal_mode: int = COUPLED
+    ghost_layer: int = 0
 
     def c(self) -> _CParams:
         return _CParams(**{f.name: getattr(self, f.name) for f in fields(self)})

@@ -113,6 +113,57 @@ def _poly_field(nx, ny, c):
     return c[0] + c[1] * x + c[2] * y + c[3] * x * x + c[4] * x * y + c[5] * y * y, x, y
 
 
+@pytest.mark.parametrize("wall", ["bottom", "top"])
+@pytest.mark.parametrize("cx,cxx,cyy", [(0.01, 0.0, 0.02), (-0.02, 1e-3, -0.01), (0.0, -2e-3, 0.03)])
+def test_ghost_layer_force_on_mirror_quadratic(wall, cx, cxx, cyy):
+    """Ghost-layer variant (Sec. 3.2): a ghost row that mirrors the first
+    fluid row about the wall row continues any field that is even about the
+    wall row.  For psi = c0 + cx x + cxx x^2 + cyy (y - y_w)^2 the stencil
+    sum on the wall row y_w is therefore exactly grad psi = (cx + 2 cxx x, 0),
+    so F_m = -G psi grad psi (no normal part) and Q = G^2 |grad psi|^2 there;
+    without the ghost layer both are zero."""
+    nx, ny = 10, 8
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    j = 0 if wall == "bottom" else ny - 1
+    psi = 3.0 + cx * x + cxx * x * x + cyy * (y - j) ** 2
+    p = O.Params(nx=nx, ny=ny, G=-1.0, ghost_layer=1)
+    Fx, Fy, Q = O.interaction_force(p, psi)
+    gx = cx + 2 * cxx * x[j]
+    cols = slice(1, -1)  # x wraps, which a polynomial does not
+    assert np.allclose(Fx[j, cols], (-p.G * psi[j] * gx)[cols], atol=1e-13)
+    assert np.allclose(Fy[j, cols], 0.0, atol=1e-13)
+    assert np.allclose(Q[j, cols], (p.G ** 2 * gx ** 2)[cols], atol=1e-13)
+    F0 = O.interaction_force(O.Params(nx=nx, ny=ny, G=-1.0), psi)
+    assert all(np.all(a[[0, -1]] == 0) for a in F0)
+    # off the wall rows the two variants agree exactly
+    for a, b in zip((Fx, Fy, Q), F0):
+        assert np.array_equal(a[1:-1], b[1:-1])
+
+
+def test_ghost_layer_force_matches_padded_lattice():
+    """On a random positive psi the ghost-layer force on every row equals the
+    plain stencil evaluated on psi padded by one ghost row on each side (the
+    mirror images of rows 1 and ny-2) and wrapped in x; on the wall rows its
+    normal component is zero to rounding for any psi."""
+    rng = np.random.default_rng(7)
+    nx, ny = 9, 7
+    psi = 1.0 + rng.random((ny, nx))
+    pad = np.pad(psi, ((1, 1), (0, 0)), mode="reflect")
+    pad = np.pad(pad, ((0, 0), (1, 1)), mode="wrap")
+    sx = np.zeros_like(psi)
+    sy = np.zeros_like(psi)
+    for a in range(1, 9):
+        nb = pad[1 + EY[a]:1 + EY[a] + ny, 1 + EX[a]:1 + EX[a] + nx]
+        sx += WPSI[a] * EX[a] * nb
+        sy += WPSI[a] * EY[a] * nb
+    G = -1.0
+    Fx, Fy, Q = O.interaction_force(O.Params(nx=nx, ny=ny, G=G, ghost_layer=1), psi)
+    assert np.allclose(Fx, -G * psi * sx, rtol=0, atol=1e-14)
+    assert np.allclose(Fy, -G * psi * sy, rtol=0, atol=1e-14)
+    assert np.allclose(Q, G * G * (sx * sx + sy * sy), rtol=0, atol=1e-14)
+    assert np.max(np.abs(Fy[[0, -1]])) < 1e-14
+
+
 @pytest.mark.parametrize("k", range(6))
 def test_isotropic_stencils_exact_on_quadratics(k):
     c = np.zeros(6)
