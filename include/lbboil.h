@@ -81,6 +81,14 @@ typedef struct lbb_params {
     double noise_amp;        /* built-in initial state: uniform noise in
                                 [-noise_amp, noise_amp) on rho                 */
     uint64_t seed;           /* built-in initial state: SplitMix64 seed        */
+    int32_t ghost_layer;     /* 1: the fluid-fluid force of Eq. (7) also acts
+                                on the wall rows (Sec. 3.2), with a ghost fluid
+                                layer beyond each wall mirroring the first
+                                fluid row, psi(i,-1) = psi(i,1): F_m there is
+                                tangential; buoyancy still skips the wall rows.
+                                0 (default): no fluid-fluid force on them.
+                                lbb_adjoint refuses 1 (LBB_EUNSUPPORTED)       */
+    int32_t reserved;        /* must be 0                                      */
 } lbb_params;
 
 typedef struct lbb_domain lbb_domain;

@@ -168,6 +168,7 @@ enum : int { ERR_RHO = 1, ERR_PSI = 2, ERR_T = 4 };
 struct DevParams {
     int nx, ny;
     int periodic_y, mode;
+    int ghost, pad_;             // ghost: F_m on the wall rows through a ghost layer
     double a, b, R, Tc, kappa;
     double Ts, T_ref;            // saturation temperature, storage offset of T
     double G, sigma;
@@ -399,23 +400,33 @@ __device__ __forceinline__ void reduce_heat_flux(const double *__restrict__ hf_p
 // Wall rows carry no force (F = 0, Q = 0): the paper does not apply F_m
 // there (Sec. 3.2), and any body force on a Zou-He node would become a mass
 // flux through the wall.  The fluid-solid force acts on the rows next to the
-// walls, with the wall rows as the solid of Eq. (22).
+// walls, with the wall rows as the solid of Eq. (22).  In the ghost-layer
+// variant (P.ghost) the wall rows do get F_m and Q, with the neighbours
+// beyond the wall read from a ghost fluid layer that mirrors the first fluid
+// row about the wall row (so F_m has no normal part there); buoyancy still
+// skips them.
 template <int W>
 __device__ __forceinline__ void node_force(const DevParams &P, const double *psi_s, int lx, int ly, int gy,
                                            double rho, double rho_ave, double &Fx, double &Fy, double &Q)
 {
     Fx = Fy = Q = 0.0;
-    if (!P.periodic_y && (gy == 0 || gy == P.ny - 1)) return;
+    const bool bot = !P.periodic_y && gy == 0, top = !P.periodic_y && gy == P.ny - 1;
+    if ((bot || top) && !P.ghost) return;
     const int c = (ly + 1) * W + (lx + 1);
     const double pc = psi_s[c];
-    const double pE = psi_s[c + 1], pW = psi_s[c - 1], pN = psi_s[c + W], pS = psi_s[c - W];
-    const double pNE = psi_s[c + W + 1], pNW = psi_s[c + W - 1], pSW = psi_s[c - W - 1], pSE = psi_s[c - W + 1];
+    const double pE = psi_s[c + 1], pW = psi_s[c - 1];
+    // the LDS row beyond a wall holds no lattice node; the ghost layer
+    // replaces it by the mirror image of the row on the other side
+    const int cn = top ? c - W : c + W, cs = bot ? c + W : c - W;
+    const double pN = psi_s[cn], pS = psi_s[cs];
+    const double pNE = psi_s[cn + 1], pNW = psi_s[cn - 1], pSW = psi_s[cs - 1], pSE = psi_s[cs + 1];
     // sum_a w_a psi(x + e_a) e_a with w = 1/3 (axes), 1/12 (diagonals)
     const double sx = (pE - pW) * (1.0 / 3.0) + (pNE - pNW - pSW + pSE) * (1.0 / 12.0);
     const double sy = (pN - pS) * (1.0 / 3.0) + (pNE + pNW - pSW - pSE) * (1.0 / 12.0);
     Fx = -P.G * pc * sx;
     Fy = -P.G * pc * sy;
     Q = P.G * P.G * (sx * sx + sy * sy);
+    if (bot || top) return;
     // fluid-solid force on the rows next to the walls (wall rows are the solid)
     if (!P.periodic_y) {
         if (gy == 1) Fy += P.Gw_bottom * pc * pc * (1.0 / 6.0);

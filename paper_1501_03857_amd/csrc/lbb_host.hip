@@ -189,6 +189,8 @@ struct lbb_param_dims {
     int nx, ny;
 };
 
+static_assert(sizeof(lbb_params) == 216, "lbb_params layout changed: update the Python binding");
+
 namespace {
 
 int validate(const lbb_params *p)
@@ -213,6 +215,8 @@ int validate(const lbb_params *p)
     if (p->rho_L < 0 || p->rho_V < 0) return fail(LBB_EINVAL, "rho_L, rho_V must be >= 0");
     if (p->noise_amp < 0) return fail(LBB_EINVAL, "noise_amp must be >= 0");
     if (p->liquid_rows < 0 || p->liquid_rows > p->ny) return fail(LBB_EINVAL, "liquid_rows out of range");
+    if (p->ghost_layer != 0 && p->ghost_layer != 1) return fail(LBB_EINVAL, "ghost_layer must be 0 or 1");
+    if (p->reserved != 0) return fail(LBB_EINVAL, "reserved must be 0");
     return LBB_OK;
 }
 
@@ -647,6 +651,7 @@ int lbb_init_domain(const lbb_params *pin, const double *T_bottom, const double 
     q.ny = p.ny;
     q.periodic_y = p.periodic_y ? 1 : 0;
     q.mode = p.thermal_mode;
+    q.ghost = p.ghost_layer && !p.periodic_y ? 1 : 0;
     q.a = p.a;
     q.b = p.b;
     q.R = p.R;
@@ -1915,6 +1920,8 @@ int adjoint_checks(const lbb_domain *d)
 {
     if (d->p.periodic_y || d->p.thermal_mode != LBB_COUPLED)
         return fail(LBB_EUNSUPPORTED, "the adjoint covers the coupled model with walls");
+    if (d->p.ghost_layer)
+        return fail(LBB_EUNSUPPORTED, "the adjoint does not cover the ghost-layer wall variant");
     if (d->poisoned) return fail(LBB_ESTATE, "domain poisoned by an earlier invalid state; load a state first");
     return LBB_OK;
 }

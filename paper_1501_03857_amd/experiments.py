@@ -166,19 +166,22 @@ def boiling_curve(superheats: Sequence[float] = PAPER_SUPERHEATS, wall_strengths
         b.close()
 
 
-def drop_angle(rho: np.ndarray, rho_L: float, rho_V: float) -> float:
+def drop_angle(rho: np.ndarray, rho_L: float, rho_V: float, base_row: int = 1, plane: float = 1.0) -> float:
     """Contact angle (liquid side, degrees) of a drop resting on the bottom
-    wall, from its circular cap: base width w on row 1 (the first fluid row),
-    apex height h above that row on the centre column, tan(theta / 2) = 2 h / w.
-    The interface is where the density crosses (rho_L + rho_V) / 2, located
-    between nodes by linear interpolation.  NaN when the drop has left the
-    wall (no liquid on row 1 or on the centre column) or spread over the
-    whole width."""
+    wall, from its circular cap: base width w on `base_row`, apex height h
+    above the contact plane y = `plane` on the centre column,
+    tan(theta / 2) = 2 h / w.  With the fluid-solid force the wall row is the
+    solid and the plane is row 1, the first fluid row; with the ghost-layer
+    wall the wall row, about which the ghost layer mirrors the fluid, is the
+    contact plane (y = 0) and the base is read on it.  The interface is
+    where the density crosses (rho_L + rho_V) / 2, located between nodes by
+    linear interpolation.  NaN when the drop has left the wall (no liquid on
+    the base row or on the centre column) or spread over the whole width."""
     mid = 0.5 * (rho_L + rho_V)
     ny, nx = rho.shape
     col = rho[:, nx // 2]
     inside = np.nonzero(col > mid)[0]
-    base = rho[1]
+    base = rho[base_row]
     wet = np.nonzero(base > mid)[0]
     if len(inside) == 0 or len(wet) == 0:
         return float("nan")
@@ -188,24 +191,29 @@ def drop_angle(rho: np.ndarray, rho_L: float, rho_V: float) -> float:
     if i0 == 0 or i1 == nx - 1 or j + 1 >= ny:
         return float("nan")
     w = (i1 - i0) + (base[i0] - mid) / (base[i0] - base[i0 - 1]) + (base[i1] - mid) / (base[i1] - base[i1 + 1])
-    return float(2.0 * np.degrees(np.arctan(2.0 * (apex - 1.0) / w)))
+    return float(2.0 * np.degrees(np.arctan(2.0 * (apex - plane) / w)))
 
 
 def sessile_drops(wall_strengths: Sequence[float], a: float = PAPER_A, nx: int = 160, ny: int = 60,
-                  radius: float = 22.0, steps: int = 5000, precision: int = L.FP64) -> List[float]:
+                  radius: float = 22.0, steps: int = 5000, precision: int = L.FP64, ghost_layer: int = 0,
+                  centre_y: float = 0.0) -> List[float]:
     """Equilibrium contact angles of a drop on the bottom wall for each wall
     strength G_w (Eq. (22)), all drops in one batch: isothermal at T_s, no
-    gravity, a half-disc of liquid of the given radius centred on the wall,
-    relaxed for `steps` steps (Sec. 3.2, 3.3)."""
+    gravity, a disc of liquid of the given radius centred at height
+    `centre_y` above the wall row (0: a half-disc, 90 degrees to start with),
+    relaxed for `steps` steps (Sec. 3.2, 3.3).  ghost_layer = 1 runs the wall
+    variant with the fluid-fluid force on the wall rows through a ghost fluid
+    layer (Sec. 3.2), whose contact plane is the wall row."""
     Ts, rv, rl = saturation(a=a)
     y, x = np.mgrid[0:ny, 0:nx].astype(float)
-    rho0 = rv + (rl - rv) * 0.5 * (1.0 - np.tanh((np.hypot(x - nx / 2, y) - radius) / 2.0))
+    rho0 = rv + (rl - rv) * 0.5 * (1.0 - np.tanh((np.hypot(x - nx / 2, y - centre_y) - radius) / 2.0))
     params = [L.Params(nx=nx, ny=ny, precision=precision, a=a, rho_L=rl, rho_V=rv, g=0.0, Gw_bottom=float(Gw),
-                       thermal_mode=L.ISOTHERMAL, liquid_rows=1) for Gw in wall_strengths]
+                       thermal_mode=L.ISOTHERMAL, liquid_rows=1, ghost_layer=ghost_layer) for Gw in wall_strengths]
+    geom = dict(base_row=0, plane=0.0) if ghost_layer else {}
     b = L.Batch(params, None, [rho0] * len(params))
     try:
         b.step(steps)
-        return [drop_angle(b.domain(i).fields(f=False)["rho"], rl, rv) for i in range(len(params))]
+        return [drop_angle(b.domain(i).fields(f=False)["rho"], rl, rv, **geom) for i in range(len(params))]
     finally:
         b.close()
 

@@ -43,7 +43,7 @@ class CParams(C.Structure):
         ("s_rho", _d), ("s_e", _d), ("s_zeta", _d), ("s_j", _d), ("s_q", _d),
         ("nu_L", _d), ("nu_V", _d), ("rho_L", _d), ("rho_V", _d),
         ("cv", _d), ("cv_chi", _d), ("g", _d), ("Gw_bottom", _d), ("Gw_top", _d),
-        ("noise_amp", _d), ("seed", C.c_uint64),
+        ("noise_amp", _d), ("seed", C.c_uint64), ("ghost_layer", _i32), ("reserved", _i32),
     ]
 
 
@@ -168,6 +168,8 @@ class Params:
     Gw_top: float = 0.0
     noise_amp: float = 1e-3
     seed: int = 1
+    ghost_layer: int = 0
+    reserved: int = 0
 
     def c(self) -> CParams:
         return CParams(**{f.name: getattr(self, f.name) for f in fields(self)})

@@ -33,6 +33,12 @@ def test_library_exports_every_declared_symbol():
     assert not missing, missing
 
 
+def test_params_struct_size():
+    """The binding's lbb_params has the size the library asserts at compile
+    time (216 bytes: 6 int32, 22 doubles, a uint64, 2 int32)."""
+    assert C.sizeof(L.CParams) == 216
+
+
 def test_default_params_match_binding_layout():
     """lbb_default_params fills the struct the binding declares (layout check)."""
     p = L.default_params()
@@ -48,7 +54,7 @@ def test_default_params_match_binding_layout():
 @pytest.mark.parametrize("field,value", [
     ("nx", 2), ("ny", 3), ("precision", 7), ("thermal_mode", 3), ("G", 1.0), ("a", -1.0),
     ("s_e", 2.0), ("nu_L", 0.0), ("cv", float("nan")), ("liquid_rows", 65), ("noise_amp", -1.0),
-    ("nx", 1 << 16), ("Ts_over_Tc", 0.0),
+    ("nx", 1 << 16), ("Ts_over_Tc", 0.0), ("ghost_layer", 2), ("ghost_layer", -1), ("reserved", 1),
 ])
 def test_init_rejects_invalid_parameters(field, value):
     p = L.Params()

@@ -65,6 +65,23 @@ def test_drop_angle_recovers_a_circular_cap(theta):
     assert abs(got - theta) < 1.5, (theta, got)
 
 
+@pytest.mark.parametrize("theta", [60.0, 90.0, 120.0])
+def test_drop_angle_ghost_layer_geometry(theta):
+    """With the ghost-layer wall the contact plane is the wall row (y = 0) and
+    the base is read on it: a circle meeting that row at angle theta is
+    measured as theta (geometry only)."""
+    nx, ny, rl, rv = 200, 90, 6.5, 0.38
+    base_half = 30.0
+    t = np.radians(theta)
+    R = base_half / np.sin(t)
+    yc = -R * np.cos(t)
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    d = np.hypot(x - nx / 2, y - yc) - R
+    rho = rv + (rl - rv) * 0.5 * (1.0 - np.tanh(d / 1.0))
+    got = E.drop_angle(rho, rl, rv, base_row=0, plane=0.0)
+    assert abs(got - theta) < 1.5, (theta, got)
+
+
 def test_drop_angle_is_nan_without_contact():
     rho = np.full((40, 100), 0.38)
     rho[20:30, 40:60] = 6.5           # a drop that does not touch row 1
