@@ -441,16 +441,21 @@ __device__ __forceinline__ void node_force(const DevParams &P, const double *psi
 __device__ __forceinline__ void collide(const DevParams &P, double f[9], double rho, double vx, double vy,
                                         double Fx, double Fy, double Q)
 {
-    const double s14 = f[1] + f[2] + f[3] + f[4];
-    const double s58 = f[5] + f[6] + f[7] + f[8];
+    // moments m = M f, from sums and differences shared between the rows of M
+    const double d13 = f[1] - f[3], d24 = f[2] - f[4];
+    const double d57 = f[5] - f[7], d68 = f[6] - f[8];
+    const double s13 = f[1] + f[3], s24 = f[2] + f[4];
+    const double s57 = f[5] + f[7], s68 = f[6] + f[8];
+    const double s14 = s13 + s24, s58 = s57 + s68;
     const double m_e = -(4) * f[0] - s14 + (2) * s58;
     const double m_z = (4) * f[0] - (2) * s14 + s58;
-    const double jx = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
-    const double qx = -(2) * f[1] + (2) * f[3] + f[5] - f[6] - f[7] + f[8];
-    const double jy = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
-    const double qy = -(2) * f[2] + (2) * f[4] + f[5] + f[6] - f[7] - f[8];
-    const double pxx = f[1] - f[2] + f[3] - f[4];
-    const double pxy = f[5] - f[6] + f[7] - f[8];
+    const double dx58 = d57 - d68, dy58 = d57 + d68;  // sum over the diagonals of e_x f, e_y f
+    const double jx = d13 + dx58;
+    const double qx = -(2) * d13 + dx58;
+    const double jy = d24 + dy58;
+    const double qy = -(2) * d24 + dy58;
+    const double pxx = s13 - s24;
+    const double pxy = s57 - s68;
 
     const double v2 = vx * vx + vy * vy;
     const double vF = vx * Fx + vy * Fy;
@@ -476,15 +481,22 @@ __device__ __forceinline__ void collide(const DevParams &P, double f[9], double 
     const double pxx4 = pxx_s * (0.25), pxy4 = pxy_s * (0.25);
     const double axis = r9 - e36 - (2) * z36;
     const double diag = r9 + (2) * e36 + z36;
+    // shared sums of the columns of M^T: axis and diagonal pairs differ only
+    // in the signs of these
+    const double ax = jx6 - (2) * qx12, ay = jy6 - (2) * qy12;
+    const double cx = jx6 + qx12, cy = jy6 + qy12;
+    const double ap = axis + pxx4, am = axis - pxx4;
+    const double dp = diag + pxy4, dm = diag - pxy4;
+    const double cp = cx + cy, cm = cx - cy;
     f[0] = r9 - (4) * e36 + (4) * z36;
-    f[1] = axis + jx6 - (2) * qx12 + pxx4;
-    f[2] = axis + jy6 - (2) * qy12 - pxx4;
-    f[3] = axis - jx6 + (2) * qx12 + pxx4;
-    f[4] = axis - jy6 + (2) * qy12 - pxx4;
-    f[5] = diag + jx6 + jy6 + qx12 + qy12 + pxy4;
-    f[6] = diag - jx6 + jy6 - qx12 + qy12 - pxy4;
-    f[7] = diag - jx6 - jy6 - qx12 - qy12 + pxy4;
-    f[8] = diag + jx6 - jy6 + qx12 - qy12 - pxy4;
+    f[1] = ap + ax;
+    f[2] = am + ay;
+    f[3] = ap - ax;
+    f[4] = am - ay;
+    f[5] = dp + cp;
+    f[6] = dm - cm;
+    f[7] = dp - cp;
+    f[8] = dm + cm;
 }
 
 __constant__ const int kEX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
