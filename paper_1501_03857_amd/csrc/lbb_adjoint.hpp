@@ -6,14 +6,15 @@
 // work arrays.  A launch covers any number of lattices through a lattice
 // table (one lattice, or every member of a batch); the per-node kernels work
 // on 64 x 4 patches (lane = column, wave = row), the temperature kernel on
-// tiles with a halo in LDS.  Four launches per reverse step of state
+// tiles with a halo in LDS.  Three launches per reverse step of state
 // t -> t+1:
-//   a_force    forces (Eqs. (7), (9), (22)), velocity (Eq. (6)), grad rho;
-//              rho_ave from the mass partials of the state
-//   a_theradj  the RK4 temperature step (Eqs. (18)-(20)) transposed: div v
-//              and the coefficients of Eq. (18) formed on the tile and its
-//              halo, stage inputs recomputed and the four stages transposed
-//              in one tile
+//   a_theradj  forces (Eqs. (7), (9), (22)) and velocity (Eq. (6)) of the
+//              state on the tile and its halo (rho_ave from the mass
+//              partials of the state), the tile's own nodes stored for a_lb;
+//              then the RK4 temperature step (Eqs. (18)-(20)) transposed:
+//              div v and the coefficients of Eq. (18) formed on the tile and
+//              its halo, stage inputs recomputed and the four stages
+//              transposed in one tile
 //   a_lb       stencil transposes of grad rho and div v (gather), push
 //              streaming transposed (gather), MRT collision transposed in
 //              moment space, velocity transposed, per-node force parts
@@ -43,7 +44,7 @@ struct AdjWT {
     // rho, j, psi and T of the state being reversed; a_final replaces them
     // by those of the state before it
     D *rho, *jx, *jy, *psi, *T1;
-    D *sx, *sy, *Fx, *Fy, *vx, *vy, *Drx, *Dry;
+    D *sx, *sy, *Fx, *Fy, *vx, *vy;
     D *gDrx, *gDry, *gdiv, *grho, *gvx, *gvy, *gpsi, *gsx, *gsy;
     D *mpart;   // block mass partials of the state being reversed
     D *fpart;   // block partials of the force adjoint: [2b] rho_ave, [2b+1] G_w
@@ -219,43 +220,50 @@ __global__ __launch_bounds__(NTA) void a_macro(A_ARGS, int k)
     if (threadIdx.x == 0) w.mpart[q] = s;
 }
 
-__global__ __launch_bounds__(NTA) void a_force(A_ARGS)
+// Force (Eqs. (7), (22), (9)) and velocity (Eq. (6)) of the stored state at
+// node (gi, gj) from the state's psi and rho: the stencil sums sx, sy of
+// psi, F, the isotropic gradient of rho and v.  Wall rows carry no force.
+struct NodeForce {
+    double sx, sy, Fx, Fy, rx, ry, vx, vy;
+};
+
+// isotropic gradient of rho at interior node (gi, gj)
+__device__ __forceinline__ void grad_rho(const DevParams &P, const AdjWG &w, int gi, int gj, double &rx, double &ry)
 {
-    __shared__ double red[NTA / 64 + 1];
-    A_INST
-    const double rho_ave = block_sum_all(w.mpart, I.nb, 1, 0, red) / ((double)P.nx * (double)P.ny);
-    A_NODE
-    if (!on) return;
-    double sx = 0.0, sy = 0.0, Fx = 0.0, Fy = 0.0, rx = 0.0, ry = 0.0;
+    rx = ry = 0.0;
+#pragma unroll
+    for (int a = 1; a < 9; ++a) {
+        const double rn = w.rho[a_at(P, gi, gj, kEX[a], kEY[a])];
+        rx += 3.0 * kW[a] * kEX[a] * rn;
+        ry += 3.0 * kW[a] * kEY[a] * rn;
+    }
+}
+
+__device__ __forceinline__ NodeForce force_node(const DevParams &P, const AdjWG &w, int gi, int gj, size_t c,
+                                                double rho_ave)
+{
+    NodeForce o;
+    o.sx = o.sy = o.Fx = o.Fy = o.rx = o.ry = 0.0;
     const double r = w.rho[c];
-    const bool in = a_int(P, gj);
-    if (in) {
+    if (a_int(P, gj)) {
 #pragma unroll
         for (int a = 1; a < 9; ++a) {
-            const size_t cn = a_at(P, gi, gj, kEX[a], kEY[a]);
-            const double pn = w.psi[cn], rn = w.rho[cn];
-            sx += kWpsi[a] * pn * kEX[a];
-            sy += kWpsi[a] * pn * kEY[a];
-            rx += 3.0 * kW[a] * kEX[a] * rn;
-            ry += 3.0 * kW[a] * kEY[a] * rn;
+            const double pn = w.psi[a_at(P, gi, gj, kEX[a], kEY[a])];
+            o.sx += kWpsi[a] * pn * kEX[a];
+            o.sy += kWpsi[a] * pn * kEY[a];
         }
+        grad_rho(P, w, gi, gj, o.rx, o.ry);
         const double ps = w.psi[c];
-        Fx = -P.G * ps * sx;
-        Fy = -P.G * ps * sy;
-        if (gj == 1) Fy += P.Gw_bottom * ps * ps / 6.0;
-        if (gj == P.ny - 2) Fy -= P.Gw_top * ps * ps / 6.0;
-        Fy -= (r - rho_ave) * P.g;
+        o.Fx = -P.G * ps * o.sx;
+        o.Fy = -P.G * ps * o.sy;
+        if (gj == 1) o.Fy += P.Gw_bottom * ps * ps / 6.0;
+        if (gj == P.ny - 2) o.Fy -= P.Gw_top * ps * ps / 6.0;
+        o.Fy -= (r - rho_ave) * P.g;
     }
-    w.sx[c] = sx;
-    w.sy[c] = sy;
-    w.Fx[c] = Fx;
-    w.Fy[c] = Fy;
-    w.Drx[c] = rx;
-    w.Dry[c] = ry;
     const double ir = rcp_nr(r);
-    const double vx = (w.jx[c] + 0.5 * Fx) * ir, vy = (w.jy[c] + 0.5 * Fy) * ir;
-    w.vx[c] = vx;
-    w.vy[c] = vy;
+    o.vx = (w.jx[c] + 0.5 * o.Fx) * ir;
+    o.vy = (w.jy[c] + 0.5 * o.Fy) * ir;
+    return o;
 }
 
 // div v and the coefficients of Eq. (18) at interior node (gi, gj), formed
@@ -268,27 +276,30 @@ struct DivCoef {
     double dv, ax, ay, IA, IB;
 };
 
-__device__ __forceinline__ DivCoef div_coef(const DevParams &P, const AdjWG &w, int gi, int gj, size_t c)
+// From the velocity planes VX, VY of the tile region (region row r, lane l,
+// both at least one node from the region's edge) and the node's own v_x, v_y,
+// d_x rho, d_y rho and rho.
+__device__ __forceinline__ DivCoef div_coef(const DevParams &P, const double (*VX)[64], const double (*VY)[64],
+                                            int r, int l, int gj, double vx, double vy, double rx, double ry,
+                                            double rho)
 {
     double dv = 0.0;
 #pragma unroll
     for (int a = 1; a < 9; ++a) {
         // the velocity the temperature equation sees is zero on the wall rows
-        const size_t cn = a_at(P, gi, gj, kEX[a], kEY[a]);
         const double m = a_int(P, gj + kEY[a]) ? 3.0 * kW[a] : 0.0;
-        dv += m * (kEX[a] * w.vx[cn] + kEY[a] * w.vy[cn]);
+        dv += m * (kEX[a] * VX[r + kEY[a]][l + kEX[a]] + kEY[a] * VY[r + kEY[a]][l + kEX[a]]);
     }
-    const double r = w.rho[c];
-    const double D1 = 1.0 - P.b * r, D2 = 1.0 + 2.0 * P.b * r - P.b * P.b * r * r;
-    const double inv = rcp_nr(r * D1 * D2);
-    const double ri = D1 * D2 * inv, i1 = r * D2 * inv, i2 = r * D1 * inv;
+    const double D1 = 1.0 - P.b * rho, D2 = 1.0 + 2.0 * P.b * rho - P.b * P.b * rho * rho;
+    const double inv = rcp_nr(rho * D1 * D2);
+    const double ri = D1 * D2 * inv, i1 = rho * D2 * inv, i2 = rho * D1 * inv;
     const double icv = P.inv_cv;
     DivCoef k;
     k.dv = dv;
-    k.ax = -w.vx[c] + P.chi * w.Drx[c] * ri;
-    k.ay = -w.vy[c] + P.chi * w.Dry[c] * ri;
+    k.ax = -vx + P.chi * rx * ri;
+    k.ay = -vy + P.chi * ry * ri;
     k.IA = P.R * i1 * icv;
-    k.IB = P.a * r * i2 * icv;
+    k.IB = P.a * rho * i2 * icv;
     return k;
 }
 
@@ -330,6 +341,7 @@ __global__ __launch_bounds__(64 * TAW) void a_theradj(const AdjInst *__restrict_
     // T_4 is dead, g_0 plane 2 once T_3 is.
     __shared__ double sb[6][H][64];
     __shared__ double sAX[H][64], sAY[H][64];
+    __shared__ double s_rho_ave;
     const AdjInst &I = ai[tmap[blockIdx.x]];
     const DevParams P = I.P;
     const AdjWG &w = reinterpret_cast<const AdjWG &>(I.w);
@@ -345,7 +357,6 @@ __global__ __launch_bounds__(64 * TAW) void a_theradj(const AdjInst *__restrict_
     // region row r of this wave's m-th slot: lattice row, in lattice, interior
     int gyr[RPW];
     bool inl[RPW], inr[RPW];
-    double cdv[RPW], cIA[RPW], cIB[RPW], cE1[RPW], cE2[RPW];
 #pragma unroll
     for (int m = 0; m < RPW; ++m) {
         const int r = wv + TAW * m;
@@ -353,14 +364,66 @@ __global__ __launch_bounds__(64 * TAW) void a_theradj(const AdjInst *__restrict_
         gyr[m] = gy;
         inl[m] = r < H && gy >= 0 && gy < P.ny;
         inr[m] = inl[m] && gy > 0 && gy < P.ny - 1;
+    }
+
+    // rho_ave of the stored state (Eq. (9)): every block sums the lattice's
+    // mass partials in the same fixed order
+    if (wv == 0) {
+        double sm = 0.0;
+        for (int k = lane; k < I.nb; k += 64) sm += w.mpart[k];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) sm += __shfl_xor(sm, off, 64);
+        if (lane == 0) s_rho_ave = sm / ((double)P.nx * (double)P.ny);
+    }
+    __syncthreads();
+    const double rho_ave = s_rho_ave;
+
+    // force and velocity of the stored state on the region: v into planes 1
+    // and 2 (free until the first forward stage), grad rho into the
+    // coefficient planes; the tile's own nodes also write the per-node
+    // fields the LB adjoint reads
+    const bool tile_col = lane >= TAH && lane < TAH + TAX;
+#pragma unroll
+    for (int m = 0; m < RPW; ++m) {
+        const int r = wv + TAW * m;
+        if (r >= H) continue;
+        NodeForce o;
+        o.vx = o.vy = o.rx = o.ry = 0.0;
+        if (inl[m]) {
+            const size_t c = (size_t)gyr[m] * P.nx + gx;
+            o = force_node(P, w, gx, gyr[m], c, rho_ave);
+            if (r >= TAH && r < TAH + TAY && tile_col && x0 + lane - TAH < P.nx) {
+                w.sx[c] = o.sx;
+                w.sy[c] = o.sy;
+                w.Fx[c] = o.Fx;
+                w.Fy[c] = o.Fy;
+                w.vx[c] = o.vx;
+                w.vy[c] = o.vy;
+            }
+        }
+        sb[1][r][lane] = o.vx;
+        sb[2][r][lane] = o.vy;
+        sAX[r][lane] = o.rx;
+        sAY[r][lane] = o.ry;
+    }
+    __syncthreads();
+
+    // coefficients of K at the region nodes one node in from its edge (the
+    // only ones any stage reads)
+    double cdv[RPW], cIA[RPW], cIB[RPW], cE1[RPW], cE2[RPW];
+#pragma unroll
+    for (int m = 0; m < RPW; ++m) {
+        const int r = wv + TAW * m;
         double t1 = 0.0, ax = 0.0, ay = 0.0, l1 = 0.0;
         cdv[m] = cIA[m] = cIB[m] = cE1[m] = cE2[m] = 0.0;
         if (inl[m]) {
-            const size_t c = (size_t)gy * P.nx + gx;
+            const size_t c = (size_t)gyr[m] * P.nx + gx;
             t1 = w.T1[c];
             l1 = lT1[c];
-            if (inr[m]) {
-                const DivCoef k = div_coef(P, w, gx, gy, c);
+            if (inr[m] && r >= 1 && r < H - 1 && lane >= 1 && lane < 63) {
+                const double rho = w.rho[c];
+                const DivCoef k = div_coef(P, sb[1], sb[2], r, lane, gyr[m], sb[1][r][lane], sb[2][r][lane],
+                                           sAX[r][lane], sAY[r][lane], rho);
                 ax = k.ax;
                 ay = k.ay;
                 cdv[m] = k.dv;
@@ -368,10 +431,13 @@ __global__ __launch_bounds__(64 * TAW) void a_theradj(const AdjInst *__restrict_
                 cIB[m] = k.IB;
                 if (r >= TAH && r < TAH + TAY) {
                     double ri;
-                    pw_derivs(P, w.rho[c], ri, cE1[m], cE2[m]);
+                    pw_derivs(P, rho, ri, cE1[m], cE2[m]);
                 }
             }
         }
+        // each node reads only its own grad rho entry before replacing it
+        // with the advection coefficient; the neighbours' reads above go to
+        // the velocity planes
         if (r < H) {
             sb[0][r][lane] = t1;
             sb[4][r][lane] = l1;
@@ -415,14 +481,13 @@ __global__ __launch_bounds__(64 * TAW) void a_theradj(const AdjInst *__restrict_
     }
 
     // reverse stages k = 3..0 on the region shrunk by 7 - k
-    double lt[RPW], acc[RPW][6];
+    double lt[RPW], acc[RPW][5];
 #pragma unroll
     for (int m = 0; m < RPW; ++m) {
         lt[m] = 0.0;
 #pragma unroll
-        for (int j = 0; j < 6; ++j) acc[m][j] = 0.0;
+        for (int j = 0; j < 5; ++j) acc[m][j] = 0.0;
     }
-    const bool tile_col = lane >= TAH && lane < TAH + TAX;
 #pragma unroll
     for (int k = 3; k >= 0; --k) {
         const int R = 7 - k;
@@ -467,8 +532,7 @@ __global__ __launch_bounds__(64 * TAW) void a_theradj(const AdjInst *__restrict_
                     acc[m][1] += g * dTy;
                     acc[m][2] += g * Tv;        // div v part: -g T (IA - IB d1)
                     acc[m][3] += g * Tv * d1;
-                    acc[m][4] += g * (w.Drx[(size_t)gyr[m] * P.nx + gx] * dTx + w.Dry[(size_t)gyr[m] * P.nx + gx] * dTy);
-                    acc[m][5] += g * Tv * (cE1[m] - cE2[m] * d1);
+                    acc[m][4] += g * Tv * (cE1[m] - cE2[m] * d1);
                 }
             }
             lt[m] += gT;
@@ -495,12 +559,16 @@ __global__ __launch_bounds__(64 * TAW) void a_theradj(const AdjInst *__restrict_
         if (inr[m]) {
             double ri, e1, e2;
             pw_derivs(P, w.rho[c], ri, e1, e2);
+            // grad rho is constant over the stages: its part of the rho
+            // adjoint is grad rho . (sum of g grad T), formed here
+            double rx, ry;
+            grad_rho(P, w, gx, gyr[m], rx, ry);
             aDrx = chi * ri * acc[m][0];
             aDry = chi * ri * acc[m][1];
             avx = -acc[m][0];
             avy = -acc[m][1];
             adiv = -(cIA[m] * acc[m][2] - cIB[m] * acc[m][3]);
-            arho = -chi * ri * ri * acc[m][4] - cdv[m] * acc[m][5];
+            arho = -chi * ri * ri * (rx * acc[m][0] + ry * acc[m][1]) - cdv[m] * acc[m][4];
         }
         w.gDrx[c] = aDrx;
         w.gDry[c] = aDry;

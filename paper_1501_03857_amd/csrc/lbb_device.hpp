@@ -45,12 +45,15 @@ constexpr int TXB = 64 - 2 * HB;  // thermal tile width: tile + halo is one wave
 
 // Tile shapes the launches can take (height, waves per block); the host picks
 // one of each per lattice or batch, by default or by timing them on the
-// lattice (autotune).  Index 0 is the default.
+// lattice (autotune).  Index 0 is the default.  With one lattice row per
+// wave the LB kernel needs 72 VGPRs (7 waves per SIMD), against 118 with
+// three rows per wave, and the extra waves in flight hide the load latency
+// of phase 1 behind the arithmetic of other waves.
 struct TileShape {
     int ty, nw;
 };
 constexpr int NSHAPE_A = 4, NSHAPE_B = 4;
-constexpr TileShape kShapeA[NSHAPE_A] = {{12, 4}, {8, 4}, {6, 2}, {4, 2}};
+constexpr TileShape kShapeA[NSHAPE_A] = {{8, 8}, {4, 4}, {12, 4}, {4, 2}};
 constexpr TileShape kShapeB[NSHAPE_B] = {{24, 16}, {40, 16}, {16, 16}, {8, 8}};
 
 // 1/x from the hardware reciprocal estimate (relative error near 2^-23)
