@@ -322,7 +322,7 @@ __device__ __forceinline__ void pw_derivs(const DevParams &P, double r, double &
 // first, on one tile with a halo of 7 (three forward stencil stages, four
 // reverse ones), in LDS.  Lane = column (tile TAX = 50 wide, one wave64 with
 // the halo), each of the TAW waves owns fixed region rows; tiles are TAY rows
-// high (16, or 8 where 16-row tiles would leave the chip underfilled).  Stage k's slope
+// high (16 or 24, or 4 where 16-row tiles would leave the chip underfilled).  Stage k's slope
 // adjoint is g_k = w_k lT^{t+1}/6 + c_{k+1} gT_{k+1} (RK4 weights w = (1, 2,
 // 2, 1), g_3 = lT^{t+1}/6), gT_k being the adjoint of the stage input T_k,
 // gathered from the slope adjoints of the node and its neighbours.  Outputs

@@ -1645,14 +1645,15 @@ int adjoint_run(AdjGroup &g, int64_t N, int64_t K, double *J, double *dJ_dTb, do
         tot += m[i].nb;
     }
     // temperature-adjoint tiles: 16 rows high unless that gives fewer than
-    // two tiles per compute unit, then 8 (16 waves either way, 2-3 region
-    // rows each)
+    // two tiles per compute unit, then 4 (16 waves either way; a 4-row tile
+    // and its halo are 18 region rows, so most waves own one row and the
+    // seven stencil phases are short)
     int tay = 16;
     {
         int t16 = 0;
         for (int i = 0; i < nm; ++i)
             t16 += ((g.doms[i]->p.nx + TAX - 1) / TAX) * ((g.doms[i]->p.ny + 15) / 16);
-        if (t16 < 2 * 256) tay = 8;
+        if (t16 < 2 * 256) tay = 4;
         // 24-row tiles (LDS for one block per CU) cut the halo share where
         // there are at least four tiles per CU
         int t24 = 0;
@@ -1874,7 +1875,7 @@ int adjoint_run(AdjGroup &g, int64_t N, int64_t K, double *J, double *dJ_dTb, do
             const int k = (int)(t - t0);
             if (tay == 24) hipLaunchKernelGGL((a_theradj<24, 16>), dim3(ttot), dim3(64 * 16), 0, st, ai, d_tmap, cur);
             else if (tay == 16) hipLaunchKernelGGL((a_theradj<16, 16>), dim3(ttot), dim3(64 * 16), 0, st, ai, d_tmap, cur);
-            else hipLaunchKernelGGL((a_theradj<8, 16>), dim3(ttot), dim3(64 * 16), 0, st, ai, d_tmap, cur);
+            else hipLaunchKernelGGL((a_theradj<4, 16>), dim3(ttot), dim3(64 * 16), 0, st, ai, d_tmap, cur);
             hipLaunchKernelGGL(a_lb<S>, grid, blk, 0, st, ai, d_amap, k, cur);
             hipLaunchKernelGGL(a_final<S>, grid, blk, 0, st, ai, d_amap, k, cur, t >= 1 ? wq : 0.0,
                                t > t0 ? 1 : 0);
