@@ -53,7 +53,7 @@ struct TileShape {
     int ty, nw;
 };
 constexpr int NSHAPE_A = 4, NSHAPE_B = 4;
-constexpr TileShape kShapeA[NSHAPE_A] = {{8, 8}, {4, 4}, {12, 4}, {4, 2}};
+constexpr TileShape kShapeA[NSHAPE_A] = {{4, 4}, {8, 8}, {12, 4}, {4, 2}};
 constexpr TileShape kShapeB[NSHAPE_B] = {{24, 16}, {40, 16}, {16, 16}, {8, 8}};
 
 // 1/x from the hardware reciprocal estimate (relative error near 2^-23)

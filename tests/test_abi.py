@@ -131,7 +131,7 @@ def test_tile_shape_tables():
         assert w + 2 == 64 and h % nw == 0 and 1 <= nw <= 16
     for w, h, nw in th:
         assert w + 8 == 64 and h >= 1 and 1 <= nw <= 16
-    assert lb[0] == (62, 8, 8) and th[0] == (56, 24, 16)
+    assert lb[0] == (62, 4, 4) and th[0] == (56, 24, 16)
 
 
 def test_tile_calls_reject_bad_arguments():
