@@ -36,18 +36,18 @@ ALG_BYTES_LB = {"f32": 72, "f64": 144}
 # 2.0, WRITE_SIZE 1048576 KiB -> factor 1.0).  Valid for the kernel source
 # whose hash is recorded and the same LB tile shape; null otherwise.
 MEASURED_TRAFFIC = {
-    "source_hash": "cff896f2eee886a6",
+    "source_hash": "ad841aa4fd4647fd",
     "fetch_factor": 1048576.0 / 524297.8,
     "write_factor": 1048576.0 / 1048576.0,
     "k_lb": {
         "large_1024x512_fp32": [
-            {"tiles_lb": [62, 12, 4], "fetch_kib": 10839.1, "write_kib": 24673.9},
-            {"tiles_lb": [62, 8, 4], "fetch_kib": 10745.8, "write_kib": 24627.7},
+            {"tiles_lb": [62, 4, 4], "fetch_kib": 10728.9, "write_kib": 24620.1},
+            {"tiles_lb": [62, 8, 8], "fetch_kib": 10662.2, "write_kib": 24654.0},
         ],
         "large_4096x2048_fp32": [
-            {"tiles_lb": [62, 12, 4], "fetch_kib": 178513.6, "write_kib": 398032.0},
-            {"tiles_lb": [62, 6, 2], "fetch_kib": 169547.3, "write_kib": 397648.0},
-            {"tiles_lb": [62, 8, 4], "fetch_kib": 171422.7, "write_kib": 395781.3},
+            {"tiles_lb": [62, 4, 4], "fetch_kib": 166719.5, "write_kib": 395665.0},
+            {"tiles_lb": [62, 8, 8], "fetch_kib": 171729.4, "write_kib": 397422.5},
+            {"tiles_lb": [62, 12, 4], "fetch_kib": 178490.3, "write_kib": 397972.0},
         ],
     },
 }
