@@ -147,11 +147,22 @@ def test_save_load_resume_bitwise():
     for k in ("f", "T"):
         assert np.array_equal(a[k], b[k])
     assert qa["q_mean"] == qb["q_mean"] and qa["n_samples"] == qb["n_samples"] == 127
+    # refused blobs: a flipped payload byte (checksum), cut short, cut to the
+    # header, a foreign magic, and a blob of a lattice of another shape; the
+    # state stays as it was
     bad = bytearray(blob)
     bad[len(bad) // 2] ^= 0xFF
-    with pytest.raises(L.LbbError) as e:
-        d.load(bytes(bad))
-    assert e.value.code == L.LBB_EINVAL
+    foreign_magic = bytearray(blob)
+    foreign_magic[0] ^= 0x01
+    other = L.Domain(L.Params(nx=PLAIN.nx + 1, ny=PLAIN.ny, precision=L.FP32, liquid_rows=PLAIN.liquid_rows))
+    foreign_shape = other.save()
+    other.close()
+    for broken in (bytes(bad), blob[:-1], blob[:64], blob[:8], bytes(foreign_magic), foreign_shape):
+        with pytest.raises(L.LbbError) as e:
+            d.load(broken)
+        assert e.value.code == L.LBB_EINVAL
+    c = d.fields()
+    assert d.t == 127 and all(np.array_equal(b[k], c[k]) for k in ("f", "T"))
 
 
 def test_superheat_step_and_wettability_change():
