@@ -32,22 +32,22 @@ ALG_BYTES_LB = {"f32": 72, "f64": 144}
 # HBM traffic of the LB launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
 # (KiB per dispatch, mean over the dispatches of a --profile run with the
 # given tiles), each scaled by what the same counter reads for an elementwise
-# kernel that reads 1 GiB and writes 1 GiB (FETCH_SIZE 524297.8 KiB -> factor
+# kernel that reads 1 GiB and writes 1 GiB (FETCH_SIZE 524297.7 KiB -> factor
 # 2.0, WRITE_SIZE 1048576 KiB -> factor 1.0).  Valid for the kernel source
 # whose hash is recorded and the same LB tile shape; null otherwise.
 MEASURED_TRAFFIC = {
-    "source_hash": "ad841aa4fd4647fd",
-    "fetch_factor": 1048576.0 / 524297.8,
+    "source_hash": "5841db5404206de4",
+    "fetch_factor": 1048576.0 / 524297.7,
     "write_factor": 1048576.0 / 1048576.0,
     "k_lb": {
         "large_1024x512_fp32": [
-            {"tiles_lb": [62, 4, 4], "fetch_kib": 10728.9, "write_kib": 24620.1},
-            {"tiles_lb": [62, 8, 8], "fetch_kib": 10662.2, "write_kib": 24654.0},
+            {"tiles_lb": [62, 4, 4], "fetch_kib": 10718.0, "write_kib": 24620.1},
+            {"tiles_lb": [62, 8, 8], "fetch_kib": 10650.1, "write_kib": 24653.6},
         ],
         "large_4096x2048_fp32": [
-            {"tiles_lb": [62, 4, 4], "fetch_kib": 166719.5, "write_kib": 395665.0},
-            {"tiles_lb": [62, 8, 8], "fetch_kib": 171729.4, "write_kib": 397422.5},
-            {"tiles_lb": [62, 12, 4], "fetch_kib": 178490.3, "write_kib": 397972.0},
+            {"tiles_lb": [62, 4, 4], "fetch_kib": 166704.1, "write_kib": 395668.4},
+            {"tiles_lb": [62, 8, 8], "fetch_kib": 171677.0, "write_kib": 397357.0},
+            {"tiles_lb": [62, 12, 4], "fetch_kib": 178478.2, "write_kib": 398111.1},
         ],
     },
 }
