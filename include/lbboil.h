@@ -87,6 +87,7 @@ typedef struct lbb_params {
                                 fluid row, psi(i,-1) = psi(i,1): F_m there is
                                 tangential; buoyancy still skips the wall rows.
                                 0 (default): no fluid-fluid force on them.
+                                No effect with periodic_y (no walls).
                                 lbb_adjoint refuses 1 (LBB_EUNSUPPORTED)       */
     int32_t reserved;        /* must be 0                                      */
 } lbb_params;
