@@ -538,7 +538,10 @@ __global__ __launch_bounds__(64 * TAW) void a_theradj(const AdjInst *__restrict_
             lt[m] += gT;
         }
         if (k == 0) break;
-        __syncthreads();  // every read of the planes this stage overwrites is done
+        // plane op is read by no stage-k node (stage k reads planes gp, k and
+        // 4), and its earlier contents (T_4 for k = 2, T_3 for k = 1) were last
+        // read before the previous stage's closing barrier: the writes need no
+        // barrier of their own before them
 #pragma unroll
         for (int m = 0; m < RPW; ++m) {
             const int r = wv + TAW * m;
