@@ -568,6 +568,15 @@ static int density(orc_state *s)
 }
 
 /* O3 psi = sqrt(2 (p_EOS - rho c_s^2) / (G c^2)) (Sec. 2, Eq. (21)) */
+static double round_storage(int bits, double x)
+{
+    if (bits == 0) return x;
+    if (bits == 24) return (double)(float)x;
+    const double c = ldexp(1.0, 53 - bits) + 1.0;
+    const double y = c * x;
+    return y - (y - x);
+}
+
 static int pseudopotential(orc_state *s)
 {
     const orc_params *p = &s->p;
@@ -578,6 +587,7 @@ static int pseudopotential(orc_state *s)
         double r = 2.0 * (pe - s->rho[c] / 3.0) / p->G;
         if (!(r >= 0) || !isfinite(r)) bad = 1;
         s->psi[c] = sqrt(r);
+        if (s->store_bits != 24) s->psi[c] = round_storage(s->store_bits, s->psi[c]);
     }
     return bad ? ORC_ENONFINITE : ORC_OK;
 }
@@ -661,6 +671,7 @@ static int thermal_rk4(orc_state *s)
         for (int i = 0; i < nx; ++i) {
             size_t c = (size_t)j * nx + i;
             s->T[c] = s->T[c] + s->acc[c] / 6.0;
+            if (s->store_bits != 24) s->T[c] = round_storage(s->store_bits, s->T[c]);
             if (!(s->T[c] > 0) || !isfinite(s->T[c])) bad = 1;
         }
     }
@@ -760,7 +771,7 @@ static int one_step(orc_state *s)
                 double fl[9], fp[9];
                 for (int a = 0; a < 9; ++a) fl[a] = F_AT(s, a, c);
                 orc_collide_site(p, fl, s->rho[c], s->vx[c], s->vy[c], s->Fx[c], s->Fy[c], s->Q[c], fp);
-                for (int a = 0; a < 9; ++a) s->fpost[(size_t)a * n + c] = fp[a];
+                for (int a = 0; a < 9; ++a) s->fpost[(size_t)a * n + c] = round_storage(s->store_bits, fp[a]);
             }
         }
     }
@@ -866,6 +877,21 @@ void orc_set_heater(orc_state *s, const double *T_bottom)
 }
 
 void orc_set_wettability(orc_state *s, double Gw_bottom) { s->p.Gw_bottom = Gw_bottom; }
+
+/* Rounding model (the arithmetic stays FP64).  bits = 24: the post-collision
+ * populations are rounded to the nearest float before they stream (FP32
+ * storage of f).  1 <= bits <= 52: the post-collision populations, the
+ * pseudopotential and the new temperature are rounded to `bits` significant
+ * bits by Veltkamp's splitting, x -> c - (c - x) with c = (2^(53-bits) + 1) x:
+ * at 52, about one extra FP64 rounding of every quantity a step hands from
+ * one stage to the next.  0 turns the model off (the default).  Used to
+ * measure how far rounding of that size alone moves the trajectory. */
+int orc_set_storage_rounding(orc_state *s, int bits)
+{
+    if (bits < 0 || bits > 52) return ORC_EINVAL;
+    s->store_bits = bits;
+    return ORC_OK;
+}
 
 int64_t orc_state_size(const orc_state *s) { return (int64_t)10 * s->p.nx * s->p.ny + s->p.nx + 4; }
 

@@ -99,6 +99,11 @@ void orc_heat_flux(const orc_state *s, double *q_now, double *q_sum, int64_t *n_
 void orc_reset_average(orc_state *s);
 void orc_set_heater(orc_state *s, const double *T_bottom);
 void orc_set_wettability(orc_state *s, double Gw_bottom);
+/* Rounding model: 24 rounds the post-collision populations to FP32 each step
+ * (FP32 storage of f); 1..52 rounds the post-collision populations, psi and
+ * the new T to that many significant bits (about one extra FP64 rounding of
+ * each at 52); 0 turns it off (the default).  The arithmetic stays FP64. */
+int orc_set_storage_rounding(orc_state *s, int bits);
 const char *orc_last_error(void);
 int orc_num_threads(void);
 void orc_constants(const orc_state *s, double *Tc, double *kappa, double *Ts);

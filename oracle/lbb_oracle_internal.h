@@ -20,6 +20,8 @@ struct orc_state {
     double *ws[7];               /* stencil scratch of the RK4 stages */
     double q_now, q_sum;
     int64_t n_samples;
+    int store_bits;              /* 0, or the significant bits the post-collision
+                                    populations are rounded to each step */
 };
 
 #endif

@@ -19,8 +19,17 @@ class OracleError(RuntimeError):
         self.code = code
 
 
-def _load():
+def _stale() -> bool:
+    """True when the library is missing or older than a C source or header."""
     if not os.path.exists(_LIB_PATH):
+        return True
+    t = os.path.getmtime(_LIB_PATH)
+    return any(os.path.getmtime(os.path.join(_HERE, n)) > t
+               for n in os.listdir(_HERE) if n.endswith((".c", ".h")))
+
+
+def _load():
+    if _stale():
         from . import build as _build
 
         _build.build()
@@ -115,6 +124,8 @@ lib.orc_heat_flux.argtypes = [C.c_void_p, _pd, _pd, C.POINTER(_i64), _pd]
 lib.orc_reset_average.argtypes = [C.c_void_p]
 lib.orc_set_heater.argtypes = [C.c_void_p, _pd]
 lib.orc_set_wettability.argtypes = [C.c_void_p, _d]
+lib.orc_set_storage_rounding.restype = C.c_int
+lib.orc_set_storage_rounding.argtypes = [C.c_void_p, C.c_int]
 lib.orc_last_error.restype = C.c_char_p
 lib.orc_num_threads.restype = C.c_int
 lib.orc_constants.argtypes = [C.c_void_p, _pd, _pd, _pd]
@@ -295,6 +306,16 @@ class State:
 
     def set_wettability(self, Gw):
         lib.orc_set_wettability(self._h, float(Gw))
+
+    def store_bits(self, bits: int):
+        """Rounding model: bits = 24 rounds the post-collision populations to
+        FP32 every step (FP32 storage of f); 1..52 rounds the post-collision
+        populations, psi and the new T to `bits` significant bits; 0 turns it
+        off.  The arithmetic stays FP64."""
+        rc = lib.orc_set_storage_rounding(self._h, int(bits))
+        if rc != 0:
+            raise OracleError(rc, "bits must lie in 0..52")
+        return self
 
     def adjoint(self, n_steps: int, K: int = 0):
         """J = mean of q over n_steps from the current state (unchanged), and

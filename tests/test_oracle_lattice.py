@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from paper_1501_03857_amd import workloads as WL
 
 EX, EY, W, WPSI, M = O.lattice()
 E = np.stack([EX, EY], axis=1).astype(float)
@@ -209,3 +210,41 @@ def test_interaction_force_on_quadratic_psi(k):
     assert np.all(Fx[[0, -1]] == 0) and np.all(Fy[[0, -1]] == 0) and np.all(Q[[0, -1]] == 0)
     # Q equals |F_m|^2 / psi^2 wherever F_m is applied
     assert np.allclose(Q[sl], ((Fx ** 2 + Fy ** 2) / psi ** 2)[sl], rtol=1e-12)
+
+
+@pytest.mark.parametrize("bits", [24, 52, 40])
+def test_storage_rounding_model(bits):
+    """The rounding model behind the parity bars of v and q: after a step of a
+    fully periodic box (every population streamed, none completed by a wall
+    rule) each stored population has at most `bits` significant bits (24:
+    exactly a float), and so has T when the model also rounds psi and T
+    (bits != 24).  The state stays within a small multiple of that rounding
+    of the unrounded one: a population rounding alone (24) moves f by at
+    most half a unit in the last kept place; rounding psi as well moves F,
+    and f through it, by a few tens of those units."""
+    tc = O.Tc(2.0 / 49.0, 2.0 / 21.0, 1.0)
+    rv, rl, _ = O.maxwell(2.0 / 49.0, 2.0 / 21.0, 1.0, 0.344, 0.86 * tc)
+    p = O.Params(nx=20, ny=12, rho_L=rl, rho_V=rv, periodic_y=1)
+    rho0 = WL.layered_density(p.nx, p.ny, rl, rv, 6, 1e-2, seed=3)
+    y, x = np.mgrid[0:p.ny, 0:p.nx]
+    T0 = 0.86 * tc * (1 + 0.01 * np.sin(2 * np.pi * x / p.nx))
+    a = O.State(p, rho0, T0=T0).step(1).fields()
+    bf = O.State(p, rho0, T0=T0).store_bits(bits).step(1).fields()
+    b = bf["f"]
+
+    def kept(v, n):
+        m, _ = np.frexp(v)
+        scaled = np.ldexp(m, n)
+        return np.array_equal(scaled, np.round(scaled))
+
+    assert kept(b, bits)
+    if bits == 24:
+        assert np.array_equal(b, b.astype(np.float32).astype(np.float64))
+        assert np.max(np.abs(b - a["f"]) / np.abs(a["f"])) <= 2.0 ** -bits * 1.0001
+        assert np.array_equal(bf["T"], a["T"])
+    else:
+        assert kept(bf["T"], bits)
+        assert np.max(np.abs(b - a["f"]) / np.abs(a["f"])) <= 2.0 ** -(bits - 6)
+    assert np.max(np.abs(b - a["f"])) > 0
+    with pytest.raises(O.OracleError):
+        O.State(p, rho0).store_bits(53)
