@@ -293,3 +293,36 @@ def test_contact_angles_match_paper(golden):
         assert abs(angles[-1] - theta) < 1.5, (Gw, angles[-1], theta)
         assert abs(rho.sum() / m0 - 1) < 0.02  # walls do not create mass
     assert angles[0] < angles[1] < angles[2]
+
+
+@pytest.mark.parametrize("which", ["liquid", "vapour", "metastable_vapour", "metastable_liquid"])
+def test_shear_wave_decays_at_the_paper_viscosity(which):
+    """Sec. 3.1 gives nu_L = 0.1 and nu_V = 0.5/3, with nu = (tau - 1/2)/3 in
+    lattice units; between the two, tau_nu is linear in rho.  A transverse
+    wave u_x = U sin(k y) in a uniform fluid (no interaction force, since a
+    uniform psi has no gradient) decays as exp(-nu k^2 t) up to O(k^2) lattice
+    corrections.  The decay rate measured on the oracle pins the viscous
+    relaxation rate at the coexistence densities and at two metastable
+    densities between them (rho = 0.7 and 5.5, outside the spinodal band, so
+    the uniform state stays uniform)."""
+    tc, rv, rl = _coex()
+    rho0 = {"liquid": rl, "vapour": rv, "metastable_vapour": 0.7, "metastable_liquid": 5.5}[which]
+    nu_L, nu_V = 0.1, 0.5 / 3.0
+    tau_L, tau_V = 3 * nu_L + 0.5, 3 * nu_V + 0.5
+    nu = (tau_V + (rho0 - rv) * (tau_L - tau_V) / (rl - rv) - 0.5) / 3.0
+    ny = 96
+    p = Params(nx=4, ny=ny, rho_L=rl, rho_V=rv, nu_L=nu_L, nu_V=nu_V, periodic_y=1, g=0.0,
+               thermal_mode=ISOTHERMAL)
+    k = 2 * np.pi / ny
+    y = np.arange(ny)
+    s = State(p, np.full((ny, 4), rho0), ux0=1e-4 * np.sin(k * y)[:, None] * np.ones((1, 4)))
+    ts, amps = [], []
+    for _ in range(30):
+        s.step(100)
+        fl = s.fields()
+        amps.append(2.0 / ny * np.sum(fl["ux"][:, 0] * np.sin(k * y)))
+        ts.append(s.t)
+    rate = -np.polyfit(np.array(ts[2:]), np.log(np.array(amps[2:])), 1)[0]
+    assert abs(rate / (nu * k * k) - 1.0) < 5e-4, (rate / k / k, nu)
+    # the density stayed uniform (a transverse wave does not compress)
+    assert np.ptp(fl["rho"]) < 1e-10 * rho0
