@@ -49,10 +49,14 @@ def saturation(a: float = PAPER_A, b: float = PAPER_B, R: float = PAPER_R, omega
 
 
 def paper_case(dT: float, Gw: float = 0.0, precision: int = L.FP32, seed: int = 1,
-               nx: int = PAPER_NX, ny: int = PAPER_NY):
+               nx: int = PAPER_NX, ny: int = PAPER_NY, coexistence: Optional[Tuple[float, float]] = None):
     """Params, bottom-wall temperature and initial density of the paper's pool
-    at wall superheat dT (lattice units) and bottom wall strength Gw."""
+    at wall superheat dT (lattice units) and bottom wall strength Gw.
+    `coexistence` = (rho_V, rho_L) replaces the library's Maxwell densities
+    (the initial layers and the ends of tau_nu(rho))."""
     Ts, rv, rl = saturation()
+    if coexistence is not None:
+        rv, rl = coexistence
     liquid = int(round(PAPER_LIQUID_ROWS * (ny - 1) / (PAPER_NY - 1)))
     p = L.Params(nx=nx, ny=ny, precision=precision, liquid_rows=liquid, a=PAPER_A, b=PAPER_B, R=PAPER_R,
                  omega=PAPER_OMEGA, sigma=1.2, g=3e-5, Gw_bottom=Gw, rho_L=rl, rho_V=rv, seed=seed)
@@ -95,7 +99,8 @@ def boiling_curve(superheats: Sequence[float] = PAPER_SUPERHEATS, wall_strengths
                   t_end: int = 60000, t_avg: int = 30000, t_step: int = PAPER_T_STEP, dT0: float = PAPER_DT0,
                   sample_every: int = 200, probe: Sequence[Tuple[float, float]] = (),
                   precision: int = L.FP32, seed: int = 1, nx: int = PAPER_NX, ny: int = PAPER_NY,
-                  tune_steps: int = 10, log=None) -> Tuple[List[BoilingRun], dict]:
+                  tune_steps: int = 10, log=None, coexistence: Optional[Tuple[float, float]] = None,
+                  inspect=None) -> Tuple[List[BoilingRun], dict]:
     """Every (dT, Gw) pair as one member of a single batch.
 
     Protocol (Sec. 3.2): members whose superheat exceeds dT0 heat at dT0 until
@@ -103,13 +108,15 @@ def boiling_curve(superheats: Sequence[float] = PAPER_SUPERHEATS, wall_strengths
     superheat throughout.  q(t) is sampled every `sample_every` steps and
     q_mean is the library's average over the last t_avg steps.  Members listed
     in `probe` as (dT, Gw) also record the top-wall-centre pressure.
+    `coexistence` is passed to paper_case; `inspect(batch, cases)`, if given,
+    is called on the batch after the last step, before it is released.
     Returns the runs and the wall time of the stepping (read-backs included)
     with the lattice-update rate it amounts to."""
     cases = [(dT, Gw) for Gw in wall_strengths for dT in superheats]
     params, Tbs, rhos = [], [], []
     Ts, _, _ = saturation()
     for dT, Gw in cases:
-        p, Tb, rho0 = paper_case(min(dT, dT0) if t_step > 0 else dT, Gw, precision, seed, nx, ny)
+        p, Tb, rho0 = paper_case(min(dT, dT0) if t_step > 0 else dT, Gw, precision, seed, nx, ny, coexistence)
         params.append(p)
         Tbs.append(Tb)
         rhos.append(rho0)
@@ -151,6 +158,8 @@ def boiling_curve(superheats: Sequence[float] = PAPER_SUPERHEATS, wall_strengths
                 log(f"[boiling] t = {t}")
         hf = b.heat_flux()
         seconds = time.perf_counter() - wall0
+        if inspect is not None:
+            inspect(b, cases)
         updates = float(t_end) * sum(p.nx * p.ny for p in params)
         info = {"members": len(cases), "nx": nx, "ny": ny, "steps": t_end, "seconds": seconds,
                 "mlups": updates / seconds / 1e6, "tiles": list(b.domain(0).tiles)}

@@ -15,16 +15,31 @@ agreement only):
 import numpy as np
 import pytest
 
+import oracle as O
 from paper_1501_03857_amd import experiments as E
+from paper_1501_03857_amd import lbboil as L
+from parity_utils import STORE_FACTOR, Twin, compare_read, normwise
 
 pytestmark = pytest.mark.gpu
+
+SEEDS = (1, 2)
 
 
 @pytest.fixture(scope="module")
 def curve():
-    print("[gpu-case] boiling curves: 33 x 600x151, 60000 steps", flush=True)
-    runs, info = E.boiling_curve(probe=[(0.0137, 0.0), (0.0165, 0.0)])
-    print(f"[gpu-case] {info}", flush=True)
+    """The boiling curves for two noise seeds; q_mean is averaged over them
+    (the regime checks are on the average, the pressure probe on seed 1)."""
+    per_seed = []
+    for seed in SEEDS:
+        print(f"[gpu-case] boiling curves: 33 x 600x151, 60000 steps, seed {seed}", flush=True)
+        runs, info = E.boiling_curve(probe=[(0.0137, 0.0), (0.0165, 0.0)] if seed == SEEDS[0] else (), seed=seed)
+        print(f"[gpu-case] {info}", flush=True)
+        per_seed.append(runs)
+    runs = per_seed[0]
+    for k, r in enumerate(runs):
+        qs = [rs[k].q_mean for rs in per_seed]
+        assert all(rs[k].dT == r.dT and rs[k].Gw == r.Gw for rs in per_seed)
+        r.q_mean = float(np.mean(qs))
     reg = E.regimes(runs)
     for Gw, r in reg.items():
         print(f"[gpu-case] G_w {Gw}: " + " ".join(f"{d}:{q:.3e}" for d, q in zip(r["dT"], r["q_mean"])), flush=True)
@@ -37,11 +52,11 @@ def _q(reg, Gw, dT):
 
 
 def test_boiling_curve_regimes(curve):
-    """Thresholds leave room for the run-to-run spread of these chaotic runs:
-    any change of rounding moves individual bubbles, and near the transition
-    a 30000-step average still varies by some 20% (the q at 0.035 over the
-    critical heat flux has ranged over 0.33-0.47, 0.47-0.60 and 0.10-0.16 for
-    the three walls)."""
+    """The runs are chaotic (any change of rounding moves individual
+    bubbles), so q_mean is the 30000-step average of two noise seeds.  Past
+    the critical heat flux the flux must fall to film boiling: at 0.035 it
+    is below 0.6 of the critical heat flux on every wall (single-seed runs
+    have given 0.33-0.47, 0.47-0.60 and 0.10-0.16 for the three walls)."""
     _, reg = curve
     drops = []
     for Gw, r in reg.items():
@@ -49,9 +64,9 @@ def test_boiling_curve_regimes(curve):
         assert _q(reg, Gw, 0.008) < 0.25 * chf, (Gw, "boiling at the lowest superheat")
         assert 0.019 <= r["dT_chf"] <= 0.029, (Gw, r["dT_chf"])
         drops.append(_q(reg, Gw, 0.035) / chf)
-        assert drops[-1] < 0.75, (Gw, "no drop towards film boiling")
         assert r["dT_hmax"] < r["dT_chf"], (Gw, r["dT_hmax"], r["dT_chf"])
-    assert np.mean(drops) < 0.6, drops
+    print(f"[gpu-case] q(0.035) / q_chf per wall: {drops}", flush=True)
+    assert max(drops) < 0.6, drops
 
 
 def test_wettability_trends(curve):
@@ -67,3 +82,54 @@ def test_top_wall_pressure_rises(curve):
     before = p[0.0137].p_top[p[0.0137].t <= 20000].mean()
     late = {d: r.p_top[r.t > 40000].mean() for d, r in p.items()}
     assert late[0.0137] > before and late[0.0165] > late[0.0137], (before, late)
+
+
+def test_boiling_curve_batch_matches_oracle_paper_preset():
+    """The boiling-curve harness's batch path on the paper's preset (Sec. 3.1:
+    600 x 151 wet-node rows, a = 3/49, sigma = 1.2, liquid below y = 90,
+    g = 3e-5) in FP64, with the superheat-step protocol of Sec. 3.2 shortened:
+    members above 0.0137 heat at 0.0137 until t = 150, then at their own
+    superheat; the average restarts at t = 200; 300 steps.  Four members (two
+    superheats x two wall strengths) in one batch against the oracle run of
+    the same protocol: every field and the heat flux at the end, and q(t) at
+    every sample, at the FP64 bars of the parity tests (1e-12; v and q
+    against the oracle's FP64 rounding twin)."""
+    tc = O.Tc(E.PAPER_A, E.PAPER_B, E.PAPER_R)
+    Ts = 0.86 * tc
+    rv, rl, _ = O.maxwell(E.PAPER_A, E.PAPER_B, E.PAPER_R, E.PAPER_OMEGA, Ts)
+    superheats, walls = (0.01, 0.025), (0.0, 0.105)
+    t_step, t_reset, t_end, every = 150, 200, 300, 50
+    got = {}
+
+    def grab(b, cases):
+        for i, c in enumerate(cases):
+            got[c] = (b.domain(i).fields(), b.domain(i).heat_flux())
+
+    print("[gpu-case] boiling harness 4 x 600x151 fp64 vs oracle, 300 steps", flush=True)
+    runs, _ = E.boiling_curve(superheats, walls, t_end=t_end, t_avg=t_end - t_reset, t_step=t_step,
+                              sample_every=every, precision=L.FP64, tune_steps=0, coexistence=(rv, rl),
+                              inspect=grab)
+    assert len(runs) == 4 and list(runs[0].t) == list(range(every, t_end + 1, every))
+    for r in runs:
+        p, _, rho0 = E.paper_case(min(r.dT, E.PAPER_DT0), r.Gw, L.FP64, coexistence=(rv, rl))
+        op = O.Params(nx=p.nx, ny=p.ny, a=p.a, b=p.b, R=p.R, omega=p.omega, Ts_over_Tc=p.Ts_over_Tc,
+                      sigma=p.sigma, g=p.g, Gw_bottom=p.Gw_bottom, rho_L=rl, rho_V=rv)
+        Tb0 = np.full(p.nx, Ts + min(r.dT, E.PAPER_DT0))
+        o = Twin(O.State(op, rho0, T_bottom=Tb0), O.State(op, rho0, T_bottom=Tb0).store_bits(52))
+        t, q_trace = 0, []
+        for target in r.t:
+            if t == t_step and r.dT > E.PAPER_DT0:
+                o.set_heater(np.full(p.nx, Ts + r.dT))
+            if t == t_reset:
+                o.reset_average()
+            o.step(int(target) - t)
+            t = int(target)
+            q_trace.append((o.heat_flux()["q_now"], o.twin_heat_flux()["q_now"]))
+        fg, hg = got[(r.dT, r.Gw)]
+        errs, bad = compare_read(o, fg, hg, 1e-12, label=f"dT={r.dT} Gw={r.Gw} ")
+        qo, qt = np.array(q_trace).T
+        err_trace, twin_trace = normwise(r.q, qo), normwise(qt, qo)
+        print(f"[parity] q_trace={err_trace:.3g} twin:q_trace={twin_trace:.3g}", flush=True)
+        assert not bad, (r.dT, r.Gw, errs)
+        assert err_trace <= max(1e-12, STORE_FACTOR * twin_trace), (err_trace, twin_trace)
+        assert hg["n_samples"] == o.heat_flux()["n_samples"] == t_end - t_reset

@@ -1,10 +1,13 @@
 """GPU (HIP, gfx950) vs CPU oracle parity of the coupled time step.
 
-Every comparison feeds both sides the same seeded inputs and compares the
-fields normwise (max |gpu - oracle| / max |oracle| per field):
+Every comparison feeds both sides the same seeded inputs and compares every
+field, and on lattices with walls the heat flux (q_local, q_now, q_mean),
+normwise: max |gpu - oracle| / max |oracle| per quantity.
   FP64 storage: <= 1e-12 over the horizon (rounding-order differences only);
-  FP32 storage: <= 1e-5 (FP32 f and T, FP64 EOS and reductions).
-Sizes span several LB tiles (62x12) and thermal tiles (56x24) with ragged
+  FP32 storage: rho, T, f <= 1e-5 (FP32 f and T, FP64 EOS and reductions);
+      v and q <= max(1e-5, 4 x the error that FP32 storage of the
+      populations alone makes in the oracle, measured on the same run).
+Sizes span several LB tiles (62x4) and thermal tiles (56x24) with ragged
 tails in x and y.
 """
 import json
@@ -16,7 +19,7 @@ import pytest
 import oracle as O
 from paper_1501_03857_amd import lbboil as L
 from paper_1501_03857_amd import workloads as WL
-from parity_utils import compare, heat_flux_scale, make_pair, normwise
+from parity_utils import compare, make_pair
 
 pytestmark = pytest.mark.gpu
 
@@ -36,13 +39,7 @@ def test_plain_fp64_matches_oracle(steps):
     d.step(steps)
     errs, bad = compare(o, d, TOL64)
     assert not bad, errs
-    ho, hd = o.heat_flux(), d.heat_flux()
-    assert hd["n_samples"] == ho["n_samples"] == steps
-    qs = heat_flux_scale(o)
-    assert abs(hd["q_now"] - ho["q_now"]) <= TOL64 * qs
-    if steps:
-        assert abs(hd["q_mean"] - ho["q_mean"]) <= TOL64 * qs
-    assert normwise(hd["q_local"], ho["q_local"], qs) <= TOL64
+    assert d.heat_flux()["n_samples"] == o.heat_flux()["n_samples"] == steps
 
 
 def test_plain_fp32_matches_oracle():
@@ -52,7 +49,6 @@ def test_plain_fp32_matches_oracle():
     d.step(200)
     errs, bad = compare(o, d, TOL32)
     assert not bad, errs
-    assert abs(d.heat_flux()["q_mean"] / o.heat_flux()["q_mean"] - 1) < 1e-4
 
 
 @pytest.mark.parametrize("nx,ny", [(100, 37), (3, 4), (65, 9), (130, 17), (300, 77)])
@@ -184,7 +180,6 @@ def test_superheat_step_and_wettability_change():
     errs, bad = compare(o, d, TOL64)
     assert not bad, errs
     assert d.heat_flux()["n_samples"] == 90
-    assert abs(d.heat_flux()["q_mean"] - o.heat_flux()["q_mean"]) <= TOL64 * heat_flux_scale(o)
 
 
 def test_invalid_state_is_reported_and_recoverable():
@@ -222,7 +217,6 @@ def test_large_fp32_matches_oracle_200_steps():
     o.step(200)
     errs, bad = compare(o, d, TOL32)
     assert not bad, errs
-    assert abs(d.heat_flux()["q_mean"] / o.heat_flux()["q_mean"] - 1) < 1e-4
 
 
 def test_large_fp32_long_run_heat_flux_within_2_percent_of_oracle():
@@ -347,5 +341,3 @@ def test_parameter_variants_match_oracle(variant):
     d.step(150)
     errs, bad = compare(o, d, TOL64)
     assert not bad, errs
-    ho, hd = o.heat_flux(), d.heat_flux()
-    assert abs(hd["q_mean"] - ho["q_mean"]) <= TOL64 * heat_flux_scale(o)
