@@ -186,6 +186,7 @@ struct DevParams {
     // scalar FP64 unit, so each wave would otherwise divide in its vector ALU)
     double R_cv, a_cv, inv_cv;    // R / c_v, a / c_v, 1 / c_v
     double k1k, k2_Tc;            // kappa (1 + kappa), kappa^2 / T_c
+    double k1k_rsTc;              // kappa (1 + kappa) / sqrt(T_c)
 };
 
 // Device-resident scalars of one domain.  tA is the state index seen by the
@@ -477,7 +478,11 @@ __device__ __forceinline__ void collide(const DevParams &P, double f[9], double 
     // rho* = rho (s_rho drops out: m_eq,rho = rho and S_rho = 0)
 
     // f* = M^{-1} m* with M^{-1} = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
-    const double r9 = rho * (1.0 / 9.0);
+    // rho/9 rounded once: 1/9 as its nearest double plus the remainder.
+    // rho * fl(1/9) alone is biased (fl(1/9) < 1/9), and the nine outputs
+    // sum to 9 r9, so every node would lose a fixed 5.6e-17 rho of mass per
+    // step; this product gives the correctly rounded quotient instead.
+    const double r9 = fma(rho, 1.0 / 9.0, rho * 0x1.c71c71c71c71cp-58);
     const double e36 = e_s * (1.0 / 36.0), z36 = z_s * (1.0 / 36.0);
     const double jx6 = jx_s * (1.0 / 6.0), jy6 = jy_s * (1.0 / 6.0);
     const double qx12 = qx_s * (1.0 / 12.0), qy12 = qy_s * (1.0 / 12.0);
@@ -740,11 +745,15 @@ __global__ __launch_bounds__(64 * NWA) void k_lb(const Inst *__restrict__ insts,
 
 // ---------------------------------------------------------------------------
 // Thermal step: RK4 of Eq. (18) with rho, v frozen; heat-flux partials.
-//   K = -(ax d_x T + ay d_y T) + chi lap T - cw T + cq T phi'(T)
-// with ax = vx - chi d_x rho / rho, ay likewise, w = div v / (rho c_v),
-// cw = A(rho) w, cq = B(rho) w, A = rho R/(1 - b rho),
-// B = a rho^2/(1 + 2 b rho - b^2 rho^2), so that (dp/dT)_rho = A - B phi'(T)
-// and T phi'(T) = kappa^2 T/T_c - kappa (1 + kappa) sqrt(T/T_c).
+//   K = -(ax d_x T + ay d_y T) + chi lap T + c1 T + c2 sqrt(T)
+// with ax = vx - chi d_x rho / rho, ay likewise, and the pressure-work term
+// -w T (dp/dT)_rho, w = div v / (rho c_v), written through
+// (dp/dT)_rho = A - B phi'(T), A = rho R/(1 - b rho),
+// B = a rho^2/(1 + 2 b rho - b^2 rho^2) and
+// T phi'(T) = kappa^2 T/T_c - kappa (1 + kappa) sqrt(T/T_c):
+//   c1 = w (-A + B kappa^2/T_c),  c2 = -w B kappa (1 + kappa)/sqrt(T_c),
+// both formed once per node in FP64 (rho is frozen over the step) and
+// rounded once to the stage type; each stage then needs one square root.
 // Layout: the tile (TXB x TY) with its halo of HB nodes is 64 columns wide,
 // so lane = column and each of the NWB waves owns every NWB-th row of the
 // region; stage k is evaluated on the region shrunk by k+1 nodes.  The
@@ -868,12 +877,12 @@ __global__ __launch_bounds__(64 * NWB) void k_thermal(const Inst *__restrict__ i
             const C chi_rho = (C)(P.chi * D1 * D2 * inv);
             cfr[0][m] = uc - chi_rho * drx;
             cfr[1][m] = X[2][r][lane] - chi_rho * dry;
-            cfr[2][m] = (C)(P.R_cv * div * (rho * D2 * inv));
-            cfr[3][m] = (C)(P.a_cv * rho * div * (rho * D1 * inv));
+            const double Aw = P.R_cv * div * (rho * D2 * inv), Bw = P.a_cv * rho * div * (rho * D1 * inv);
+            cfr[2][m] = (C)(Bw * P.k2_Tc - Aw);
+            cfr[3][m] = (C)(-Bw * P.k1k_rsTc);
         }
 
-        const C k1k = (C)P.k1k, k2 = (C)P.k2_Tc;
-        const C inv_Tc = (C)P.inv_Tc, Tref = (C)P.T_ref;
+        const C Tref = (C)P.T_ref;
         const C cst[3] = {C(0.5), C(0.5), C(1.0)};
         const C wst[4] = {C(1), C(2), C(2), C(1)};
         // stage st reads T0 (st = 0) or Ts[(st - 1) & 1] and writes Ts[st & 1]:
@@ -903,8 +912,7 @@ __global__ __launch_bounds__(64 * NWB) void k_thermal(const Inst *__restrict__ i
                     const C dTy = (wW + wE + C(4) * w) * C(1.0 / 12.0);
                     const C lap = (vW + vE + C(4) * v - C(36) * tc) * C(1.0 / 6.0);
                     const C T = Tref + tc;
-                    const C Tphi = k2 * T - k1k * stage_sqrt(T * inv_Tc);
-                    h = -(cfr[0][m] * dTx + cfr[1][m] * dTy) + chi * lap - cfr[2][m] * T + cfr[3][m] * Tphi;
+                    h = -(cfr[0][m] * dTx + cfr[1][m] * dTy) + chi * lap + cfr[2][m] * T + cfr[3][m] * stage_sqrt(T);
                     acc[m] += wst[st] * h;
                 }
                 if (st < 3) Ts[st & 1][r][lane] = T0[r][lane] + cst[st] * h;
