@@ -60,71 +60,122 @@ constexpr int kGraphSteps = 32;  // steps per captured graph (even: buffers retu
 
 struct Eos {
     double a, b, R, Tc, kappa, T;
-    double phi() const
+    double alpha() const  // the temperature factor phi(T) of the attraction
     {
         const double s = 1.0 + kappa * (1.0 - std::sqrt(T / Tc));
         return s * s;
     }
-    double p(double r) const { return r * R * T / (1.0 - b * r) - a * phi() * r * r / (1.0 + 2.0 * b * r - b * b * r * r); }
+    double p(double r) const { return r * R * T / (1.0 - b * r) - a * alpha() * r * r / (1.0 + 2.0 * b * r - b * b * r * r); }
     double dp(double r) const
     {
         const double q = 1.0 + 2.0 * b * r - b * b * r * r;
-        return R * T / ((1.0 - b * r) * (1.0 - b * r)) - 2.0 * a * phi() * r * (1.0 + b * r) / (q * q);
+        return R * T / ((1.0 - b * r) * (1.0 - b * r)) - 2.0 * a * alpha() * r * (1.0 + b * r) / (q * q);
     }
-    // antiderivative of p/rho^2: R T ln(rho/(1 - b rho)) - a phi int drho/(2 - (1 - b rho)^2)
-    double prim(double r) const
+    // Gibbs free energy per unit mass, up to a constant: G = F + p/rho with
+    // F = int p/rho^2 drho.  The attraction term integrates through the
+    // factorisation 1 + 2 b rho - b^2 rho^2 = (sqrt2 - 1 + b rho)(sqrt2 + 1 - b rho).
+    // Along an isotherm dG = dp/rho (Gibbs-Duhem).
+    double gibbs(double r) const
     {
-        const double x = 1.0 - b * r, s2 = std::sqrt(2.0);
-        return R * T * std::log(r / x) + a * phi() / (2.0 * s2 * b) * std::log((s2 + x) / (s2 - x));
+        const double s2 = std::sqrt(2.0);
+        const double F = R * T * std::log(r / (1.0 - b * r)) -
+                         a * alpha() / (2.0 * s2 * b) * std::log((s2 - 1.0 + b * r) / (s2 + 1.0 - b * r));
+        return F + p(r) / r;
     }
 };
 
+// Extremum of a function that is unimodal on [lo, hi] by golden-section
+// search (sign = +1: maximum, -1: minimum).
 template <typename Fn>
-double solve_bracket(Fn fn, double lo, double hi)
+double golden_extremum(Fn fn, double lo, double hi, double sign)
 {
-    double flo = fn(lo);
-    for (int it = 0; it < 300; ++it) {
-        const double mid = 0.5 * (lo + hi);
-        if (!(mid > lo && mid < hi)) break;
-        const double fm = fn(mid);
-        if ((fm < 0.0) == (flo < 0.0)) {
-            lo = mid;
-            flo = fm;
+    const double g = 0.5 * (std::sqrt(5.0) - 1.0);
+    double x1 = hi - g * (hi - lo), x2 = lo + g * (hi - lo);
+    double f1 = sign * fn(x1), f2 = sign * fn(x2);
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * hi; ++it) {
+        if (f1 > f2) {
+            hi = x2;
+            x2 = x1;
+            f2 = f1;
+            x1 = hi - g * (hi - lo);
+            f1 = sign * fn(x1);
         } else {
-            hi = mid;
+            lo = x1;
+            x1 = x2;
+            f1 = f2;
+            x2 = lo + g * (hi - lo);
+            f2 = sign * fn(x2);
         }
     }
     return 0.5 * (lo + hi);
 }
 
-// Maxwell equal-area rule: p(rho_V) = p(rho_L) = p0 and
-// int_{rho_V}^{rho_L} (p - p0)/rho^2 drho = 0.
+// Root of fn on [lo, hi] (fn(lo), fn(hi) of opposite signs) by Newton steps
+// with derivative dfn, falling back to halving the bracket whenever a step
+// would leave it.
+template <typename Fn, typename Dfn>
+double newton_bracketed(Fn fn, Dfn dfn, double lo, double hi)
+{
+    const bool rising = fn(lo) < fn(hi);
+    double x = 0.5 * (lo + hi);
+    for (int it = 0; it < 400; ++it) {
+        const double f = fn(x);
+        if (f == 0.0) return x;
+        if ((f > 0.0) == rising) hi = x; else lo = x;
+        const double d = dfn(x);
+        double xn = (d != 0.0 && std::isfinite(d)) ? x - f / d : lo - 1.0;
+        if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+        if (std::fabs(xn - x) <= 4e-16 * std::fabs(x) || !(hi > lo)) return xn;
+        x = xn;
+    }
+    return x;
+}
+
+// Coexisting densities by the equal-area (equal chemical potential) rule:
+// p(rho_V) = p(rho_L) = p0 and G(rho_V) = G(rho_L).  The two spinodals, the
+// local maximum and minimum of the van der Waals loop, lie on either side of
+// the critical density rho_c = 0.0778/(Z_c b) with Z_c = 0.3074 of the
+// Peng-Robinson EOS.  For a trial p0 between the loop's extremes, rho_V and
+// rho_L are the outer roots of p = p0; dG/dp0 = 1/rho along each branch, so
+// the difference D(p0) = G(rho_L) - G(rho_V) falls with slope
+// 1/rho_L - 1/rho_V, and Newton's method on D (kept inside a sign-change
+// bracket) gives the saturation pressure.
 bool maxwell(const Eos &e, double &rv, double &rl)
 {
-    const double top = (1.0 / e.b) * (1.0 - 1e-10);
-    // spinodals: the two roots of dp/drho on (0, 1/b)
-    double sp[2];
-    int ns = 0;
-    const int n = 100000;
-    double r0 = top / n, d0 = e.dp(r0);
-    for (int k = 2; k <= n && ns < 2; ++k) {
-        const double r1 = top * k / n, d1 = e.dp(r1);
-        if ((d0 < 0.0) != (d1 < 0.0)) sp[ns++] = solve_bracket([&](double r) { return e.dp(r); }, r0, r1);
-        r0 = r1;
-        d0 = d1;
-    }
-    if (ns != 2) return false;
-    double plo = e.p(sp[1]), phi_ = e.p(sp[0]);
-    if (plo < 1e-14 * phi_) plo = 1e-14 * phi_;
+    const double rmax = 1.0 / e.b;
+    const double rc = 0.0778 / (0.3074 * e.b);
+    auto P = [&](double r) { return e.p(r); };
+    auto dP = [&](double r) { return e.dp(r); };
+    const double s1 = golden_extremum(P, 0.0, rc, 1.0);          // vapour spinodal (maximum)
+    const double s2 = golden_extremum(P, rc, rmax * (1.0 - 1e-9), -1.0);  // liquid spinodal (minimum)
+    if (!(e.dp(0.5 * (s1 + s2)) < 0.0) || !(s1 < s2)) return false;  // no loop: T >= T_c
+    double p_hi = e.p(s1);
+    double p_lo = std::max(e.p(s2), 0.0);
+    if (!(p_hi > p_lo)) return false;
+    auto roots = [&](double p0, double &v, double &l) {
+        auto g = [&](double r) { return e.p(r) - p0; };
+        v = newton_bracketed(g, dP, 0.0, s1);
+        // p grows without bound towards 1/b: a finite upper end of the bracket
+        double top = s2 + 0.5 * (rmax - s2);
+        while (g(top) < 0.0) top = top + 0.5 * (rmax - top);
+        l = newton_bracketed(g, dP, s2, top);
+    };
+    double v = 0, l = 0;
+    roots(p_hi, v, l);
+    if (!(e.gibbs(l) - e.gibbs(v) < 0.0)) return false;
+    double p0 = 0.5 * (p_lo + p_hi);
     for (int it = 0; it < 200; ++it) {
-        const double p0 = 0.5 * (plo + phi_);
-        if (!(p0 > plo && p0 < phi_)) break;
-        rv = solve_bracket([&](double r) { return e.p(r) - p0; }, 1e-300, sp[0]);
-        rl = solve_bracket([&](double r) { return e.p(r) - p0; }, sp[1], top);
-        const double area = (e.prim(rl) + p0 / rl) - (e.prim(rv) + p0 / rv);
-        if (area > 0.0) plo = p0; else phi_ = p0;
+        roots(p0, v, l);
+        const double D = e.gibbs(l) - e.gibbs(v);
+        if (D > 0.0) p_lo = p0; else p_hi = p0;
+        double pn = p0 - D / (1.0 / l - 1.0 / v);
+        if (!(pn > p_lo && pn < p_hi)) pn = 0.5 * (p_lo + p_hi);
+        const bool done = std::fabs(pn - p0) <= 1e-15 * p0;
+        p0 = pn;
+        if (done) break;
     }
-    return true;
+    roots(p0, rv, rl);
+    return rv > 0.0 && rl > rv;
 }
 
 // ---- SplitMix64 (Steele, Lea, Flood 2014), counter-based use -------------
@@ -218,6 +269,52 @@ int validate(const lbb_params *p)
     if (p->ghost_layer != 0 && p->ghost_layer != 1) return fail(LBB_EINVAL, "ghost_layer must be 0 or 1");
     if (p->reserved != 0) return fail(LBB_EINVAL, "reserved must be 0");
     return LBB_OK;
+}
+
+// Device parameters of a validated parameter set (rho_L, rho_V resolved).
+void make_dev_params(const lbb_params &p, double Tc, double kap, lbb::DevParams &q)
+{
+    q = lbb::DevParams{};
+    const double Ts = p.Ts_over_Tc * Tc;
+    q.nx = p.nx;
+    q.ny = p.ny;
+    q.periodic_y = p.periodic_y ? 1 : 0;
+    q.mode = p.thermal_mode;
+    q.ghost = p.ghost_layer && !p.periodic_y ? 1 : 0;
+    q.a = p.a;
+    q.b = p.b;
+    q.R = p.R;
+    q.Tc = Tc;
+    q.kappa = kap;
+    q.Ts = Ts;
+    q.T_ref = p.precision == LBB_FP64 ? 0.0 : Ts;
+    q.G = p.G;
+    q.sigma = p.sigma;
+    q.s_rho = p.s_rho;
+    q.s_e = p.s_e;
+    q.s_zeta = p.s_zeta;
+    q.s_j = p.s_j;
+    q.s_q = p.s_q;
+    const double tauL = 3.0 * p.nu_L + 0.5, tauV = 3.0 * p.nu_V + 0.5;
+    q.tau_V = tauV;
+    q.tau_slope = (tauL - tauV) / (p.rho_L - p.rho_V);
+    q.rho_V = p.rho_V;
+    q.cv = p.cv;
+    q.cv_chi = p.cv_chi;
+    q.chi = p.cv_chi / p.cv;
+    q.g = p.g;
+    q.Gw_bottom = p.Gw_bottom;
+    q.Gw_top = p.Gw_top;
+    q.sig_e = p.sigma / (1.0 / p.s_e - 0.5);
+    q.sig_z = p.sigma / (1.0 / p.s_zeta - 0.5);
+    q.inv_Tc = 1.0 / Tc;
+    q.two_over_G = 2.0 / p.G;
+    q.R_cv = p.R / p.cv;
+    q.a_cv = p.a / p.cv;
+    q.inv_cv = 1.0 / p.cv;
+    q.k1k = kap * (1.0 + kap);
+    q.k2_Tc = kap * kap / Tc;
+    q.k1k_rsTc = kap * (1.0 + kap) / std::sqrt(Tc);
 }
 
 uint64_t param_hash(const lbb_params &p)
@@ -646,45 +743,7 @@ int lbb_init_domain(const lbb_params *pin, const double *T_bottom, const double 
     d->N = N;
     d->esz = p.precision == LBB_FP64 ? 8 : 4;
     d->Tb = Tb;
-    lbb::DevParams &q = d->dp;
-    q.nx = p.nx;
-    q.ny = p.ny;
-    q.periodic_y = p.periodic_y ? 1 : 0;
-    q.mode = p.thermal_mode;
-    q.ghost = p.ghost_layer && !p.periodic_y ? 1 : 0;
-    q.a = p.a;
-    q.b = p.b;
-    q.R = p.R;
-    q.Tc = Tc;
-    q.kappa = kap;
-    q.Ts = Ts;
-    q.T_ref = p.precision == LBB_FP64 ? 0.0 : Ts;
-    q.G = p.G;
-    q.sigma = p.sigma;
-    q.s_rho = p.s_rho;
-    q.s_e = p.s_e;
-    q.s_zeta = p.s_zeta;
-    q.s_j = p.s_j;
-    q.s_q = p.s_q;
-    const double tauL = 3.0 * p.nu_L + 0.5, tauV = 3.0 * p.nu_V + 0.5;
-    q.tau_V = tauV;
-    q.tau_slope = (tauL - tauV) / (p.rho_L - p.rho_V);
-    q.rho_V = p.rho_V;
-    q.cv = p.cv;
-    q.cv_chi = p.cv_chi;
-    q.chi = p.cv_chi / p.cv;
-    q.g = p.g;
-    q.Gw_bottom = p.Gw_bottom;
-    q.Gw_top = p.Gw_top;
-    q.sig_e = p.sigma / (1.0 / p.s_e - 0.5);
-    q.sig_z = p.sigma / (1.0 / p.s_zeta - 0.5);
-    q.inv_Tc = 1.0 / Tc;
-    q.two_over_G = 2.0 / p.G;
-    q.R_cv = p.R / p.cv;
-    q.a_cv = p.a / p.cv;
-    q.inv_cv = 1.0 / p.cv;
-    q.k1k = kap * (1.0 + kap);
-    q.k2_Tc = kap * kap / Tc;
+    make_dev_params(p, Tc, kap, d->dp);
     set_grid(d);
     const lbb_param_dims dims{p.nx, p.ny};
     const int mbA = max_blocks_A(dims), mbB = max_blocks_B(dims);
@@ -2034,3 +2093,4 @@ int lbb_destroy(lbb_domain *d)
 }
 
 }  // extern "C"
+

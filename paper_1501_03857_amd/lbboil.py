@@ -480,3 +480,4 @@ class Batch:
         if not h:
             raise IndexError(i)
         return Domain.borrowed(h, self.params[i])
+

@@ -97,14 +97,30 @@ def test_eos_constants_match_oracle(a):
     assert k == pytest.approx(O.kappa(0.344), rel=1e-15)
 
 
-@pytest.mark.parametrize("theta", [0.6, 0.86, 0.97])
-def test_library_coexistence_matches_oracle(theta):
-    a, b = 2.0 / 49.0, 2.0 / 21.0
+@pytest.mark.parametrize("a,omega,theta", [(2.0 / 49.0, 0.344, 0.5), (2.0 / 49.0, 0.344, 0.6),
+                                           (2.0 / 49.0, 0.344, 0.86), (2.0 / 49.0, 0.344, 0.97),
+                                           (2.0 / 49.0, 0.344, 0.995), (3.0 / 49.0, 0.344, 0.86),
+                                           (3.0 / 49.0, 0.2, 0.9), (3.0 / 49.0, 0.0, 0.75)])
+def test_library_coexistence_matches_oracle(a, omega, theta):
+    """The library's coexistence (Newton on the chemical-potential difference)
+    against the oracle's (bisection on the equal-area sign): two methods, one
+    construction."""
+    b = 2.0 / 21.0
     tc = O.Tc(a, b, 1.0)
-    rv, rl = L.coexistence(a, b, 1.0, 0.344, theta * tc)
-    orv, orl, _ = O.maxwell(a, b, 1.0, 0.344, theta * tc)
+    rv, rl = L.coexistence(a, b, 1.0, omega, theta * tc)
+    orv, orl, _ = O.maxwell(a, b, 1.0, omega, theta * tc)
     assert rv == pytest.approx(orv, rel=1e-9)
     assert rl == pytest.approx(orl, rel=1e-9)
+
+
+def test_library_coexistence_paper_densities():
+    """Sec. 3.1: at T_s = 0.86 T_c the coexistence densities are about 6.5 and 0.38."""
+    a, b = 3.0 / 49.0, 2.0 / 21.0
+    tc, _ = L.eos_constants(a, b, 1.0, 0.344)
+    rv, rl = L.coexistence(a, b, 1.0, 0.344, 0.86 * tc)
+    assert abs(rl - 6.5) < 0.01 and abs(rv - 0.38) < 0.005
+    pl, pv = L.eos_pressure(a, b, 1.0, 0.344, rl, 0.86 * tc), L.eos_pressure(a, b, 1.0, 0.344, rv, 0.86 * tc)
+    assert pl == pytest.approx(pv, rel=1e-10)
 
 
 def test_coexistence_rejects_supercritical():
@@ -156,3 +172,4 @@ def test_device_budget_refuses_a_domain_before_touching_the_device():
         assert lib.lbb_device_bytes_held() == 0
     finally:
         assert lib.lbb_set_device_budget(0) == L.LBB_OK
+
