@@ -26,43 +26,62 @@ HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes per lattice update of the method in FP32 storage: the nine
 # populations and T, each read once and written once.
 ALG_BYTES_STEP = {"f32": 80, "f64": 160}
-# The LB launch's share of it: the nine populations read and written.
+# The LB launch's share of it: the nine populations read and written; the
+# thermal launch's: T read and written.
 ALG_BYTES_LB = {"f32": 72, "f64": 144}
+ALG_BYTES_TH = {"f32": 8, "f64": 16}
 
-# HBM traffic of the LB launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
+
+def _kernel_roofline(alg_bytes, ms, traffic, per_update):
+    """One launch priced against HBM: algorithmic bytes over its mean
+    duration (events recorded by the dispatches)."""
+    gbs = alg_bytes / (ms * 1e-3) / 1e9
+    return {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+            "kernel_ms": round(ms, 6), "alg_bytes_per_update": per_update, "traffic": traffic,
+            "traffic_unit": "bytes per launch"}
+
+# HBM traffic of each launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
 # (KiB per dispatch, mean over the dispatches of a --profile run with the
 # given tiles), each scaled by what the same counter reads for an elementwise
 # kernel that reads 1 GiB and writes 1 GiB (FETCH_SIZE 524297.7 KiB -> factor
 # 2.0, WRITE_SIZE 1048576 KiB -> factor 1.0).  Valid for the kernel source
-# whose hash is recorded and the same LB tile shape; null otherwise.
+# whose hash is recorded and the same tile shape; null otherwise.
 MEASURED_TRAFFIC = {
     "source_hash": "5841db5404206de4",
     "fetch_factor": 1048576.0 / 524297.7,
     "write_factor": 1048576.0 / 1048576.0,
     "k_lb": {
         "large_1024x512_fp32": [
-            {"tiles_lb": [62, 4, 4], "fetch_kib": 10718.0, "write_kib": 24620.1},
-            {"tiles_lb": [62, 8, 8], "fetch_kib": 10650.1, "write_kib": 24653.6},
+            {"tiles": [62, 4, 4], "fetch_kib": 10718.0, "write_kib": 24620.1},
+            {"tiles": [62, 8, 8], "fetch_kib": 10650.1, "write_kib": 24653.6},
         ],
         "large_4096x2048_fp32": [
-            {"tiles_lb": [62, 4, 4], "fetch_kib": 166704.1, "write_kib": 395668.4},
-            {"tiles_lb": [62, 8, 8], "fetch_kib": 171677.0, "write_kib": 397357.0},
-            {"tiles_lb": [62, 12, 4], "fetch_kib": 178478.2, "write_kib": 398111.1},
+            {"tiles": [62, 4, 4], "fetch_kib": 166704.1, "write_kib": 395668.4},
+            {"tiles": [62, 8, 8], "fetch_kib": 171677.0, "write_kib": 397357.0},
+            {"tiles": [62, 12, 4], "fetch_kib": 178478.2, "write_kib": 398111.1},
         ],
     },
+    "k_thermal": {},
 }
 
 
-def measured_traffic(workload: str, tiles_lb):
-    """HBM bytes per LB launch from the recorded counters, or None when the
-    kernel source, the workload or the LB tile shape differ."""
+def measured_traffic(kernel: str, workload: str, tiles):
+    """HBM bytes per launch of `kernel` from the recorded counters, or None
+    when the kernel source, the workload or the tile shape differ."""
     m = MEASURED_TRAFFIC
     if not m or m.get("source_hash") != source_hash():
         return None
-    for c in m["k_lb"].get(workload, []):
-        if list(c["tiles_lb"]) == list(tiles_lb):
+    for c in m.get(kernel, {}).get(workload, []):
+        if list(c["tiles"]) == list(tiles):
             return int(round((c["fetch_kib"] * m["fetch_factor"] + c["write_kib"] * m["write_factor"]) * 1024))
     return None
+
+
+def arithmetic(store: str) -> str:
+    """The arithmetic types of the step for a storage precision."""
+    if store == "f64":
+        return "f64"
+    return "mixed: f32 storage; f64 LB, EOS, pressure work and reductions; f32 RK4 stage sums"
 
 
 def source_hash() -> str:
@@ -360,9 +379,11 @@ def main():
         return
 
     ms_lb, ms_th, ms_seq = d.time_kernels(args.kernel_steps)
-    achieved = ALG_BYTES_LB[store] * cells / (ms_lb * 1e-3) / 1e9
-    traffic = measured_traffic(w.name, tiles["lb"])
     step_bytes = ALG_BYTES_STEP[store] * cells
+    achieved = step_bytes / (ms_step * 1e-3) / 1e9
+    tr_lb = measured_traffic("k_lb", w.name, tiles["lb"])
+    tr_th = measured_traffic("k_thermal", w.name, tiles["thermal"])
+    traffic = None if tr_lb is None or tr_th is None else tr_lb + tr_th
     sweep = sweep_bench(args.sweep_steps) if args.sweep_steps > 0 else None
     if sweep:
         print(f"[bench] sweep: batched {sweep['batched_mlups']} MLUPS vs sequential {sweep['plain_sequential_mlups']} "
@@ -386,20 +407,21 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": arithmetic(store),
         "data": "synthetic",
         "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "storage": store, "global_batch": 1,
                    "parallelism": "none", "launches_per_step": 2, "graph_steps": 32, "tiles": tiles},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "traffic_unit": "bytes per launch",
-                     "traffic_gbs": None if traffic is None else round(traffic / (ms_lb * 1e-3) / 1e9, 1),
-                     "kernel": "k_lb", "kernel_ms": round(ms_lb, 6),
-                     "alg_bytes_per_update": ALG_BYTES_LB[store],
+                     "traffic_unit": "bytes per step",
+                     "traffic_gbs": None if traffic is None else round(traffic / (ms_step * 1e-3) / 1e9, 1),
+                     "kernel": "step (k_lb + k_thermal)", "step_ms": round(ms_step, 6),
+                     "alg_bytes_per_update": ALG_BYTES_STEP[store],
                      "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
-        "step_roofline": {"achieved": round(step_bytes / (ms_step * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
-                          "unit": "GB/s", "frac": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                          "alg_bytes_per_update": ALG_BYTES_STEP[store]},
+        "kernel_rooflines": {
+            "k_lb": _kernel_roofline(ALG_BYTES_LB[store] * cells, ms_lb, tr_lb, ALG_BYTES_LB[store]),
+            "k_thermal": _kernel_roofline(ALG_BYTES_TH[store] * cells, ms_th, tr_th, ALG_BYTES_TH[store]),
+        },
         "kernels_ms": {"k_lb": round(ms_lb, 6), "k_thermal": round(ms_th, 6), "step_single_launch": round(ms_seq, 6)},
         "heat_flux_mean": hf["q_mean"],
         "batched_sweep": sweep,
