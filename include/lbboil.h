@@ -288,6 +288,66 @@ int lbb_batch_autotune(lbb_batch *b, int32_t steps, int32_t *shape_lb, int32_t *
 int lbb_set_device_budget(int64_t bytes);
 int64_t lbb_device_bytes_held(void);
 
+/* ---- Stepping without allocation ---------------------------------------
+ * For callers that cannot allocate device memory: code running under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * The same n time steps as lbb_step (the same kernels and default tile
+ * shapes) on a lattice whose state the caller holds in its own device
+ * buffers.  The domain-mean density of the first step is summed from the
+ * given state as lbb_init_domain and lbb_set_fields sum it, so the result is
+ * bitwise that of lbb_step on a domain just created with the same state; from
+ * a domain that has stepped it differs by that sum's rounding order.  The library allocates nothing: the
+ * per-block partial sums, the launch table and the scalars (domain-mean
+ * density, heat-flux accumulators, error flag) live in one static device
+ * array of LBB_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends
+ * and shared by every call on that GPU, so calls that overlap on one GPU
+ * (two host threads, or two streams in flight) race and must not be made.
+ * Each call re-initialises what it uses; nothing carries over between calls.
+ *   p           : parameters, validated as lbb_init_domain (rho_L = rho_V = 0:
+ *                 Maxwell coexistence at T_s); the lattice's scratch need is
+ *                 8 (ceil(nx/62) ny + ceil(nx/56)) + 4 (blocks + 2) + 1 KiB
+ *                 bytes and must not exceed LBB_NOALLOC_SCRATCH_BYTES (EINVAL
+ *                 with the need in the message): up to about 1e6 rows of
+ *                 nx = 62, or 8192 x 6500.
+ *   f[2]        : two device buffers of 9*nx*ny values of the storage type
+ *                 (double for LBB_FP64, float for LBB_FP32), layout
+ *                 [a][y][x], velocities rest, E, N, W, S, NE, NW, SW, SE:
+ *                 post-streaming populations; on wall rows the three
+ *                 populations arriving from outside are ignored (completed
+ *                 by the Zou-He rule on read).  The layout lbb_save_state
+ *                 writes after its header.
+ *   T[2]        : two device buffers of nx*ny values of the storage type
+ *                 holding T - T_ref (T_ref = 0 in FP64, T_s in FP32); both
+ *                 must hold the Dirichlet wall rows (T_b on row 0, T_s on
+ *                 row ny-1), which the steps never write.
+ *   rho, vx, vy : device buffers of nx*ny values of the storage type
+ *                 (overwritten: rho and the velocity the temperature equation
+ *                 sees, of the last step's old state).
+ *   phase [2]   : host, in/out: which buffer of f (phase[0]) and of T
+ *                 (phase[1]) holds the state, 0 or 1; updated on return (f
+ *                 alternates every step unless THERMAL_ONLY, T unless
+ *                 ISOTHERMAL).
+ *   n           : steps, >= 0.
+ *   result      : device pointer to an lbb_noalloc_result, written after the
+ *                 last step: q(t) of the final state, the mean of the n
+ *                 samples (NaN for n = 0), the sample count, and the first
+ *                 failing step and error bits (err_step = -1 when none;
+ *                 bits 1: rho, 2: pseudopotential radicand, 4: T).
+ *   stream      : hipStream_t the work is enqueued on (NULL: null stream).
+ * Asynchronous: returns once the work is enqueued; the caller synchronises
+ * the stream and reads *result.  EINVAL on invalid parameters, NULL buffers,
+ * n < 0, a phase other than 0/1 or a lattice beyond the scratch; EDEVICE on
+ * a HIP error (no usable gfx950 device, launch failure). */
+#define LBB_NOALLOC_SCRATCH_BYTES (8u << 20)
+typedef struct lbb_noalloc_result {
+    double q_now, q_mean;
+    int64_t n_samples;
+    int64_t err_step;
+    uint32_t err_code, reserved;
+} lbb_noalloc_result;
+int lbb_step_noalloc(const lbb_params *p, void *const f[2], void *const T[2], void *rho, void *vx, void *vy,
+                     int32_t phase[2], int64_t n, lbb_noalloc_result *result, void *stream);
+
 /* Current step count, grid shape and device bytes held by the domain. */
 int lbb_info(lbb_domain *d, int64_t *t, int32_t *nx, int32_t *ny, int64_t *device_bytes);
 

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
 #include <functional>
+#include <mutex>
 
 #include <atomic>
 #include <cmath>
@@ -2094,3 +2095,184 @@ int lbb_destroy(lbb_domain *d)
 
 }  // extern "C"
 
+// ---- stepping without allocation -----------------------------------------
+//
+// The per-block partial sums, the one-entry launch table, the block maps and
+// the scalars of lbb_step_noalloc live in this array.  Its host-side name
+// is only a stand-in for the symbol: the device address of each GPU's copy
+// comes from hipGetSymbolAddress (noalloc_scratch below), and only that
+// address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[LBB_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+// Device address of `scratch` on device `dev`, resolved once per device
+// with that device current.
+int noalloc_scratch(int dev, unsigned char **out)
+{
+    static std::mutex mu;
+    static unsigned char *addr[kMaxDevices] = {};
+    if (dev < 0 || dev >= kMaxDevices) return fail(LBB_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(LBB_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        addr[dev] = static_cast<unsigned char *>(p);
+    }
+    *out = addr[dev];
+    return LBB_OK;
+}
+
+// Byte offsets of the pieces of the scratch array for one lattice (default
+// tile shapes), each 256-byte aligned; `total` is the bytes needed.
+struct NoallocLayout {
+    size_t inst, sc, blkA, blkB, mass, hf, total;
+    int nbxA, nbyA, nbxB, nbyB;
+};
+
+NoallocLayout noalloc_layout(int nx, int ny)
+{
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    NoallocLayout L{};
+    L.nbxA = (nx + lbb::TXA - 1) / lbb::TXA;
+    L.nbyA = (ny + lbb::kShapeA[0].ty - 1) / lbb::kShapeA[0].ty;
+    L.nbxB = (nx + lbb::TXB - 1) / lbb::TXB;
+    L.nbyB = (ny + lbb::kShapeB[0].ty - 1) / lbb::kShapeB[0].ty;
+    const size_t nA = (size_t)L.nbxA * L.nbyA + 1, nB = (size_t)L.nbxB * L.nbyB + 1;
+    const size_t nmass = std::max((size_t)L.nbxA * ny, (size_t)L.nbxA * L.nbyA);
+    size_t o = 0;
+    L.inst = o;
+    o += up(sizeof(lbb::Inst));
+    L.sc = o;
+    o += up(sizeof(lbb::Scalars));
+    L.blkA = o;
+    o += up(nA * sizeof(int));
+    L.blkB = o;
+    o += up(nB * sizeof(int));
+    L.mass = o;
+    o += up(nmass * sizeof(double));
+    L.hf = o;
+    o += up((size_t)L.nbxB * sizeof(double));
+    L.total = o;
+    return L;
+}
+
+// Launch table, zeroed block maps (a single lattice: every block belongs to
+// entry 0) and reset scalars, written by a kernel so that nothing is copied
+// from host memory and no memset node is involved.
+__global__ void k_noalloc_setup(lbb::Inst I, lbb::Inst *inst, int *blkA, int nA, int *blkB, int nB, lbb::Scalars *sc)
+{
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
+    if (tid == 0) {
+        *inst = I;
+        lbb::Scalars s{};
+        s.err_step = ~0ULL;
+        *sc = s;
+    }
+    for (int k = tid; k < nA; k += stride) blkA[k] = 0;
+    for (int k = tid; k < nB; k += stride) blkB[k] = 0;
+}
+
+__global__ void k_noalloc_result(const lbb::Scalars *sc, lbb_noalloc_result *out)
+{
+    if (threadIdx.x != 0) return;
+    lbb_noalloc_result r{};
+    r.q_now = sc->q_now;
+    r.n_samples = sc->n_samples;
+    r.q_mean = sc->n_samples > 0 ? sc->q_sum / (double)sc->n_samples : __builtin_nan("");
+    r.err_step = sc->err_step == ~0ULL ? -1 : (int64_t)sc->err_step;
+    r.err_code = sc->err_code;
+    *out = r;
+}
+
+// The work of lbb_step_noalloc after validation: the set-up reductions of
+// the given state (as lbb_init_domain's), n steps of single launches, the
+// final heat-flux bookkeeping and the result.
+template <typename S>
+void noalloc_enqueue(const lbb::Inst &I, unsigned char *base, const NoallocLayout &L, int &cf, int &cT, int64_t n,
+                     lbb_noalloc_result *result, hipStream_t st)
+{
+    using namespace lbb;
+    Inst *inst = reinterpret_cast<Inst *>(base + L.inst);
+    Scalars *sc = reinterpret_cast<Scalars *>(base + L.sc);
+    int *blkA = reinterpret_cast<int *>(base + L.blkA);
+    int *blkB = reinterpret_cast<int *>(base + L.blkB);
+    const int nA = L.nbxA * L.nbyA + 1, nB = L.nbxB * L.nbyB + 1;
+    hipLaunchKernelGGL(k_noalloc_setup, dim3((std::max(nA, nB) + 255) / 256), dim3(256), 0, st, I, inst, blkA, nA,
+                       blkB, nB, sc);
+    const int nm = L.nbxA * L.nbyA;
+    const S *f = static_cast<const S *>(I.f[cf]);
+    hipLaunchKernelGGL(k_mass<S>, dim3(nm), dim3(NT), 0, st, I.P, f, I.mass_part);
+    hipLaunchKernelGGL(k_reduce_mass, dim3(1), dim3(NT), 0, st, I.P, I.mass_part, nm, sc);
+    hipLaunchKernelGGL(k_heat_flux_state<S>, dim3(L.nbxB), dim3(64), 0, st, I.P, f,
+                       static_cast<const S *>(I.T[cT]), I.hf_part, (double *)nullptr);
+    hipLaunchKernelGGL(k_flush_heat_flux, dim3(1), dim3(NT), 0, st, inst);
+    for (int64_t k = 0; k < n; ++k) {
+        launch_lb<S>(st, inst, blkA, nA, cf, cT, 0);
+        launch_thermal<S>(st, inst, blkB, nB, cf, cT, 0);
+        if (I.P.mode != MODE_THERMAL_ONLY) cf ^= 1;
+        if (I.P.mode != MODE_ISOTHERMAL) cT ^= 1;
+    }
+    hipLaunchKernelGGL(k_flush_heat_flux, dim3(1), dim3(NT), 0, st, inst);
+    hipLaunchKernelGGL(k_noalloc_result, dim3(1), dim3(64), 0, st, sc, result);
+}
+
+}  // namespace
+
+extern "C" int lbb_step_noalloc(const lbb_params *pin, void *const f[2], void *const T[2], void *rho, void *vx,
+                                void *vy, int32_t phase[2], int64_t n, lbb_noalloc_result *result, void *stream)
+{
+    int rc = validate(pin);
+    if (rc) return rc;
+    if (!f || !T || !f[0] || !f[1] || !T[0] || !T[1] || !rho || !vx || !vy || !phase || !result)
+        return fail(LBB_EINVAL, "lbb_step_noalloc: every buffer, phase and result are required");
+    if (n < 0) return fail(LBB_EINVAL, "lbb_step_noalloc: n must be >= 0");
+    if ((phase[0] != 0 && phase[0] != 1) || (phase[1] != 0 && phase[1] != 1))
+        return fail(LBB_EINVAL, "lbb_step_noalloc: phase entries must be 0 or 1");
+    lbb_params p = *pin;
+    double Tc = 0, kap = 0;
+    lbb_eos_constants(p.a, p.b, p.R, p.omega, &Tc, &kap);
+    if (p.rho_L == 0.0 && p.rho_V == 0.0) {
+        rc = lbb_coexistence(p.a, p.b, p.R, p.omega, p.Ts_over_Tc * Tc, &p.rho_V, &p.rho_L);
+        if (rc) return fail(LBB_EINVAL, "rho_L = rho_V = 0 needs T_s < T_c for the Maxwell densities");
+    }
+    if (p.rho_L == p.rho_V) return fail(LBB_EINVAL, "rho_L must differ from rho_V");
+    const NoallocLayout L = noalloc_layout(p.nx, p.ny);
+    if (L.total > LBB_NOALLOC_SCRATCH_BYTES)
+        return fail(LBB_EINVAL, "lbb_step_noalloc: a " + std::to_string(p.nx) + "x" + std::to_string(p.ny) +
+                                    " lattice needs " + std::to_string(L.total) + " scratch bytes, more than the " +
+                                    std::to_string((size_t)LBB_NOALLOC_SCRATCH_BYTES) + " the library holds");
+    int dev = 0;
+    LBB_HIP(hipGetDevice(&dev));
+    unsigned char *base = nullptr;
+    rc = noalloc_scratch(dev, &base);
+    if (rc) return rc;
+    lbb::Inst I{};
+    make_dev_params(p, Tc, kap, I.P);
+    I.f[0] = f[0];
+    I.f[1] = f[1];
+    I.T[0] = T[0];
+    I.T[1] = T[1];
+    I.rho = rho;
+    I.vx = vx;
+    I.vy = vy;
+    I.mass_part = reinterpret_cast<double *>(base + L.mass);
+    I.hf_part = reinterpret_cast<double *>(base + L.hf);
+    I.sc = reinterpret_cast<lbb::Scalars *>(base + L.sc);
+    I.nbxA = L.nbxA;
+    I.nbyA = L.nbyA;
+    I.nbxB = L.nbxB;
+    I.nbyB = L.nbyB;
+    int cf = phase[0], cT = phase[1];
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (p.precision == LBB_FP64) noalloc_enqueue<double>(I, base, L, cf, cT, n, result, st);
+    else noalloc_enqueue<float>(I, base, L, cf, cT, n, result, st);
+    LBB_HIP(hipGetLastError());
+    phase[0] = cf;
+    phase[1] = cT;
+    return LBB_OK;
+}

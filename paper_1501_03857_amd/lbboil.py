@@ -110,6 +110,7 @@ def lib():
             "lbb_batch_set_tiles": (C.c_int, [vp, C.c_int32, C.c_int32]),
             "lbb_batch_autotune": (C.c_int, [vp, C.c_int32, _pi32, _pi32, _pd, _pd]),
             "lbb_batch_info": (C.c_int, [vp, C.POINTER(_i64)]),
+            "lbb_step_noalloc": (C.c_int, [_P, C.POINTER(vp), C.POINTER(vp), vp, vp, vp, _pi32, _i64, vp, vp]),
             "lbb_last_error": (C.c_char_p, []),
         }
         for name, (res, args) in sig.items():
@@ -481,3 +482,26 @@ class Batch:
             raise IndexError(i)
         return Domain.borrowed(h, self.params[i])
 
+
+NOALLOC_SCRATCH_BYTES = 8 << 20
+
+
+class NoallocResult(C.Structure):
+    """lbb_noalloc_result: written to device memory by lbb_step_noalloc."""
+    _fields_ = [("q_now", _d), ("q_mean", _d), ("n_samples", _i64), ("err_step", _i64),
+                ("err_code", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+def step_noalloc(p: "Params", f, T, rho, vx, vy, phase, n: int, result: int, stream: int = 0):
+    """lbb_step_noalloc on caller-held device buffers (raw device addresses as
+    ints): f = (f0, f1), T = (T0, T1), rho, vx, vy; phase = [phase_f,
+    phase_T] (a list, updated in place); result = device address of an
+    lbb_noalloc_result; stream = hipStream_t as an int (0: null stream)."""
+    cp = p.c()
+    fa = (C.c_void_p * 2)(int(f[0]), int(f[1]))
+    ta = (C.c_void_p * 2)(int(T[0]), int(T[1]))
+    ph = (_i32 * 2)(int(phase[0]), int(phase[1]))
+    _check(lib().lbb_step_noalloc(C.byref(cp), fa, ta, C.c_void_p(int(rho)), C.c_void_p(int(vx)),
+                                  C.c_void_p(int(vy)), ph, int(n), C.c_void_p(int(result)),
+                                  C.c_void_p(int(stream)) if stream else None))
+    phase[0], phase[1] = ph[0], ph[1]

@@ -173,3 +173,24 @@ def test_device_budget_refuses_a_domain_before_touching_the_device():
     finally:
         assert lib.lbb_set_device_budget(0) == L.LBB_OK
 
+
+def test_step_noalloc_argument_checks():
+    """lbb_step_noalloc refuses bad arguments before touching the device:
+    missing buffers, n < 0, a phase other than 0/1, and a lattice whose
+    partial sums would not fit the library's static scratch array (the
+    message names the bytes needed)."""
+    p = L.Params(nx=64, ny=32)
+    fake = [0x1000, 0x2000]
+    with pytest.raises(L.LbbError) as e:
+        L.step_noalloc(p, [0, 0], fake, 0x3000, 0x4000, 0x5000, [0, 0], 1, 0x6000)
+    assert e.value.code == L.LBB_EINVAL
+    with pytest.raises(L.LbbError) as e:
+        L.step_noalloc(p, fake, fake, 0x3000, 0x4000, 0x5000, [0, 0], -1, 0x6000)
+    assert e.value.code == L.LBB_EINVAL
+    with pytest.raises(L.LbbError) as e:
+        L.step_noalloc(p, fake, fake, 0x3000, 0x4000, 0x5000, [2, 0], 1, 0x6000)
+    assert e.value.code == L.LBB_EINVAL
+    big = L.Params(nx=8192, ny=8192, precision=L.FP32)
+    with pytest.raises(L.LbbError) as e:
+        L.step_noalloc(big, fake, fake, 0x3000, 0x4000, 0x5000, [0, 0], 1, 0x6000)
+    assert e.value.code == L.LBB_EINVAL and "scratch bytes" in str(e.value)
