@@ -81,7 +81,7 @@ def arithmetic(store: str) -> str:
     """The arithmetic types of the step for a storage precision."""
     if store == "f64":
         return "f64"
-    return "mixed: f32 storage; f64 LB, EOS, pressure work and reductions; f32 RK4 stage sums"
+    return "mixed: f32 storage; f64 LB, EOS and reductions; f32 RK4 stages (pressure-work coefficients formed in f64)"
 
 
 def source_hash() -> str:
