@@ -187,6 +187,7 @@ struct DevParams {
     double R_cv, a_cv, inv_cv;    // R / c_v, a / c_v, 1 / c_v
     double k1k, k2_Tc;            // kappa (1 + kappa), kappa^2 / T_c
     double k1k_rsTc;              // kappa (1 + kappa) / sqrt(T_c)
+    double R_cv12, a_cv12;        // R / (12 c_v), a / (12 c_v)
 };
 
 // Device-resident scalars of one domain.  tA is the state index seen by the
@@ -827,7 +828,6 @@ __global__ __launch_bounds__(64 * NWB) void k_thermal(const Inst *__restrict__ i
     }
     __syncthreads();
 
-    const C chi = (C)P.chi;
     C acc[RPW];
 #pragma unroll
     for (int m = 0; m < RPW; ++m) acc[m] = C(0);
@@ -863,26 +863,28 @@ __global__ __launch_bounds__(64 * NWB) void k_thermal(const Inst *__restrict__ i
             const C dvW = lane_from_left(dv), dvE = lane_from_right(dv);
             if (lane < 1 || lane >= 63) continue;
             const double rho = (double)rc;
-            const C drx = (srE - srW) * C(1.0 / 12.0);
-            const C dry = (drW + drE + C(4) * dr) * C(1.0 / 12.0);
-            const C dux = (suE - suW) * C(1.0 / 12.0);
-            const C dvy = (dvW + dvE + C(4) * dv) * C(1.0 / 12.0);
+            // 12 d_x rho, 12 d_y rho and 12 div v from the column sums
+            const C gx = srE - srW, gy = fma(C(4), dr, drW + drE);
+            const double div12 = (double)((suE - suW) + fma(C(4), dv, dvW + dvE));
             // A w = (R/c_v) div v / D1 and B w = (a/c_v) rho div v / D2 with
             // D1 = 1 - b rho, D2 = 1 + 2 b rho - b^2 rho^2; one reciprocal
             // 1/(rho D1 D2) gives 1/rho, 1/D1 and 1/D2
             const double D1 = 1.0 - P.b * rho;
             const double D2 = 1.0 + 2.0 * P.b * rho - P.b * P.b * rho * rho;
             const double inv = rcp_nr(rho * D1 * D2);
-            const double div = (double)(dux + dvy);
-            const C chi_rho = (C)(P.chi * D1 * D2 * inv);
-            cfr[0][m] = uc - chi_rho * drx;
-            cfr[1][m] = X[2][r][lane] - chi_rho * dry;
-            const double Aw = P.R_cv * div * (rho * D2 * inv), Bw = P.a_cv * rho * div * (rho * D1 * inv);
+            // the stages read the column sums unscaled: 12 d_x T and 12 d_y T,
+            // so the advection coefficients carry the 1/12
+            // (a_x/12 = (chi/rho) d_x rho/12 - v_x/12 = (chi/rho) gx/144 - v_x/12)
+            const C k144 = (C)(P.chi * (1.0 / 144.0) * D1 * D2 * inv);
+            cfr[0][m] = fma(k144, gx, -uc * C(1.0 / 12.0));
+            cfr[1][m] = fma(k144, gy, -X[2][r][lane] * C(1.0 / 12.0));
+            const double Aw = P.R_cv12 * div12 * (rho * D2 * inv), Bw = P.a_cv12 * rho * div12 * (rho * D1 * inv);
             cfr[2][m] = (C)(Bw * P.k2_Tc - Aw);
             cfr[3][m] = (C)(-Bw * P.k1k_rsTc);
         }
 
         const C Tref = (C)P.T_ref;
+        const C chi6 = (C)(P.chi * (1.0 / 6.0));
         const C cst[3] = {C(0.5), C(0.5), C(1.0)};
         const C wst[4] = {C(1), C(2), C(2), C(1)};
         // stage st reads T0 (st = 0) or Ts[(st - 1) & 1] and writes Ts[st & 1]:
@@ -900,22 +902,25 @@ __global__ __launch_bounds__(64 * NWB) void k_thermal(const Inst *__restrict__ i
                 // v = T_S + 4 T_c + T_N, w = T_N - T_S give
                 //   d_x T = (v_E - v_W)/12, d_y T = (w_W + 4 w + w_E)/12,
                 //   lap T = (v_W + v_E + 4 v - 36 T_c)/6,
-                // the isotropic stencils of the gradient and the Laplacian.
+                // the isotropic stencils of the gradient and the Laplacian
+                // (the 1/12 and 1/6 are carried by the coefficients).
                 const C tc = in[r][lane], tN = in[r + 1][lane], tS = in[r - 1][lane];
-                const C v = (tN + tS) + C(4) * tc, w = tN - tS;
+                const C v = fma(C(4), tc, tN + tS), w = tN - tS;
                 const C vW = lane_from_left(v), vE = lane_from_right(v);
                 const C wW = lane_from_left(w), wE = lane_from_right(w);
                 if (lane < HB - rad || lane >= HB + TXB + rad) continue;
                 C h = C(0);
                 if (act[m]) {
-                    const C dTx = (vE - vW) * C(1.0 / 12.0);
-                    const C dTy = (wW + wE + C(4) * w) * C(1.0 / 12.0);
-                    const C lap = (vW + vE + C(4) * v - C(36) * tc) * C(1.0 / 6.0);
                     const C T = Tref + tc;
-                    h = -(cfr[0][m] * dTx + cfr[1][m] * dTy) + chi * lap + cfr[2][m] * T + cfr[3][m] * stage_sqrt(T);
-                    acc[m] += wst[st] * h;
+                    const C lap6 = fma(C(-36), tc, fma(C(4), v, vW + vE));
+                    h = cfr[2][m] * T;
+                    h = fma(cfr[3][m], stage_sqrt(T), h);
+                    h = fma(chi6, lap6, h);
+                    h = fma(cfr[0][m], vE - vW, h);
+                    h = fma(cfr[1][m], fma(C(4), w, wW + wE), h);
+                    acc[m] = st == 0 ? h : fma(wst[st], h, acc[m]);
                 }
-                if (st < 3) Ts[st & 1][r][lane] = T0[r][lane] + cst[st] * h;
+                if (st < 3) Ts[st & 1][r][lane] = fma(cst[st], h, T0[r][lane]);
             }
             if (st < 3) __syncthreads();
         }

@@ -316,6 +316,8 @@ void make_dev_params(const lbb_params &p, double Tc, double kap, lbb::DevParams 
     q.k1k = kap * (1.0 + kap);
     q.k2_Tc = kap * kap / Tc;
     q.k1k_rsTc = kap * (1.0 + kap) / std::sqrt(Tc);
+    q.R_cv12 = p.R / (12.0 * p.cv);
+    q.a_cv12 = p.a / (12.0 * p.cv);
 }
 
 uint64_t param_hash(const lbb_params &p)
