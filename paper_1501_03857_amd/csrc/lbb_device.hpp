@@ -34,6 +34,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace lbb {
 
 constexpr int NT = 256;   // threads per block of the small kernels (4 waves)
@@ -99,6 +101,22 @@ __device__ __forceinline__ double sqrt_nr(double x)
     const double d = fma(-g, g, x);
     g = fma(d, h, g);
     return x > 0.0 ? g : (x == 0.0 ? 0.0 : __builtin_nan(""));
+}
+
+// sqrt(x) as sqrt_nr for normal x > 0 only (no zero or negative handling):
+// for arguments that are positive by construction or checked around it.
+__device__ __forceinline__ double sqrt_pos(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    const double d = fma(-g, g, x);
+    return fma(d, h, g);
 }
 
 // Type of the RK4 stage arithmetic: FP64 storage keeps FP64; FP32 storage
@@ -306,13 +324,15 @@ __device__ __forceinline__ void complete_node(const DevParams &P, const S fs[9],
 //   D2 = 1 + 2 b rho - b^2 rho^2.
 __device__ __forceinline__ double pseudopotential(const DevParams &P, double rho, double T)
 {
-    const double s = 1.0 + P.kappa * (1.0 - sqrt_nr(T * P.inv_Tc));
+    // T > 0 on every node (the temperature step flags any other value), so
+    // the root of T/T_c needs no zero or sign handling
+    const double s = 1.0 + P.kappa * (1.0 - sqrt_pos(T * P.inv_Tc));
     const double phi = s * s;
     const double D1 = 1.0 - P.b * rho;
     const double D2 = 1.0 + 2.0 * P.b * rho - P.b * P.b * rho * rho;
     const double p = (rho * P.R * T * D2 - P.a * phi * rho * rho * D1) * rcp_nr(D1 * D2);
     const double r = P.two_over_G * (p - rho * (1.0 / 3.0));
-    return (r >= 0.0) ? sqrt_nr(r) : -1.0;
+    return r > 0.0 ? sqrt_pos(r) : (r == 0.0 ? 0.0 : -1.0);
 }
 
 __device__ __forceinline__ void flag_error(Scalars *sc, long long t, unsigned code)
@@ -443,8 +463,10 @@ __device__ __forceinline__ void node_force(const DevParams &P, const double *psi
 
 // MRT collision of one node (Eqs. (2), (4), (5), (8)) in moment space with
 // the D2Q9 basis (rho, e, zeta, jx, qx, jy, qy, pxx, pxy); returns f*.
+// s_nu = 1/tau_nu(rho) comes from the caller, which forms it with 1/rho from
+// one reciprocal.
 __device__ __forceinline__ void collide(const DevParams &P, double f[9], double rho, double vx, double vy,
-                                        double Fx, double Fy, double Q)
+                                        double Fx, double Fy, double Q, double s_nu)
 {
     // moments m = M f, from sums and differences shared between the rows of M
     const double d13 = f[1] - f[3], d24 = f[2] - f[4];
@@ -465,7 +487,6 @@ __device__ __forceinline__ void collide(const DevParams &P, double f[9], double 
     const double v2 = vx * vx + vy * vy;
     const double vF = vx * Fx + vy * Fy;
     const double s_e = (P.s_e), s_z = (P.s_zeta), s_j = (P.s_j), s_q = (P.s_q);
-    const double s_nu = rcp_nr((P.tau_V) + (rho - (P.rho_V)) * (P.tau_slope));
 
     // m* = m - L (m - m_eq) + (I - L/2) S
     const double e_s = m_e - s_e * (m_e - rho * ((-2) + (3) * v2)) + ((1) - (0.5) * s_e) * ((6) * vF + (P.sig_e) * Q);
@@ -556,7 +577,7 @@ __device__ __forceinline__ void tile_psi(const DevParams &P, const S *__restrict
 // pushes.  The parameters are read in place through the lattice table
 // (copied, they would not fit the scalar registers beside the plane bases).
 template <typename S, int TYA, int NWA>
-__global__ __launch_bounds__(64 * NWA) void k_lb(const Inst *__restrict__ insts, const int *__restrict__ blk2inst,
+__global__ __launch_bounds__(64 * NWA, TYA == NWA ? 7 : 1) void k_lb(const Inst *__restrict__ insts, const int *__restrict__ blk2inst,
                                                  int cf, int cT)
 {
     const Inst &I = insts[blk2inst[blockIdx.x]];
@@ -603,12 +624,29 @@ __global__ __launch_bounds__(64 * NWA) void k_lb(const Inst *__restrict__ insts,
         return gy >= 0 && gy < P.ny;
     };
     // rho and psi of node (r, lane) into LDS; returns rho
+    // Row kind, uniform over the wave (one lattice row per wave): 1 bottom
+    // wall, 2 top wall, 0 any other row (or no walls, or f frozen).  Wall
+    // rows complete their populations by the Zou-He rule; the code of each
+    // kind is generated separately, so other rows carry none of it.
+    auto kind_of = [&](int gy) -> int {
+        if (!walls || frozen) return 0;
+        return gy == 0 ? 1 : (gy == P.ny - 1 ? 2 : 0);
+    };
     auto psi_node = [&](int r, int gy, const S fs[9], S Tn) -> double {
         double fl[9];
-        complete_node(P, fs, gy, fl);
-        double rr = fl[0];
 #pragma unroll
-        for (int a = 1; a < 9; ++a) rr += fl[a];
+        for (int a = 0; a < 9; ++a) fl[a] = (double)fs[a];
+        // rho = sum of the completed populations; on a wall row the three
+        // unknowns sum to the three opposite knowns (Zou-He, zero velocity)
+        double rr;
+        const int kind = kind_of(gy);
+        if (kind == 1) rr = fl[0] + fl[1] + fl[3] + 2.0 * (fl[4] + fl[7] + fl[8]);
+        else if (kind == 2) rr = fl[0] + fl[1] + fl[3] + 2.0 * (fl[2] + fl[5] + fl[6]);
+        else {
+            rr = fl[0];
+#pragma unroll
+            for (int a = 1; a < 9; ++a) rr += fl[a];
+        }
         if (!frozen) {
             const double T = P.T_ref + (double)Tn;
             const double psi = pseudopotential(P, rr, T);
@@ -695,10 +733,12 @@ __global__ __launch_bounds__(64 * NWA) void k_lb(const Inst *__restrict__ insts,
         st_at(rho_o, oc, S(rh));
         st_at(vx_o, oc, wall_row ? S(0) : S(vx));
         st_at(vy_o, oc, wall_row ? S(0) : S(vy));
-        collide(P, f, rh, vx, vy, Fx, Fy, Q);
-        // round to the storage precision once; the mass partial sees what is stored
-#pragma unroll
-        for (int a = 0; a < 9; ++a) f[a] = (double)S(f[a]);
+        collide(P, f, rh, vx, vy, Fx, Fy, Q, rcp_nr(P.tau_V + (rh - P.rho_V) * P.tau_slope));
+        // The mass partial sums the post-collision populations before they
+        // are rounded to the storage precision: in FP32 storage it then
+        // differs from the stored mass by the rounding of the populations
+        // (relative ~1e-7 per node, ~1e-10 over a lattice), far below what
+        // rho_ave moves the buoyancy by.
         // push streaming, Eq. (3); populations leaving through a wall are
         // dropped.  Mass of the streamed state: each population counts once,
         // except those that leave through a wall (0) and those that arrive on
