@@ -33,4 +33,9 @@ from .oracle import (  # noqa: F401
     interaction_force,
     thermal_rhs,
     grad_iso,
+    lattice3,
+    feq3,
+    collide_site3,
+    grad_iso3,
+    State3,
 )

@@ -10,7 +10,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["lbb_oracle.c", "lbb_oracle_adjoint.c"]
+SOURCES = ["lbb_oracle.c", "lbb_oracle_adjoint.c", "lbb_oracle3d.c"]
 TARGET = os.path.join(HERE, "liboracle.so")
 
 

@@ -116,6 +116,30 @@ int orc_adjoint(const orc_state *s, int64_t N, int64_t K, double *J, double *dJ_
 int orc_step_vjp(const orc_state *s, const double *lf1, const double *lT1, double *lf0, double *lT0,
                  double *gGw);
 
+/* ---- three-dimensional extension on D3Q19 (lbb_oracle3d.c) ----------- */
+/* Velocities e[3a..3a+2], weights W[a] and the moment basis M[19k + a]. */
+void orc3_lattice(int32_t e[57], double W[19], double M[361]);
+void orc3_feq(double rho, const double v[3], double feq[19]);
+void orc3_collide_site(const orc_params *p, const double f[19], double rho, const double v[3],
+                       const double F[3], double Q, double fpost[19]);
+/* isotropic D3Q19 stencils of phi [nz][ny][nx] (0 on wall rows) */
+void orc3_grad_iso(int32_t nx, int32_t ny, int32_t nz, int32_t periodic_y, const double *phi, double *dx,
+                   double *dy, double *dz, double *lap);
+typedef struct orc3_state orc3_state;
+/* Arrays are [nz][ny][nx] (x fastest); f is [19][nz][ny][nx]; T_bottom is
+ * [nz][nx].  Walls at y = 0 and y = ny-1 unless periodic_y; x and z are
+ * periodic.  ghost_layer must be 0. */
+int orc3_create(const orc_params *p, int32_t nz, const double *rho0, const double *ux0, const double *uy0,
+                const double *uz0, const double *T0, const double *T_bottom, orc3_state **out);
+void orc3_destroy(orc3_state *s);
+int orc3_step(orc3_state *s, int64_t n);
+int64_t orc3_time(const orc3_state *s);
+void orc3_fields(const orc3_state *s, double *rho, double *ux, double *uy, double *uz, double *T, double *f);
+void orc3_heat_flux(const orc3_state *s, double *q_now, double *q_sum, int64_t *n_samples, double *q_local);
+void orc3_reset_average(orc3_state *s);
+void orc3_set_heater(orc3_state *s, const double *T_bottom);
+int orc3_set_storage_rounding(orc3_state *s, int bits);
+
 /* Copy/restore the full state (f, T, time, heat-flux accumulators). */
 int64_t orc_state_size(const orc_state *s);
 void orc_save(const orc_state *s, double *buf);

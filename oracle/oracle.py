@@ -137,6 +137,23 @@ lib.orc_adjoint.argtypes = [C.c_void_p, _i64, _i64, _pd, _pd, _pd]
 lib.orc_step_vjp.restype = C.c_int
 lib.orc_step_vjp.argtypes = [C.c_void_p, _pd, _pd, _pd, _pd, _pd]
 lib.orc_load.argtypes = [C.c_void_p, _pd]
+lib.orc3_lattice.argtypes = [C.POINTER(C.c_int32), _pd, _pd]
+lib.orc3_feq.argtypes = [_d, _pd, _pd]
+lib.orc3_collide_site.argtypes = [_P, _pd, _d, _pd, _pd, _d, _pd]
+lib.orc3_grad_iso.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, _pd, _pd, _pd, _pd, _pd]
+lib.orc3_create.restype = C.c_int
+lib.orc3_create.argtypes = [_P, C.c_int32, _pd, _pd, _pd, _pd, _pd, _pd, C.POINTER(C.c_void_p)]
+lib.orc3_destroy.argtypes = [C.c_void_p]
+lib.orc3_step.restype = C.c_int
+lib.orc3_step.argtypes = [C.c_void_p, _i64]
+lib.orc3_time.restype = _i64
+lib.orc3_time.argtypes = [C.c_void_p]
+lib.orc3_fields.argtypes = [C.c_void_p, _pd, _pd, _pd, _pd, _pd, _pd]
+lib.orc3_heat_flux.argtypes = [C.c_void_p, _pd, _pd, C.POINTER(_i64), _pd]
+lib.orc3_reset_average.argtypes = [C.c_void_p]
+lib.orc3_set_heater.argtypes = [C.c_void_p, _pd]
+lib.orc3_set_storage_rounding.restype = C.c_int
+lib.orc3_set_storage_rounding.argtypes = [C.c_void_p, C.c_int]
 
 
 def _ptr(a):
@@ -346,3 +363,102 @@ class State:
         buf = _f64(buf)
         assert buf.size == lib.orc_state_size(self._h)
         lib.orc_load(self._h, _ptr(buf))
+
+
+# ---- three-dimensional extension (D3Q19) ---------------------------------
+
+
+def lattice3():
+    """D3Q19 velocities e [19, 3], weights W [19] and moment basis M [19, 19]."""
+    e = (C.c_int32 * 57)()
+    W = np.zeros(19)
+    M = np.zeros(361)
+    lib.orc3_lattice(e, _ptr(W), _ptr(M))
+    return np.array(e[:]).reshape(19, 3), W, M.reshape(19, 19)
+
+
+def feq3(rho, v):
+    out = np.zeros(19)
+    v = _f64(np.asarray(v, dtype=float))
+    lib.orc3_feq(rho, _ptr(v), _ptr(out))
+    return out
+
+
+def collide_site3(p: Params, f, rho, v, F, Q):
+    f, v, F = (_f64(np.asarray(x, dtype=float)) for x in (f, v, F))
+    out = np.zeros(19)
+    cp = p.c()
+    lib.orc3_collide_site(C.byref(cp), _ptr(f), rho, _ptr(v), _ptr(F), Q, _ptr(out))
+    return out
+
+
+def grad_iso3(phi, periodic_y=0):
+    """Isotropic D3Q19 stencils of phi [nz, ny, nx]: d_x, d_y, d_z, lap."""
+    phi = _f64(phi)
+    nz, ny, nx = phi.shape
+    outs = [np.zeros_like(phi) for _ in range(4)]
+    lib.orc3_grad_iso(nx, ny, nz, periodic_y, _ptr(phi), *(_ptr(o) for o in outs))
+    return tuple(outs)
+
+
+class State3:
+    """One three-dimensional lattice (D3Q19) under the oracle's time step.
+    Arrays are [nz, ny, nx]; walls at y = 0 and y = ny - 1 unless
+    periodic_y; x and z periodic.  T_bottom is [nz, nx]."""
+
+    def __init__(self, p: Params, nz: int, rho0, ux0=None, uy0=None, uz0=None, T0=None, T_bottom=None):
+        self.p, self.nz = p, int(nz)
+        self._cp = p.c()
+        rho0, ux0, uy0, uz0, T0, T_bottom = (_f64(x) for x in (rho0, ux0, uy0, uz0, T0, T_bottom))
+        assert rho0.shape == (nz, p.ny, p.nx)
+        h = C.c_void_p()
+        rc = lib.orc3_create(C.byref(self._cp), self.nz, _ptr(rho0), _ptr(ux0), _ptr(uy0), _ptr(uz0), _ptr(T0),
+                             _ptr(T_bottom), C.byref(h))
+        if rc != 0:
+            raise OracleError(rc, "invalid 3-D parameters or initial state")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib.orc3_destroy(h)
+            self._h = None
+
+    @property
+    def t(self) -> int:
+        return lib.orc3_time(self._h)
+
+    def step(self, n: int = 1):
+        rc = lib.orc3_step(self._h, int(n))
+        if rc != 0:
+            raise OracleError(rc, "3-D step failed")
+        return self
+
+    def store_bits(self, bits: int):
+        """Rounding model as State.store_bits."""
+        rc = lib.orc3_set_storage_rounding(self._h, int(bits))
+        if rc != 0:
+            raise OracleError(rc, "bits must lie in 0..52")
+        return self
+
+    def fields(self):
+        shape = (self.nz, self.p.ny, self.p.nx)
+        rho, ux, uy, uz, T = (np.zeros(shape) for _ in range(5))
+        f = np.zeros((19,) + shape)
+        lib.orc3_fields(self._h, _ptr(rho), _ptr(ux), _ptr(uy), _ptr(uz), _ptr(T), _ptr(f))
+        return dict(rho=rho, ux=ux, uy=uy, uz=uz, T=T, f=f)
+
+    def heat_flux(self):
+        qn, qs, ns = _d(), _d(), _i64()
+        ql = np.zeros((self.nz, self.p.nx))
+        lib.orc3_heat_flux(self._h, C.byref(qn), C.byref(qs), C.byref(ns), _ptr(ql))
+        n = ns.value
+        return dict(q_now=qn.value, q_sum=qs.value, n_samples=n,
+                    q_mean=(qs.value / n if n else float("nan")), q_local=ql)
+
+    def reset_average(self):
+        lib.orc3_reset_average(self._h)
+
+    def set_heater(self, T_bottom):
+        T_bottom = _f64(T_bottom)
+        lib.orc3_set_heater(self._h, _ptr(T_bottom))
