@@ -348,6 +348,47 @@ typedef struct lbb_noalloc_result {
 int lbb_step_noalloc(const lbb_params *p, void *const f[2], void *const T[2], void *rho, void *vx, void *vy,
                      int32_t phase[2], int64_t n, lbb_noalloc_result *result, void *stream);
 
+/* ---- Three-dimensional lattices (D3Q19) ---------------------------------
+ * The same time step on a nx x ny x nz lattice: the extension to three
+ * dimensions the paper names as its future work (Sec. 4).  The D3Q19 MRT
+ * collision in the standard orthogonal moment basis with the improved
+ * forcing (Eqs. (2), (4), (5), (8); the sigma term adds to each diagonal
+ * component of the second moment the increment of the two-dimensional
+ * term), the interaction force Eq. (7) with weights 1/6 (axes) and 1/12
+ * (edges), the fluid-solid force Eq. (22), buoyancy Eq. (9), zero-velocity
+ * Zou-He walls at y = 0 and y = ny-1 with transverse-momentum correction
+ * (periodic x and z), and the RK4 temperature step Eqs. (18)-(20) with the
+ * isotropic D3Q19 stencils; the bottom-wall heat flux averages over x and z.
+ * Arrays are row-major [nz][ny][nx] (x fastest), FP64 host buffers:
+ *   T_bottom [nz*nx], rho0 [nz*ny*nx] (NULL: layered state with noise as
+ *   lbb_init_domain, counter (z*ny + y)*nx + x), u [3][nz][ny][nx],
+ *   f [19][nz][ny][nx] with velocities rest, +x, -x, +y, -y, +z, -z,
+ *   (1,1,0), (-1,-1,0), (1,-1,0), (-1,1,0), (1,0,1), (-1,0,-1), (1,0,-1),
+ *   (-1,0,1), (0,1,1), (0,-1,-1), (0,1,-1), (0,-1,1); q_local [nz][nx].
+ * Parameters as lbb_init_domain; the relaxation rates of the D3Q19 basis are
+ * s_rho, s_e, s_zeta (epsilon and the pi moments), s_j, s_q (q and the m
+ * moments) and s_nu.  EINVAL for nz < 3 or a lattice of 2^32 / 19 nodes or
+ * more; EUNSUPPORTED for ghost_layer = 1.  Steps, errors, poisoning,
+ * samples and averages behave as in two dimensions. */
+typedef struct lbb3_domain lbb3_domain;
+int lbb3_init_domain(const lbb_params *p, int32_t nz, const double *T_bottom, const double *rho0,
+                     lbb3_domain **out);
+/* Replace the state: f = f_eq(rho, u), T (u, T may be NULL: rest; T_s),
+ * Dirichlet rows reset; counters and average reset. */
+int lbb3_set_fields(lbb3_domain *d, const double *rho, const double *u, const double *T);
+int lbb3_step(lbb3_domain *d, int64_t n);
+int lbb3_step_async(lbb3_domain *d, int64_t n);
+int lbb3_sync(lbb3_domain *d);
+void *lbb3_stream(lbb3_domain *d);
+/* rho, u (Eq. (6) with the force of the current state), T, f (completed),
+ * widened to FP64; any pointer may be NULL. */
+int lbb3_read_fields(lbb3_domain *d, double *rho, double *u, double *T, double *f);
+int lbb3_wall_heat_flux(lbb3_domain *d, double *q_now, double *q_mean, double *q_local, int64_t *n_samples);
+int lbb3_reset_average(lbb3_domain *d);
+int lbb3_set_heater(lbb3_domain *d, const double *T_bottom);
+int lbb3_info(lbb3_domain *d, int64_t *t, int64_t *device_bytes);
+int lbb3_destroy(lbb3_domain *d);
+
 /* Current step count, grid shape and device bytes held by the domain. */
 int lbb_info(lbb_domain *d, int64_t *t, int32_t *nx, int32_t *ny, int64_t *device_bytes);
 

@@ -1,0 +1,610 @@
+// Device code of the three-dimensional path: the time step of the hybrid
+// thermal pseudopotential LB boiling model (arXiv:1501.03857, Sec. 2) on the
+// D3Q19 lattice, the extension the paper names as its future work (Sec. 4).
+// gfx950, wave64.
+//
+// Data layout in HBM (structure of arrays, x fastest, then y, then z):
+//   f[2][19][nz][ny][nx]  post-streaming populations, double-buffered; wall
+//                         rows never store the five populations arriving
+//                         from outside (completed by the Zou-He rule on read)
+//   T[2][nz][ny][nx]      T - T_ref (T_ref = 0 in FP64, T_s in FP32)
+//   rho, v[3]             density and the velocity the temperature equation
+//                         sees (zero on wall rows), storage precision
+//   psi                   pseudopotential, FP64
+//   coef[5]               per-node coefficients of the temperature equation
+//   Ts[2], acc            RK4 stage values and slope sum
+// Walls at y = 0 and y = ny-1 (gravity along -y), periodic x and z.
+//
+// One step t -> t+1 is seven launches, each one node per thread:
+//   k3_psi      rho (Eq. (6)) and psi (FP64 Peng-Robinson EOS, Eq. (21)) of
+//               state t; per-block FP64 partials of the mass and, on the
+//               bottom wall, of the heat flux of state t (Sec. 3.2)
+//   k3_reduce   one block: rho_ave (Eq. (9)) and the heat-flux sample
+//   k3_lb       forces (Eqs. (7), (9), (22)), velocity, MRT collision with
+//               the improved forcing (Eqs. (2), (4), (5), (8)) and push
+//               streaming (Eq. (3))
+//   k3_stage x4 the four RK4 stages (Eqs. (19)-(20)) of Eq. (18); the first
+//               also forms the per-node coefficients, the last writes T
+// All reductions run in a fixed order, so results are reproducible bitwise.
+#pragma once
+
+#include "lbb_device.hpp"
+
+namespace lbb3 {
+
+using lbb::DevParams;
+using lbb::gmem;
+using lbb::rcp_nr;
+using lbb::sqrt_pos;
+
+constexpr int NT3 = 256;  // threads per block (4 waves)
+constexpr int Q19 = 19;
+
+// D3Q19 velocities: rest, +x, -x, +y, -y, +z, -z, then the edges
+constexpr int EX3[Q19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int EY3[Q19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int EZ3[Q19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+// lattice weight of velocity a, times 36
+constexpr int W36[Q19] = {12, 2, 2, 2, 2, 2, 2, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1};
+
+// Row k of the orthogonal D3Q19 moment basis at velocity a (rho, e,
+// epsilon, j_x, q_x, j_y, q_y, j_z, q_z, 3p_xx, 3pi_xx, p_ww, pi_ww, p_xy,
+// p_yz, p_xz, m_x, m_y, m_z); all entries are integers.
+constexpr int basis3(int k, int a)
+{
+    const int x = EX3[a], y = EY3[a], z = EZ3[a];
+    const int e2 = x * x + y * y + z * z;
+    switch (k) {
+    case 0: return 1;
+    case 1: return 19 * e2 - 30;
+    case 2: return (21 * e2 * e2 - 53 * e2 + 24) / 2;
+    case 3: return x;
+    case 4: return (5 * e2 - 9) * x;
+    case 5: return y;
+    case 6: return (5 * e2 - 9) * y;
+    case 7: return z;
+    case 8: return (5 * e2 - 9) * z;
+    case 9: return 3 * x * x - e2;
+    case 10: return (3 * e2 - 5) * (3 * x * x - e2);
+    case 11: return y * y - z * z;
+    case 12: return (3 * e2 - 5) * (y * y - z * z);
+    case 13: return x * y;
+    case 14: return y * z;
+    case 15: return x * z;
+    case 16: return (y * y - z * z) * x;
+    case 17: return (z * z - x * x) * y;
+    default: return (x * x - y * y) * z;
+    }
+}
+// squared row norms: M M^T = diag(NORM3)
+constexpr double NORM3[Q19] = {19, 2394, 252, 10, 40, 10, 40, 10, 40, 36, 72, 12, 24, 4, 4, 4, 8, 8, 8};
+
+// sum_a B_ka v_a with the integer basis, zeros skipped and +-1 folded at
+// compile time (k and a are constants after unrolling)
+template <int K>
+__device__ __forceinline__ double row_dot(const double v[Q19])
+{
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < Q19; ++a) {
+        const int c = basis3(K, a);
+        if (c == 0) continue;
+        if (c == 1) s += v[a];
+        else if (c == -1) s -= v[a];
+        else s = fma((double)c, v[a], s);
+    }
+    return s;
+}
+
+template <int K = 0>
+__device__ __forceinline__ void moments(const double f[Q19], double m[Q19])
+{
+    if constexpr (K < Q19) {
+        m[K] = row_dot<K>(f);
+        moments<K + 1>(f, m);
+    }
+}
+
+// f_a = sum_k B_ka mh_k (mh = moments already divided by the row norms)
+__device__ __forceinline__ void from_moments(const double mh[Q19], double f[Q19])
+{
+#pragma unroll
+    for (int a = 0; a < Q19; ++a) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < Q19; ++k) {
+            const int c = basis3(k, a);
+            if (c == 0) continue;
+            if (c == 1) s += mh[k];
+            else if (c == -1) s -= mh[k];
+            else s = fma((double)c, mh[k], s);
+        }
+        f[a] = s;
+    }
+}
+
+__device__ __forceinline__ int wrap3(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// Zou-He completion of a wall node with zero velocity: the unknowns are the
+// reflected knowns, corrected by the transverse momentum of the populations
+// parallel to the wall, so the node carries no momentum.
+__device__ __forceinline__ void zou_he3(double f[Q19], bool bottom)
+{
+    const double Nx = 0.5 * (f[1] - f[2] + f[11] - f[12] + f[13] - f[14]);
+    const double Nz = 0.5 * (f[5] - f[6] + f[11] - f[12] - f[13] + f[14]);
+    if (bottom) {
+        f[3] = f[4];
+        f[7] = f[8] - Nx;
+        f[10] = f[9] + Nx;
+        f[15] = f[16] - Nz;
+        f[17] = f[18] + Nz;
+    } else {
+        f[4] = f[3];
+        f[8] = f[7] + Nx;
+        f[9] = f[10] - Nx;
+        f[16] = f[15] + Nz;
+        f[18] = f[17] - Nz;
+    }
+}
+
+struct Geom3 {
+    int nx, ny, nz;
+    unsigned n;  // nx ny nz
+};
+
+// node c -> (x, y, z)
+__device__ __forceinline__ void coords(const Geom3 &g, unsigned c, int &x, int &y, int &z)
+{
+    const unsigned xy = (unsigned)g.nx * (unsigned)g.ny;
+    z = (int)(c / xy);
+    const unsigned r = c - (unsigned)z * xy;
+    y = (int)(r / (unsigned)g.nx);
+    x = (int)(r - (unsigned)y * (unsigned)g.nx);
+}
+
+__device__ __forceinline__ unsigned node(const Geom3 &g, int x, int y, int z)
+{
+    return ((unsigned)z * (unsigned)g.ny + (unsigned)y) * (unsigned)g.nx + (unsigned)x;
+}
+
+// neighbour along sign * e_a (x, z periodic; y periodic or bounded): false
+// beyond a wall
+__device__ __forceinline__ bool nbr(const DevParams &P, const Geom3 &g, int x, int y, int z, int a, int sign,
+                                    unsigned &out)
+{
+    const int xx = wrap3(x + sign * EX3[a], g.nx), zz = wrap3(z + sign * EZ3[a], g.nz);
+    int yy = y + sign * EY3[a];
+    if (P.periodic_y) yy = wrap3(yy, g.ny);
+    else if (yy < 0 || yy >= g.ny) return false;
+    out = node(g, xx, yy, zz);
+    return true;
+}
+
+template <typename S>
+__device__ __forceinline__ void load_f(const DevParams &P, const Geom3 &g, const S *__restrict__ f, unsigned c, int y,
+                                       double fl[Q19])
+{
+#pragma unroll
+    for (int a = 0; a < Q19; ++a) fl[a] = (double)((const gmem<S> *)f)[(size_t)a * g.n + c];
+    if (!P.periodic_y && P.mode != lbb::MODE_THERMAL_ONLY) {
+        if (y == 0) zou_he3(fl, true);
+        else if (y == g.ny - 1) zou_he3(fl, false);
+    }
+}
+
+struct Scalars3 {
+    double rho_ave;
+    double q_now, q_sum;
+    long long n_samples, last_counted, t;
+    unsigned long long err_step;
+    unsigned int err_code, pad;
+};
+
+__device__ __forceinline__ void flag3(Scalars3 *sc, long long t, unsigned code)
+{
+    atomicMin(&sc->err_step, (unsigned long long)t);
+    atomicOr(&sc->err_code, code);
+}
+
+// block sum of one double per thread in a fixed order; valid in thread 0
+__device__ __forceinline__ double block_sum3(double v, double *red)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < NT3 / 64; ++k) s += red[k];
+    return s;
+}
+
+// psi = sqrt(2 (p_EOS - rho/3) / G), FP64 (Eq. (21)); negative on a negative radicand
+__device__ __forceinline__ double psi_of(const DevParams &P, double rho, double T)
+{
+    const double s = 1.0 + P.kappa * (1.0 - sqrt_pos(T * P.inv_Tc));
+    const double phi = s * s;
+    const double D1 = 1.0 - P.b * rho;
+    const double D2 = 1.0 + 2.0 * P.b * rho - P.b * P.b * rho * rho;
+    const double p = (rho * P.R * T * D2 - P.a * phi * rho * rho * D1) * rcp_nr(D1 * D2);
+    const double r = P.two_over_G * (p - rho * (1.0 / 3.0));
+    return r > 0.0 ? sqrt_pos(r) : (r == 0.0 ? 0.0 : -1.0);
+}
+
+// ---------------------------------------------------------------------------
+// rho and psi of state t; mass and bottom-wall heat-flux partials per block.
+// In THERMAL_ONLY mode (f frozen) it also writes v = sum e f / rho.
+template <typename S>
+__global__ __launch_bounds__(NT3) void k3_psi(DevParams P, Geom3 g, const S *__restrict__ f, const S *__restrict__ T,
+                                             S *__restrict__ rho_o, double *__restrict__ psi_o, S *__restrict__ vx_o,
+                                             S *__restrict__ vy_o, S *__restrict__ vz_o, double *__restrict__ mpart,
+                                             double *__restrict__ hpart, Scalars3 *sc)
+{
+    __shared__ double red[NT3 / 64];
+    const unsigned c = blockIdx.x * NT3 + threadIdx.x;
+    double mass = 0.0, qw = 0.0;
+    const long long t = sc->t;
+    if (c < g.n) {
+        int x, y, z;
+        coords(g, c, x, y, z);
+        double fl[Q19];
+        load_f(P, g, f, c, y, fl);
+        double r = fl[0];
+#pragma unroll
+        for (int a = 1; a < Q19; ++a) r += fl[a];
+        mass = r;
+        const double Tc_ = P.T_ref + (double)((const gmem<S> *)T)[c];
+        if (!(r > 0.0) || !(r < 1e300)) flag3(sc, t, lbb::ERR_RHO);
+        ((gmem<S> *)rho_o)[c] = S(r);
+        if (P.mode == lbb::MODE_THERMAL_ONLY) {
+            const bool wall = !P.periodic_y && (y == 0 || y == g.ny - 1);
+            double j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int a = 1; a < Q19; ++a) {
+                j[0] += EX3[a] * fl[a];
+                j[1] += EY3[a] * fl[a];
+                j[2] += EZ3[a] * fl[a];
+            }
+            ((gmem<S> *)vx_o)[c] = wall ? S(0) : S(j[0] / r);
+            ((gmem<S> *)vy_o)[c] = wall ? S(0) : S(j[1] / r);
+            ((gmem<S> *)vz_o)[c] = wall ? S(0) : S(j[2] / r);
+        } else {
+            const double psi = psi_of(P, r, Tc_);
+            if (!(psi >= 0.0) || !(psi < 1e300)) flag3(sc, t, lbb::ERR_PSI);
+            ((gmem<double> *)psi_o)[c] = psi;
+        }
+        if (!P.periodic_y && y == 0) {
+            const double t0 = (double)((const gmem<S> *)T)[c];
+            const double t1 = (double)((const gmem<S> *)T)[c + (unsigned)g.nx];
+            const double t2 = (double)((const gmem<S> *)T)[c + 2u * (unsigned)g.nx];
+            qw = -P.cv_chi * r * (-3.0 * t0 + 4.0 * t1 - t2) / 2.0;
+        }
+    }
+    const double ms = block_sum3(mass, red);
+    __syncthreads();
+    const double hs = block_sum3(qw, red);
+    if (threadIdx.x == 0) {
+        mpart[blockIdx.x] = ms;
+        hpart[blockIdx.x] = hs;
+    }
+}
+
+// rho_ave of state t and its heat-flux sample (counted once per state index
+// t >= 1), one block; with `advance` the state index then moves to t + 1,
+// the state the rest of the step produces.
+__global__ __launch_bounds__(NT3) void k3_reduce(Geom3 g, const double *__restrict__ mpart,
+                                                 const double *__restrict__ hpart, int nb, Scalars3 *sc, int advance)
+{
+    __shared__ double red[NT3 / 64];
+    double m = 0.0, h = 0.0;
+    for (int k = threadIdx.x; k < nb; k += NT3) {
+        m += mpart[k];
+        h += hpart[k];
+    }
+    const double ms = block_sum3(m, red);
+    __syncthreads();
+    const double hs = block_sum3(h, red);
+    if (threadIdx.x == 0) {
+        sc->rho_ave = ms / (double)g.n;
+        const double q = hs / ((double)g.nx * (double)g.nz);
+        sc->q_now = q;
+        if (sc->t > sc->last_counted) {
+            sc->q_sum += q;
+            sc->n_samples += 1;
+            sc->last_counted = sc->t;
+        }
+        if (advance) sc->t += 1;
+    }
+}
+
+// total force on a node of state t (Eq. (7) + Eq. (22) + Eq. (9)) and
+// Q = |F_m|^2/psi^2 (Eq. (8)): none on the wall rows; the fluid-solid force
+// on the rows next to them, the wall rows being the solid
+__device__ __forceinline__ void force3(const DevParams &P, const Geom3 &g, const double *__restrict__ psi, int x,
+                                       int y, int z, unsigned c, double rho, double rho_ave, double F[3], double &Q)
+{
+    F[0] = F[1] = F[2] = 0.0;
+    Q = 0.0;
+    if (!P.periodic_y && (y == 0 || y == g.ny - 1)) return;
+    const double pc = ((const gmem<double> *)psi)[c];
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+#pragma unroll
+    for (int a = 1; a < Q19; ++a) {
+        unsigned o = c;
+        nbr(P, g, x, y, z, a, 1, o);
+        const double w = (a < 7 ? 1.0 / 6.0 : 1.0 / 12.0) * ((const gmem<double> *)psi)[o];
+        if (EX3[a]) sx = fma((double)EX3[a], w, sx);
+        if (EY3[a]) sy = fma((double)EY3[a], w, sy);
+        if (EZ3[a]) sz = fma((double)EZ3[a], w, sz);
+    }
+    F[0] = -P.G * pc * sx;
+    F[1] = -P.G * pc * sy;
+    F[2] = -P.G * pc * sz;
+    Q = P.G * P.G * (sx * sx + sy * sy + sz * sz);
+    if (!P.periodic_y) {
+        if (y == 1) F[1] += P.Gw_bottom * pc * pc * (1.0 / 6.0);
+        if (y == g.ny - 2) F[1] -= P.Gw_top * pc * pc * (1.0 / 6.0);
+    }
+    F[1] -= (rho - rho_ave) * P.g;
+}
+
+// MRT collision of one node in the D3Q19 basis with the improved forcing.
+__device__ __forceinline__ void collide3(const DevParams &P, double f[Q19], double rho, const double v[3],
+                                         const double F[3], double Q, double s_nu)
+{
+    double m[Q19];
+    moments(f, m);
+    const double vx = v[0], vy = v[1], vz = v[2];
+    const double v2 = vx * vx + vy * vy + vz * vz, vF = vx * F[0] + vy * F[1] + vz * F[2];
+    const double pxx = rho * (3.0 * vx * vx - v2), pww = rho * (vy * vy - vz * vz);
+    const double Sxx = 2.0 * (3.0 * vx * F[0] - vF), Sww = 2.0 * (vy * F[1] - vz * F[2]);
+    // equilibrium moments (M f_eq) and forcing moments (M F' of the Guo term)
+    const double meq[Q19] = {rho, rho * (19.0 * v2 - 11.0), rho * (3.0 - 5.5 * v2), rho * vx, -(2.0 / 3.0) * rho * vx,
+                             rho * vy, -(2.0 / 3.0) * rho * vy, rho * vz, -(2.0 / 3.0) * rho * vz, pxx, -0.5 * pxx,
+                             pww, -0.5 * pww, rho * vx * vy, rho * vy * vz, rho * vx * vz, 0.0, 0.0, 0.0};
+    const double S[Q19] = {0.0,
+                           38.0 * vF + P.sig_e * 9.5 * Q,
+                           -11.0 * vF - P.sig_z * 3.8 * Q,
+                           F[0], -(2.0 / 3.0) * F[0], F[1], -(2.0 / 3.0) * F[1], F[2], -(2.0 / 3.0) * F[2],
+                           Sxx, -0.5 * Sxx, Sww, -0.5 * Sww,
+                           vx * F[1] + vy * F[0], vy * F[2] + vz * F[1], vx * F[2] + vz * F[0], 0.0, 0.0, 0.0};
+    const double L[Q19] = {P.s_rho, P.s_e, P.s_zeta, P.s_j, P.s_q, P.s_j, P.s_q, P.s_j, P.s_q, s_nu,
+                           P.s_zeta, s_nu, P.s_zeta, s_nu, s_nu, s_nu, P.s_q, P.s_q, P.s_q};
+    double mh[Q19];
+#pragma unroll
+    for (int k = 0; k < Q19; ++k)
+        mh[k] = (m[k] - L[k] * (m[k] - meq[k]) + (1.0 - 0.5 * L[k]) * S[k]) * (1.0 / NORM3[k]);
+    from_moments(mh, f);
+}
+
+// forces, velocity, collision and push streaming of state t
+template <typename S>
+__global__ __launch_bounds__(NT3) void k3_lb(DevParams P, Geom3 g, const S *__restrict__ fin, S *__restrict__ fout,
+                                            const double *__restrict__ psi, S *__restrict__ vx_o,
+                                            S *__restrict__ vy_o, S *__restrict__ vz_o, const Scalars3 *sc)
+{
+    const unsigned c = blockIdx.x * NT3 + threadIdx.x;
+    if (c >= g.n) return;
+    int x, y, z;
+    coords(g, c, x, y, z);
+    double f[Q19];
+    load_f(P, g, fin, c, y, f);
+    double rho = f[0];
+#pragma unroll
+    for (int a = 1; a < Q19; ++a) rho += f[a];
+    double F[3], Q;
+    force3(P, g, psi, x, y, z, c, rho, sc->rho_ave, F, Q);
+    double j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 1; a < Q19; ++a) {
+        if (EX3[a]) j[0] += EX3[a] * f[a];
+        if (EY3[a]) j[1] += EY3[a] * f[a];
+        if (EZ3[a]) j[2] += EZ3[a] * f[a];
+    }
+    const double inv = rcp_nr(rho);
+    const double v[3] = {(j[0] + 0.5 * F[0]) * inv, (j[1] + 0.5 * F[1]) * inv, (j[2] + 0.5 * F[2]) * inv};
+    const bool wall = !P.periodic_y && (y == 0 || y == g.ny - 1);
+    ((gmem<S> *)vx_o)[c] = wall ? S(0) : S(v[0]);
+    ((gmem<S> *)vy_o)[c] = wall ? S(0) : S(v[1]);
+    ((gmem<S> *)vz_o)[c] = wall ? S(0) : S(v[2]);
+    collide3(P, f, rho, v, F, Q, rcp_nr(P.tau_V + (rho - P.rho_V) * P.tau_slope));
+#pragma unroll
+    for (int a = 0; a < Q19; ++a) {
+        unsigned o;
+        if (nbr(P, g, x, y, z, a, 1, o)) ((gmem<S> *)fout)[(size_t)a * g.n + o] = S(f[a]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Temperature equation (Eq. (18)) by RK4: K = -(a . grad T) + chi lap T +
+// c1 T + c2 sqrt(T), with a = v - chi grad(rho)/rho and the pressure work
+// -w T (dp/dT)_rho = c1 T + c2 sqrt(T), w = div v / (rho c_v) (the same
+// split of (dp/dT)_rho as in two dimensions), on rows 1..ny-2; the wall rows
+// keep their Dirichlet values in every stage.
+
+// isotropic D3Q19 stencil sums at node (x,y,z) of field p: 3 sum W e p and
+// 6 sum W (p(nbr) - p(c)), the wall-row nodes not evaluated
+template <typename T_>
+__device__ __forceinline__ void stencil3(const DevParams &P, const Geom3 &g, const T_ *__restrict__ p, int x, int y,
+                                         int z, unsigned c, double off, double grad[3], double *lap)
+{
+    const double pc = off + (double)((const gmem<T_> *)p)[c];
+    double gx = 0.0, gy = 0.0, gz = 0.0, l = 0.0;
+#pragma unroll
+    for (int a = 1; a < Q19; ++a) {
+        unsigned o = c;
+        nbr(P, g, x, y, z, a, 1, o);
+        const double w = W36[a] * (1.0 / 36.0);
+        const double val = off + (double)((const gmem<T_> *)p)[o];
+        if (EX3[a]) gx = fma(EX3[a] * w, val, gx);
+        if (EY3[a]) gy = fma(EY3[a] * w, val, gy);
+        if (EZ3[a]) gz = fma(EZ3[a] * w, val, gz);
+        l = fma(w, val - pc, l);
+    }
+    grad[0] = 3.0 * gx;
+    grad[1] = 3.0 * gy;
+    grad[2] = 3.0 * gz;
+    if (lap) *lap = 6.0 * l;
+}
+
+// Stage K (0..3).  Reads the stage input (T^t for K = 0, else Tin), writes
+// the next stage input Tout = T^t + c_{K+1} h (K < 3) or T^{t+1} (K = 3).
+template <typename S, int K>
+__global__ __launch_bounds__(NT3) void k3_stage(DevParams P, Geom3 g, const S *__restrict__ T0,
+                                               const S *__restrict__ Tin, S *__restrict__ Tout,
+                                               S *__restrict__ acc, S *__restrict__ coef,
+                                               const S *__restrict__ rho, const S *__restrict__ vx,
+                                               const S *__restrict__ vy, const S *__restrict__ vz, Scalars3 *sc)
+{
+    const unsigned c = blockIdx.x * NT3 + threadIdx.x;
+    if (c >= g.n) return;
+    int x, y, z;
+    coords(g, c, x, y, z);
+    const bool wall = !P.periodic_y && (y == 0 || y == g.ny - 1);
+    const double t0 = (double)((const gmem<S> *)T0)[c];
+    double h = 0.0;
+    if (!wall) {
+        double a[3], c1, c2;
+        gmem<S> *cf = (gmem<S> *)coef;
+        if constexpr (K == 0) {
+            // coefficients, once per step: grad rho, div v, A(rho), B(rho)
+            const double r = (double)((const gmem<S> *)rho)[c];
+            double gr[3], gv[3], d[3];
+            stencil3(P, g, rho, x, y, z, c, 0.0, gr, nullptr);
+            stencil3(P, g, vx, x, y, z, c, 0.0, d, nullptr);
+            gv[0] = d[0];
+            stencil3(P, g, vy, x, y, z, c, 0.0, d, nullptr);
+            gv[1] = d[1];
+            stencil3(P, g, vz, x, y, z, c, 0.0, d, nullptr);
+            gv[2] = d[2];
+            const double div = gv[0] + gv[1] + gv[2];
+            const double D1 = 1.0 - P.b * r, D2 = 1.0 + 2.0 * P.b * r - P.b * P.b * r * r;
+            const double inv = rcp_nr(r * D1 * D2);
+            const double chi_r = P.chi * D1 * D2 * inv;
+            const double Aw = P.R_cv * div * (r * D2 * inv), Bw = P.a_cv * r * div * (r * D1 * inv);
+            a[0] = (double)((const gmem<S> *)vx)[c] - chi_r * gr[0];
+            a[1] = (double)((const gmem<S> *)vy)[c] - chi_r * gr[1];
+            a[2] = (double)((const gmem<S> *)vz)[c] - chi_r * gr[2];
+            c1 = Bw * P.k2_Tc - Aw;
+            c2 = -Bw * P.k1k_rsTc;
+            cf[0 * (size_t)g.n + c] = S(a[0]);
+            cf[1 * (size_t)g.n + c] = S(a[1]);
+            cf[2 * (size_t)g.n + c] = S(a[2]);
+            cf[3 * (size_t)g.n + c] = S(c1);
+            cf[4 * (size_t)g.n + c] = S(c2);
+            a[0] = (double)S(a[0]);
+            a[1] = (double)S(a[1]);
+            a[2] = (double)S(a[2]);
+            c1 = (double)S(c1);
+            c2 = (double)S(c2);
+        } else {
+            a[0] = (double)cf[0 * (size_t)g.n + c];
+            a[1] = (double)cf[1 * (size_t)g.n + c];
+            a[2] = (double)cf[2 * (size_t)g.n + c];
+            c1 = (double)cf[3 * (size_t)g.n + c];
+            c2 = (double)cf[4 * (size_t)g.n + c];
+        }
+        double gT[3], lap;
+        const S *src = K == 0 ? T0 : Tin;
+        stencil3(P, g, src, x, y, z, c, 0.0, gT, &lap);
+        const double Tabs = P.T_ref + (double)((const gmem<S> *)src)[c];
+        h = -(a[0] * gT[0] + a[1] * gT[1] + a[2] * gT[2]) + P.chi * lap + c1 * Tabs + c2 * sqrt_pos(Tabs);
+    }
+    gmem<S> *ac = (gmem<S> *)acc;
+    constexpr double wst = (K == 0 || K == 3) ? 1.0 : 2.0;
+    const double sum = K == 0 ? h : (double)ac[c] + wst * h;
+    if constexpr (K < 3) {
+        constexpr double cst = K < 2 ? 0.5 : 1.0;
+        ac[c] = S(sum);
+        ((gmem<S> *)Tout)[c] = S(t0 + cst * h);
+    } else {
+        const double Tn = wall ? t0 : (double)S(t0 + sum * (1.0 / 6.0));
+        if (!wall && !(P.T_ref + Tn > 0.0)) flag3(sc, sc->t, lbb::ERR_T);
+        ((gmem<S> *)Tout)[c] = S(Tn);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Set-up and read-back.
+
+template <typename S>
+__global__ void k3_set_state(DevParams P, Geom3 g, const double *__restrict__ rho, const double *__restrict__ u,
+                             const double *__restrict__ T, const double *__restrict__ Tb, S *__restrict__ f,
+                             S *__restrict__ T0, S *__restrict__ T1, Scalars3 *sc)
+{
+    const unsigned c = blockIdx.x * NT3 + threadIdx.x;
+    if (c >= g.n) return;
+    int x, y, z;
+    coords(g, c, x, y, z);
+    const bool wall = !P.periodic_y && (y == 0 || y == g.ny - 1);
+    const double r = rho[c];
+    const double vx = (u && !wall) ? u[c] : 0.0, vy = (u && !wall) ? u[g.n + c] : 0.0,
+                 vz = (u && !wall) ? u[2 * (size_t)g.n + c] : 0.0;
+    const double v2 = vx * vx + vy * vy + vz * vz;
+#pragma unroll
+    for (int a = 0; a < Q19; ++a) {
+        const double eu = EX3[a] * vx + EY3[a] * vy + EZ3[a] * vz;
+        const double W = a == 0 ? 1.0 / 3.0 : (a < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+        f[(size_t)a * g.n + c] = S(W * r * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * v2));
+    }
+    double Tv = T ? T[c] : P.Ts;
+    if (!P.periodic_y && y == 0) Tv = Tb[(size_t)z * g.nx + x];
+    if (!P.periodic_y && y == g.ny - 1) Tv = P.Ts;
+    T0[c] = S(Tv - P.T_ref);
+    T1[c] = S(Tv - P.T_ref);
+    if (!(r > 0.0) || !(Tv > 0.0) || !(P.b * r < 1.0)) flag3(sc, 0, lbb::ERR_RHO);
+}
+
+// rho, v of Eq. (6) with the force of the current state (psi and rho_ave of
+// the current state must be up to date), T and the completed f, in FP64
+template <typename S>
+__global__ __launch_bounds__(NT3) void k3_read(DevParams P, Geom3 g, const S *__restrict__ fin,
+                                              const S *__restrict__ Tin, const double *__restrict__ psi,
+                                              const Scalars3 *sc, double *__restrict__ rho_o, double *__restrict__ u_o,
+                                              double *__restrict__ T_o, double *__restrict__ f_o,
+                                              double *__restrict__ qloc)
+{
+    const unsigned c = blockIdx.x * NT3 + threadIdx.x;
+    if (c >= g.n) return;
+    int x, y, z;
+    coords(g, c, x, y, z);
+    double f[Q19];
+    load_f(P, g, fin, c, y, f);
+    double r = f[0];
+#pragma unroll
+    for (int a = 1; a < Q19; ++a) r += f[a];
+    double F[3] = {0.0, 0.0, 0.0}, Q;
+    if (P.mode != lbb::MODE_THERMAL_ONLY) force3(P, g, psi, x, y, z, c, r, sc->rho_ave, F, Q);
+    double j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 1; a < Q19; ++a) {
+        j[0] += EX3[a] * f[a];
+        j[1] += EY3[a] * f[a];
+        j[2] += EZ3[a] * f[a];
+    }
+    if (rho_o) rho_o[c] = r;
+    if (u_o)
+        for (int d = 0; d < 3; ++d) u_o[(size_t)d * g.n + c] = (j[d] + 0.5 * F[d]) / r;
+    if (T_o) T_o[c] = P.T_ref + (double)Tin[c];
+    if (f_o)
+        for (int a = 0; a < Q19; ++a) f_o[(size_t)a * g.n + c] = f[a];
+    if (qloc && !P.periodic_y && y == 0) {
+        const double t0 = (double)Tin[c], t1 = (double)Tin[c + (unsigned)g.nx], t2 = (double)Tin[c + 2u * (unsigned)g.nx];
+        qloc[(size_t)z * g.nx + x] = -P.cv_chi * r * (-3.0 * t0 + 4.0 * t1 - t2) / 2.0;
+    }
+}
+
+template <typename S>
+__global__ void k3_set_heater(DevParams P, Geom3 g, const double *__restrict__ Tb, S *__restrict__ T0,
+                              S *__restrict__ T1)
+{
+    const unsigned k = blockIdx.x * NT3 + threadIdx.x;
+    if (P.periodic_y || k >= (unsigned)g.nx * (unsigned)g.nz) return;
+    const unsigned z = k / (unsigned)g.nx, x = k - z * (unsigned)g.nx;
+    const unsigned c = node(g, (int)x, 0, (int)z);
+    T0[c] = S(Tb[k] - P.T_ref);
+    T1[c] = S(Tb[k] - P.T_ref);
+}
+
+}  // namespace lbb3

@@ -2278,3 +2278,6 @@ extern "C" int lbb_step_noalloc(const lbb_params *pin, void *const f[2], void *c
     phase[1] = cT;
     return LBB_OK;
 }
+
+// ---- three-dimensional lattices ------------------------------------------
+#include "lbb3_host.hpp"

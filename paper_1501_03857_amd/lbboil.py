@@ -111,6 +111,18 @@ def lib():
             "lbb_batch_autotune": (C.c_int, [vp, C.c_int32, _pi32, _pi32, _pd, _pd]),
             "lbb_batch_info": (C.c_int, [vp, C.POINTER(_i64)]),
             "lbb_step_noalloc": (C.c_int, [_P, C.POINTER(vp), C.POINTER(vp), vp, vp, vp, _pi32, _i64, vp, vp]),
+            "lbb3_init_domain": (C.c_int, [_P, _i32, _pd, _pd, C.POINTER(vp)]),
+            "lbb3_set_fields": (C.c_int, [vp, _pd, _pd, _pd]),
+            "lbb3_step": (C.c_int, [vp, _i64]),
+            "lbb3_step_async": (C.c_int, [vp, _i64]),
+            "lbb3_sync": (C.c_int, [vp]),
+            "lbb3_stream": (vp, [vp]),
+            "lbb3_read_fields": (C.c_int, [vp, _pd, _pd, _pd, _pd]),
+            "lbb3_wall_heat_flux": (C.c_int, [vp, _pd, _pd, _pd, C.POINTER(_i64)]),
+            "lbb3_reset_average": (C.c_int, [vp]),
+            "lbb3_set_heater": (C.c_int, [vp, _pd]),
+            "lbb3_info": (C.c_int, [vp, C.POINTER(_i64), C.POINTER(_i64)]),
+            "lbb3_destroy": (C.c_int, [vp]),
             "lbb_last_error": (C.c_char_p, []),
         }
         for name, (res, args) in sig.items():
@@ -505,3 +517,93 @@ def step_noalloc(p: "Params", f, T, rho, vx, vy, phase, n: int, result: int, str
                                   C.c_void_p(int(vy)), ph, int(n), C.c_void_p(int(result)),
                                   C.c_void_p(int(stream)) if stream else None))
     phase[0], phase[1] = ph[0], ph[1]
+
+
+class Domain3:
+    """One three-dimensional (D3Q19) lattice on the current GPU
+    (lbb3_init_domain ... lbb3_destroy).  Arrays are [nz, ny, nx]; T_bottom
+    is [nz, nx]."""
+
+    def __init__(self, p: Params, nz: int, T_bottom=None, rho0=None):
+        self.p, self.nz = p, int(nz)
+        self._cp = p.c()
+        T_bottom, rho0 = _f64(T_bottom), _f64(rho0)
+        if rho0 is not None:
+            assert rho0.shape == (nz, p.ny, p.nx)
+        if T_bottom is not None:
+            assert T_bottom.shape == (nz, p.nx)
+        h = C.c_void_p()
+        _check(lib().lbb3_init_domain(C.byref(self._cp), self.nz, _ptr(T_bottom), _ptr(rho0), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().lbb3_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def shape(self):
+        return (self.nz, self.p.ny, self.p.nx)
+
+    def step(self, n: int = 1):
+        _check(lib().lbb3_step(self._h, int(n)))
+        return self
+
+    def step_async(self, n: int):
+        _check(lib().lbb3_step_async(self._h, int(n)))
+
+    def sync(self):
+        _check(lib().lbb3_sync(self._h))
+
+    @property
+    def stream(self) -> int:
+        return lib().lbb3_stream(self._h) or 0
+
+    @property
+    def t(self) -> int:
+        t = _i64()
+        _check(lib().lbb3_info(self._h, C.byref(t), None))
+        return t.value
+
+    def set_fields(self, rho, u=None, T=None):
+        rho = _f64(rho)
+        u = None if u is None else _f64(np.asarray(u, dtype=float).reshape(3, *self.shape))
+        T = _f64(T)
+        _check(lib().lbb3_set_fields(self._h, _ptr(rho), _ptr(u), _ptr(T)))
+
+    def fields(self, f: bool = True):
+        rho, T = np.zeros(self.shape), np.zeros(self.shape)
+        u = np.zeros((3,) + self.shape)
+        ff = np.zeros((19,) + self.shape) if f else None
+        _check(lib().lbb3_read_fields(self._h, _ptr(rho), _ptr(u), _ptr(T), _ptr(ff)))
+        out = dict(rho=rho, ux=u[0], uy=u[1], uz=u[2], T=T)
+        if f:
+            out["f"] = ff
+        return out
+
+    def heat_flux(self, local: bool = True):
+        qn, qm, ns = _d(), _d(), _i64()
+        ql = np.zeros((self.nz, self.p.nx)) if local else None
+        _check(lib().lbb3_wall_heat_flux(self._h, C.byref(qn), C.byref(qm), _ptr(ql), C.byref(ns)))
+        return dict(q_now=qn.value, q_mean=qm.value, n_samples=ns.value, q_local=ql)
+
+    def reset_average(self):
+        _check(lib().lbb3_reset_average(self._h))
+
+    def set_heater(self, T_bottom):
+        T_bottom = _f64(T_bottom)
+        assert T_bottom.shape == (self.nz, self.p.nx)
+        _check(lib().lbb3_set_heater(self._h, _ptr(T_bottom)))

@@ -48,6 +48,15 @@ def layered_density(nx: int, ny: int, rho_L: float, rho_V: float, liquid_rows: i
     return base + noise_amp * (2.0 * u - 1.0)
 
 
+def layered_density3(nx: int, ny: int, nz: int, rho_L: float, rho_V: float, liquid_rows: int,
+                     noise_amp: float, seed: int) -> np.ndarray:
+    """Three-dimensional lattices: rho0[k, j, i] = (rho_L if j < liquid_rows
+    else rho_V) + A (2u - 1), u from counter (k ny + j) nx + i."""
+    u = uniform01(seed, nx * ny * nz).reshape(nz, ny, nx)
+    base = np.where(np.arange(ny)[None, :, None] < liquid_rows, rho_L, rho_V) * np.ones((nz, 1, nx))
+    return base + noise_amp * (2.0 * u - 1.0)
+
+
 def heater_profile(nx: int, T_s: float, T_heater: float, lo: int = 0, hi: Optional[int] = None) -> np.ndarray:
     """Bottom-wall temperature: T_heater on cells [lo, hi), T_s elsewhere."""
     hi = nx if hi is None else hi

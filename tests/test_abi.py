@@ -21,7 +21,7 @@ def _declared_symbols():
         if fn.endswith(".h"):
             src = open(os.path.join(inc, fn)).read()
             src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-            names |= set(re.findall(r"\b(lbb_[a-z0-9_]+)\s*\(", src))
+            names |= set(re.findall(r"\b(lbb3?_[a-z0-9_]+)\s*\(", src))
     return names
 
 
