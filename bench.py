@@ -291,6 +291,43 @@ def batch_adjoint_bench(steps=600):
             "library_device_bytes": int(dev), "hip_free_bytes_drop": int(free0 - free1)}
 
 
+def three_d_bench(steps=300, warmup=64, nx=150, ny=151, nz=150):
+    """The three-dimensional (D3Q19) step on a pool of nx x ny x nz nodes in
+    FP32 storage (a = 3/49, liquid below 0.6 ny, full-width heater at
+    0.10 T_c, G_w = 0.065): MLUPS over graph replays timed with HIP events on
+    the library's stream, and the step priced against HBM with its
+    algorithmic 160 B/update (19 populations and T read and written)."""
+    import torch
+    from paper_1501_03857_amd import lbboil as L
+    from paper_1501_03857_amd import workloads as WL
+
+    a = 3.0 / 49.0
+    Tc, _ = L.eos_constants(a, 2.0 / 21.0, 1.0, 0.344)
+    rv, rl = L.coexistence(a, 2.0 / 21.0, 1.0, 0.344, 0.86 * Tc)
+    liquid = int(0.6 * ny)
+    p = L.Params(nx=nx, ny=ny, precision=L.FP32, liquid_rows=liquid, a=a, rho_L=rl, rho_V=rv, g=3e-5,
+                 Gw_bottom=0.065, seed=7)
+    d = L.Domain3(p, nz, T_bottom=np.full((nz, nx), 0.96 * Tc),
+                  rho0=WL.layered_density3(nx, ny, nz, rl, rv, liquid, 1e-3, 7))
+    d.step(warmup)
+    st = torch.cuda.ExternalStream(d.stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    d.step_async(steps)
+    e1.record(st)
+    d.sync()
+    ms = e0.elapsed_time(e1) / steps
+    cells = nx * ny * nz
+    gbs = 160 * cells / (ms * 1e-3) / 1e9
+    q = d.heat_flux(local=False)
+    d.close()
+    return {"workload": f"pool3d_{nx}x{ny}x{nz}_fp32", "nodes": cells, "steps": steps, "ms_per_step": round(ms, 4),
+            "mlups": round(cells / (ms * 1e-3) / 1e6, 1),
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4), "alg_bytes_per_update": 160},
+            "launches_per_step": 7, "q_mean": q["q_mean"]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -305,6 +342,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=300, help="oracle steps for the CPU baseline (0: skip)")
     ap.add_argument("--sweep-steps", type=int, default=2000, help="steps of the 48-lattice sweep comparison (0: skip)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost measurement")
+    ap.add_argument("--three-d-steps", type=int, default=300, help="steps of the 3-D pool measurement (0: skip)")
+    ap.add_argument("--three-d-only", action="store_true", help="only the 3-D pool measurement (profiling)")
     ap.add_argument("--adjoint-only", action="store_true", help="only the adjoint/forward cost measurement (profiling)")
     ap.add_argument("--profile", action="store_true", help="timed region only (for rocprofv3 runs)")
     ap.add_argument("--copy-probe", action="store_true", help="run a plain 1 GiB device copy (counter calibration)")
@@ -328,6 +367,10 @@ def main():
             torch.neg(a, out=b)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "launches": 5}))
+        return
+
+    if args.three_d_only:
+        print(json.dumps({"three_d": three_d_bench(args.three_d_steps or 300)}), flush=True)
         return
 
     if args.adjoint_only:
@@ -393,6 +436,10 @@ def main():
     if adj:
         print(f"[bench] adjoint/forward: f64 {adj['f64']['ratio']}x, f32 {adj['f32']['ratio']}x; "
               f"batch of {badj['instances']}: {badj['ratio']}x", file=sys.stderr, flush=True)
+    three = three_d_bench(args.three_d_steps) if args.three_d_steps > 0 else None
+    if three:
+        print(f"[bench] 3-D pool {three['workload']}: {three['mlups']} MLUPS, {three['ms_per_step']} ms/step, "
+              f"{three['roofline']['frac']} of HBM peak", file=sys.stderr, flush=True)
     cpu = cpu_baseline(w, args.cpu_steps) if args.cpu_steps > 0 else None
     copy_gbs = copy_bandwidth()
 
@@ -427,6 +474,7 @@ def main():
         "batched_sweep": sweep,
         "adjoint": adj,
         "batch_adjoint": badj,
+        "three_d": three,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -167,17 +167,43 @@ __device__ __forceinline__ unsigned node(const Geom3 &g, int x, int y, int z)
     return ((unsigned)z * (unsigned)g.ny + (unsigned)y) * (unsigned)g.nx + (unsigned)x;
 }
 
-// neighbour along sign * e_a (x, z periodic; y periodic or bounded): false
-// beyond a wall
-__device__ __forceinline__ bool nbr(const DevParams &P, const Geom3 &g, int x, int y, int z, int a, int sign,
-                                    unsigned &out)
+// Node-index offsets of the neighbours of one node along each axis (-1, 0,
+// +1), periodic wraps folded in: the neighbour along e_a is
+// c + dx[e_ax + 1] + dy[e_ay + 1] + dz[e_az + 1].  Beyond a wall (y not
+// periodic) the y offset is that of the node itself; has_s / has_n say
+// whether the rows below and above exist.
+struct Nb3 {
+    int dx[3], dy[3], dz[3];
+    bool has_s, has_n;
+};
+
+__device__ __forceinline__ Nb3 neighbours(const DevParams &P, const Geom3 &g, int x, int y, int z)
 {
-    const int xx = wrap3(x + sign * EX3[a], g.nx), zz = wrap3(z + sign * EZ3[a], g.nz);
-    int yy = y + sign * EY3[a];
-    if (P.periodic_y) yy = wrap3(yy, g.ny);
-    else if (yy < 0 || yy >= g.ny) return false;
-    out = node(g, xx, yy, zz);
-    return true;
+    Nb3 b;
+    const int sy = g.nx, sz = g.nx * g.ny;
+    b.dx[0] = x == 0 ? g.nx - 1 : -1;
+    b.dx[1] = 0;
+    b.dx[2] = x == g.nx - 1 ? 1 - g.nx : 1;
+    b.dz[0] = (z == 0 ? g.nz - 1 : -1) * sz;
+    b.dz[1] = 0;
+    b.dz[2] = (z == g.nz - 1 ? 1 - g.nz : 1) * sz;
+    b.has_s = P.periodic_y || y > 0;
+    b.has_n = P.periodic_y || y < g.ny - 1;
+    b.dy[0] = !b.has_s ? 0 : (y == 0 ? (g.ny - 1) * sy : -sy);
+    b.dy[1] = 0;
+    b.dy[2] = !b.has_n ? 0 : (y == g.ny - 1 ? (1 - g.ny) * sy : sy);
+    return b;
+}
+
+template <int A>
+__device__ __forceinline__ unsigned nb_at(const Nb3 &b, unsigned c)
+{
+    return (unsigned)((int)c + b.dx[EX3[A] + 1] + b.dy[EY3[A] + 1] + b.dz[EZ3[A] + 1]);
+}
+
+__device__ __forceinline__ unsigned nb_at(const Nb3 &b, unsigned c, int a)
+{
+    return (unsigned)((int)c + b.dx[EX3[a] + 1] + b.dy[EY3[a] + 1] + b.dz[EZ3[a] + 1]);
 }
 
 template <typename S>
@@ -293,18 +319,48 @@ __global__ __launch_bounds__(NT3) void k3_psi(DevParams P, Geom3 g, const S *__r
 // rho_ave of state t and its heat-flux sample (counted once per state index
 // t >= 1), one block; with `advance` the state index then moves to t + 1,
 // the state the rest of the step produces.
-__global__ __launch_bounds__(NT3) void k3_reduce(Geom3 g, const double *__restrict__ mpart,
+constexpr int NR3 = 1024;  // threads of the reduction block
+
+// sum of one double per thread over a block of NR3 threads, fixed order;
+// valid in thread 0
+__device__ __forceinline__ double block_sum_r(double v, double *red)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < NR3 / 64; ++k) s += red[k];
+    return s;
+}
+
+// s + a[k0] + a[k0 + NR3] + ... (below n), in that order, 16 loads in flight
+__device__ __forceinline__ double strided_sum(const double *__restrict__ a_, int k0, int n)
+{
+    const gmem<double> *__restrict__ a = (const gmem<double> *)a_;
+    double s = 0.0;
+    int k = k0;
+    for (; k + 15 * NR3 < n; k += 16 * NR3) {
+        double v[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) v[j] = a[k + j * NR3];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) s += v[j];
+    }
+    for (; k < n; k += NR3) s += a[k];
+    return s;
+}
+
+__global__ __launch_bounds__(NR3) void k3_reduce(Geom3 g, const double *__restrict__ mpart,
                                                  const double *__restrict__ hpart, int nb, Scalars3 *sc, int advance)
 {
-    __shared__ double red[NT3 / 64];
-    double m = 0.0, h = 0.0;
-    for (int k = threadIdx.x; k < nb; k += NT3) {
-        m += mpart[k];
-        h += hpart[k];
-    }
-    const double ms = block_sum3(m, red);
+    __shared__ double red[NR3 / 64];
+    const double m = strided_sum(mpart, threadIdx.x, nb), h = strided_sum(hpart, threadIdx.x, nb);
+    const double ms = block_sum_r(m, red);
     __syncthreads();
-    const double hs = block_sum3(h, red);
+    const double hs = block_sum_r(h, red);
     if (threadIdx.x == 0) {
         sc->rho_ave = ms / (double)g.n;
         const double q = hs / ((double)g.nx * (double)g.nz);
@@ -321,8 +377,8 @@ __global__ __launch_bounds__(NT3) void k3_reduce(Geom3 g, const double *__restri
 // total force on a node of state t (Eq. (7) + Eq. (22) + Eq. (9)) and
 // Q = |F_m|^2/psi^2 (Eq. (8)): none on the wall rows; the fluid-solid force
 // on the rows next to them, the wall rows being the solid
-__device__ __forceinline__ void force3(const DevParams &P, const Geom3 &g, const double *__restrict__ psi, int x,
-                                       int y, int z, unsigned c, double rho, double rho_ave, double F[3], double &Q)
+__device__ __forceinline__ void force3(const DevParams &P, const Geom3 &g, const Nb3 &nb, const double *__restrict__ psi,
+                                       int y, unsigned c, double rho, double rho_ave, double F[3], double &Q)
 {
     F[0] = F[1] = F[2] = 0.0;
     Q = 0.0;
@@ -331,9 +387,7 @@ __device__ __forceinline__ void force3(const DevParams &P, const Geom3 &g, const
     double sx = 0.0, sy = 0.0, sz = 0.0;
 #pragma unroll
     for (int a = 1; a < Q19; ++a) {
-        unsigned o = c;
-        nbr(P, g, x, y, z, a, 1, o);
-        const double w = (a < 7 ? 1.0 / 6.0 : 1.0 / 12.0) * ((const gmem<double> *)psi)[o];
+        const double w = (a < 7 ? 1.0 / 6.0 : 1.0 / 12.0) * ((const gmem<double> *)psi)[nb_at(nb, c, a)];
         if (EX3[a]) sx = fma((double)EX3[a], w, sx);
         if (EY3[a]) sy = fma((double)EY3[a], w, sy);
         if (EZ3[a]) sz = fma((double)EZ3[a], w, sz);
@@ -393,8 +447,9 @@ __global__ __launch_bounds__(NT3) void k3_lb(DevParams P, Geom3 g, const S *__re
     double rho = f[0];
 #pragma unroll
     for (int a = 1; a < Q19; ++a) rho += f[a];
+    const Nb3 nb = neighbours(P, g, x, y, z);
     double F[3], Q;
-    force3(P, g, psi, x, y, z, c, rho, sc->rho_ave, F, Q);
+    force3(P, g, nb, psi, y, c, rho, sc->rho_ave, F, Q);
     double j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int a = 1; a < Q19; ++a) {
@@ -411,8 +466,8 @@ __global__ __launch_bounds__(NT3) void k3_lb(DevParams P, Geom3 g, const S *__re
     collide3(P, f, rho, v, F, Q, rcp_nr(P.tau_V + (rho - P.rho_V) * P.tau_slope));
 #pragma unroll
     for (int a = 0; a < Q19; ++a) {
-        unsigned o;
-        if (nbr(P, g, x, y, z, a, 1, o)) ((gmem<S> *)fout)[(size_t)a * g.n + o] = S(f[a]);
+        const bool keep = EY3[a] < 0 ? nb.has_s : (EY3[a] > 0 ? nb.has_n : true);
+        if (keep) ((gmem<S> *)fout)[(size_t)a * g.n + nb_at(nb, c, a)] = S(f[a]);
     }
 }
 
@@ -423,24 +478,26 @@ __global__ __launch_bounds__(NT3) void k3_lb(DevParams P, Geom3 g, const S *__re
 // split of (dp/dT)_rho as in two dimensions), on rows 1..ny-2; the wall rows
 // keep their Dirichlet values in every stage.
 
-// isotropic D3Q19 stencil sums at node (x,y,z) of field p: 3 sum W e p and
-// 6 sum W (p(nbr) - p(c)), the wall-row nodes not evaluated
-template <typename T_>
-__device__ __forceinline__ void stencil3(const DevParams &P, const Geom3 &g, const T_ *__restrict__ p, int x, int y,
-                                         int z, unsigned c, double off, double grad[3], double *lap)
+// isotropic D3Q19 stencils at node c of field p: d_i p = 3 sum_a W_a e_ai
+// p(c + e_a) for the directions i in the mask, and
+// lap p = 6 sum_a W_a (p(c + e_a) - p(c)) when lap is non-null; only the
+// velocities a stencil needs are read (interior rows only)
+template <int MASK, typename T_>
+__device__ __forceinline__ void stencil3(const Nb3 &nb, const T_ *__restrict__ p, unsigned c, double grad[3],
+                                         double *lap)
 {
-    const double pc = off + (double)((const gmem<T_> *)p)[c];
+    const double pc = (double)((const gmem<T_> *)p)[c];
     double gx = 0.0, gy = 0.0, gz = 0.0, l = 0.0;
 #pragma unroll
     for (int a = 1; a < Q19; ++a) {
-        unsigned o = c;
-        nbr(P, g, x, y, z, a, 1, o);
+        const bool need = lap || ((MASK & 1) && EX3[a]) || ((MASK & 2) && EY3[a]) || ((MASK & 4) && EZ3[a]);
+        if (!need) continue;
         const double w = W36[a] * (1.0 / 36.0);
-        const double val = off + (double)((const gmem<T_> *)p)[o];
-        if (EX3[a]) gx = fma(EX3[a] * w, val, gx);
-        if (EY3[a]) gy = fma(EY3[a] * w, val, gy);
-        if (EZ3[a]) gz = fma(EZ3[a] * w, val, gz);
-        l = fma(w, val - pc, l);
+        const double val = (double)((const gmem<T_> *)p)[nb_at(nb, c, a)];
+        if ((MASK & 1) && EX3[a]) gx = fma(EX3[a] * w, val, gx);
+        if ((MASK & 2) && EY3[a]) gy = fma(EY3[a] * w, val, gy);
+        if ((MASK & 4) && EZ3[a]) gz = fma(EZ3[a] * w, val, gz);
+        if (lap) l = fma(w, val - pc, l);
     }
     grad[0] = 3.0 * gx;
     grad[1] = 3.0 * gy;
@@ -465,20 +522,18 @@ __global__ __launch_bounds__(NT3) void k3_stage(DevParams P, Geom3 g, const S *_
     const double t0 = (double)((const gmem<S> *)T0)[c];
     double h = 0.0;
     if (!wall) {
+        const Nb3 nb = neighbours(P, g, x, y, z);
         double a[3], c1, c2;
         gmem<S> *cf = (gmem<S> *)coef;
         if constexpr (K == 0) {
             // coefficients, once per step: grad rho, div v, A(rho), B(rho)
             const double r = (double)((const gmem<S> *)rho)[c];
-            double gr[3], gv[3], d[3];
-            stencil3(P, g, rho, x, y, z, c, 0.0, gr, nullptr);
-            stencil3(P, g, vx, x, y, z, c, 0.0, d, nullptr);
-            gv[0] = d[0];
-            stencil3(P, g, vy, x, y, z, c, 0.0, d, nullptr);
-            gv[1] = d[1];
-            stencil3(P, g, vz, x, y, z, c, 0.0, d, nullptr);
-            gv[2] = d[2];
-            const double div = gv[0] + gv[1] + gv[2];
+            double gr[3], dx_[3], dy_[3], dz_[3];
+            stencil3<7>(nb, rho, c, gr, nullptr);
+            stencil3<1>(nb, vx, c, dx_, nullptr);
+            stencil3<2>(nb, vy, c, dy_, nullptr);
+            stencil3<4>(nb, vz, c, dz_, nullptr);
+            const double div = dx_[0] + dy_[1] + dz_[2];
             const double D1 = 1.0 - P.b * r, D2 = 1.0 + 2.0 * P.b * r - P.b * P.b * r * r;
             const double inv = rcp_nr(r * D1 * D2);
             const double chi_r = P.chi * D1 * D2 * inv;
@@ -507,7 +562,7 @@ __global__ __launch_bounds__(NT3) void k3_stage(DevParams P, Geom3 g, const S *_
         }
         double gT[3], lap;
         const S *src = K == 0 ? T0 : Tin;
-        stencil3(P, g, src, x, y, z, c, 0.0, gT, &lap);
+        stencil3<7>(nb, src, c, gT, &lap);
         const double Tabs = P.T_ref + (double)((const gmem<S> *)src)[c];
         h = -(a[0] * gT[0] + a[1] * gT[1] + a[2] * gT[2]) + P.chi * lap + c1 * Tabs + c2 * sqrt_pos(Tabs);
     }
@@ -575,7 +630,7 @@ __global__ __launch_bounds__(NT3) void k3_read(DevParams P, Geom3 g, const S *__
 #pragma unroll
     for (int a = 1; a < Q19; ++a) r += f[a];
     double F[3] = {0.0, 0.0, 0.0}, Q;
-    if (P.mode != lbb::MODE_THERMAL_ONLY) force3(P, g, psi, x, y, z, c, r, sc->rho_ave, F, Q);
+    if (P.mode != lbb::MODE_THERMAL_ONLY) force3(P, g, neighbours(P, g, x, y, z), psi, y, c, r, sc->rho_ave, F, Q);
     double j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int a = 1; a < Q19; ++a) {

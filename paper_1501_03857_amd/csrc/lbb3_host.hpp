@@ -49,7 +49,7 @@ void enqueue_reductions3(lbb3_domain *d, int advance)
                        static_cast<const S *>(d->f[d->cf]), static_cast<const S *>(d->T[d->cT]),
                        static_cast<S *>(d->rho), d->psi, v, v + d->g.n, v + 2 * (size_t)d->g.n, d->mpart, d->hpart,
                        d->sc);
-    hipLaunchKernelGGL(k3_reduce, dim3(1), dim3(NT3), 0, d->stream, d->g, d->mpart, d->hpart, d->nb, d->sc, advance);
+    hipLaunchKernelGGL(k3_reduce, dim3(1), dim3(NR3), 0, d->stream, d->g, d->mpart, d->hpart, d->nb, d->sc, advance);
 }
 
 // One time step: reductions of state t, LB update, RK4 temperature step.
