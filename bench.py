@@ -340,7 +340,7 @@ def main():
     ap.add_argument("--tiles", default=None,
                     help="LB,thermal tile shape indices to use instead of the autotuner (profiling runs)")
     ap.add_argument("--cpu-steps", type=int, default=300, help="oracle steps for the CPU baseline (0: skip)")
-    ap.add_argument("--sweep-steps", type=int, default=2000, help="steps of the 48-lattice sweep comparison (0: skip)")
+    ap.add_argument("--sweep-steps", type=int, default=10000, help="steps of the 48-lattice sweep comparison (0: skip)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward cost measurement")
     ap.add_argument("--three-d-steps", type=int, default=300, help="steps of the 3-D pool measurement (0: skip)")
     ap.add_argument("--three-d-only", action="store_true", help="only the 3-D pool measurement (profiling)")

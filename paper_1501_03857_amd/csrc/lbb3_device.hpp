@@ -147,6 +147,15 @@ __device__ __forceinline__ void zou_he3(double f[Q19], bool bottom)
     }
 }
 
+// Node of a thread in the per-node launches.  Workgroups are dispatched to
+// the 8 XCDs round-robin; block q takes the chunk lbb::xcd_tile(q, nb), so
+// each XCD works through one contiguous run of the lattice and the rows and
+// planes its stencils share stay in its own L2.
+__device__ __forceinline__ unsigned node_of_thread()
+{
+    return (unsigned)lbb::xcd_tile((int)blockIdx.x, (int)gridDim.x) * 256u + threadIdx.x;
+}
+
 struct Geom3 {
     int nx, ny, nz;
     unsigned n;  // nx ny nz
@@ -268,7 +277,7 @@ __global__ __launch_bounds__(NT3) void k3_psi(DevParams P, Geom3 g, const S *__r
                                              double *__restrict__ hpart, Scalars3 *sc)
 {
     __shared__ double red[NT3 / 64];
-    const unsigned c = blockIdx.x * NT3 + threadIdx.x;
+    const unsigned c = node_of_thread();
     double mass = 0.0, qw = 0.0;
     const long long t = sc->t;
     if (c < g.n) {
@@ -311,8 +320,9 @@ __global__ __launch_bounds__(NT3) void k3_psi(DevParams P, Geom3 g, const S *__r
     __syncthreads();
     const double hs = block_sum3(qw, red);
     if (threadIdx.x == 0) {
-        mpart[blockIdx.x] = ms;
-        hpart[blockIdx.x] = hs;
+        const int chunk = lbb::xcd_tile((int)blockIdx.x, (int)gridDim.x);
+        mpart[chunk] = ms;
+        hpart[chunk] = hs;
     }
 }
 
@@ -438,7 +448,7 @@ __global__ __launch_bounds__(NT3) void k3_lb(DevParams P, Geom3 g, const S *__re
                                             const double *__restrict__ psi, S *__restrict__ vx_o,
                                             S *__restrict__ vy_o, S *__restrict__ vz_o, const Scalars3 *sc)
 {
-    const unsigned c = blockIdx.x * NT3 + threadIdx.x;
+    const unsigned c = node_of_thread();
     if (c >= g.n) return;
     int x, y, z;
     coords(g, c, x, y, z);
@@ -514,7 +524,7 @@ __global__ __launch_bounds__(NT3) void k3_stage(DevParams P, Geom3 g, const S *_
                                                const S *__restrict__ rho, const S *__restrict__ vx,
                                                const S *__restrict__ vy, const S *__restrict__ vz, Scalars3 *sc)
 {
-    const unsigned c = blockIdx.x * NT3 + threadIdx.x;
+    const unsigned c = node_of_thread();
     if (c >= g.n) return;
     int x, y, z;
     coords(g, c, x, y, z);
@@ -588,7 +598,7 @@ __global__ void k3_set_state(DevParams P, Geom3 g, const double *__restrict__ rh
                              const double *__restrict__ T, const double *__restrict__ Tb, S *__restrict__ f,
                              S *__restrict__ T0, S *__restrict__ T1, Scalars3 *sc)
 {
-    const unsigned c = blockIdx.x * NT3 + threadIdx.x;
+    const unsigned c = node_of_thread();
     if (c >= g.n) return;
     int x, y, z;
     coords(g, c, x, y, z);
@@ -620,7 +630,7 @@ __global__ __launch_bounds__(NT3) void k3_read(DevParams P, Geom3 g, const S *__
                                               double *__restrict__ T_o, double *__restrict__ f_o,
                                               double *__restrict__ qloc)
 {
-    const unsigned c = blockIdx.x * NT3 + threadIdx.x;
+    const unsigned c = node_of_thread();
     if (c >= g.n) return;
     int x, y, z;
     coords(g, c, x, y, z);
