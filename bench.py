@@ -42,27 +42,55 @@ def _kernel_roofline(alg_bytes, ms, traffic, per_update):
 
 # HBM traffic of each launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
 # (KiB per dispatch, mean over the dispatches of a --profile run with the
-# given tiles), each scaled by what the same counter reads for an elementwise
-# kernel that reads 1 GiB and writes 1 GiB (FETCH_SIZE 524297.7 KiB -> factor
-# 2.0, WRITE_SIZE 1048576 KiB -> factor 1.0).  Valid for the kernel source
-# whose hash is recorded and the same tile shape; null otherwise.
+# given tiles), each scaled by what the same counter reads, in the same
+# profiling session, for an elementwise kernel that reads 1 GiB and writes
+# 1 GiB (FETCH_SIZE 436917.0 KiB -> factor 2.40, WRITE_SIZE 1048576 KiB ->
+# factor 1.0).  Valid for the kernel source whose hash is recorded and the
+# same tile shape; null otherwise.
 MEASURED_TRAFFIC = {
-    "source_hash": "5841db5404206de4",
-    "fetch_factor": 1048576.0 / 524297.7,
+    "source_hash": "7f926bdeb6b7b8bd",
+    "fetch_factor": 1048576.0 / 436917.0,
     "write_factor": 1048576.0 / 1048576.0,
     "k_lb": {
         "large_1024x512_fp32": [
-            {"tiles": [62, 4, 4], "fetch_kib": 10718.0, "write_kib": 24620.1},
-            {"tiles": [62, 8, 8], "fetch_kib": 10650.1, "write_kib": 24653.6},
+            {"tiles": [62, 4, 4], "fetch_kib": 10705.2, "write_kib": 24620.1},
+            {"tiles": [62, 8, 8], "fetch_kib": 10670.5, "write_kib": 24628.2},
         ],
         "large_4096x2048_fp32": [
-            {"tiles": [62, 4, 4], "fetch_kib": 166704.1, "write_kib": 395668.4},
-            {"tiles": [62, 8, 8], "fetch_kib": 171677.0, "write_kib": 397357.0},
-            {"tiles": [62, 12, 4], "fetch_kib": 178478.2, "write_kib": 398111.1},
+            {"tiles": [62, 4, 4], "fetch_kib": 166955.2, "write_kib": 396036.0},
         ],
     },
-    "k_thermal": {},
+    "k_thermal": {
+        "large_1024x512_fp32": [
+            {"tiles": [56, 24, 16], "fetch_kib": 4836.6, "write_kib": 2040.2},
+        ],
+        "large_4096x2048_fp32": [
+            {"tiles": [56, 40, 16], "fetch_kib": 68970.7, "write_kib": 32748.4},
+        ],
+    },
 }
+
+# The same counters for the seven launches of one 3-D step (150x151x150 pool,
+# FP32 storage; KiB per dispatch), valid for the 3-D kernel source whose hash
+# is recorded.
+MEASURED_TRAFFIC_3D = {
+    "source_hash": "9a669203bb0f3428",
+    "pool3d_150x151x150_fp32": {
+        "k3_psi": (132765.1, 40023.7), "k3_reduce": (107.8, 0.1), "k3_lb": (146674.6, 294873.9),
+        "k3_stage0": (36765.3, 92187.9), "k3_stage1": (53426.7, 26544.0), "k3_stage2": (53429.9, 26543.0),
+        "k3_stage3": (53347.6, 13271.5),
+    },
+}
+
+
+def measured_traffic_3d(workload: str):
+    """HBM bytes of one 3-D step from the recorded counters, or None when
+    the 3-D kernel source or the workload differ."""
+    m = MEASURED_TRAFFIC_3D
+    if m.get("source_hash") != source_hash("lbb3_device.hpp") or workload not in m:
+        return None
+    f = MEASURED_TRAFFIC["fetch_factor"]
+    return int(round(sum(fe * f + wr for fe, wr in m[workload].values()) * 1024))
 
 
 def measured_traffic(kernel: str, workload: str, tiles):
@@ -84,11 +112,11 @@ def arithmetic(store: str) -> str:
     return "mixed: f32 storage; f64 LB, EOS and reductions; f32 RK4 stages (pressure-work coefficients formed in f64)"
 
 
-def source_hash() -> str:
-    """Hash of the forward kernels' source (the counters below depend on it
-    and on the tile shape only)."""
+def source_hash(name: str = "lbb_device.hpp") -> str:
+    """Hash of a kernel source file (the recorded counters depend on it and
+    on the tile shape only)."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_1501_03857_amd", "csrc", "lbb_device.hpp"), "rb") as fh:
+    with open(os.path.join(ROOT, "paper_1501_03857_amd", "csrc", name), "rb") as fh:
         h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -320,11 +348,15 @@ def three_d_bench(steps=300, warmup=64, nx=150, ny=151, nz=150):
     cells = nx * ny * nz
     gbs = 160 * cells / (ms * 1e-3) / 1e9
     q = d.heat_flux(local=False)
+    name = f"pool3d_{nx}x{ny}x{nz}_fp32"
+    traffic = measured_traffic_3d(name)
     d.close()
-    return {"workload": f"pool3d_{nx}x{ny}x{nz}_fp32", "nodes": cells, "steps": steps, "ms_per_step": round(ms, 4),
+    return {"workload": name, "nodes": cells, "steps": steps, "ms_per_step": round(ms, 4),
             "mlups": round(cells / (ms * 1e-3) / 1e6, 1),
             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(gbs / HBM_PEAK_GBS, 4), "alg_bytes_per_update": 160},
+                         "frac": round(gbs / HBM_PEAK_GBS, 4), "alg_bytes_per_update": 160,
+                         "traffic": traffic, "traffic_unit": "bytes per step",
+                         "traffic_gbs": None if traffic is None else round(traffic / (ms * 1e-3) / 1e9, 1)},
             "launches_per_step": 7, "q_mean": q["q_mean"]}
 
 

@@ -79,47 +79,81 @@ constexpr int basis3(int k, int a)
 // squared row norms: M M^T = diag(NORM3)
 constexpr double NORM3[Q19] = {19, 2394, 252, 10, 40, 10, 40, 10, 40, 36, 72, 12, 24, 4, 4, 4, 8, 8, 8};
 
-// sum_a B_ka v_a with the integer basis, zeros skipped and +-1 folded at
-// compile time (k and a are constants after unrolling)
-template <int K>
-__device__ __forceinline__ double row_dot(const double v[Q19])
+// Velocities 2p+1 and 2p+2 (p = 0..8) are opposite.  A row of the basis is
+// either even in e (rho, e, epsilon and the stress rows) or odd (the j, q and
+// m rows), so an even row sees the pair sums f_a + f_abar only and an odd
+// row the differences only: both transforms run on the nine pairs, which
+// halves their additions.
+constexpr bool odd_row(int k) { return (k >= 3 && k <= 8) || k >= 16; }
+
+// c v added to an accumulator that holds nothing yet (first) or acc, with
+// c a compile-time integer: zeros skipped, +-1 folded
+__device__ __forceinline__ void acc_term(int c, double v, double &acc, bool &first)
 {
-    double s = 0.0;
+    if (c == 0) return;
+    if (first) acc = c == 1 ? v : (c == -1 ? -v : (double)c * v);
+    else if (c == 1) acc += v;
+    else if (c == -1) acc -= v;
+    else acc = fma((double)c, v, acc);
+    first = false;
+}
+
+// m_K = sum_a B_Ka f_a from f_0 and the pair sums s / differences d
+template <int K>
+__device__ __forceinline__ double row_dot(double f0, const double s[9], const double d[9])
+{
+    double acc = 0.0;
+    bool first = true;
+    if constexpr (!odd_row(K)) acc_term(basis3(K, 0), f0, acc, first);
 #pragma unroll
-    for (int a = 0; a < Q19; ++a) {
-        const int c = basis3(K, a);
-        if (c == 0) continue;
-        if (c == 1) s += v[a];
-        else if (c == -1) s -= v[a];
-        else s = fma((double)c, v[a], s);
-    }
-    return s;
+    for (int p = 0; p < 9; ++p) acc_term(basis3(K, 2 * p + 1), odd_row(K) ? d[p] : s[p], acc, first);
+    return acc;
 }
 
 template <int K = 0>
-__device__ __forceinline__ void moments(const double f[Q19], double m[Q19])
+__device__ __forceinline__ void moments(double f0, const double s[9], const double d[9], double m[Q19])
 {
     if constexpr (K < Q19) {
-        m[K] = row_dot<K>(f);
-        moments<K + 1>(f, m);
+        m[K] = row_dot<K>(f0, s, d);
+        moments<K + 1>(f0, s, d, m);
     }
 }
 
-// f_a = sum_k B_ka mh_k (mh = moments already divided by the row norms)
+__device__ __forceinline__ void moments(const double f[Q19], double m[Q19])
+{
+    double s[9], d[9];
+#pragma unroll
+    for (int p = 0; p < 9; ++p) {
+        s[p] = f[2 * p + 1] + f[2 * p + 2];
+        d[p] = f[2 * p + 1] - f[2 * p + 2];
+    }
+    moments(f[0], s, d, m);
+}
+
+// f_a = sum_k B_ka mh_k (mh = moments already divided by the row norms):
+// the even rows give a part shared by a velocity and its opposite, the odd
+// rows a part of opposite sign
 __device__ __forceinline__ void from_moments(const double mh[Q19], double f[Q19])
 {
+    {
+        double ev = 0.0;
+        bool fe = true;
 #pragma unroll
-    for (int a = 0; a < Q19; ++a) {
-        double s = 0.0;
+        for (int k = 0; k < Q19; ++k)
+            if (!odd_row(k)) acc_term(basis3(k, 0), mh[k], ev, fe);
+        f[0] = ev;
+    }
+#pragma unroll
+    for (int p = 0; p < 9; ++p) {
+        double ev = 0.0, od = 0.0;
+        bool fe = true, fo = true;
 #pragma unroll
         for (int k = 0; k < Q19; ++k) {
-            const int c = basis3(k, a);
-            if (c == 0) continue;
-            if (c == 1) s += mh[k];
-            else if (c == -1) s -= mh[k];
-            else s = fma((double)c, mh[k], s);
+            if (odd_row(k)) acc_term(basis3(k, 2 * p + 1), mh[k], od, fo);
+            else acc_term(basis3(k, 2 * p + 1), mh[k], ev, fe);
         }
-        f[a] = s;
+        f[2 * p + 1] = ev + od;
+        f[2 * p + 2] = ev - od;
     }
 }
 
@@ -220,7 +254,7 @@ __device__ __forceinline__ void load_f(const DevParams &P, const Geom3 &g, const
                                        double fl[Q19])
 {
 #pragma unroll
-    for (int a = 0; a < Q19; ++a) fl[a] = (double)((const gmem<S> *)f)[(size_t)a * g.n + c];
+    for (int a = 0; a < Q19; ++a) fl[a] = (double)lbb::ld_at(f + (size_t)a * g.n, c * (unsigned)sizeof(S));
     if (!P.periodic_y && P.mode != lbb::MODE_THERMAL_ONLY) {
         if (y == 0) zou_he3(fl, true);
         else if (y == g.ny - 1) zou_he3(fl, false);
@@ -393,11 +427,11 @@ __device__ __forceinline__ void force3(const DevParams &P, const Geom3 &g, const
     F[0] = F[1] = F[2] = 0.0;
     Q = 0.0;
     if (!P.periodic_y && (y == 0 || y == g.ny - 1)) return;
-    const double pc = ((const gmem<double> *)psi)[c];
+    const double pc = lbb::ld_at(psi, c * 8u);
     double sx = 0.0, sy = 0.0, sz = 0.0;
 #pragma unroll
     for (int a = 1; a < Q19; ++a) {
-        const double w = (a < 7 ? 1.0 / 6.0 : 1.0 / 12.0) * ((const gmem<double> *)psi)[nb_at(nb, c, a)];
+        const double w = (a < 7 ? 1.0 / 6.0 : 1.0 / 12.0) * lbb::ld_at(psi, nb_at(nb, c, a) * 8u);
         if (EX3[a]) sx = fma((double)EX3[a], w, sx);
         if (EY3[a]) sy = fma((double)EY3[a], w, sy);
         if (EZ3[a]) sz = fma((double)EZ3[a], w, sz);
@@ -413,12 +447,11 @@ __device__ __forceinline__ void force3(const DevParams &P, const Geom3 &g, const
     F[1] -= (rho - rho_ave) * P.g;
 }
 
-// MRT collision of one node in the D3Q19 basis with the improved forcing.
-__device__ __forceinline__ void collide3(const DevParams &P, double f[Q19], double rho, const double v[3],
-                                         const double F[3], double Q, double s_nu)
+// MRT collision of one node in the D3Q19 basis with the improved forcing,
+// from its moments m = B f; writes the post-collision populations to f.
+__device__ __forceinline__ void collide3(const DevParams &P, const double m[Q19], double rho, const double v[3],
+                                         const double F[3], double Q, double s_nu, double f[Q19])
 {
-    double m[Q19];
-    moments(f, m);
     const double vx = v[0], vy = v[1], vz = v[2];
     const double v2 = vx * vx + vy * vy + vz * vz, vF = vx * F[0] + vy * F[1] + vz * F[2];
     const double pxx = rho * (3.0 * vx * vx - v2), pww = rho * (vy * vy - vz * vz);
@@ -439,6 +472,12 @@ __device__ __forceinline__ void collide3(const DevParams &P, double f[Q19], doub
 #pragma unroll
     for (int k = 0; k < Q19; ++k)
         mh[k] = (m[k] - L[k] * (m[k] - meq[k]) + (1.0 - 0.5 * L[k]) * S[k]) * (1.0 / NORM3[k]);
+    // the density moment is conserved (m_eq = rho, S = 0), and rho/19 is
+    // rounded once: 1/19 as its nearest double plus the remainder.  rho *
+    // fl(1/19) alone is biased (fl(1/19) < 1/19); the outputs carry 19 times
+    // this value, so every node would lose a fixed 5.6e-17 rho of mass per
+    // step.
+    mh[0] = fma(rho, 1.0 / 19.0, rho * 0x1.af286bca1af28p-59);
     from_moments(mh, f);
 }
 
@@ -452,32 +491,24 @@ __global__ __launch_bounds__(NT3) void k3_lb(DevParams P, Geom3 g, const S *__re
     if (c >= g.n) return;
     int x, y, z;
     coords(g, c, x, y, z);
-    double f[Q19];
+    double f[Q19], m[Q19];
     load_f(P, g, fin, c, y, f);
-    double rho = f[0];
-#pragma unroll
-    for (int a = 1; a < Q19; ++a) rho += f[a];
+    moments(f, m);  // m_0 = rho, (m_3, m_5, m_7) = sum e f
+    const double rho = m[0];
     const Nb3 nb = neighbours(P, g, x, y, z);
     double F[3], Q;
     force3(P, g, nb, psi, y, c, rho, sc->rho_ave, F, Q);
-    double j[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int a = 1; a < Q19; ++a) {
-        if (EX3[a]) j[0] += EX3[a] * f[a];
-        if (EY3[a]) j[1] += EY3[a] * f[a];
-        if (EZ3[a]) j[2] += EZ3[a] * f[a];
-    }
     const double inv = rcp_nr(rho);
-    const double v[3] = {(j[0] + 0.5 * F[0]) * inv, (j[1] + 0.5 * F[1]) * inv, (j[2] + 0.5 * F[2]) * inv};
+    const double v[3] = {(m[3] + 0.5 * F[0]) * inv, (m[5] + 0.5 * F[1]) * inv, (m[7] + 0.5 * F[2]) * inv};
     const bool wall = !P.periodic_y && (y == 0 || y == g.ny - 1);
     ((gmem<S> *)vx_o)[c] = wall ? S(0) : S(v[0]);
     ((gmem<S> *)vy_o)[c] = wall ? S(0) : S(v[1]);
     ((gmem<S> *)vz_o)[c] = wall ? S(0) : S(v[2]);
-    collide3(P, f, rho, v, F, Q, rcp_nr(P.tau_V + (rho - P.rho_V) * P.tau_slope));
+    collide3(P, m, rho, v, F, Q, rcp_nr(P.tau_V + (rho - P.rho_V) * P.tau_slope), f);
 #pragma unroll
     for (int a = 0; a < Q19; ++a) {
         const bool keep = EY3[a] < 0 ? nb.has_s : (EY3[a] > 0 ? nb.has_n : true);
-        if (keep) ((gmem<S> *)fout)[(size_t)a * g.n + nb_at(nb, c, a)] = S(f[a]);
+        if (keep) lbb::st_at(fout + (size_t)a * g.n, nb_at(nb, c, a) * (unsigned)sizeof(S), S(f[a]));
     }
 }
 
@@ -496,14 +527,14 @@ template <int MASK, typename T_>
 __device__ __forceinline__ void stencil3(const Nb3 &nb, const T_ *__restrict__ p, unsigned c, double grad[3],
                                          double *lap)
 {
-    const double pc = (double)((const gmem<T_> *)p)[c];
+    const double pc = (double)lbb::ld_at(p, c * (unsigned)sizeof(T_));
     double gx = 0.0, gy = 0.0, gz = 0.0, l = 0.0;
 #pragma unroll
     for (int a = 1; a < Q19; ++a) {
         const bool need = lap || ((MASK & 1) && EX3[a]) || ((MASK & 2) && EY3[a]) || ((MASK & 4) && EZ3[a]);
         if (!need) continue;
         const double w = W36[a] * (1.0 / 36.0);
-        const double val = (double)((const gmem<T_> *)p)[nb_at(nb, c, a)];
+        const double val = (double)lbb::ld_at(p, nb_at(nb, c, a) * (unsigned)sizeof(T_));
         if ((MASK & 1) && EX3[a]) gx = fma(EX3[a] * w, val, gx);
         if ((MASK & 2) && EY3[a]) gy = fma(EY3[a] * w, val, gy);
         if ((MASK & 4) && EZ3[a]) gz = fma(EZ3[a] * w, val, gz);
