@@ -44,28 +44,28 @@ def _kernel_roofline(alg_bytes, ms, traffic, per_update):
 # (KiB per dispatch, mean over the dispatches of a --profile run with the
 # given tiles), each scaled by what the same counter reads, in the same
 # profiling session, for an elementwise kernel that reads 1 GiB and writes
-# 1 GiB (FETCH_SIZE 436917.0 KiB -> factor 2.40, WRITE_SIZE 1048576 KiB ->
+# 1 GiB (FETCH_SIZE 436918.5 KiB -> factor 2.40, WRITE_SIZE 1048576 KiB ->
 # factor 1.0).  Valid for the kernel source whose hash is recorded and the
 # same tile shape; null otherwise.
 MEASURED_TRAFFIC = {
     "source_hash": "7f926bdeb6b7b8bd",
-    "fetch_factor": 1048576.0 / 436917.0,
+    "fetch_factor": 1048576.0 / 436918.5,
     "write_factor": 1048576.0 / 1048576.0,
     "k_lb": {
         "large_1024x512_fp32": [
-            {"tiles": [62, 4, 4], "fetch_kib": 10705.2, "write_kib": 24620.1},
-            {"tiles": [62, 8, 8], "fetch_kib": 10670.5, "write_kib": 24628.2},
+            {"tiles": [62, 4, 4], "fetch_kib": 10724.6, "write_kib": 24620.1},
+            {"tiles": [62, 8, 8], "fetch_kib": 10720.2, "write_kib": 24639.8},
         ],
         "large_4096x2048_fp32": [
-            {"tiles": [62, 4, 4], "fetch_kib": 166955.2, "write_kib": 396036.0},
+            {"tiles": [62, 4, 4], "fetch_kib": 166694.6, "write_kib": 395574.9},
         ],
     },
     "k_thermal": {
         "large_1024x512_fp32": [
-            {"tiles": [56, 24, 16], "fetch_kib": 4836.6, "write_kib": 2040.2},
+            {"tiles": [56, 24, 16], "fetch_kib": 4838.3, "write_kib": 2040.2},
         ],
         "large_4096x2048_fp32": [
-            {"tiles": [56, 40, 16], "fetch_kib": 68970.7, "write_kib": 32748.4},
+            {"tiles": [56, 40, 16], "fetch_kib": 68763.9, "write_kib": 32748.0},
         ],
     },
 }
@@ -76,8 +76,8 @@ MEASURED_TRAFFIC = {
 MEASURED_TRAFFIC_3D = {
     "source_hash": "9a669203bb0f3428",
     "pool3d_150x151x150_fp32": {
-        "k3_psi": (132765.1, 40023.7), "k3_reduce": (107.8, 0.1), "k3_lb": (146674.6, 294873.9),
-        "k3_stage0": (36765.3, 92187.9), "k3_stage1": (53426.7, 26544.0), "k3_stage2": (53429.9, 26543.0),
+        "k3_psi": (132765.1, 40023.5), "k3_reduce": (107.8, 0.1), "k3_lb": (146639.3, 294859.4),
+        "k3_stage0": (36764.9, 92169.3), "k3_stage1": (53426.7, 26544.2), "k3_stage2": (53429.9, 26543.0),
         "k3_stage3": (53347.6, 13271.5),
     },
 }
