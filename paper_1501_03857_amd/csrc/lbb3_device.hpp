@@ -23,8 +23,9 @@
 //   k3_lb       forces (Eqs. (7), (9), (22)), velocity, MRT collision with
 //               the improved forcing (Eqs. (2), (4), (5), (8)) and push
 //               streaming (Eq. (3))
-//   k3_stage x4 the four RK4 stages (Eqs. (19)-(20)) of Eq. (18); the first
-//               also forms the per-node coefficients, the last writes T
+//   k3_stage0   the first RK4 stage (Eqs. (19)-(20)) of Eq. (18) on LDS
+//               tiles; it also forms the per-node coefficients
+//   k3_stage x3 the other three stages; the last writes T
 // All reductions run in a fixed order, so results are reproducible bitwise.
 #pragma once
 
@@ -546,70 +547,38 @@ __device__ __forceinline__ void stencil3(const Nb3 &nb, const T_ *__restrict__ p
     if (lap) *lap = 6.0 * l;
 }
 
-// Stage K (0..3).  Reads the stage input (T^t for K = 0, else Tin), writes
-// the next stage input Tout = T^t + c_{K+1} h (K < 3) or T^{t+1} (K = 3).
+// Stage K (1..3).  Reads the stage input Tin and the per-node coefficients
+// the first stage formed, writes the next stage input Tout = T^t + c_{K+1} h
+// (K < 3) or T^{t+1} (K = 3).
 template <typename S, int K>
 __global__ __launch_bounds__(NT3) void k3_stage(DevParams P, Geom3 g, const S *__restrict__ T0,
                                                const S *__restrict__ Tin, S *__restrict__ Tout,
-                                               S *__restrict__ acc, S *__restrict__ coef,
-                                               const S *__restrict__ rho, const S *__restrict__ vx,
-                                               const S *__restrict__ vy, const S *__restrict__ vz, Scalars3 *sc)
+                                               S *__restrict__ acc, const S *__restrict__ coef, Scalars3 *sc)
 {
+    static_assert(K >= 1 && K <= 3, "the first stage is k3_stage0");
     const unsigned c = node_of_thread();
     if (c >= g.n) return;
     int x, y, z;
     coords(g, c, x, y, z);
     const bool wall = !P.periodic_y && (y == 0 || y == g.ny - 1);
-    const double t0 = (double)((const gmem<S> *)T0)[c];
+    const double t0 = (double)lbb::ld_at(T0, c * (unsigned)sizeof(S));
     double h = 0.0;
     if (!wall) {
         const Nb3 nb = neighbours(P, g, x, y, z);
         double a[3], c1, c2;
-        gmem<S> *cf = (gmem<S> *)coef;
-        if constexpr (K == 0) {
-            // coefficients, once per step: grad rho, div v, A(rho), B(rho)
-            const double r = (double)((const gmem<S> *)rho)[c];
-            double gr[3], dx_[3], dy_[3], dz_[3];
-            stencil3<7>(nb, rho, c, gr, nullptr);
-            stencil3<1>(nb, vx, c, dx_, nullptr);
-            stencil3<2>(nb, vy, c, dy_, nullptr);
-            stencil3<4>(nb, vz, c, dz_, nullptr);
-            const double div = dx_[0] + dy_[1] + dz_[2];
-            const double D1 = 1.0 - P.b * r, D2 = 1.0 + 2.0 * P.b * r - P.b * P.b * r * r;
-            const double inv = rcp_nr(r * D1 * D2);
-            const double chi_r = P.chi * D1 * D2 * inv;
-            const double Aw = P.R_cv * div * (r * D2 * inv), Bw = P.a_cv * r * div * (r * D1 * inv);
-            a[0] = (double)((const gmem<S> *)vx)[c] - chi_r * gr[0];
-            a[1] = (double)((const gmem<S> *)vy)[c] - chi_r * gr[1];
-            a[2] = (double)((const gmem<S> *)vz)[c] - chi_r * gr[2];
-            c1 = Bw * P.k2_Tc - Aw;
-            c2 = -Bw * P.k1k_rsTc;
-            cf[0 * (size_t)g.n + c] = S(a[0]);
-            cf[1 * (size_t)g.n + c] = S(a[1]);
-            cf[2 * (size_t)g.n + c] = S(a[2]);
-            cf[3 * (size_t)g.n + c] = S(c1);
-            cf[4 * (size_t)g.n + c] = S(c2);
-            a[0] = (double)S(a[0]);
-            a[1] = (double)S(a[1]);
-            a[2] = (double)S(a[2]);
-            c1 = (double)S(c1);
-            c2 = (double)S(c2);
-        } else {
-            a[0] = (double)cf[0 * (size_t)g.n + c];
-            a[1] = (double)cf[1 * (size_t)g.n + c];
-            a[2] = (double)cf[2 * (size_t)g.n + c];
-            c1 = (double)cf[3 * (size_t)g.n + c];
-            c2 = (double)cf[4 * (size_t)g.n + c];
-        }
+        a[0] = (double)lbb::ld_at(coef + 0 * (size_t)g.n, c * (unsigned)sizeof(S));
+        a[1] = (double)lbb::ld_at(coef + 1 * (size_t)g.n, c * (unsigned)sizeof(S));
+        a[2] = (double)lbb::ld_at(coef + 2 * (size_t)g.n, c * (unsigned)sizeof(S));
+        c1 = (double)lbb::ld_at(coef + 3 * (size_t)g.n, c * (unsigned)sizeof(S));
+        c2 = (double)lbb::ld_at(coef + 4 * (size_t)g.n, c * (unsigned)sizeof(S));
         double gT[3], lap;
-        const S *src = K == 0 ? T0 : Tin;
-        stencil3<7>(nb, src, c, gT, &lap);
-        const double Tabs = P.T_ref + (double)((const gmem<S> *)src)[c];
+        stencil3<7>(nb, Tin, c, gT, &lap);
+        const double Tabs = P.T_ref + (double)lbb::ld_at(Tin, c * (unsigned)sizeof(S));
         h = -(a[0] * gT[0] + a[1] * gT[1] + a[2] * gT[2]) + P.chi * lap + c1 * Tabs + c2 * sqrt_pos(Tabs);
     }
     gmem<S> *ac = (gmem<S> *)acc;
-    constexpr double wst = (K == 0 || K == 3) ? 1.0 : 2.0;
-    const double sum = K == 0 ? h : (double)ac[c] + wst * h;
+    constexpr double wst = K == 3 ? 1.0 : 2.0;
+    const double sum = (double)ac[c] + wst * h;
     if constexpr (K < 3) {
         constexpr double cst = K < 2 ? 0.5 : 1.0;
         ac[c] = S(sum);
@@ -619,6 +588,127 @@ __global__ __launch_bounds__(NT3) void k3_stage(DevParams P, Geom3 g, const S *_
         if (!wall && !(P.T_ref + Tn > 0.0)) flag3(sc, sc->t, lbb::ERR_T);
         ((gmem<S> *)Tout)[c] = S(Tn);
     }
+}
+
+// First RK4 stage on LDS tiles.  Besides the temperature stencil it forms
+// the per-node coefficients of the slope from the gradient of rho and the
+// divergence of v: 66 neighbour values a node, which as gathers through the
+// caches bound the launch.  A block instead loads its tile of TX3 x TY3 x
+// TZ3 nodes with a halo of one node (rho, v and T: every cell once) into
+// LDS in FP64, and every stencil reads LDS.  The stencils add the same terms
+// in the same order as stencil3, so the arithmetic is that of the per-node
+// stages.
+constexpr int TX3 = 30, TY3 = 4, TZ3 = 4;                     // interior tile
+constexpr int RX3 = TX3 + 2, RY3 = TY3 + 2, RZ3 = TZ3 + 2;  // tile with its halo
+constexpr int NC3 = RX3 * RY3 * RZ3;                           // region cells
+constexpr int NS3 = 512;                                       // threads of a block
+static_assert(TX3 * TY3 * TZ3 <= NS3, "a block needs a thread per tile node");
+
+struct Tiles3 {
+    int ntx, nty, ntz;  // tiles along x, y, z
+};
+
+// LDS offset of the neighbour of a region cell along velocity a
+constexpr int cell_off3(int a) { return EX3[a] + RX3 * (EY3[a] + RY3 * EZ3[a]); }
+
+template <int MASK, typename T_>
+__device__ __forceinline__ void stencil3_lds(const T_ *p, int cell, double grad[3], double *lap)
+{
+    const double pc = (double)p[cell];
+    double gx = 0.0, gy = 0.0, gz = 0.0, l = 0.0;
+#pragma unroll
+    for (int a = 1; a < Q19; ++a) {
+        const bool need = lap || ((MASK & 1) && EX3[a]) || ((MASK & 2) && EY3[a]) || ((MASK & 4) && EZ3[a]);
+        if (!need) continue;
+        const double w = W36[a] * (1.0 / 36.0);
+        const double val = (double)p[cell + cell_off3(a)];
+        if ((MASK & 1) && EX3[a]) gx = fma(EX3[a] * w, val, gx);
+        if ((MASK & 2) && EY3[a]) gy = fma(EY3[a] * w, val, gy);
+        if ((MASK & 4) && EZ3[a]) gz = fma(EZ3[a] * w, val, gz);
+        if (lap) l = fma(w, val - pc, l);
+    }
+    grad[0] = 3.0 * gx;
+    grad[1] = 3.0 * gy;
+    grad[2] = 3.0 * gz;
+    if (lap) *lap = 6.0 * l;
+}
+
+template <typename S>
+__global__ __launch_bounds__(NS3) void k3_stage0(DevParams P, Geom3 g, Tiles3 tl, const S *__restrict__ T0,
+                                                S *__restrict__ Tout, S *__restrict__ acc, S *__restrict__ coef,
+                                                const S *__restrict__ rho, const S *__restrict__ vx,
+                                                const S *__restrict__ vy, const S *__restrict__ vz)
+{
+    __shared__ double sh[5][NC3];  // rho, vx, vy, vz, T of the region, converted once
+    const int nt = tl.ntx * tl.nty * tl.ntz;
+    const int tile = lbb::xcd_tile((int)blockIdx.x, nt);
+    const int bx = tile % tl.ntx, by = (tile / tl.ntx) % tl.nty, bz = tile / (tl.ntx * tl.nty);
+    const int x0 = bx * TX3, y0 = by * TY3, z0 = bz * TZ3;
+    const bool walls = !P.periodic_y;
+    const S *src[5] = {rho, vx, vy, vz, T0};
+    // the region, every cell once (x and z periodic, y periodic or cut at the walls)
+    for (int k = threadIdx.x; k < NC3; k += NS3) {
+        const int rx = k % RX3, ry = (k / RX3) % RY3, rz = k / (RX3 * RY3);
+        int y = y0 + ry - 1;
+        if (walls) {
+            if (y < 0 || y >= g.ny) continue;  // beyond a wall: never read
+        } else {
+            y %= g.ny;
+            if (y < 0) y += g.ny;
+        }
+        int x = (x0 + rx - 1) % g.nx;
+        if (x < 0) x += g.nx;
+        int z = (z0 + rz - 1) % g.nz;
+        if (z < 0) z += g.nz;
+        const unsigned off = node(g, x, y, z) * (unsigned)sizeof(S);
+#pragma unroll
+        for (int f = 0; f < 5; ++f) sh[f][k] = (double)lbb::ld_at(src[f], off);
+    }
+    __syncthreads();
+    if ((int)threadIdx.x >= TX3 * TY3 * TZ3) return;
+    const int ix = threadIdx.x % TX3, iy = (threadIdx.x / TX3) % TY3, iz = threadIdx.x / (TX3 * TY3);
+    const int x = x0 + ix, y = y0 + iy, z = z0 + iz;
+    if (x >= g.nx || y >= g.ny || z >= g.nz) return;
+    const unsigned c = node(g, x, y, z);
+    const int cell = (ix + 1) + RX3 * ((iy + 1) + RY3 * (iz + 1));
+    const bool wall = walls && (y == 0 || y == g.ny - 1);
+    const double t0 = (double)sh[4][cell];
+    double h = 0.0;
+    if (!wall) {
+        // coefficients, once per step: grad rho, div v, A(rho), B(rho)
+        const double r = (double)sh[0][cell];
+        double gr[3], dx_[3], dy_[3], dz_[3];
+        stencil3_lds<7>(sh[0], cell, gr, nullptr);
+        stencil3_lds<1>(sh[1], cell, dx_, nullptr);
+        stencil3_lds<2>(sh[2], cell, dy_, nullptr);
+        stencil3_lds<4>(sh[3], cell, dz_, nullptr);
+        const double div = dx_[0] + dy_[1] + dz_[2];
+        const double D1 = 1.0 - P.b * r, D2 = 1.0 + 2.0 * P.b * r - P.b * P.b * r * r;
+        const double inv = rcp_nr(r * D1 * D2);
+        const double chi_r = P.chi * D1 * D2 * inv;
+        const double Aw = P.R_cv * div * (r * D2 * inv), Bw = P.a_cv * r * div * (r * D1 * inv);
+        double a[3] = {(double)sh[1][cell] - chi_r * gr[0], (double)sh[2][cell] - chi_r * gr[1],
+                       (double)sh[3][cell] - chi_r * gr[2]};
+        double c1 = Bw * P.k2_Tc - Aw;
+        double c2 = -Bw * P.k1k_rsTc;
+        gmem<S> *cf = (gmem<S> *)coef;
+        cf[0 * (size_t)g.n + c] = S(a[0]);
+        cf[1 * (size_t)g.n + c] = S(a[1]);
+        cf[2 * (size_t)g.n + c] = S(a[2]);
+        cf[3 * (size_t)g.n + c] = S(c1);
+        cf[4 * (size_t)g.n + c] = S(c2);
+        a[0] = (double)S(a[0]);
+        a[1] = (double)S(a[1]);
+        a[2] = (double)S(a[2]);
+        c1 = (double)S(c1);
+        c2 = (double)S(c2);
+        double gT[3], lap;
+        stencil3_lds<7>(sh[4], cell, gT, &lap);
+        const double Tabs = P.T_ref + t0;
+        h = -(a[0] * gT[0] + a[1] * gT[1] + a[2] * gT[2]) + P.chi * lap + c1 * Tabs + c2 * sqrt_pos(Tabs);
+    }
+    ((gmem<S> *)acc)[c] = S(h);
+    ((gmem<S> *)Tout)[c] = S(t0 + 0.5 * h);
 }
 
 // ---------------------------------------------------------------------------

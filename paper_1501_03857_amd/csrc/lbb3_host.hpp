@@ -52,6 +52,13 @@ void enqueue_reductions3(lbb3_domain *d, int advance)
     hipLaunchKernelGGL(k3_reduce, dim3(1), dim3(NR3), 0, d->stream, d->g, d->mpart, d->hpart, d->nb, d->sc, advance);
 }
 
+// Tiles of the first RK4 stage.
+lbb3::Tiles3 stage0_tiles(const lbb3::Geom3 &g)
+{
+    using namespace lbb3;
+    return Tiles3{(g.nx + TX3 - 1) / TX3, (g.ny + TY3 - 1) / TY3, (g.nz + TZ3 - 1) / TZ3};
+}
+
 // One time step: reductions of state t, LB update, RK4 temperature step.
 template <typename S>
 void enqueue_step3(lbb3_domain *d)
@@ -70,14 +77,15 @@ void enqueue_step3(lbb3_domain *d)
         S *Ts0 = static_cast<S *>(d->Ts), *Ts1 = Ts0 + n;
         S *acc = static_cast<S *>(d->acc), *coef = static_cast<S *>(d->coef);
         const S *rho = static_cast<const S *>(d->rho);
-        hipLaunchKernelGGL((k3_stage<S, 0>), dim3(d->nb), dim3(NT3), 0, d->stream, d->dp, d->g, T0, T0, Ts0, acc, coef,
-                           rho, v, v + n, v + 2 * n, d->sc);
+        const Tiles3 tl = stage0_tiles(d->g);
+        hipLaunchKernelGGL(k3_stage0<S>, dim3(tl.ntx * tl.nty * tl.ntz), dim3(NS3), 0, d->stream, d->dp, d->g, tl, T0,
+                           Ts0, acc, coef, rho, v, v + n, v + 2 * n);
         hipLaunchKernelGGL((k3_stage<S, 1>), dim3(d->nb), dim3(NT3), 0, d->stream, d->dp, d->g, T0, Ts0, Ts1, acc,
-                           coef, rho, v, v + n, v + 2 * n, d->sc);
+                           coef, d->sc);
         hipLaunchKernelGGL((k3_stage<S, 2>), dim3(d->nb), dim3(NT3), 0, d->stream, d->dp, d->g, T0, Ts1, Ts0, acc,
-                           coef, rho, v, v + n, v + 2 * n, d->sc);
+                           coef, d->sc);
         hipLaunchKernelGGL((k3_stage<S, 3>), dim3(d->nb), dim3(NT3), 0, d->stream, d->dp, d->g, T0, Ts0, T1, acc,
-                           coef, rho, v, v + n, v + 2 * n, d->sc);
+                           coef, d->sc);
     }
     if (d->dp.mode != lbb::MODE_THERMAL_ONLY) d->cf ^= 1;
     if (d->dp.mode != lbb::MODE_ISOTHERMAL) d->cT ^= 1;
