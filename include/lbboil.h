@@ -159,10 +159,22 @@ void *lbb_stream(lbb_domain *d);
  * measurement only; the state advances exactly as with lbb_step. */
 int lbb_time_kernels(lbb_domain *d, int64_t n, double *ms_lb, double *ms_thermal, double *ms_step);
 
+/* Fields of lbb_read_fields' mask. */
+#define LBB_FIELD_RHO 1u
+#define LBB_FIELD_UX 2u
+#define LBB_FIELD_UY 4u
+#define LBB_FIELD_T 8u
+#define LBB_FIELD_F 16u
+#define LBB_FIELD_ALL 31u
+
 /* Read the current state, widened to FP64: rho = sum_a f_a; v from Eq. (6)
  * with the total force of the current state; T; and f (post-streaming, wall
- * rule applied).  Any pointer may be NULL. */
-int lbb_read_fields(lbb_domain *d, double *rho, double *ux, double *uy, double *T, double *f);
+ * rule applied).  Host buffers, nx*ny each, f 9*nx*ny, layout [a][y][x].  A
+ * field is written when its LBB_FIELD_* bit is set in `mask` and its pointer
+ * is not NULL; the others are left alone.  The domain's state is not
+ * changed. */
+int lbb_read_fields(const lbb_domain *d, uint32_t mask, double *rho, double *ux, double *uy, double *T,
+                    double *f);
 /* The same fields into caller-owned device buffers (FP64, nx*ny each, f
  * 9*nx*ny, layout [a][y][x]; NULL skipped), without a host wait.  The read
  * is ordered after the library's earlier work on the domain, after the
@@ -175,7 +187,7 @@ int lbb_read_fields_dev(lbb_domain *d, double *rho, double *ux, double *uy, doub
  * = mean of the samples since creation or lbb_reset_average, n_samples their
  * count; q_local [nx] (optional) = q_w(x) of the current state.
  * q_w = -c_v chi rho (-3 T_0 + 4 T_1 - T_2)/2 at each bottom-wall node. */
-int lbb_wall_heat_flux(lbb_domain *d, double *q_now, double *q_mean, double *q_local,
+int lbb_wall_heat_flux(const lbb_domain *d, double *q_now, double *q_mean, double *q_local,
                        int64_t *n_samples);
 int lbb_reset_average(lbb_domain *d);
 
@@ -224,10 +236,12 @@ int lbb_batch_destroy(lbb_batch *b);
 /* ---- Adjoint -----------------------------------------------------------
  * J = (1/N) sum_{n=1..N} q^n, the bottom-wall heat flux (Sec. 3.2) averaged
  * over the next N steps from the current state, and its gradient with
- * respect to the bottom-wall temperatures T_b(x) (all nx nodes, FP64 [nx])
- * and the bottom wall strength G_w (Eq. (22)), by a hand-written discrete
- * adjoint of the whole coupled step (FP64 arithmetic, FP64 adjoint fields).
- * J is required; dJ_dTb and dJ_dGw may be NULL.  States are checkpointed
+ * respect to the bottom-wall temperatures of the heater nodes,
+ * dJ_dTb[k] = dJ/dT_b(heater_idx[k]) for k < n_heater (heater_idx NULL: all
+ * nx nodes in order, n_heater must be nx), and the bottom wall strength G_w
+ * (Eq. (22)), by a hand-written discrete adjoint of the whole coupled step
+ * (FP64 arithmetic, FP64 adjoint fields).  J is required; dJ_dTb and dJ_dGw
+ * may be NULL.  EINVAL for a heater index outside [0, nx).  States are checkpointed
  * every K steps and each segment but the last is recomputed before its
  * reverse sweep.  K <= 0 lets the library choose: every state kept (K = N,
  * no recompute) when N + 2 states take at most a quarter of the free device
@@ -237,7 +251,8 @@ int lbb_batch_destroy(lbb_batch *b);
  * (N/K + K + 2) * 10 * nx*ny * sizeof(real) + 55 * nx*ny * 8 bytes.
  * EUNSUPPORTED for periodic_y or a test mode; EINVAL for N < 1; ENOMEM when
  * the workspace cannot be allocated. */
-int lbb_adjoint(lbb_domain *d, int64_t N, int64_t K, double *J, double *dJ_dTb, double *dJ_dGw);
+int lbb_adjoint(lbb_domain *d, int64_t N, int64_t K, const int32_t *heater_idx, int32_t n_heater, double *J,
+                double *dJ_dTb, double *dJ_dGw);
 
 /* The adjoint of every batch member at once (the same N and K for all),
  * each lattice's forward, recompute and reverse steps sharing the batch's

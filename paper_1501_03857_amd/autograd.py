@@ -30,8 +30,8 @@ class HeatFluxFn(torch.autograd.Function):
         Tb[idx] = T_heater.detach().cpu().double().numpy()
         domain.set_heater(Tb)
         domain.set_wettability(float(Gw.detach().cpu()))
-        J, gTb, gGw = domain.adjoint(n_steps, K)
-        ctx.save_for_backward(torch.as_tensor(gTb[idx], dtype=torch.float64),
+        J, gTb, gGw = domain.adjoint(n_steps, K, heater_idx=idx)
+        ctx.save_for_backward(torch.as_tensor(gTb, dtype=torch.float64),
                               torch.tensor(gGw, dtype=torch.float64))
         ctx.dev = (T_heater.device, Gw.device)
         return torch.tensor(J, dtype=torch.float64, device=T_heater.device)

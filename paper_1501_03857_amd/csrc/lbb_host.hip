@@ -903,15 +903,24 @@ int lbb_read_fields_dev(lbb_domain *d, double *rho, double *ux, double *uy, doub
     return LBB_OK;
 }
 
-int lbb_read_fields(lbb_domain *d, double *rho, double *ux, double *uy, double *T, double *f)
+int lbb_read_fields(const lbb_domain *dc, uint32_t mask, double *rho, double *ux, double *uy, double *T, double *f)
 {
-    if (!d) return fail(LBB_EINVAL, "domain is NULL");
+    if (!dc) return fail(LBB_EINVAL, "domain is NULL");
+    // reading uses the domain's stream and staging buffers but leaves its state alone
+    lbb_domain *d = const_cast<lbb_domain *>(dc);
+    if (!(mask & LBB_FIELD_RHO)) rho = nullptr;
+    if (!(mask & LBB_FIELD_UX)) ux = nullptr;
+    if (!(mask & LBB_FIELD_UY)) uy = nullptr;
+    if (!(mask & LBB_FIELD_T)) T = nullptr;
+    if (!(mask & LBB_FIELD_F)) f = nullptr;
     return d->p.precision == LBB_FP64 ? read_impl<double>(d, rho, ux, uy, T, f) : read_impl<float>(d, rho, ux, uy, T, f);
 }
 
-int lbb_wall_heat_flux(lbb_domain *d, double *q_now, double *q_mean, double *q_local, int64_t *n_samples)
+int lbb_wall_heat_flux(const lbb_domain *dc, double *q_now, double *q_mean, double *q_local, int64_t *n_samples)
 {
-    if (!d) return fail(LBB_EINVAL, "domain is NULL");
+    if (!dc) return fail(LBB_EINVAL, "domain is NULL");
+    // the read-back uses the domain's stream but leaves its state alone
+    lbb_domain *d = const_cast<lbb_domain *>(dc);
     lbb::Scalars s;
     LBB_HIP(hipMemcpyAsync(&s, d->sc, sizeof s, hipMemcpyDeviceToHost, d->stream));
     if (q_local) {
@@ -1997,10 +2006,18 @@ int adjoint_group(AdjGroup &g, int precision, int64_t N, int64_t K, double *J, d
 
 }  // namespace
 
-extern "C" int lbb_adjoint(lbb_domain *d, int64_t N, int64_t K, double *J, double *dJ_dTb, double *dJ_dGw)
+extern "C" int lbb_adjoint(lbb_domain *d, int64_t N, int64_t K, const int32_t *heater_idx, int32_t n_heater,
+                           double *J, double *dJ_dTb, double *dJ_dGw)
 {
     if (!d || !J) return fail(LBB_EINVAL, "domain and J are required");
     if (N < 1) return fail(LBB_EINVAL, "N must be >= 1");
+    if (!heater_idx && dJ_dTb && n_heater != d->p.nx) return fail(LBB_EINVAL, "without heater_idx, n_heater must be nx");
+    if (heater_idx && n_heater < 0) return fail(LBB_EINVAL, "n_heater must be >= 0");
+    if (heater_idx)
+        for (int32_t k = 0; k < n_heater; ++k)
+            if (heater_idx[k] < 0 || heater_idx[k] >= d->p.nx) return fail(LBB_EINVAL, "heater index outside [0, nx)");
+    // the gradient over the whole bottom wall, then the heater nodes' entries
+    std::vector<double> gTb(dJ_dTb ? (size_t)d->p.nx : 0);
     int rc = adjoint_checks(d);
     if (rc) return rc;
     AdjGroup g;
@@ -2022,8 +2039,10 @@ extern "C" int lbb_adjoint(lbb_domain *d, int64_t N, int64_t K, double *J, doubl
     g.bytes = &d->adj_bytes;
     g.held = &d->held;
     g.advance = [d](int64_t n) { return enqueue_steps(d, n); };
-    rc = adjoint_group(g, d->p.precision, N, K, J, dJ_dTb, dJ_dGw);
+    rc = adjoint_group(g, d->p.precision, N, K, J, dJ_dTb ? gTb.data() : nullptr, dJ_dGw);
     d->dev_bytes += (int64_t)d->adj_bytes - (int64_t)before;
+    if (rc == LBB_OK && dJ_dTb)
+        for (int32_t k = 0; k < (heater_idx ? n_heater : d->p.nx); ++k) dJ_dTb[k] = gTb[heater_idx ? heater_idx[k] : k];
     return rc;
 }
 

@@ -18,6 +18,9 @@ LIB_PATH = os.path.join(_HERE, "liblbboil.so")
 
 LBB_OK, LBB_EINVAL, LBB_ENOMEM, LBB_EDEVICE, LBB_ENONFINITE, LBB_EUNSUPPORTED, LBB_ESTATE = 0, -1, -2, -3, -4, -5, -6
 FP64, FP32 = 0, 1
+# fields of lbb_read_fields' mask
+FIELD_RHO, FIELD_UX, FIELD_UY, FIELD_T, FIELD_F = 1, 2, 4, 8, 16
+FIELD_ALL = 31
 COUPLED, ISOTHERMAL, THERMAL_ONLY = 0, 1, 2
 
 
@@ -80,7 +83,7 @@ def lib():
             "lbb_sync": (C.c_int, [vp]),
             "lbb_stream": (vp, [vp]),
             "lbb_time_kernels": (C.c_int, [vp, _i64, _pd, _pd, _pd]),
-            "lbb_read_fields": (C.c_int, [vp, _pd, _pd, _pd, _pd, _pd]),
+            "lbb_read_fields": (C.c_int, [vp, C.c_uint32, _pd, _pd, _pd, _pd, _pd]),
             "lbb_wall_heat_flux": (C.c_int, [vp, _pd, _pd, _pd, C.POINTER(_i64)]),
             "lbb_reset_average": (C.c_int, [vp]),
             "lbb_set_heater": (C.c_int, [vp, _pd]),
@@ -98,7 +101,7 @@ def lib():
             "lbb_batch_domain": (vp, [vp, C.c_int]),
             "lbb_batch_size": (C.c_int, [vp]),
             "lbb_batch_destroy": (C.c_int, [vp]),
-            "lbb_adjoint": (C.c_int, [vp, _i64, _i64, _pd, _pd, _pd]),
+            "lbb_adjoint": (C.c_int, [vp, _i64, _i64, C.POINTER(C.c_int32), C.c_int32, _pd, _pd, _pd]),
             "lbb_batch_adjoint": (C.c_int, [vp, _i64, _i64, _pd, _pd, _pd]),
             "lbb_read_fields_dev": (C.c_int, [vp, vp, vp, vp, vp, vp, vp]),
             "lbb_set_device_budget": (C.c_int, [_i64]),
@@ -301,19 +304,27 @@ class Domain:
         is left unchanged.  Returns the choice and the per-shape times (ms)."""
         return _autotune(lib().lbb_autotune, self._h, steps)
 
-    def adjoint(self, n_steps: int, K: int = 0):
+    def adjoint(self, n_steps: int, K: int = 0, heater_idx=None):
         """J = mean bottom-wall heat flux over the next n_steps and its
-        gradient w.r.t. T_b (all nx) and G_w; the state is left unchanged."""
+        gradient w.r.t. T_b of the heater nodes heater_idx (None: all nx, in
+        order) and G_w; the state is left unchanged."""
         J, gGw = _d(), _d()
-        gTb = np.zeros(self.p.nx)
-        _check(lib().lbb_adjoint(self._h, int(n_steps), int(K), C.byref(J), _ptr(gTb), C.byref(gGw)))
+        if heater_idx is None:
+            idx, n = None, self.p.nx
+        else:
+            idx = np.ascontiguousarray(heater_idx, dtype=np.int32)
+            n = len(idx)
+        gTb = np.zeros(n)
+        _check(lib().lbb_adjoint(self._h, int(n_steps), int(K),
+                                 None if idx is None else idx.ctypes.data_as(C.POINTER(C.c_int32)), n,
+                                 C.byref(J), _ptr(gTb), C.byref(gGw)))
         return J.value, gTb, gGw.value
 
     def fields(self, f: bool = True):
         ny, nx = self.p.ny, self.p.nx
         rho, ux, uy, T = (np.zeros((ny, nx)) for _ in range(4))
         ff = np.zeros((9, ny, nx)) if f else None
-        _check(lib().lbb_read_fields(self._h, _ptr(rho), _ptr(ux), _ptr(uy), _ptr(T), _ptr(ff)))
+        _check(lib().lbb_read_fields(self._h, FIELD_ALL, _ptr(rho), _ptr(ux), _ptr(uy), _ptr(T), _ptr(ff)))
         out = dict(rho=rho, ux=ux, uy=uy, T=T)
         if f:
             out["f"] = ff
@@ -329,7 +340,7 @@ class Domain:
     def bottom_temperature(self) -> np.ndarray:
         """The current bottom-wall temperatures T_b(x)."""
         T = np.zeros((self.p.ny, self.p.nx))
-        _check(lib().lbb_read_fields(self._h, None, None, None, _ptr(T), None))
+        _check(lib().lbb_read_fields(self._h, FIELD_T, None, None, None, _ptr(T), None))
         return T[0].copy()
 
     def heat_flux(self, local: bool = True):

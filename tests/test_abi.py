@@ -194,3 +194,13 @@ def test_step_noalloc_argument_checks():
     with pytest.raises(L.LbbError) as e:
         L.step_noalloc(big, fake, fake, 0x3000, 0x4000, 0x5000, [0, 0], 1, 0x6000)
     assert e.value.code == L.LBB_EINVAL and "scratch bytes" in str(e.value)
+
+
+def test_read_and_adjoint_reject_a_null_domain():
+    """The read-back, heat-flux and adjoint calls check their handle before
+    touching the device (this runs without a GPU)."""
+    lib = L.lib()
+    assert lib.lbb_read_fields(None, L.FIELD_ALL, None, None, None, None, None) == L.LBB_EINVAL
+    assert lib.lbb_wall_heat_flux(None, None, None, None, None) == L.LBB_EINVAL
+    assert lib.lbb_adjoint(None, 10, 0, None, 0, None, None, None) == L.LBB_EINVAL
+    assert L.FIELD_ALL == L.FIELD_RHO | L.FIELD_UX | L.FIELD_UY | L.FIELD_T | L.FIELD_F

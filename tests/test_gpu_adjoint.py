@@ -122,3 +122,21 @@ def _budget_case():
     assert L.device_bytes_held() > held1
     d.close()
     assert L.device_bytes_held() == held0
+
+
+def test_adjoint_heater_index_selection():
+    """dJ_dTb for a list of heater nodes (any order, repeats allowed) is the
+    full bottom-wall gradient at those nodes, bit for bit, and J is the same;
+    an index outside [0, nx) is EINVAL and leaves the domain usable."""
+    _say("adjoint heater_idx")
+    _, d, _ = make_pair(SMALL)
+    J, g, gw = d.adjoint(20, K=5)
+    idx = [7, 3, 3, SMALL.nx - 1, 0]
+    Js, gs, gws = d.adjoint(20, K=5, heater_idx=idx)
+    assert Js == J and gws == gw
+    assert np.array_equal(gs, g[idx])
+    with pytest.raises(L.LbbError) as e:
+        d.adjoint(20, K=5, heater_idx=[SMALL.nx])
+    assert e.value.code == L.LBB_EINVAL
+    J2, g2, _ = d.adjoint(20, K=5)
+    assert J2 == J and np.array_equal(g2, g)

@@ -341,3 +341,26 @@ def test_parameter_variants_match_oracle(variant):
     d.step(150)
     errs, bad = compare(o, d, TOL64)
     assert not bad, errs
+
+
+def test_read_fields_mask_selects_fields():
+    """lbb_read_fields writes a field only when its mask bit is set and its
+    pointer is given; the others stay as the caller left them."""
+    import ctypes as C
+
+    _say("read mask")
+    w = WL.PLAIN_128x64.resized(40, 20)
+    _, d, _ = make_pair(w)
+    d.step(5)
+    full = d.fields()
+    lib = L.lib()
+    ptr = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+    for bit, key in ((L.FIELD_RHO, "rho"), (L.FIELD_UX, "ux"), (L.FIELD_UY, "uy"), (L.FIELD_T, "T"), (L.FIELD_F, "f")):
+        bufs = {k: np.full(full[k].shape, -7.0) for k in ("rho", "ux", "uy", "T", "f")}
+        assert lib.lbb_read_fields(d._h, bit, ptr(bufs["rho"]), ptr(bufs["ux"]), ptr(bufs["uy"]), ptr(bufs["T"]),
+                                   ptr(bufs["f"])) == L.LBB_OK
+        for k, b in bufs.items():
+            if k == key:
+                assert np.array_equal(b, full[k]), key
+            else:
+                assert np.all(b == -7.0), (key, k)
