@@ -26,8 +26,8 @@
  *   O12 RK4 temperature step  T^{t+1} from K(T), rho, v at t      Eqs. (18)-(20)
  *   O13 wall heat flux        q_w = -lambda dT/dy at y = 0        Sec. 3.2
  *
- * Readings of points the paper leaves open (each one is listed in the design
- * notes; both this oracle and the GPU library implement the same reading):
+ * Readings of points the paper leaves open (both this oracle and the GPU
+ * library implement the same reading):
  *  - G = -1; pseudopotential weights w = 1/3 (axes), 1/12 (diagonals).
  *  - M is the standard D2Q9 moment basis (rho, e, zeta, jx, qx, jy, qy, pxx,
  *    pxy) with velocities ordered rest, E, N, W, S, NE, NW, SW, SE.

@@ -8,8 +8,7 @@
  * checked against it; the product never loads it and shares nothing with it.
  *
  * The time step is the paper's (Sec. 2) with every two-dimensional piece
- * carried to three dimensions; the readings (each one also in the design
- * notes) are:
+ * carried to three dimensions; the readings are:
  *  - D3Q19 velocities ordered rest, +x, -x, +y, -y, +z, -z, then the twelve
  *    edges (1,1,0), (-1,-1,0), (1,-1,0), (-1,1,0), (1,0,1), (-1,0,-1),
  *    (1,0,-1), (-1,0,1), (0,1,1), (0,-1,-1), (0,1,-1), (0,-1,1); lattice
