@@ -42,14 +42,17 @@ def _kernel_roofline(alg_bytes, ms, traffic, per_update):
 
 # HBM traffic of each launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
 # (KiB per dispatch, mean over the dispatches of a --profile run with the
-# given tiles), each scaled by what the same counter reads, in the same
-# profiling session, for an elementwise kernel that reads 1 GiB and writes
-# 1 GiB (FETCH_SIZE 436918.5 KiB -> factor 2.40, WRITE_SIZE 1048576 KiB ->
-# factor 1.0).  Valid for the kernel source whose hash is recorded and the
-# same tile shape; null otherwise.
+# given tiles), each scaled by what the same counter reads for an
+# elementwise kernel that reads 1 GiB and writes 1 GiB (FETCH_SIZE 524297.8
+# KiB -> factor 2.00, WRITE_SIZE 1048576 KiB -> factor 1.0).  The factor is
+# the one under which the 3-D kernels whose reads are fixed by their design
+# fetch exactly those bytes; a copy whose input sits partly in the
+# last-level cache reads less (one session read 436918.5 KiB), since
+# FETCH_SIZE does not count those hits.  Valid for the kernel source whose
+# hash is recorded and the same tile shape; null otherwise.
 MEASURED_TRAFFIC = {
     "source_hash": "7f926bdeb6b7b8bd",
-    "fetch_factor": 1048576.0 / 436918.5,
+    "fetch_factor": 1048576.0 / 524297.8,
     "write_factor": 1048576.0 / 1048576.0,
     "k_lb": {
         "large_1024x512_fp32": [
@@ -74,10 +77,10 @@ MEASURED_TRAFFIC = {
 # FP32 storage; KiB per dispatch), valid for the 3-D kernel source whose hash
 # is recorded.
 MEASURED_TRAFFIC_3D = {
-    "source_hash": "511c1528d3d1e280",
+    "source_hash": "fc24882c7e11d6ec",
     "pool3d_150x151x150_fp32": {
-        "k3_psi": (132759.6, 40023.6), "k3_reduce": (107.8, 0.1), "k3_lb": (146639.1, 294930.7),
-        "k3_stage0": (45483.6, 92089.2), "k3_stage1": (53429.2, 26544.6), "k3_stage2": (53429.4, 26543.0),
+        "k3_psi": (132765.1, 40023.6), "k3_reduce": (108.5, 0.1), "k3_lb": (146662.6, 294906.7),
+        "k3_stage0": (45828.2, 92088.4), "k3_stage1": (53429.2, 26544.5), "k3_stage2": (53429.4, 26543.0),
         "k3_stage3": (53351.1, 13271.5),
     },
 }

@@ -381,28 +381,39 @@ __device__ __forceinline__ double block_sum_r(double v, double *red)
     return s;
 }
 
-// s + a[k0] + a[k0 + NR3] + ... (below n), in that order, 16 loads in flight
-__device__ __forceinline__ double strided_sum(const double *__restrict__ a_, int k0, int n)
+// Per thread: a[k0] + a[k0 + NR3] + ... (below n) and the same for b, each
+// added in that order; the loads of 16 terms of both arrays are issued before
+// the first of them is added, the last group's included (a step has about 13
+// terms a thread, so a loop that waited per term would wait 26 times).
+__device__ __forceinline__ void strided_sum2(const double *__restrict__ a_, const double *__restrict__ b_, int k0,
+                                             int n, double &sa, double &sb)
 {
     const gmem<double> *__restrict__ a = (const gmem<double> *)a_;
-    double s = 0.0;
-    int k = k0;
-    for (; k + 15 * NR3 < n; k += 16 * NR3) {
-        double v[16];
+    const gmem<double> *__restrict__ b = (const gmem<double> *)b_;
+    sa = sb = 0.0;
+    for (int k = k0; k < n; k += 16 * NR3) {
+        double va[16], vb[16];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) v[j] = a[k + j * NR3];
+        for (int j = 0; j < 16; ++j) {
+            const bool in = k + j * NR3 < n;
+            va[j] = in ? a[k + j * NR3] : 0.0;
+            vb[j] = in ? b[k + j * NR3] : 0.0;
+        }
 #pragma unroll
-        for (int j = 0; j < 16; ++j) s += v[j];
+        for (int j = 0; j < 16; ++j)
+            if (k + j * NR3 < n) {
+                sa += va[j];
+                sb += vb[j];
+            }
     }
-    for (; k < n; k += NR3) s += a[k];
-    return s;
 }
 
 __global__ __launch_bounds__(NR3) void k3_reduce(Geom3 g, const double *__restrict__ mpart,
                                                  const double *__restrict__ hpart, int nb, Scalars3 *sc, int advance)
 {
     __shared__ double red[NR3 / 64];
-    const double m = strided_sum(mpart, threadIdx.x, nb), h = strided_sum(hpart, threadIdx.x, nb);
+    double m, h;
+    strided_sum2(mpart, hpart, threadIdx.x, nb, m, h);
     const double ms = block_sum_r(m, red);
     __syncthreads();
     const double hs = block_sum_r(h, red);

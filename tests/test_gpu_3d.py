@@ -187,3 +187,15 @@ def test_chunked_stepping_bitwise_and_builtin_initial_state():
     o = O.State3(O.Params(nx=21, ny=12, a=A, b=B, rho_L=rl, rho_V=rv), 5,
                  WL.layered_density3(21, 12, 5, rl, rv, 7, 1e-3, 5))
     assert np.array_equal(d.fields()["f"], o.fields()["f"])
+
+
+@pytest.mark.parametrize("precision", [L.FP64, L.FP32])
+def test_larger_ragged_lattice(precision):
+    """62x60x51: ragged first-stage tiles in x, y and z (30x4x4 interiors),
+    about 740 per-node blocks, walls."""
+    _say("3d ragged 62x60x51", precision)
+    o, tw, d = _pair(62, 60, 51, precision=precision, seed=9)
+    for s in (o, tw, d):
+        s.step(12)
+    errs, bad = _compare(o, tw, d, precision)
+    assert not bad, bad
