@@ -23,7 +23,7 @@ from typing import Dict, List, Optional, Sequence, Tuple
 import numpy as np
 
 from . import lbboil as L
-from .workloads import layered_density
+from .workloads import layered_density, smooth_layered_density
 
 # Sec. 2 and Sec. 3.1: a = 3/49, b = 2/21, R = 1, omega = 0.344, sigma = 1.2,
 # T_s = 0.86 T_c, nu_L = 0.1, nu_V = 0.5/3, c_v = 6, c_v chi = 0.028,
@@ -250,6 +250,94 @@ def calibrate_wall_strength(targets_deg: Sequence[float], a: float = PAPER_A,
     for t in targets_deg:
         out[float(t)] = float(np.interp(t, th, gs)) if th[0] <= t <= th[-1] else None
     return {"a": a, "grid": g.tolist(), "angles": angles.tolist(), "Gw": out}
+
+
+# ---------------------------------------------------------------------------
+# Larger density ratios (Sec. 4 names boiling at large density ratios as the
+# model's next step).  Lowering T_s / T_c raises rho_L / rho_V along the
+# Peng-Robinson coexistence curve: 17 at 0.86 T_c, 71 at 0.75, 145 at 0.70,
+# 853 at 0.60 (a drops out of these reduced densities).  The model is
+# unchanged; only the initial layers start smooth.
+
+def large_ratio_pool(Ts_over_Tc: float, dT_over_Tc: float, a: float = 2.0 / 49.0, Gw: float = 0.0,
+                     precision: int = L.FP32, seed: int = 1, nx: int = PAPER_NX, ny: int = PAPER_NY,
+                     width: float = 2.5):
+    """The paper's pool at T_s = Ts_over_Tc T_c with the whole bottom wall at
+    T_s + dT_over_Tc T_c, liquid below row 90 (of 151) at the coexistence
+    densities of T_s with a tanh interface of half-width `width`, gravity
+    scaled with a from the paper's 3e-5 at a = 3/49 (the hydrostatic load then
+    keeps its ratio to the pressure scale).  Returns (Params, T_bottom, rho0,
+    rho_L / rho_V)."""
+    Tc, _ = L.eos_constants(a, PAPER_B, PAPER_R, PAPER_OMEGA)
+    Ts = Ts_over_Tc * Tc
+    rv, rl = L.coexistence(a, PAPER_B, PAPER_R, PAPER_OMEGA, Ts)
+    liquid = int(round(PAPER_LIQUID_ROWS * (ny - 1) / (PAPER_NY - 1)))
+    p = L.Params(nx=nx, ny=ny, precision=precision, liquid_rows=liquid, a=a, b=PAPER_B, R=PAPER_R,
+                 omega=PAPER_OMEGA, Ts_over_Tc=Ts_over_Tc, sigma=1.2, g=3e-5 * a / PAPER_A, Gw_bottom=Gw,
+                 rho_L=rl, rho_V=rv, seed=seed)
+    Tb = np.full(nx, Ts + dT_over_Tc * Tc)
+    rho0 = smooth_layered_density(nx, ny, rl, rv, liquid, width, p.noise_amp, seed)
+    return p, Tb, rho0, rl / rv
+
+
+def large_ratio_boiling(cases: Sequence[Tuple[float, float, float]], steps: int = 40000, t_avg: int = 20000,
+                        sample_every: int = 200, precision: int = L.FP32, nx: int = PAPER_NX,
+                        ny: int = PAPER_NY) -> List[dict]:
+    """Boiling pools of large_ratio_pool, one per (Ts_over_Tc, dT_over_Tc, a)
+    case, in one batch: q(t) sampled every `sample_every` steps, its mean over
+    the last t_avg steps, and at the end the vapour fraction of the two
+    fluid rows next to the heater (near 1 once a vapour film covers it)."""
+    built = [large_ratio_pool(th, dT, a, precision=precision, nx=nx, ny=ny) for th, dT, a in cases]
+    b = L.Batch([x[0] for x in built], [x[1] for x in built], [x[2] for x in built])
+    qs = [[] for _ in cases]
+    ts = []
+    try:
+        for t in range(sample_every, steps + 1, sample_every):
+            b.step(sample_every)
+            hf = b.heat_flux()
+            ts.append(t)
+            for i in range(len(cases)):
+                qs[i].append(float(hf["q_now"][i]))
+        out = []
+        for i, ((th, dT, a), (p, _, _, ratio)) in enumerate(zip(cases, built)):
+            rho = b.domain(i).fields(f=False)["rho"]
+            t_arr, q_arr = np.array(ts), np.array(qs[i])
+            win = t_arr > steps - t_avg
+            out.append({"Ts_over_Tc": th, "dT_over_Tc": dT, "a": a, "density_ratio": ratio, "t": t_arr, "q": q_arr,
+                        "q_mean": float(q_arr[win].mean()),
+                        "vapour_at_heater": float(np.mean(rho[1:3] < 0.5 * (p.rho_L + p.rho_V)))})
+        return out
+    finally:
+        b.close()
+
+
+def flat_interfaces(thetas: Sequence[float], a: float = 2.0 / 49.0, sigma: float = 1.2, steps: int = 20000,
+                    ny: int = 100, precision: int = L.FP64) -> List[dict]:
+    """Coexistence on the lattice: one periodic 4 x ny slab per T_s / T_c
+    (liquid in the middle half, smooth interfaces, no gravity, T fixed), all
+    in one batch; the densities at the slab centre and half a period away
+    after `steps` steps against the Maxwell densities."""
+    params, rhos, maxwell = [], [], []
+    for th in thetas:
+        Tc, _ = L.eos_constants(a, PAPER_B, PAPER_R, PAPER_OMEGA)
+        rv, rl = L.coexistence(a, PAPER_B, PAPER_R, PAPER_OMEGA, th * Tc)
+        params.append(L.Params(nx=4, ny=ny, precision=precision, a=a, b=PAPER_B, R=PAPER_R, omega=PAPER_OMEGA,
+                               Ts_over_Tc=th, sigma=sigma, g=0.0, rho_L=rl, rho_V=rv, periodic_y=1,
+                               thermal_mode=L.ISOTHERMAL))
+        j = np.abs(np.arange(ny) + 0.5 - ny / 2)
+        rhos.append((rv + (rl - rv) * 0.5 * (1 - np.tanh((j - ny / 4) / 2.5)))[:, None] * np.ones((1, 4)))
+        maxwell.append((rv, rl))
+    b = L.Batch(params, None, rhos)
+    try:
+        b.step(steps)
+        out = []
+        for i, th in enumerate(thetas):
+            r = b.domain(i).fields(f=False)["rho"]
+            out.append({"Ts_over_Tc": th, "rho_V": float(r[0, 0]), "rho_L": float(r[ny // 2, 0]),
+                        "maxwell": maxwell[i], "rho": r})
+        return out
+    finally:
+        b.close()
 
 
 def regimes(runs: Sequence[BoilingRun]) -> Dict[float, dict]:

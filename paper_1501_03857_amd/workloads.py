@@ -57,6 +57,29 @@ def layered_density3(nx: int, ny: int, nz: int, rho_L: float, rho_V: float, liqu
     return base + noise_amp * (2.0 * u - 1.0)
 
 
+def smooth_layered_density(nx: int, ny: int, rho_L: float, rho_V: float, liquid_rows: int, width: float,
+                           noise_amp: float, seed: int) -> np.ndarray:
+    """The liquid layer with a tanh interface of half-width `width` at
+    y = liquid_rows - 1/2: rho0[j, i] = rho_V + (rho_L - rho_V)(1 - tanh((j +
+    1/2 - liquid_rows)/width))/2 + A (2u - 1).  At density ratios far above
+    the paper's, the force of a one-row jump empties the vapour row next to
+    it in the first steps; a smooth start avoids that."""
+    u = uniform01(seed, nx * ny).reshape(ny, nx)
+    j = np.arange(ny, dtype=np.float64)[:, None]
+    base = rho_V + (rho_L - rho_V) * 0.5 * (1.0 - np.tanh((j + 0.5 - liquid_rows) / width))
+    return base * np.ones((1, nx)) + noise_amp * (2.0 * u - 1.0)
+
+
+def smooth_layered_density3(nx: int, ny: int, nz: int, rho_L: float, rho_V: float, liquid_rows: int,
+                            width: float, noise_amp: float, seed: int) -> np.ndarray:
+    """smooth_layered_density on three-dimensional lattices (u from counter
+    (k ny + j) nx + i)."""
+    u = uniform01(seed, nx * ny * nz).reshape(nz, ny, nx)
+    j = np.arange(ny, dtype=np.float64)[None, :, None]
+    base = rho_V + (rho_L - rho_V) * 0.5 * (1.0 - np.tanh((j + 0.5 - liquid_rows) / width))
+    return base * np.ones((nz, 1, nx)) + noise_amp * (2.0 * u - 1.0)
+
+
 def heater_profile(nx: int, T_s: float, T_heater: float, lo: int = 0, hi: Optional[int] = None) -> np.ndarray:
     """Bottom-wall temperature: T_heater on cells [lo, hi), T_s elsewhere."""
     hi = nx if hi is None else hi

@@ -1,0 +1,161 @@
+"""Larger density ratios: boiling at large density ratios is the step the
+paper names after three dimensions (Sec. 4).  The model is unchanged; a
+lower saturation temperature raises rho_L / rho_V along the Peng-Robinson
+coexistence curve (17 at T_s = 0.86 T_c, 71 at 0.75, 145 at 0.70, 853 at
+0.60).  Covered here:
+  - GPU vs oracle parity (the measures and bars of test_gpu_parity.py) of a
+    boiling pool at ratio 145 in FP64 and FP32, of a two-dimensional slab at
+    ratio 853, and of a three-dimensional pool at ratio 145;
+  - flat interfaces at ratios 17 to 853 over 20000 steps, against the oracle
+    run over the same steps and against the Maxwell densities;
+  - boiling pools at ratios 71 and 145 on the batched path: nucleate boiling
+    that lasts, and at ratio 71 the drop of the heat flux past the critical
+    superheat into film boiling (Sec. 3.2).
+The layers start with smooth interfaces (workloads.smooth_layered_density):
+a one-row jump at these ratios empties the vapour next to it in the first
+steps."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1501_03857_amd import experiments as E
+from paper_1501_03857_amd import lbboil as L
+from paper_1501_03857_amd import workloads as WL
+from parity_utils import STORE_FACTOR, compare, make_pair, normwise
+
+pytestmark = pytest.mark.gpu
+
+A2, A3 = 2.0 / 49.0, 3.0 / 49.0
+TOL = {L.FP64: 1e-12, L.FP32: 1e-5}
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+def _coex(a, theta):
+    w = WL.PLAIN_128x64
+    tc = O.Tc(a, w.b, w.R)
+    rv, rl, _ = O.maxwell(a, w.b, w.R, w.omega, theta * tc)
+    return tc, rv, rl
+
+
+@pytest.mark.parametrize("precision", [L.FP64, L.FP32])
+def test_boiling_pool_at_ratio_145_matches_oracle(precision):
+    """96x60 pool, a = 2/49, T_s = 0.70 T_c (rho_L / rho_V = 145), the whole
+    bottom wall 0.35 T_c above T_s, 300 steps from smooth layers."""
+    _say("ratio 145 pool 96x60", precision)
+    a, theta = A2, 0.70
+    tc, rv, rl = _coex(a, theta)
+    assert rl / rv > 140
+    w = WL.PLAIN_128x64.resized(96, 60, a=a, Ts_over_Tc=theta, dT_over_Tc=0.35, heater=(0, -1), Gw_bottom=0.0,
+                                seed=4, g=3e-5 * a / A3)
+    rho0 = WL.smooth_layered_density(w.nx, w.ny, rl, rv, w.liquid_rows, 2.5, w.noise_amp, w.seed)
+    o, d, _ = make_pair(w, precision=precision, rho0=rho0)
+    o.step(300)
+    d.step(300)
+    errs, bad = compare(o, d, TOL[precision])
+    assert not bad, errs
+
+
+def test_slab_at_ratio_853_matches_oracle():
+    """Periodic 48x80 slab (liquid in the middle half, smooth interfaces with
+    noise), a = 2/49, T = 0.60 T_c fixed (rho_L / rho_V = 853), FP64, 400
+    steps."""
+    _say("ratio 853 slab 48x80")
+    a, theta = A2, 0.60
+    tc, rv, rl = _coex(a, theta)
+    assert rl / rv > 800
+    nx, ny = 48, 80
+    j = np.abs(np.arange(ny) + 0.5 - ny / 2)[:, None]
+    u = WL.uniform01(6, nx * ny).reshape(ny, nx)
+    rho0 = (rv + (rl - rv) * 0.5 * (1 - np.tanh((j - ny / 4) / 2.5))) * (1 + 1e-3 * (2 * u - 1))
+    w = WL.PLAIN_128x64.resized(nx, ny, a=a, Ts_over_Tc=theta, g=0.0, seed=6)
+    o, d, _ = make_pair(w, precision=L.FP64, rho0=rho0, periodic_y=1, mode=O.ISOTHERMAL)
+    o.step(400)
+    d.step(400)
+    errs, bad = compare(o, d, TOL[L.FP64])
+    assert not bad, errs
+    r = d.fields()["rho"]
+    assert r.max() / r.min() > 700
+
+
+def test_three_dimensional_pool_at_ratio_145_matches_oracle():
+    """29x21x11 pool of the D3Q19 path, a = 2/49, T_s = 0.70 T_c, heater
+    0.35 T_c above T_s, smooth layers, FP64, 40 steps."""
+    _say("ratio 145 3-D pool 29x21x11")
+    a, theta = A2, 0.70
+    tc, rv, rl = _coex(a, theta)
+    nx, ny, nz = 29, 21, 11
+    liquid = int(0.6 * ny)
+    rho0 = WL.smooth_layered_density3(nx, ny, nz, rl, rv, liquid, 2.5, 1e-3, 5)
+    Tb = np.full((nz, nx), (theta + 0.35) * tc)
+    common = dict(nx=nx, ny=ny, a=a, Ts_over_Tc=theta, rho_L=rl, rho_V=rv, Gw_bottom=0.0, g=3e-5 * a / A3)
+    o = O.State3(O.Params(**common), nz, rho0, T_bottom=Tb)
+    tw = O.State3(O.Params(**common), nz, rho0, T_bottom=Tb).store_bits(52)
+    d = L.Domain3(L.Params(precision=L.FP64, liquid_rows=liquid, **common), nz, T_bottom=Tb, rho0=rho0)
+    for s in (o, tw, d):
+        s.step(40)
+    a_, b_, t_ = d.fields(), o.fields(), tw.fields()
+    errs, bars = {}, {}
+    for k in ("rho", "ux", "uy", "uz", "T", "f"):
+        errs[k] = normwise(a_[k], b_[k])
+        bars[k] = TOL[L.FP64]
+        if k in ("ux", "uy", "uz"):
+            bars[k] = max(TOL[L.FP64], STORE_FACTOR * normwise(t_[k], b_[k]))
+    ha, hb, ht = d.heat_flux(), o.heat_flux(), tw.heat_flux()
+    errs["q_local"] = normwise(ha["q_local"], hb["q_local"])
+    bars["q_local"] = max(TOL[L.FP64], STORE_FACTOR * normwise(ht["q_local"], hb["q_local"]))
+    print("[parity]", " ".join(f"{k}={v:.3g}" for k, v in errs.items()), flush=True)
+    bad = {k: (errs[k], bars[k]) for k in bars if not errs[k] <= bars[k]}
+    assert not bad, bad
+
+
+def test_flat_interfaces_long_runs_match_oracle():
+    """Periodic 4x100 slabs at T_s = 0.86, 0.80, 0.70 and 0.60 T_c (a = 2/49,
+    sigma = 1.2) in one FP64 batch, 20000 steps each: the densities of both
+    phases equal the oracle's over the same steps to 1e-10, the ratio of
+    the coldest slab exceeds 800, and the liquid sits within 0.1% of its
+    Maxwell density.  The vapour follows the mechanical-stability condition
+    of the forcing scheme rather than Maxwell's construction (sigma = 1.2 is
+    the paper's choice for a = 3/49), so its measured offset is printed, not
+    asserted."""
+    thetas = (0.86, 0.80, 0.70, 0.60)
+    _say("flat interfaces", thetas)
+    res = E.flat_interfaces(thetas, a=A2, sigma=1.2, steps=20000)
+    for r in res:
+        th = r["Ts_over_Tc"]
+        tc, rv, rl = _coex(A2, th)
+        p = O.Params(nx=4, ny=100, a=A2, Ts_over_Tc=th, sigma=1.2, g=0.0, rho_L=rl, rho_V=rv, periodic_y=1,
+                     thermal_mode=O.ISOTHERMAL)
+        j = np.abs(np.arange(100) + 0.5 - 50)
+        rho0 = (rv + (rl - rv) * 0.5 * (1 - np.tanh((j - 25) / 2.5)))[:, None] * np.ones((1, 4))
+        ro = O.State(p, rho0).step(20000).fields()["rho"]
+        err = normwise(r["rho"], ro)
+        print(f"[ratio] T_s = {th} T_c: rho_L/rho_V = {r['rho_L'] / r['rho_V']:.1f} (Maxwell {rl / rv:.1f}); "
+              f"rho_V {r['rho_V'] / rv - 1:+.3%}, rho_L {r['rho_L'] / rl - 1:+.4%} against Maxwell; "
+              f"gpu vs oracle {err:.2e}", flush=True)
+        assert err < 1e-10, (th, err)
+        assert abs(r["rho_L"] / rl - 1) < 1e-3, th
+    assert res[-1]["rho_L"] / res[-1]["rho_V"] > 800
+
+
+def test_boiling_at_larger_density_ratios():
+    """600x151 pools, FP32, 40000 steps in one batch: at ratio 71 (a = 3/49,
+    T_s = 0.75 T_c) a superheat of 0.35 T_c boils nucleately and 0.50 T_c
+    blankets the heater in vapour, with a far smaller mean heat flux over the
+    last 20000 steps (the drop past the critical heat flux, Sec. 3.2); at
+    ratio 145 (a = 2/49, T_s = 0.70 T_c) 0.35 T_c boils nucleately for the
+    whole run."""
+    cases = [(0.75, 0.35, A3), (0.75, 0.50, A3), (0.70, 0.35, A2)]
+    _say("boiling at ratios 71 and 145", cases)
+    res = E.large_ratio_boiling(cases, steps=40000, t_avg=20000)
+    for r in res:
+        print(f"[ratio] {r['density_ratio']:.0f}: T_s = {r['Ts_over_Tc']} T_c, dT = {r['dT_over_Tc']} T_c: "
+              f"q_mean = {r['q_mean']:.3e}, vapour next to the heater {r['vapour_at_heater']:.2f}", flush=True)
+    nucleate71, film71, nucleate145 = res
+    assert nucleate71["q_mean"] > 5 * film71["q_mean"]
+    assert film71["vapour_at_heater"] > 0.9
+    assert nucleate71["vapour_at_heater"] < 0.9
+    assert nucleate145["q_mean"] > 5e-4
+    assert np.all(np.isfinite(nucleate145["q"]))
