@@ -86,3 +86,25 @@ def test_drop_angle_is_nan_without_contact():
     rho = np.full((40, 100), 0.38)
     rho[20:30, 40:60] = 6.5           # a drop that does not touch row 1
     assert np.isnan(E.drop_angle(rho, 6.5, 0.38))
+
+
+@pytest.mark.parametrize("theta,ratio", [(0.75, 70.7), (0.70, 145.2), (0.60, 852.8)])
+def test_large_ratio_pool_setup(theta, ratio):
+    """The pool at a lower saturation temperature: the Maxwell densities of
+    T_s give the stated density ratio, the layers are smooth (tanh of
+    half-width 2.5 about y = 89.5, plus the seeded noise), gravity scales with
+    a from the paper's 3e-5 at a = 3/49, and the heater sits dT above T_s."""
+    a = 2.0 / 49.0
+    p, Tb, rho0, r = E.large_ratio_pool(theta, 0.35, a=a)
+    Tc, _ = L.eos_constants(a, E.PAPER_B, E.PAPER_R, E.PAPER_OMEGA)
+    tc_o = O.Tc(a, E.PAPER_B, E.PAPER_R)
+    rv, rl, _ = O.maxwell(a, E.PAPER_B, E.PAPER_R, E.PAPER_OMEGA, theta * tc_o)
+    assert abs(r / (rl / rv) - 1) < 1e-9 and abs(r - ratio) < 0.1
+    assert (p.nx, p.ny, p.liquid_rows, p.Ts_over_Tc) == (600, 151, 90, theta)
+    assert abs(p.g - 2e-5) < 1e-18
+    assert np.allclose(Tb, (theta + 0.35) * Tc, rtol=0, atol=1e-15)
+    prof = rho0.mean(axis=1)
+    j = np.arange(151) + 0.5
+    want = rv + (rl - rv) * 0.5 * (1 - np.tanh((j - 90) / 2.5))
+    assert np.max(np.abs(prof - want)) < 2e-4  # the noise averages out over 600 columns
+    assert np.max(np.abs(rho0 - want[:, None])) <= p.noise_amp * (1 + 1e-12)
