@@ -23,7 +23,7 @@ from typing import Dict, List, Optional, Sequence, Tuple
 import numpy as np
 
 from . import lbboil as L
-from .workloads import layered_density, smooth_layered_density
+from .workloads import layered_density, smooth_layered_density, smooth_layered_density3
 
 # Sec. 2 and Sec. 3.1: a = 3/49, b = 2/21, R = 1, omega = 0.344, sigma = 1.2,
 # T_s = 0.86 T_c, nu_L = 0.1, nu_V = 0.5/3, c_v = 6, c_v chi = 0.028,
@@ -309,6 +309,44 @@ def large_ratio_boiling(cases: Sequence[Tuple[float, float, float]], steps: int 
         return out
     finally:
         b.close()
+
+
+def large_ratio_boiling3(cases: Sequence[Tuple[float, float, float]], nx: int = 120, ny: int = 81, nz: int = 60,
+                         steps: int = 20000, t_avg: int = 10000, sample_every: int = 500,
+                         precision: int = L.FP32) -> List[dict]:
+    """Three-dimensional pools (the D3Q19 path), one per (Ts_over_Tc,
+    dT_over_Tc, a) case, run one after another: liquid below row 0.6 ny with
+    a smooth interface, the whole bottom wall dT above T_s, gravity scaled
+    with a.  Per case: q(t) sampled every `sample_every` steps, the mean of
+    q over the last t_avg steps (the library's running average, restarted
+    there), and the vapour fraction of the two fluid rows next to the heater
+    at every sample."""
+    out = []
+    for th, dT, a in cases:
+        Tc, _ = L.eos_constants(a, PAPER_B, PAPER_R, PAPER_OMEGA)
+        Ts = th * Tc
+        rv, rl = L.coexistence(a, PAPER_B, PAPER_R, PAPER_OMEGA, Ts)
+        liquid = int(0.6 * ny)
+        p = L.Params(nx=nx, ny=ny, precision=precision, liquid_rows=liquid, a=a, b=PAPER_B, R=PAPER_R,
+                     omega=PAPER_OMEGA, Ts_over_Tc=th, sigma=1.2, g=3e-5 * a / PAPER_A, rho_L=rl, rho_V=rv)
+        rho0 = smooth_layered_density3(nx, ny, nz, rl, rv, liquid, 2.5, p.noise_amp, p.seed)
+        d = L.Domain3(p, nz, T_bottom=np.full((nz, nx), Ts + dT * Tc), rho0=rho0)
+        ts, qs, vap = [], [], []
+        try:
+            for t in range(sample_every, steps + 1, sample_every):
+                if t - sample_every == steps - t_avg:
+                    d.reset_average()
+                d.step(sample_every)
+                ts.append(t)
+                qs.append(d.heat_flux(local=False)["q_now"])
+                rho = d.fields(f=False)["rho"]
+                vap.append(float(np.mean(rho[:, 1:3, :] < 0.5 * (rl + rv))))
+            q_mean = d.heat_flux(local=False)["q_mean"]
+        finally:
+            d.close()
+        out.append({"Ts_over_Tc": th, "dT_over_Tc": dT, "a": a, "density_ratio": rl / rv, "t": np.array(ts),
+                    "q": np.array(qs), "q_mean": float(q_mean), "vapour_at_heater": np.array(vap)})
+    return out
 
 
 def flat_interfaces(thetas: Sequence[float], a: float = 2.0 / 49.0, sigma: float = 1.2, steps: int = 20000,

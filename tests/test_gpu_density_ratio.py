@@ -10,7 +10,9 @@ coexistence curve (17 at T_s = 0.86 T_c, 71 at 0.75, 145 at 0.70, 853 at
     run over the same steps and against the Maxwell densities;
   - boiling pools at ratios 71 and 145 on the batched path: nucleate boiling
     that lasts, and at ratio 71 the drop of the heat flux past the critical
-    superheat into film boiling (Sec. 3.2).
+    superheat into film boiling (Sec. 3.2);
+  - three-dimensional pools at ratio 71: no boiling, nucleate boiling and
+    film boiling as the superheat rises.
 The layers start with smooth interfaces (workloads.smooth_layered_density):
 a one-row jump at these ratios empties the vapour next to it in the first
 steps."""
@@ -159,3 +161,25 @@ def test_boiling_at_larger_density_ratios():
     assert nucleate71["vapour_at_heater"] < 0.9
     assert nucleate145["q_mean"] > 5e-4
     assert np.all(np.isfinite(nucleate145["q"]))
+
+
+def test_three_dimensional_boiling_regimes_at_ratio_71():
+    """120x81x60 pools of the D3Q19 path, a = 3/49, T_s = 0.75 T_c (rho_L /
+    rho_V = 71), FP32, 20000 steps each: at a superheat of 0.20 T_c the
+    heater only conducts (no vapour at it), at 0.25 T_c bubbles form and the
+    mean heat flux over the last 10000 steps is several times larger, at
+    0.50 T_c a vapour film covers the heater and the flux falls far below
+    the nucleate one (the boiling curve's three regimes, Sec. 3.2)."""
+    cases = [(0.75, 0.20, A3), (0.75, 0.25, A3), (0.75, 0.50, A3)]
+    _say("3-D boiling regimes at ratio 71", cases)
+    res = E.large_ratio_boiling3(cases)
+    for r in res:
+        print(f"[ratio] 3-D {r['density_ratio']:.0f}: dT = {r['dT_over_Tc']} T_c: q_mean = {r['q_mean']:.3e}, "
+              f"vapour at the heater max {r['vapour_at_heater'].max():.2f} end {r['vapour_at_heater'][-1]:.2f}",
+              flush=True)
+    conduct, nucleate, film = res
+    assert conduct["vapour_at_heater"].max() < 0.01
+    assert nucleate["vapour_at_heater"].max() > 0.1 and nucleate["vapour_at_heater"].min() < 0.9
+    assert nucleate["q_mean"] > 2 * conduct["q_mean"]
+    assert film["vapour_at_heater"][-1] > 0.9
+    assert film["q_mean"] < 0.2 * nucleate["q_mean"]
