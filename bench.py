@@ -77,10 +77,10 @@ MEASURED_TRAFFIC = {
 # FP32 storage; KiB per dispatch), valid for the 3-D kernel source whose hash
 # is recorded.
 MEASURED_TRAFFIC_3D = {
-    "source_hash": "fc24882c7e11d6ec",
+    "source_hash": "b58727298629e549",
     "pool3d_150x151x150_fp32": {
-        "k3_psi": (132765.1, 40023.6), "k3_reduce": (108.5, 0.1), "k3_lb": (146662.6, 294906.7),
-        "k3_stage0": (45828.2, 92088.4), "k3_stage1": (53429.2, 26544.5), "k3_stage2": (53429.4, 26543.0),
+        "k3_psi": (132765.1, 40023.5), "k3_reduce": (108.5, 0.1), "k3_lb": (146640.1, 294904.3),
+        "k3_stage0": (37460.4, 93766.5), "k3_stage1": (53429.2, 26544.7), "k3_stage2": (53429.4, 26543.0),
         "k3_stage3": (53351.1, 13271.5),
     },
 }
@@ -90,7 +90,7 @@ def measured_traffic_3d(workload: str):
     """HBM bytes of one 3-D step from the recorded counters, or None when
     the 3-D kernel source or the workload differ."""
     m = MEASURED_TRAFFIC_3D
-    if m.get("source_hash") != source_hash("lbb3_device.hpp") or workload not in m:
+    if m.get("source_hash") != source_hash("lbb3_device.hpp", "lbb3_host.hpp") or workload not in m:
         return None
     f = MEASURED_TRAFFIC["fetch_factor"]
     return int(round(sum(fe * f + wr for fe, wr in m[workload].values()) * 1024))
@@ -115,12 +115,14 @@ def arithmetic(store: str) -> str:
     return "mixed: f32 storage; f64 LB, EOS and reductions; f32 RK4 stages (pressure-work coefficients formed in f64)"
 
 
-def source_hash(name: str = "lbb_device.hpp") -> str:
-    """Hash of a kernel source file (the recorded counters depend on it and
-    on the tile shape only)."""
+def source_hash(*names: str) -> str:
+    """Hash of kernel source files (the recorded counters depend on them and,
+    in 2-D, on the tile shape; the 3-D launch shapes are set in the 3-D host
+    source, which is hashed with its kernels)."""
     h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_1501_03857_amd", "csrc", name), "rb") as fh:
-        h.update(fh.read())
+    for name in names or ("lbb_device.hpp",):
+        with open(os.path.join(ROOT, "paper_1501_03857_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 

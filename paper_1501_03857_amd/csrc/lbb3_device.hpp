@@ -601,42 +601,47 @@ __global__ __launch_bounds__(NT3) void k3_stage(DevParams P, Geom3 g, const S *_
     }
 }
 
-// First RK4 stage on LDS tiles.  Besides the temperature stencil it forms
-// the per-node coefficients of the slope from the gradient of rho and the
-// divergence of v: 66 neighbour values a node, which as gathers through the
-// caches bound the launch.  A block instead loads its tile of TX3 x TY3 x
-// TZ3 nodes with a halo of one node (rho, v and T: every cell once) into
-// LDS in FP64, and every stencil reads LDS.  The stencils add the same terms
-// in the same order as stencil3, so the arithmetic is that of the per-node
-// stages.
-constexpr int TX3 = 30, TY3 = 4, TZ3 = 4;                     // interior tile
-constexpr int RX3 = TX3 + 2, RY3 = TY3 + 2, RZ3 = TZ3 + 2;  // tile with its halo
-constexpr int NC3 = RX3 * RY3 * RZ3;                           // region cells
-constexpr int NS3 = 512;                                       // threads of a block
-static_assert(TX3 * TY3 * TZ3 <= NS3, "a block needs a thread per tile node");
+// First RK4 stage, marching along z.  Besides the temperature stencil it
+// forms the per-node coefficients of the slope from the gradient of rho and
+// the divergence of v: 66 neighbour values a node, which as gathers through
+// the caches bound the launch.  A block owns RXZ x RYZ region columns (TXZ x
+// TYZ interior columns and a halo of one in x and y), one thread a column, and
+// a run of tl.zc planes.  It keeps three planes of rho, v and T in LDS as a
+// ring, in the storage precision (so that in FP32 four blocks fit a CU), loads
+// plane z + 2 into registers while it works on plane z, and then moves it into
+// the slot of plane z - 1.  A value is loaded (32/30) (16/14) (zc + 2)/zc
+// times, against 2.4 times for tiles with a halo in all three directions, and
+// the loads of the next plane run under the stencils of the current one.  The
+// stencils widen each value to FP64 and add the same terms in the same order as
+// stencil3, so the arithmetic is that of the per-node stages.
+constexpr int RXZ = 32, RYZ = 16;            // region columns along x and y
+constexpr int TXZ = RXZ - 2, TYZ = RYZ - 2;  // interior columns
+constexpr int NSZ = RXZ * RYZ;               // threads of a block, one a region column
 
 struct Tiles3 {
-    int ntx, nty, ntz;  // tiles along x, y, z
+    int ntx, nty, ntz;  // column tiles along x and y, plane runs along z
+    int zc;             // planes of a run
 };
 
-// LDS offset of the neighbour of a region cell along velocity a
-constexpr int cell_off3(int a) { return EX3[a] + RX3 * (EY3[a] + RY3 * EZ3[a]); }
-
-template <int MASK, typename T_>
-__device__ __forceinline__ void stencil3_lds(const T_ *p, int cell, double grad[3], double *lap)
+// Stencil of a field at region cell `cell` of the middle plane, the planes
+// below and above given apart (terms in the order of stencil3)
+template <int MASK, typename L>
+__device__ __forceinline__ void stencil3_ring(const L *pm, const L *pc, const L *pp, int cell, double grad[3],
+                                              double *lap)
 {
-    const double pc = (double)p[cell];
+    const double v0 = (double)pc[cell];
     double gx = 0.0, gy = 0.0, gz = 0.0, l = 0.0;
 #pragma unroll
     for (int a = 1; a < Q19; ++a) {
         const bool need = lap || ((MASK & 1) && EX3[a]) || ((MASK & 2) && EY3[a]) || ((MASK & 4) && EZ3[a]);
         if (!need) continue;
         const double w = W36[a] * (1.0 / 36.0);
-        const double val = (double)p[cell + cell_off3(a)];
+        const L *pl = EZ3[a] < 0 ? pm : (EZ3[a] > 0 ? pp : pc);
+        const double val = (double)pl[cell + EX3[a] + RXZ * EY3[a]];
         if ((MASK & 1) && EX3[a]) gx = fma(EX3[a] * w, val, gx);
         if ((MASK & 2) && EY3[a]) gy = fma(EY3[a] * w, val, gy);
         if ((MASK & 4) && EZ3[a]) gz = fma(EZ3[a] * w, val, gz);
-        if (lap) l = fma(w, val - pc, l);
+        if (lap) l = fma(w, val - v0, l);
     }
     grad[0] = 3.0 * gx;
     grad[1] = 3.0 * gy;
@@ -645,81 +650,104 @@ __device__ __forceinline__ void stencil3_lds(const T_ *p, int cell, double grad[
 }
 
 template <typename S>
-__global__ __launch_bounds__(NS3) void k3_stage0(DevParams P, Geom3 g, Tiles3 tl, const S *__restrict__ T0,
+__global__ __launch_bounds__(NSZ) void k3_stage0(DevParams P, Geom3 g, Tiles3 tl, const S *__restrict__ T0,
                                                 S *__restrict__ Tout, S *__restrict__ acc, S *__restrict__ coef,
                                                 const S *__restrict__ rho, const S *__restrict__ vx,
                                                 const S *__restrict__ vy, const S *__restrict__ vz)
 {
-    __shared__ double sh[5][NC3];  // rho, vx, vy, vz, T of the region, converted once
+    __shared__ S sh[3][5][NSZ];  // ring slot (plane) x field (rho, vx, vy, vz, T) x region column
     const int nt = tl.ntx * tl.nty * tl.ntz;
     const int tile = lbb::xcd_tile((int)blockIdx.x, nt);
     const int bx = tile % tl.ntx, by = (tile / tl.ntx) % tl.nty, bz = tile / (tl.ntx * tl.nty);
-    const int x0 = bx * TX3, y0 = by * TY3, z0 = bz * TZ3;
+    const int x0 = bx * TXZ, y0 = by * TYZ, z0 = bz * tl.zc;
+    const int z1 = min(z0 + tl.zc, g.nz);  // this block's planes are z0 .. z1-1
     const bool walls = !P.periodic_y;
+    const int rx = (int)threadIdx.x % RXZ, ry = (int)threadIdx.x / RXZ;
+    // this thread's region column: x periodic, y periodic or cut at the walls
+    int x = (x0 + rx - 1) % g.nx, y = y0 + ry - 1;
+    if (x < 0) x += g.nx;
+    bool in = true;  // false beyond a wall: never read
+    if (walls) in = y >= 0 && y < g.ny;
+    else {
+        y %= g.ny;
+        if (y < 0) y += g.ny;
+    }
+    const unsigned col = in ? (unsigned)y * (unsigned)g.nx + (unsigned)x : 0u;
+    const unsigned pl = (unsigned)g.nx * (unsigned)g.ny;
     const S *src[5] = {rho, vx, vy, vz, T0};
-    // the region, every cell once (x and z periodic, y periodic or cut at the walls)
-    for (int k = threadIdx.x; k < NC3; k += NS3) {
-        const int rx = k % RX3, ry = (k / RX3) % RY3, rz = k / (RX3 * RY3);
-        int y = y0 + ry - 1;
-        if (walls) {
-            if (y < 0 || y >= g.ny) continue;  // beyond a wall: never read
-        } else {
-            y %= g.ny;
-            if (y < 0) y += g.ny;
-        }
-        int x = (x0 + rx - 1) % g.nx;
-        if (x < 0) x += g.nx;
-        int z = (z0 + rz - 1) % g.nz;
-        if (z < 0) z += g.nz;
-        const unsigned off = node(g, x, y, z) * (unsigned)sizeof(S);
+    auto load = [&](int z, S v[5]) {  // plane z in [-1, nz]
+        const unsigned off = ((unsigned)wrap3(z, g.nz) * pl + col) * (unsigned)sizeof(S);
 #pragma unroll
-        for (int f = 0; f < 5; ++f) sh[f][k] = (double)lbb::ld_at(src[f], off);
-    }
+        for (int f = 0; f < 5; ++f) v[f] = in ? lbb::ld_at(src[f], off) : S(0);
+    };
+    auto put = [&](int slot, const S v[5]) {
+#pragma unroll
+        for (int f = 0; f < 5; ++f) sh[slot][f][threadIdx.x] = v[f];
+    };
+    S nxt[5];
+    // plane q sits in slot (q - z0 + 1) mod 3
+    load(z0 - 1, nxt);
+    put(0, nxt);
+    load(z0, nxt);
+    put(1, nxt);
+    load(z0 + 1, nxt);
+    put(2, nxt);
     __syncthreads();
-    if ((int)threadIdx.x >= TX3 * TY3 * TZ3) return;
-    const int ix = threadIdx.x % TX3, iy = (threadIdx.x / TX3) % TY3, iz = threadIdx.x / (TX3 * TY3);
-    const int x = x0 + ix, y = y0 + iy, z = z0 + iz;
-    if (x >= g.nx || y >= g.ny || z >= g.nz) return;
-    const unsigned c = node(g, x, y, z);
-    const int cell = (ix + 1) + RX3 * ((iy + 1) + RY3 * (iz + 1));
-    const bool wall = walls && (y == 0 || y == g.ny - 1);
-    const double t0 = (double)sh[4][cell];
-    double h = 0.0;
-    if (!wall) {
-        // coefficients, once per step: grad rho, div v, A(rho), B(rho)
-        const double r = (double)sh[0][cell];
-        double gr[3], dx_[3], dy_[3], dz_[3];
-        stencil3_lds<7>(sh[0], cell, gr, nullptr);
-        stencil3_lds<1>(sh[1], cell, dx_, nullptr);
-        stencil3_lds<2>(sh[2], cell, dy_, nullptr);
-        stencil3_lds<4>(sh[3], cell, dz_, nullptr);
-        const double div = dx_[0] + dy_[1] + dz_[2];
-        const double D1 = 1.0 - P.b * r, D2 = 1.0 + 2.0 * P.b * r - P.b * P.b * r * r;
-        const double inv = rcp_nr(r * D1 * D2);
-        const double chi_r = P.chi * D1 * D2 * inv;
-        const double Aw = P.R_cv * div * (r * D2 * inv), Bw = P.a_cv * r * div * (r * D1 * inv);
-        double a[3] = {(double)sh[1][cell] - chi_r * gr[0], (double)sh[2][cell] - chi_r * gr[1],
-                       (double)sh[3][cell] - chi_r * gr[2]};
-        double c1 = Bw * P.k2_Tc - Aw;
-        double c2 = -Bw * P.k1k_rsTc;
-        gmem<S> *cf = (gmem<S> *)coef;
-        cf[0 * (size_t)g.n + c] = S(a[0]);
-        cf[1 * (size_t)g.n + c] = S(a[1]);
-        cf[2 * (size_t)g.n + c] = S(a[2]);
-        cf[3 * (size_t)g.n + c] = S(c1);
-        cf[4 * (size_t)g.n + c] = S(c2);
-        a[0] = (double)S(a[0]);
-        a[1] = (double)S(a[1]);
-        a[2] = (double)S(a[2]);
-        c1 = (double)S(c1);
-        c2 = (double)S(c2);
-        double gT[3], lap;
-        stencil3_lds<7>(sh[4], cell, gT, &lap);
-        const double Tabs = P.T_ref + t0;
-        h = -(a[0] * gT[0] + a[1] * gT[1] + a[2] * gT[2]) + P.chi * lap + c1 * Tabs + c2 * sqrt_pos(Tabs);
+
+    const int xi = x0 + rx - 1, yi = y0 + ry - 1;
+    const bool mine = rx >= 1 && rx <= TXZ && ry >= 1 && ry <= TYZ && xi < g.nx && yi < g.ny;
+    const bool wall = walls && (yi == 0 || yi == g.ny - 1);
+    const int cell = (int)threadIdx.x;
+    int sm = 0;  // slot of plane z - 1
+    for (int z = z0; z < z1; ++z) {
+        const bool more = z + 2 <= z1;  // plane z + 2 is the upper neighbour of a plane of this run
+        if (more) load(z + 2, nxt);
+        const int sc = sm == 2 ? 0 : sm + 1, sp = sc == 2 ? 0 : sc + 1;
+        if (mine) {
+            const unsigned c = ((unsigned)z * (unsigned)g.ny + (unsigned)yi) * (unsigned)g.nx + (unsigned)xi;
+            const double t0 = (double)sh[sc][4][cell];
+            double h = 0.0;
+            if (!wall) {
+                // coefficients, once per step: grad rho, div v, A(rho), B(rho)
+                const double r = (double)sh[sc][0][cell];
+                double gr[3], dx_[3], dy_[3], dz_[3];
+                stencil3_ring<7>(sh[sm][0], sh[sc][0], sh[sp][0], cell, gr, nullptr);
+                stencil3_ring<1>(sh[sm][1], sh[sc][1], sh[sp][1], cell, dx_, nullptr);
+                stencil3_ring<2>(sh[sm][2], sh[sc][2], sh[sp][2], cell, dy_, nullptr);
+                stencil3_ring<4>(sh[sm][3], sh[sc][3], sh[sp][3], cell, dz_, nullptr);
+                const double div = dx_[0] + dy_[1] + dz_[2];
+                const double D1 = 1.0 - P.b * r, D2 = 1.0 + 2.0 * P.b * r - P.b * P.b * r * r;
+                const double inv = rcp_nr(r * D1 * D2);
+                const double chi_r = P.chi * D1 * D2 * inv;
+                const double Aw = P.R_cv * div * (r * D2 * inv), Bw = P.a_cv * r * div * (r * D1 * inv);
+                double a[3] = {(double)sh[sc][1][cell] - chi_r * gr[0], (double)sh[sc][2][cell] - chi_r * gr[1],
+                               (double)sh[sc][3][cell] - chi_r * gr[2]};
+                double c1 = Bw * P.k2_Tc - Aw;
+                double c2 = -Bw * P.k1k_rsTc;
+                gmem<S> *cf = (gmem<S> *)coef;
+                cf[0 * (size_t)g.n + c] = S(a[0]);
+                cf[1 * (size_t)g.n + c] = S(a[1]);
+                cf[2 * (size_t)g.n + c] = S(a[2]);
+                cf[3 * (size_t)g.n + c] = S(c1);
+                cf[4 * (size_t)g.n + c] = S(c2);
+                a[0] = (double)S(a[0]);
+                a[1] = (double)S(a[1]);
+                a[2] = (double)S(a[2]);
+                c1 = (double)S(c1);
+                c2 = (double)S(c2);
+                double gT[3], lap;
+                stencil3_ring<7>(sh[sm][4], sh[sc][4], sh[sp][4], cell, gT, &lap);
+                const double Tabs = P.T_ref + t0;
+                h = -(a[0] * gT[0] + a[1] * gT[1] + a[2] * gT[2]) + P.chi * lap + c1 * Tabs + c2 * sqrt_pos(Tabs);
+            }
+            ((gmem<S> *)acc)[c] = S(h);
+            ((gmem<S> *)Tout)[c] = S(t0 + 0.5 * h);
+        }
+        __syncthreads();  // every read of plane z - 1 is done
+        if (more) put(sm, nxt);
+        __syncthreads();
+        sm = sc;
     }
-    ((gmem<S> *)acc)[c] = S(h);
-    ((gmem<S> *)Tout)[c] = S(t0 + 0.5 * h);
 }
 
 // ---------------------------------------------------------------------------

@@ -17,7 +17,8 @@ struct lbb3_domain {
     void *rho = nullptr, *v = nullptr, *coef = nullptr, *Ts = nullptr, *acc = nullptr;
     double *psi = nullptr, *mpart = nullptr, *hpart = nullptr, *Tb_dev = nullptr;
     lbb3::Scalars3 *sc = nullptr;
-    int nb = 0;  // blocks of the per-node launches
+    int nb = 0;   // blocks of the per-node launches
+    int ncu = 0;  // compute units of the device
     int cf = 0, cT = 0;
     bool poisoned = false;
     hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
@@ -52,11 +53,21 @@ void enqueue_reductions3(lbb3_domain *d, int advance)
     hipLaunchKernelGGL(k3_reduce, dim3(1), dim3(NR3), 0, d->stream, d->g, d->mpart, d->hpart, d->nb, d->sc, advance);
 }
 
-// Tiles of the first RK4 stage.
-lbb3::Tiles3 stage0_tiles(const lbb3::Geom3 &g)
+// Column tiles and plane runs of the first RK4 stage.  The runs are sized
+// for about `target` blocks: in FP32 (a 30 KB ring, four blocks a CU) short
+// runs of about three planes, several rounds of blocks; in FP64 (a 60 KB
+// ring, two blocks a CU) one round of long runs.  Timed on the 150 x 151 x
+// 150 pool: FP32 337.6 us per step with runs of 3 planes against 338.6-340.2
+// with runs of 2 to 9, FP64 626.2 us with runs of 17 against 632-638 with
+// shorter ones.
+lbb3::Tiles3 stage0_tiles(const lbb3::Geom3 &g, int target)
 {
     using namespace lbb3;
-    return Tiles3{(g.nx + TX3 - 1) / TX3, (g.ny + TY3 - 1) / TY3, (g.nz + TZ3 - 1) / TZ3};
+    Tiles3 t{(g.nx + TXZ - 1) / TXZ, (g.ny + TYZ - 1) / TYZ, 1, g.nz};
+    const int runs = std::max(1, std::min(g.nz, target / (t.ntx * t.nty)));
+    t.zc = (g.nz + runs - 1) / runs;
+    t.ntz = (g.nz + t.zc - 1) / t.zc;
+    return t;
 }
 
 // One time step: reductions of state t, LB update, RK4 temperature step.
@@ -77,8 +88,8 @@ void enqueue_step3(lbb3_domain *d)
         S *Ts0 = static_cast<S *>(d->Ts), *Ts1 = Ts0 + n;
         S *acc = static_cast<S *>(d->acc), *coef = static_cast<S *>(d->coef);
         const S *rho = static_cast<const S *>(d->rho);
-        const Tiles3 tl = stage0_tiles(d->g);
-        hipLaunchKernelGGL(k3_stage0<S>, dim3(tl.ntx * tl.nty * tl.ntz), dim3(NS3), 0, d->stream, d->dp, d->g, tl, T0,
+        const Tiles3 tl = stage0_tiles(d->g, (sizeof(S) == 4 ? 16 : 2) * d->ncu);
+        hipLaunchKernelGGL(k3_stage0<S>, dim3(tl.ntx * tl.nty * tl.ntz), dim3(NSZ), 0, d->stream, d->dp, d->g, tl, T0,
                            Ts0, acc, coef, rho, v, v + n, v + 2 * n);
         hipLaunchKernelGGL((k3_stage<S, 1>), dim3(d->nb), dim3(NT3), 0, d->stream, d->dp, d->g, T0, Ts0, Ts1, acc,
                            coef, d->sc);
@@ -257,6 +268,7 @@ int lbb3_init_domain(const lbb_params *pin, int32_t nz, const double *T_bottom, 
     make_dev_params(p, Tc, kap, d->dp);
     d->g = lbb3::Geom3{p.nx, p.ny, nz, (unsigned)n};
     d->nb = nb;
+    d->ncu = std::max(1, prop.multiProcessorCount);
     bool ok = hipStreamCreateWithFlags(&d->stream, hipStreamNonBlocking) == hipSuccess;
     auto alloc = [&](void **ptr, size_t bytes) -> bool {
         if (!ok || hipMalloc(ptr, bytes) != hipSuccess) return false;

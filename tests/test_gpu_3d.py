@@ -191,11 +191,25 @@ def test_chunked_stepping_bitwise_and_builtin_initial_state():
 
 @pytest.mark.parametrize("precision", [L.FP64, L.FP32])
 def test_larger_ragged_lattice(precision):
-    """62x60x51: ragged first-stage tiles in x, y and z (30x4x4 interiors),
-    about 740 per-node blocks, walls."""
+    """62x60x51: ragged first-stage column tiles in x and y (30x14
+    interiors; runs of one plane in FP32, of 2 in FP64 with a last run of
+    one), about 740 per-node blocks, walls."""
     _say("3d ragged 62x60x51", precision)
     o, tw, d = _pair(62, 60, 51, precision=precision, seed=9)
     for s in (o, tw, d):
         s.step(12)
+    errs, bad = _compare(o, tw, d, precision)
+    assert not bad, bad
+
+
+@pytest.mark.parametrize("precision", [L.FP64, L.FP32])
+def test_first_stage_plane_runs(precision):
+    """301x155x41: the first RK4 stage marches its 30x14 column tiles along z
+    in runs of several planes (11 x 12 tiles; runs of 2 planes in FP32, 14 in
+    FP64, the last one shorter), ragged in x, y and z, walls, 2 steps."""
+    _say("3d plane runs 301x155x41", precision)
+    o, tw, d = _pair(301, 155, 41, precision=precision, seed=11)
+    for s in (o, tw, d):
+        s.step(2)
     errs, bad = _compare(o, tw, d, precision)
     assert not bad, bad
