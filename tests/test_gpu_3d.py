@@ -213,3 +213,26 @@ def test_first_stage_plane_runs(precision):
         s.step(2)
     errs, bad = _compare(o, tw, d, precision)
     assert not bad, bad
+
+
+def test_benchmarked_pool_full_size_fp32():
+    """The benchmarked 3-D pool at its full size and launch shapes: 150x151x150
+    nodes, FP32 storage, a = 3/49, liquid below 0.6 ny, heater 0.10 T_c over
+    the whole bottom wall, G_w = 0.065, g = 3e-5; 2 steps against the oracle
+    and its FP32 twin (every node and field compared)."""
+    _say("3d benchmarked pool 150x151x150 fp32, 2 steps")
+    a = 3.0 / 49.0
+    nx, ny, nz = 150, 151, 150
+    tc = O.Tc(a, B, 1.0)
+    rv, rl, _ = O.maxwell(a, B, 1.0, 0.344, 0.86 * tc)
+    liquid = int(0.6 * ny)
+    rho0 = WL.layered_density3(nx, ny, nz, rl, rv, liquid, 1e-3, 7)
+    Tb = np.full((nz, nx), 0.96 * tc)
+    common = dict(nx=nx, ny=ny, a=a, b=B, rho_L=rl, rho_V=rv, g=3e-5, Gw_bottom=0.065)
+    o = O.State3(O.Params(**common), nz, rho0, T_bottom=Tb)
+    tw = O.State3(O.Params(**common), nz, rho0, T_bottom=Tb).store_bits(TWIN[L.FP32])
+    d = L.Domain3(L.Params(precision=L.FP32, liquid_rows=liquid, seed=7, **common), nz, T_bottom=Tb, rho0=rho0)
+    for s in (o, tw, d):
+        s.step(2)
+    errs, bad = _compare(o, tw, d, L.FP32)
+    assert not bad, bad
