@@ -68,7 +68,8 @@ struct AdjInst {
     DevParams P;
     AdjW w;
     const void *seg;          // stored states of the segment: slot k at 10 k nx ny elements
-    double *lf[2], *lT[2];    // adjoints of f and T: [cur] the later state, [cur ^ 1] the earlier
+    void *lf[2];              // adjoint of f in the storage precision: [cur] the later state, [cur ^ 1] the earlier
+    double *lT[2];            // adjoint of T (FP64), same parity
     double *gr[2];            // density adjoint of interior nodes not yet added to lf (same parity)
     int gx;                   // patches per lattice row
     int blk0;                 // first block of this lattice in the grid
@@ -592,9 +593,9 @@ __global__ __launch_bounds__(NTA) void a_lb(A_ARGS, int k, int cur)
     A_INST
     A_NODE
     const gmem<S> *__restrict__ f = a_slot<S>(I, k);
-    const gmem<double> *__restrict__ lf1 = gp(I.lf[cur]);
+    const gmem<S> *__restrict__ lf1 = gp(static_cast<const S *>(I.lf[cur]));
     const gmem<double> *__restrict__ gr1 = gp(I.gr[cur]);
-    gmem<double> *__restrict__ lf0 = gp(I.lf[cur ^ 1]);
+    gmem<S> *__restrict__ lf0 = gp(static_cast<S *>(I.lf[cur ^ 1]));
     double pr = 0.0, pg = 0.0;
     if (on) {
         const bool in = a_int(P, gj);
@@ -628,7 +629,7 @@ __global__ __launch_bounds__(NTA) void a_lb(A_ARGS, int k, int cur)
             // interior nodes keep their density adjoint apart (added here);
             // wall nodes hold the complete adjoint (Zou-He transposed)
             const size_t ct = ok ? a_at(P, gi, gj, kEX[a], kEY[a]) : c;
-            const double v = lf1[(size_t)a * N + ct] + (a_int(P, jj) ? gr1[ct] : 0.0);
+            const double v = (double)lf1[(size_t)a * N + ct] + (a_int(P, jj) ? gr1[ct] : 0.0);
             gfs[a] = ok ? v : 0.0;
         }
         double fl[9];
@@ -706,7 +707,7 @@ __global__ __launch_bounds__(NTA) void a_lb(A_ARGS, int k, int cur)
         gFx += 0.5 * gvx * ir;
         gFy += 0.5 * gvy * ir;
         gr += -(gvx * vx + gvy * vy) * ir;
-        for (int a = 0; a < 9; ++a) lf0[(size_t)a * N + c] = gf[a] + kEX[a] * gjx + kEY[a] * gjy;
+        for (int a = 0; a < 9; ++a) lf0[(size_t)a * N + c] = S(gf[a] + kEX[a] * gjx + kEY[a] * gjy);
         // per-node force parts (no force on the wall rows)
         double gpsi = 0.0, gsx = 0.0, gsy = 0.0;
         if (in) {
@@ -779,7 +780,7 @@ __global__ __launch_bounds__(NTA) void a_final(A_ARGS, int k, int cur, double wq
     const gmem<S> *__restrict__ T = f + 9 * N;
     const gmem<S> *__restrict__ fp = prev ? a_slot<S>(I, k - 1) : nullptr;
     const gmem<S> *__restrict__ Tp = prev ? fp + 9 * N : nullptr;
-    gmem<double> *__restrict__ lf0 = gp(I.lf[cur ^ 1]);
+    gmem<S> *__restrict__ lf0 = gp(static_cast<S *>(I.lf[cur ^ 1]));
     gmem<double> *__restrict__ lT0 = gp(I.lT[cur ^ 1]);
     double m = 0.0;
     if (on) {
@@ -809,11 +810,11 @@ __global__ __launch_bounds__(NTA) void a_final(A_ARGS, int k, int cur, double wq
             gp(I.gr[cur ^ 1])[c] = gr;
         } else {
             double g[9];
-            for (int a = 0; a < 9; ++a) g[a] = lf0[(size_t)a * N + c] + gr;
+            for (int a = 0; a < 9; ++a) g[a] = (double)lf0[(size_t)a * N + c] + gr;
             zou_he_T(g, gj == 0);
             if (wq != 0.0 && gj == 0)
                 for (int a = 0; a < 9; ++a) g[a] += gpop[a];
-            for (int a = 0; a < 9; ++a) lf0[(size_t)a * N + c] = g[a];
+            for (int a = 0; a < 9; ++a) lf0[(size_t)a * N + c] = S(g[a]);
         }
         lT0[c] += gT + gtem;
         // this thread's reads of the state-t values at c are done
@@ -849,8 +850,10 @@ __global__ __launch_bounds__(NTA) void a_hf(A_ARGS, int k, double wq, int cur)
     const gmem<S> *f = a_slot<S>(I, k);
     double gpop[9], gtem;
     hf_source<S>(P, f, f + 9 * N, wq, N, gi, gj, gpop, gtem);
-    if (gj == 0)
-        for (int a = 0; a < 9; ++a) gp(I.lf[cur])[(size_t)a * N + c] += gpop[a];
+    if (gj == 0) {
+        gmem<S> *lf = gp(static_cast<S *>(I.lf[cur]));
+        for (int a = 0; a < 9; ++a) lf[(size_t)a * N + c] = S((double)lf[(size_t)a * N + c] + gpop[a]);
+    }
     gp(I.lT[cur])[c] += gtem;
 }
 

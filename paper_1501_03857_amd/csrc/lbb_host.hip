@@ -1645,7 +1645,8 @@ struct AdjGroup {
 struct AdjMember {
     unsigned char *backup, *ck, *seg[2];
     lbb::Scalars *ck_sc;
-    double *hf_backup, *lf[2], *lT[2], *gr[2];
+    double *hf_backup, *lT[2], *gr[2];
+    void *lf[2];  // population adjoints, storage precision
     lbb::AdjW w;
     int gx, nb, tgx, tnb;
     size_t n, state_bytes;
@@ -1750,7 +1751,7 @@ int adjoint_run(AdjGroup &g, int64_t N, int64_t K, double *J, double *dJ_dTb, do
             a.ck_sc = cv.take<Scalars>((size_t)nck + 1);
             a.hf_backup = cv.take<double>(g.doms[i]->nbxB);
             for (int k = 0; k < 2; ++k) {
-                a.lf[k] = cv.take<double>(9 * n);
+                a.lf[k] = cv.take<S>(9 * n);
                 a.lT[k] = cv.take<double>(n);
                 a.gr[k] = cv.take<double>(n);
             }
@@ -1909,7 +1910,7 @@ int adjoint_run(AdjGroup &g, int64_t N, int64_t K, double *J, double *dJ_dTb, do
     // reverse sweep: the adjoint of the final state starts from its heat-flux sample
     const double wq = 1.0 / (double)N;
     for (int i = 0; i < nm; ++i) {
-        LBB_HIP(hipMemsetAsync(m[i].lf[0], 0, 9 * m[i].n * sizeof(double), st));
+        LBB_HIP(hipMemsetAsync(m[i].lf[0], 0, 9 * m[i].n * es, st));
         LBB_HIP(hipMemsetAsync(m[i].lT[0], 0, m[i].n * sizeof(double), st));
         LBB_HIP(hipMemsetAsync(m[i].gr[0], 0, m[i].n * sizeof(double), st));
         LBB_HIP(hipMemsetAsync(m[i].w.scal, 0, 4 * sizeof(double), st));
