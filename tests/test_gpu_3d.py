@@ -7,6 +7,9 @@ and q against the oracle's rounding twin (State3.store_bits: 52 bits of f,
 psi and T in FP64, FP32 populations in FP32), four times its own error or
 the tolerance, whichever is larger.  Sizes span several 256-node blocks with
 ragged tails, walls and fully periodic boxes, every test mode."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -236,3 +239,46 @@ def test_benchmarked_pool_full_size_fp32():
         s.step(2)
     errs, bad = _compare(o, tw, d, L.FP32)
     assert not bad, bad
+
+
+@pytest.mark.parametrize("precision", [L.FP64, L.FP32])
+def test_long_run_heat_flux_matches_stored_oracle_run(precision):
+    """A 40x51x20 pool with vapour on the heater (a = 3/49, T_s = 0.86 T_c,
+    heater 0.14 T_c above T_s, G_w = 0.065, g = 3e-5), 16000 steps, against
+    the oracle's FP64 run of the same pool stored by
+    tests/golden/make_oracle_pool3d_long_run.py: the time average of q over
+    steps 8001-16000 within 2% (the long-run bar), q every 2000 steps within
+    a factor 1.5, the mass to 1e-5 and the vapour fraction at the heater to
+    0.05."""
+    _say("3d long run 40x51x20, 16000 steps vs stored oracle run", precision)
+    with open(os.path.join(os.path.dirname(__file__), "golden", "oracle_pool3d_40x51x20.json")) as fh:
+        ref = json.load(fh)
+    nx, ny, nz = ref["nx"], ref["ny"], ref["nz"]
+    a, theta = ref["a"], ref["Ts_over_Tc"]
+    tc = O.Tc(a, B, 1.0)
+    rv, rl, _ = O.maxwell(a, B, 1.0, 0.344, theta * tc)
+    liquid = int(0.6 * ny)
+    rho0 = WL.layered_density3(nx, ny, nz, rl, rv, liquid, 1e-3, ref["seed"])
+    p = L.Params(nx=nx, ny=ny, precision=precision, liquid_rows=liquid, a=a, b=B, Ts_over_Tc=theta, rho_L=rl,
+                 rho_V=rv, g=ref["g"], Gw_bottom=ref["Gw_bottom"], seed=ref["seed"])
+    d = L.Domain3(p, nz, T_bottom=np.full((nz, nx), (theta + ref["dT_over_Tc"]) * tc), rho0=rho0)
+    trace = []
+    for k in range(ref["steps"] // 2000):
+        if k * 2000 == ref["steps"] // 2:
+            d.reset_average()
+        d.step(2000)
+        trace.append(d.heat_flux()["q_now"])
+    hf = d.heat_flux()
+    rho = d.fields()["rho"]
+    d.close()
+    assert hf["n_samples"] == ref["n_samples"] == ref["steps"] // 2
+    rel = abs(hf["q_mean"] / ref["q_mean"] - 1.0)
+    vap = float(np.mean(rho[:, 1:3, :] < 0.5 * (rl + rv)))
+    _say(f"q_mean gpu {hf['q_mean']:.6e} oracle {ref['q_mean']:.6e} rel {rel:.2e}; vapour at heater gpu {vap:.3f} "
+         f"oracle {ref['vapour_at_heater']:.3f}")
+    assert rel < 0.02
+    q_ref = np.array([q for _, q in ref["q_trace"]])
+    assert np.all(np.array(trace) > 0) and np.all(q_ref > 0)
+    assert np.all(np.abs(np.log(np.array(trace) / q_ref)) < np.log(1.5))
+    assert abs(float(np.sum(rho)) / ref["mass_final"] - 1.0) < 1e-5
+    assert abs(vap - ref["vapour_at_heater"]) < 0.05
