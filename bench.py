@@ -77,7 +77,7 @@ MEASURED_TRAFFIC = {
 # FP32 storage; KiB per dispatch), valid for the 3-D kernel source whose hash
 # is recorded.
 MEASURED_TRAFFIC_3D = {
-    "source_hash": "b58727298629e549",
+    "source_hash": "c97ad07e51234cee",
     "pool3d_150x151x150_fp32": {
         "k3_psi": (132765.1, 40023.5), "k3_reduce": (108.5, 0.1), "k3_lb": (146640.1, 294904.3),
         "k3_stage0": (37460.4, 93766.5), "k3_stage1": (53429.2, 26544.7), "k3_stage2": (53429.4, 26543.0),

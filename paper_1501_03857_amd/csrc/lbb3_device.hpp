@@ -15,7 +15,8 @@
 //   Ts[2], acc            RK4 stage values and slope sum
 // Walls at y = 0 and y = ny-1 (gravity along -y), periodic x and z.
 //
-// One step t -> t+1 is seven launches, each one node per thread:
+// One step t -> t+1 is seven launches, one node per thread except the first
+// RK4 stage:
 //   k3_psi      rho (Eq. (6)) and psi (FP64 Peng-Robinson EOS, Eq. (21)) of
 //               state t; per-block FP64 partials of the mass and, on the
 //               bottom wall, of the heat flux of state t (Sec. 3.2)
@@ -23,8 +24,9 @@
 //   k3_lb       forces (Eqs. (7), (9), (22)), velocity, MRT collision with
 //               the improved forcing (Eqs. (2), (4), (5), (8)) and push
 //               streaming (Eq. (3))
-//   k3_stage0   the first RK4 stage (Eqs. (19)-(20)) of Eq. (18) on LDS
-//               tiles; it also forms the per-node coefficients
+//   k3_stage0   the first RK4 stage (Eqs. (19)-(20)) of Eq. (18), one
+//               thread a column of nodes marching along z with a ring of
+//               planes in LDS; it also forms the per-node coefficients
 //   k3_stage x3 the other three stages; the last writes T
 // All reductions run in a fixed order, so results are reproducible bitwise.
 #pragma once
