@@ -240,8 +240,9 @@ int lbb_batch_destroy(lbb_batch *b);
  * dJ_dTb[k] = dJ/dT_b(heater_idx[k]) for k < n_heater (heater_idx NULL: all
  * nx nodes in order, n_heater must be nx), and the bottom wall strength G_w
  * (Eq. (22)), by a hand-written discrete adjoint of the whole coupled step
- * (FP64 arithmetic; the population adjoints are stored in the domain's
- * precision, every other adjoint field in FP64).  J is required; dJ_dTb and dJ_dGw
+ * (FP64 arithmetic; the population adjoints and the per-node work arrays
+ * are stored in the domain's precision, the adjoint of T and the sums in
+ * FP64).  J is required; dJ_dTb and dJ_dGw
  * may be NULL.  EINVAL for a heater index outside [0, nx).  States are checkpointed
  * every K steps and each segment but the last is recomputed before its
  * reverse sweep.  K <= 0 lets the library choose: every state kept (K = N,
@@ -249,8 +250,8 @@ int lbb_batch_destroy(lbb_batch *b);
  * memory, else K = ceil(sqrt(N)).  The domain's state, step count and
  * heat-flux average are restored afterwards.  Device memory, allocated on
  * the first call and kept by the domain (reported by lbb_info): about
- * (N/K + K + 2) * 10 * nx*ny * sizeof(real) + 18 * nx*ny * sizeof(real) +
- * 37 * nx*ny * 8 bytes.
+ * (N/K + K + 2) * 10 * nx*ny * sizeof(real) + 38 * nx*ny * sizeof(real) +
+ * 4 * nx*ny * 8 bytes.
  * EUNSUPPORTED for periodic_y or a test mode; EINVAL for N < 1; ENOMEM when
  * the workspace cannot be allocated. */
 int lbb_adjoint(lbb_domain *d, int64_t N, int64_t K, const int32_t *heater_idx, int32_t n_heater, double *J,

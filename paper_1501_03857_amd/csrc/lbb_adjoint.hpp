@@ -36,22 +36,27 @@ namespace lbb {
 constexpr int NTA = 256;          // threads per adjoint block
 constexpr int AXB = 64, AYB = 4;  // node patch of one block
 
-// Work arrays of one lattice.  The host fills AdjW (= AdjWT<double>); the
-// kernels read the same pointers as AdjWT<gmem<double>>, so every access is
-// a global (not flat) memory instruction.
-template <typename D>
+// Work arrays of one lattice.  The per-node arrays are in the lattice's
+// storage precision S (the forward values they hold are formed in FP64 from
+// the stored state and rounded once; the adjoint parts are rounded once per
+// reverse step), the partial sums and accumulators in FP64.  The host fills
+// AdjW, whose per-node pointers are untyped; the kernels read the same
+// pointers as AdjWG<S>, so every access is a global (not flat) memory
+// instruction.
+template <typename D, typename R>
 struct AdjWT {
     // rho, j, psi and T of the state being reversed; a_final replaces them
     // by those of the state before it
     D *rho, *jx, *jy, *psi, *T1;
     D *sx, *sy, *Fx, *Fy, *vx, *vy;
     D *gDrx, *gDry, *gdiv, *grho, *gvx, *gvy, *gpsi, *gsx, *gsy;
-    D *mpart;   // block mass partials of the state being reversed
-    D *fpart;   // block partials of the force adjoint: [2b] rho_ave, [2b+1] G_w
-    D *scal;    // [2] dJ/dG_w, accumulated over the steps
+    R *mpart;   // block mass partials of the state being reversed
+    R *fpart;   // block partials of the force adjoint: [2b] rho_ave, [2b+1] G_w
+    R *scal;    // [2] dJ/dG_w, accumulated over the steps
 };
-using AdjW = AdjWT<double>;
-using AdjWG = AdjWT<gmem<double>>;
+using AdjW = AdjWT<void, double>;
+template <typename S>
+using AdjWG = AdjWT<gmem<S>, gmem<double>>;
 
 // a device array as a global-address-space pointer
 template <typename T>
@@ -80,7 +85,7 @@ struct AdjInst {
 #define A_INST                                            \
     const AdjInst &I = ai[amap[blockIdx.x]];              \
     const DevParams &P = I.P;                             \
-    const AdjWG &w = reinterpret_cast<const AdjWG &>(I.w); \
+    const AdjWG<S> &w = reinterpret_cast<const AdjWG<S> &>(I.w); \
     const int q = (int)blockIdx.x - I.blk0;               \
     (void)w;
 
@@ -194,7 +199,7 @@ __device__ __forceinline__ void zou_he_T(double g[9], int bottom)
 template <typename S>
 __device__ __forceinline__ double a_macro_node(const DevParams &P, const gmem<S> *__restrict__ f,
                                                const gmem<S> *__restrict__ T, size_t N, size_t c, int gj,
-                                               const AdjWG &w)
+                                               const AdjWG<S> &w)
 {
     double fl[9];
     load_node(P, f, N, c, gj, fl);
@@ -229,7 +234,8 @@ struct NodeForce {
 };
 
 // isotropic gradient of rho at interior node (gi, gj)
-__device__ __forceinline__ void grad_rho(const DevParams &P, const AdjWG &w, int gi, int gj, double &rx, double &ry)
+template <typename WG>
+__device__ __forceinline__ void grad_rho(const DevParams &P, const WG &w, int gi, int gj, double &rx, double &ry)
 {
     rx = ry = 0.0;
 #pragma unroll
@@ -240,7 +246,8 @@ __device__ __forceinline__ void grad_rho(const DevParams &P, const AdjWG &w, int
     }
 }
 
-__device__ __forceinline__ NodeForce force_node(const DevParams &P, const AdjWG &w, int gi, int gj, size_t c,
+template <typename WG>
+__device__ __forceinline__ NodeForce force_node(const DevParams &P, const WG &w, int gi, int gj, size_t c,
                                                 double rho_ave)
 {
     NodeForce o;
@@ -332,7 +339,7 @@ __device__ __forceinline__ void pw_derivs(const DevParams &P, double r, double &
 constexpr int TAH = 7;
 constexpr int TAX = 64 - 2 * TAH;
 
-template <int TAY, int TAW>
+template <typename S, int TAY, int TAW>
 __global__ __launch_bounds__(64 * TAW) void a_theradj(const AdjInst *__restrict__ ai, const int *__restrict__ tmap,
                                                       int cur)
 {
@@ -345,7 +352,7 @@ __global__ __launch_bounds__(64 * TAW) void a_theradj(const AdjInst *__restrict_
     __shared__ double s_rho_ave;
     const AdjInst &I = ai[tmap[blockIdx.x]];
     const DevParams P = I.P;
-    const AdjWG &w = reinterpret_cast<const AdjWG &>(I.w);
+    const AdjWG<S> &w = reinterpret_cast<const AdjWG<S> &>(I.w);
     const int q = (int)blockIdx.x - I.tblk0;
     const int x0 = (q % I.tgx) * TAX, y0 = (q / I.tgx) * TAY;
     static_assert(RPW * TAW >= H, "every region row has a wave");

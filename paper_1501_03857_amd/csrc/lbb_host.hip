@@ -1756,9 +1756,9 @@ int adjoint_run(AdjGroup &g, int64_t N, int64_t K, double *J, double *dJ_dTb, do
                 a.gr[k] = cv.take<double>(n);
             }
             AdjW &w = a.w;
-            double **arr[] = {&w.rho, &w.jx, &w.jy, &w.psi, &w.T1, &w.sx, &w.sy, &w.Fx, &w.Fy, &w.vx,
-                              &w.vy, &w.gDrx, &w.gDry, &w.gdiv, &w.grho, &w.gvx, &w.gvy, &w.gpsi, &w.gsx, &w.gsy};
-            for (double **p : arr) *p = cv.take<double>(n);
+            void **arr[] = {&w.rho, &w.jx, &w.jy, &w.psi, &w.T1, &w.sx, &w.sy, &w.Fx, &w.Fy, &w.vx,
+                            &w.vy, &w.gDrx, &w.gDry, &w.gdiv, &w.grho, &w.gvx, &w.gvy, &w.gpsi, &w.gsx, &w.gsy};
+            for (void **p : arr) *p = cv.take<S>(n);
             w.mpart = cv.take<double>(a.nb);
             w.fpart = cv.take<double>(2 * (size_t)a.nb);
             w.scal = cv.take<double>(4);
@@ -1945,9 +1945,9 @@ int adjoint_run(AdjGroup &g, int64_t N, int64_t K, double *J, double *dJ_dTb, do
         hipLaunchKernelGGL(a_macro<S>, grid, blk, 0, st, ai, d_amap, (int)(t1 - 1 - t0));
         for (int64_t t = t1 - 1; t >= t0; --t) {
             const int k = (int)(t - t0);
-            if (tay == 24) hipLaunchKernelGGL((a_theradj<24, 16>), dim3(ttot), dim3(64 * 16), 0, st, ai, d_tmap, cur);
-            else if (tay == 16) hipLaunchKernelGGL((a_theradj<16, 16>), dim3(ttot), dim3(64 * 16), 0, st, ai, d_tmap, cur);
-            else hipLaunchKernelGGL((a_theradj<4, 16>), dim3(ttot), dim3(64 * 16), 0, st, ai, d_tmap, cur);
+            if (tay == 24) hipLaunchKernelGGL((a_theradj<S, 24, 16>), dim3(ttot), dim3(64 * 16), 0, st, ai, d_tmap, cur);
+            else if (tay == 16) hipLaunchKernelGGL((a_theradj<S, 16, 16>), dim3(ttot), dim3(64 * 16), 0, st, ai, d_tmap, cur);
+            else hipLaunchKernelGGL((a_theradj<S, 4, 16>), dim3(ttot), dim3(64 * 16), 0, st, ai, d_tmap, cur);
             hipLaunchKernelGGL(a_lb<S>, grid, blk, 0, st, ai, d_amap, k, cur);
             hipLaunchKernelGGL(a_final<S>, grid, blk, 0, st, ai, d_amap, k, cur, t >= 1 ? wq : 0.0,
                                t > t0 ? 1 : 0);
