@@ -240,9 +240,9 @@ int lbb_batch_destroy(lbb_batch *b);
  * dJ_dTb[k] = dJ/dT_b(heater_idx[k]) for k < n_heater (heater_idx NULL: all
  * nx nodes in order, n_heater must be nx), and the bottom wall strength G_w
  * (Eq. (22)), by a hand-written discrete adjoint of the whole coupled step
- * (FP64 arithmetic; the population adjoints and the per-node work arrays
- * are stored in the domain's precision, the adjoint of T and the sums in
- * FP64).  J is required; dJ_dTb and dJ_dGw
+ * (FP64 arithmetic; the population adjoints, the per-node work arrays and
+ * the temperature adjoint's LDS planes are stored in the domain's precision,
+ * the adjoint of T and the sums in FP64).  J is required; dJ_dTb and dJ_dGw
  * may be NULL.  EINVAL for a heater index outside [0, nx).  States are checkpointed
  * every K steps and each segment but the last is recomputed before its
  * reverse sweep.  K <= 0 lets the library choose: every state kept (K = N,

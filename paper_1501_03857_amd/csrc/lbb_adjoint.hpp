@@ -287,7 +287,8 @@ struct DivCoef {
 // From the velocity planes VX, VY of the tile region (region row r, lane l,
 // both at least one node from the region's edge) and the node's own v_x, v_y,
 // d_x rho, d_y rho and rho.
-__device__ __forceinline__ DivCoef div_coef(const DevParams &P, const double (*VX)[64], const double (*VY)[64],
+template <typename PT>
+__device__ __forceinline__ DivCoef div_coef(const DevParams &P, const PT (*VX)[64], const PT (*VY)[64],
                                             int r, int l, int gj, double vx, double vy, double rx, double ry,
                                             double rho)
 {
@@ -346,9 +347,13 @@ __global__ __launch_bounds__(64 * TAW) void a_theradj(const AdjInst *__restrict_
     constexpr int H = TAY + 2 * TAH;          // region rows
     constexpr int RPW = (H + TAW - 1) / TAW;  // region rows per wave
     // planes 0..3: T_1..T_4; 4: lT^{t+1}; 5: g_2.  g_1 reuses plane 3 once
-    // T_4 is dead, g_0 plane 2 once T_3 is.
-    __shared__ double sb[6][H][64];
-    __shared__ double sAX[H][64], sAY[H][64];
+    // T_4 is dead, g_0 plane 2 once T_3 is.  The planes hold the storage
+    // precision (the forward stages of an FP32 lattice run in FP32 too); the
+    // arithmetic is FP64.  In FP32 they take half the LDS, which leaves room
+    // for taller tiles.
+    using LT = S;
+    __shared__ LT sb[6][H][64];
+    __shared__ LT sAX[H][64], sAY[H][64];
     __shared__ double s_rho_ave;
     const AdjInst &I = ai[tmap[blockIdx.x]];
     const DevParams P = I.P;
@@ -465,7 +470,7 @@ __global__ __launch_bounds__(64 * TAW) void a_theradj(const AdjInst *__restrict_
             if (r < s || r >= H - s) continue;
             // the gradient and Laplacian stencils from column sums shifted
             // between lanes, as in the forward thermal step
-            const double(*F)[64] = sb[s - 1];
+            const LT(*F)[64] = sb[s - 1];
             const double tc = F[r][lane], tN = F[r + 1][lane], tS = F[r - 1][lane];
             const double cv = (tN + tS) + 4.0 * tc, cw = tN - tS;
             const double vW = lane_from_left(cv), vE = lane_from_right(cv);
@@ -511,7 +516,7 @@ __global__ __launch_bounds__(64 * TAW) void a_theradj(const AdjInst *__restrict_
             const int r = wv + TAW * m;
             gnext[m] = 0.0;
             if (r < R || r >= H - R || lane < R || lane >= 64 - R || !inl[m]) continue;
-            const double(*G)[64] = sb[gp];
+            const LT(*G)[64] = sb[gp];
             const int l = lane;
             double gT = 0.0;
 #pragma unroll
@@ -523,7 +528,7 @@ __global__ __launch_bounds__(64 * TAW) void a_theradj(const AdjInst *__restrict_
             }
             if (inr[m]) {
                 const double g = gs * G[r][l];
-                const double(*F)[64] = sb[k];
+                const LT(*F)[64] = sb[k];
                 const double Tv = F[r][l];
                 double d1, d2;
                 phi_derivs(P, Tv, d1, d2);

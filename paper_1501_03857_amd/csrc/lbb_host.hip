@@ -1732,6 +1732,14 @@ int adjoint_run(AdjGroup &g, int64_t N, int64_t K, double *J, double *dJ_dTb, do
         for (int i = 0; i < nm; ++i)
             t24 += ((g.doms[i]->p.nx + TAX - 1) / TAX) * ((g.doms[i]->p.ny + 23) / 24);
         if (t24 >= 4 * 256) tay = 24;
+        // FP32 planes take half the LDS: 32-row tiles where there are at
+        // least three per CU
+        if (sizeof(S) == 4) {
+            int t32 = 0;
+            for (int i = 0; i < nm; ++i)
+                t32 += ((g.doms[i]->p.nx + TAX - 1) / TAX) * ((g.doms[i]->p.ny + 31) / 32);
+            if (t32 >= 3 * 256) tay = 32;
+        }
     }
     for (int i = 0; i < nm; ++i) {
         const lbb_domain *d = g.doms[i];
@@ -1945,7 +1953,10 @@ int adjoint_run(AdjGroup &g, int64_t N, int64_t K, double *J, double *dJ_dTb, do
         hipLaunchKernelGGL(a_macro<S>, grid, blk, 0, st, ai, d_amap, (int)(t1 - 1 - t0));
         for (int64_t t = t1 - 1; t >= t0; --t) {
             const int k = (int)(t - t0);
-            if (tay == 24) hipLaunchKernelGGL((a_theradj<S, 24, 16>), dim3(ttot), dim3(64 * 16), 0, st, ai, d_tmap, cur);
+            if (tay == 32) {
+                if constexpr (sizeof(S) == 4)
+                    hipLaunchKernelGGL((a_theradj<S, 32, 16>), dim3(ttot), dim3(64 * 16), 0, st, ai, d_tmap, cur);
+            } else if (tay == 24) hipLaunchKernelGGL((a_theradj<S, 24, 16>), dim3(ttot), dim3(64 * 16), 0, st, ai, d_tmap, cur);
             else if (tay == 16) hipLaunchKernelGGL((a_theradj<S, 16, 16>), dim3(ttot), dim3(64 * 16), 0, st, ai, d_tmap, cur);
             else hipLaunchKernelGGL((a_theradj<S, 4, 16>), dim3(ttot), dim3(64 * 16), 0, st, ai, d_tmap, cur);
             hipLaunchKernelGGL(a_lb<S>, grid, blk, 0, st, ai, d_amap, k, cur);
