@@ -297,7 +297,7 @@ __device__ __forceinline__ DivCoef div_coef(const DevParams &P, const PT (*VX)[6
     for (int a = 1; a < 9; ++a) {
         // the velocity the temperature equation sees is zero on the wall rows
         const double m = a_int(P, gj + kEY[a]) ? 3.0 * kW[a] : 0.0;
-        dv += m * (kEX[a] * VX[r + kEY[a]][l + kEX[a]] + kEY[a] * VY[r + kEY[a]][l + kEX[a]]);
+        dv += m * (kEX[a] * (double)VX[r + kEY[a]][l + kEX[a]] + kEY[a] * (double)VY[r + kEY[a]][l + kEX[a]]);
     }
     const double D1 = 1.0 - P.b * rho, D2 = 1.0 + 2.0 * P.b * rho - P.b * P.b * rho * rho;
     const double inv = rcp_nr(rho * D1 * D2);
@@ -524,7 +524,8 @@ __global__ __launch_bounds__(64 * TAW) void a_theradj(const AdjInst *__restrict_
                 const int rp = r - kEY[a], lp = l - kEX[a];
                 const int gyp = gyr[m] - kEY[a];
                 const double mk = (gyp > 0 && gyp < P.ny - 1) ? gs : 0.0;
-                gT += mk * G[rp][lp] * (3.0 * kW[a] * (sAX[rp][lp] * kEX[a] + sAY[rp][lp] * kEY[a]) + 6.0 * kW[a] * chi);
+                gT += mk * (double)G[rp][lp] *
+                      (3.0 * kW[a] * ((double)sAX[rp][lp] * kEX[a] + (double)sAY[rp][lp] * kEY[a]) + 6.0 * kW[a] * chi);
             }
             if (inr[m]) {
                 const double g = gs * G[r][l];
@@ -537,10 +538,11 @@ __global__ __launch_bounds__(64 * TAW) void a_theradj(const AdjInst *__restrict_
                 const bool tile_row = r >= TAH && r < TAH + TAY;
                 if (tile_row && tile_col) {
                     // this stage's part of the rho, grad rho, v, div v adjoints at the node
-                    const double dTx = (F[r][l + 1] - F[r][l - 1]) * (1.0 / 3.0) +
-                                       (F[r + 1][l + 1] - F[r + 1][l - 1] + F[r - 1][l + 1] - F[r - 1][l - 1]) * (1.0 / 12.0);
-                    const double dTy = (F[r + 1][l] - F[r - 1][l]) * (1.0 / 3.0) +
-                                       (F[r + 1][l + 1] + F[r + 1][l - 1] - F[r - 1][l + 1] - F[r - 1][l - 1]) * (1.0 / 12.0);
+                    const double tE = F[r][l + 1], tW = F[r][l - 1], tN = F[r + 1][l], tS = F[r - 1][l];
+                    const double tNE = F[r + 1][l + 1], tNW = F[r + 1][l - 1];
+                    const double tSE = F[r - 1][l + 1], tSW = F[r - 1][l - 1];
+                    const double dTx = (tE - tW) * (1.0 / 3.0) + (tNE - tNW + tSE - tSW) * (1.0 / 12.0);
+                    const double dTy = (tN - tS) * (1.0 / 3.0) + (tNE + tNW - tSE - tSW) * (1.0 / 12.0);
                     acc[m][0] += g * dTx;       // chi RI applied at the end
                     acc[m][1] += g * dTy;
                     acc[m][2] += g * Tv;        // div v part: -g T (IA - IB d1)
@@ -621,7 +623,7 @@ __global__ __launch_bounds__(NTA) void a_lb(A_ARGS, int k, int cur)
                 bool ok;
                 const size_t cp = a_src(P, gi, gj, a, c, ok);
                 const double m = ok ? 3.0 * kW[a] : 0.0;
-                tr += m * (kEX[a] * w.gDrx[cp] + kEY[a] * w.gDry[cp]);
+                tr += m * (kEX[a] * (double)w.gDrx[cp] + kEY[a] * (double)w.gDry[cp]);
                 const double gd = w.gdiv[cp];
                 tu += m * kEX[a] * gd;
                 tv += m * kEY[a] * gd;
@@ -802,7 +804,7 @@ __global__ __launch_bounds__(NTA) void a_final(A_ARGS, int k, int cur, double wq
             bool ok;
             const size_t cp = a_src(P, gi, gj, a, c, ok);
             const double m = ok ? kWpsi[a] : 0.0;
-            gpsi += m * (kEX[a] * w.gsx[cp] + kEY[a] * w.gsy[cp]);
+            gpsi += m * (kEX[a] * (double)w.gsx[cp] + kEY[a] * (double)w.gsy[cp]);
         }
         double gr = w.grho[c] + sr / ((double)P.nx * (double)P.ny);
         double gT = 0.0;
