@@ -10,7 +10,7 @@ T_s + 0.14 T_c, where vapour forms on the heater, G_w = 0.065, g = 3e-5) for
     8000), the window the GPU test compares with,
   * the total mass and the vapour fraction of the two fluid rows next to the
     heater after step 16000.
-Only the oracle and the seeded input generator are used.  Takes about twenty
+Only the oracle and the seeded input generator are used.  Takes about twelve
 minutes on 8 cores.
 
     python tests/golden/make_oracle_pool3d_long_run.py
