@@ -74,8 +74,8 @@ MEASURED_TRAFFIC = {
 }
 
 # The same counters for the seven launches of one 3-D step (150x151x150 pool,
-# FP32 storage; KiB per dispatch), valid for the 3-D kernel source whose hash
-# is recorded.
+# FP32 storage; KiB per dispatch), valid for the 3-D kernel and host sources
+# whose hash is recorded (the host source sets the first stage's plane runs).
 MEASURED_TRAFFIC_3D = {
     "source_hash": "c97ad07e51234cee",
     "pool3d_150x151x150_fp32": {
